@@ -1,0 +1,192 @@
+/*
+ * pbgpu: MI355X (gfx950) solver for the linear finite-difference
+ * Poisson-Boltzmann equation by Jacobi-preconditioned conjugate gradient.
+ *
+ * The system is Eq. 3 of Qi, Botello-Smith and Luo, "Acceleration of Linear
+ * Finite-Difference Poisson-Boltzmann Methods on Graphics Processing Units"
+ * (section 2.1): the 7-point stencil with edge dielectrics eps_i, eps_j,
+ * eps_k between neighbouring nodes, a diagonal salt term kappa^2 and a
+ * right-hand side h^-3 q(i,j,k). It is solved by the preconditioned CG of
+ * section 2.2 with M = diag(A) (section 2.4).
+ *
+ * Conventions shared by every entry point:
+ *   - Grid nx*ny*nz; every node is an unknown. Node (i,j,k) sits at
+ *     origin + h*(i,j,k) (Angstrom) and has flat index i + nx*(j + ny*k)
+ *     (x fastest). Dirichlet values live on a ghost layer one h outside.
+ *   - Units are Gaussian: the operator is -div(eps grad phi) + kbar^2 phi
+ *     and the right-hand side is 4*pi*q_node/h^3 plus the boundary terms, so
+ *     phi is in e/Angstrom; energies are returned in kcal/mol.
+ *   - Every array argument is a DEVICE pointer owned by the caller, 8-byte
+ *     aligned, unless marked "host". The library never frees caller memory.
+ *     Workspaces are caller-allocated device memory of at least the size
+ *     the matching *_workspace_bytes query returns (256-byte aligned).
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Work is enqueued on that stream. Entry points that return results to
+ *     the host (pb_solve with info, pb_energy) synchronise the stream.
+ *   - Arguments are validated before any launch; a bad argument returns
+ *     PB_ERR_ARG and touches no memory. pb_last_error() then describes it.
+ *   - All reductions run in a fixed order: the same inputs give bitwise
+ *     identical outputs on every call.
+ */
+#ifndef PBGPU_H
+#define PBGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PB_OK = 0,
+    PB_NOT_CONVERGED = 1,   /* maxiter (or refinement stagnation) reached; x holds the last iterate */
+    PB_ERR_ARG = -1,        /* invalid argument (dims, pointers, sizes, negative dielectric, ...) */
+    PB_ERR_BREAKDOWN = -2,  /* p.Ap <= 0 or non-finite during CG; x holds the last good iterate */
+    PB_ERR_NONFINITE = -3,  /* NaN/Inf in the right-hand side or the initial guess */
+    PB_ERR_NOMEM = -4,      /* workspace smaller than required */
+    PB_ERR_HIP = -5,        /* a HIP runtime call failed */
+    PB_ERR_TIMEOUT = -6     /* a device-side wait exceeded its bound (the kernel exited cleanly) */
+} pb_status;
+
+typedef enum {
+    PB_F64 = 0,             /* FP64 coefficients, state and arithmetic */
+    PB_F32 = 1,             /* FP32 coefficients and state; dot products accumulated in FP64 */
+    PB_F32_REFINE64 = 2     /* FP32 inner JPCG inside an FP64 iterative-refinement loop */
+} pb_precision;
+
+typedef enum {
+    PB_OP_STENCIL = 0,      /* matrix-free stencil fused into one persistent JPCG kernel */
+    PB_OP_DIA = 1           /* 7-diagonal (DIA) SpMV and separate vector kernels, host-driven loop */
+} pb_operator;
+
+typedef struct {
+    int32_t nx, ny, nz;     /* nodes per axis (>= 2 for pb_setup / pb_energy, >= 1 for pb_solve) */
+    int32_t reserved;
+    double h;               /* grid spacing, Angstrom (> 0) */
+    double origin[3];       /* position of node (0,0,0), Angstrom */
+} pb_grid;
+
+typedef struct {
+    double tol;             /* stop when ||r||/||b|| < tol (strict, recurrence residual; outer residual for REFINE64) */
+    int32_t maxiter;        /* CG iteration limit (per inner solve for REFINE64); <= 0 selects 10*max(nx,ny,nz) */
+    int32_t precision;      /* pb_precision */
+    int32_t op;             /* pb_operator */
+    int32_t warm_start;     /* nonzero: x holds the initial guess on entry; zero: start from x = 0 */
+    double inner_tol;       /* REFINE64: inner tolerance relative to the current outer residual; 0 selects 1e-4 */
+    int32_t max_outer;      /* REFINE64: outer step limit; 0 selects 20 */
+    int32_t reserved;
+} pb_solve_opts;
+
+typedef struct {
+    int32_t iters;          /* CG iterations (summed over inner solves for REFINE64) */
+    int32_t outer_iters;    /* refinement steps (0 for plain solves) */
+    int32_t status;         /* pb_status of the solve */
+    int32_t reserved;
+    double relres_recur;    /* recurrence residual ||r||/||b|| at exit (outer FP64 residual for REFINE64) */
+    double relres_true;     /* ||b - A x||/||b|| recomputed in FP64 with the FP64 coefficients */
+    double seconds;         /* wall time of the call */
+} pb_info;
+
+/* Library version string (static storage). */
+const char* pb_version(void);
+
+/* Description of the last error on the calling thread (static storage per thread). */
+const char* pb_last_error(void);
+
+/*
+ * Device workspace needed by pb_setup for this grid and atom count.
+ * Returns 0 for invalid arguments.
+ */
+size_t pb_setup_workspace_bytes(const pb_grid* grid, int64_t natoms);
+
+/*
+ * pb_setup: build the linear system of Eq. 3 from atoms (section 2.7).
+ *
+ *   xyz[3*natoms]       atom centres (x,y,z interleaved), Angstrom
+ *   radius[natoms]      sphere radii, Angstrom
+ *   charge[natoms]      partial charges, e
+ *   eps_in, eps_out     solute / solvent dielectric constants (> 0)
+ *   kappa_d2            Debye screening constant kappa_D^2, Angstrom^-2 (>= 0; 0 = no salt)
+ * Outputs (device, written completely):
+ *   eps_x[(nx+1)*ny*nz] edge dielectric; entry e + (nx+1)*(j + ny*k) is the
+ *                       edge between nodes (e-1,j,k) and (e,j,k), e = 0..nx
+ *                       (index -1 and nx are ghost nodes)
+ *   eps_y[nx*(ny+1)*nz] entry i + nx*(e + (ny+1)*k): nodes (i,e-1,k)-(i,e,k)
+ *   eps_z[nx*ny*(nz+1)] entry i + nx*(j + ny*e):     nodes (i,j,e-1)-(i,j,e)
+ *   kappa2[N]           kbar^2 = eps_out*kappa_D^2 at solvent nodes, 0 inside
+ *   rhs[N]              4*pi*q_node/h^3 + Debye-Hueckel Dirichlet boundary terms
+ *   qgrid[N]            (nullable) the spread node charges q(i,j,k), e
+ *   mask[(nx+2)*(ny+2)*(nz+2)] (nullable) 1 where the node (ghosts included,
+ *                       padded index (i+1) + (nx+2)*((j+1) + (ny+2)*(k+1)))
+ *                       lies strictly inside an atom sphere, else 0
+ * Steps: node classification (|x-c|^2 < R^2 in FP64, no contraction), node
+ * dielectric eps_in/eps_out, two-point harmonic edge means 2ab/(a+b),
+ * trilinear charge spreading (g = (c-o)/h, i0 = clamp(floor g, 0, n-2)),
+ * and the screened Coulomb sum sum_a q_a exp(-kappa_D d)/(eps_out d) on the
+ * six ghost faces folded into rhs through the ghost-side edge dielectric.
+ * Errors: PB_ERR_ARG for dims < 2, h <= 0, natoms < 0 or > 2^21-1, null
+ * required pointers, eps <= 0, kappa_d2 < 0, or an atom centre outside the
+ * node box (checked on the device; outputs are then undefined).
+ */
+pb_status pb_setup(const pb_grid* grid, int64_t natoms,
+                   const double* xyz, const double* radius, const double* charge,
+                   double eps_in, double eps_out, double kappa_d2,
+                   double* eps_x, double* eps_y, double* eps_z,
+                   double* kappa2, double* rhs, double* qgrid, uint8_t* mask,
+                   void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Device workspace needed by pb_solve for this grid and option set
+ * (precision and operator). Returns 0 for invalid arguments.
+ */
+size_t pb_solve_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, const pb_solve_opts* opts);
+
+/*
+ * pb_solve: Jacobi-preconditioned CG (section 2.2 with M = diag(A), section
+ * 2.4) on the system of Eq. 3 given by the arrays pb_setup writes:
+ *   eps_x, eps_y, eps_z  staggered edge dielectrics (layouts as in pb_setup), >= 0
+ *   kappa2[N]            kbar^2 per node, >= 0
+ *   rhs[N]               right-hand side (boundary terms already folded in)
+ *   x[N]                 in: initial guess when opts->warm_start, else ignored;
+ *                        out: the potential phi
+ * The library applies the 1/h^2 factor. With precision PB_F32 the
+ * coefficients are rounded to FP32; PB_F32_REFINE64 repeats
+ * { r = b - A x in FP64; FP32 JPCG on A d = r to opts->inner_tol; x += d }
+ * until the FP64 residual is below opts->tol.
+ * A zero right-hand side returns x = 0 after 0 iterations.
+ * info (host, nullable) receives the iteration counts and residuals.
+ * Errors: PB_ERR_ARG (dims < 1, h <= 0, tol <= 0, null pointers, negative
+ * or non-finite coefficients), PB_ERR_NOMEM (workspace too small),
+ * PB_ERR_NONFINITE (NaN/Inf in rhs or guess), PB_ERR_BREAKDOWN,
+ * PB_NOT_CONVERGED, PB_ERR_TIMEOUT, PB_ERR_HIP.
+ */
+pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h,
+                   const double* eps_x, const double* eps_y, const double* eps_z,
+                   const double* kappa2, const double* rhs, double* x,
+                   const pb_solve_opts* opts,
+                   void* workspace, size_t workspace_bytes, void* stream,
+                   pb_info* info);
+
+/* Device workspace needed by pb_energy. Returns 0 for invalid arguments. */
+size_t pb_energy_workspace_bytes(int64_t natoms);
+
+/*
+ * pb_energy: electrostatic energy 1/2 sum_a q_a phi(c_a) in kcal/mol
+ * (section 3.1 reports energies), with phi(c_a) the trilinear interpolation
+ * of x at the atom centre using the spreading weights of pb_setup.
+ *   x[N]           the potential (device)
+ *   atom_phi       (nullable, device, natoms) receives phi(c_a)
+ *   energy         (host) receives the energy
+ * The atom sum runs in a fixed order. Errors: PB_ERR_ARG as for pb_setup.
+ */
+pb_status pb_energy(const pb_grid* grid, int64_t natoms,
+                    const double* xyz, const double* charge, const double* x,
+                    double* atom_phi, double* energy,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PBGPU_H */

@@ -1,0 +1,228 @@
+"""pbgpu: linear finite-difference Poisson-Boltzmann solver for MI355X.
+
+Thin Python binding over the C ABI in include/pbgpu.h (libpbgpu.so, built
+in-tree for gfx950). This module only marshals arguments: every step of the
+computation runs in the HIP library. PyTorch provides device memory and the
+current stream. If the library is missing, importing this package raises.
+
+    sysm = pbgpu.setup(grid, xyz, radius, charge)        # section 2.7 setup
+    x, info = pbgpu.solve(sysm, tol=1e-6, precision="f32")  # Jacobi PCG
+    e = pbgpu.energy(grid, xyz, charge, x)                # kcal/mol
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpbgpu.so")
+
+PB_OK, PB_NOT_CONVERGED = 0, 1
+PB_ERR_ARG, PB_ERR_BREAKDOWN, PB_ERR_NONFINITE = -1, -2, -3
+PB_ERR_NOMEM, PB_ERR_HIP, PB_ERR_TIMEOUT = -4, -5, -6
+STATUS_NAMES = {0: "PB_OK", 1: "PB_NOT_CONVERGED", -1: "PB_ERR_ARG", -2: "PB_ERR_BREAKDOWN",
+                -3: "PB_ERR_NONFINITE", -4: "PB_ERR_NOMEM", -5: "PB_ERR_HIP", -6: "PB_ERR_TIMEOUT"}
+PRECISIONS = {"f64": 0, "f32": 1, "f32_refine64": 2}
+OPERATORS = {"stencil": 0, "dia": 1}
+
+# Every entry point declared in include/pbgpu.h.
+EXPORTS = ("pb_version", "pb_last_error", "pb_setup_workspace_bytes", "pb_setup",
+           "pb_solve_workspace_bytes", "pb_solve", "pb_energy_workspace_bytes", "pb_energy")
+
+
+class PBError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("h", ctypes.c_double),
+                ("origin", ctypes.c_double * 3)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("op", ctypes.c_int32),
+                ("warm_start", ctypes.c_int32), ("inner_tol", ctypes.c_double),
+                ("max_outer", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("relres_recur", ctypes.c_double), ("relres_true", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"pbgpu: {LIB_PATH} is not built; run paper_1704_02745_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, sz, i32, i64, dbl = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    G = ctypes.POINTER(Grid)
+    lib.pb_version.restype = ctypes.c_char_p
+    lib.pb_version.argtypes = []
+    lib.pb_last_error.restype = ctypes.c_char_p
+    lib.pb_last_error.argtypes = []
+    lib.pb_setup_workspace_bytes.restype = sz
+    lib.pb_setup_workspace_bytes.argtypes = [G, i64]
+    lib.pb_setup.restype = ctypes.c_int
+    lib.pb_setup.argtypes = [G, i64, vp, vp, vp, dbl, dbl, dbl, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.pb_solve_workspace_bytes.restype = sz
+    lib.pb_solve_workspace_bytes.argtypes = [i32, i32, i32, ctypes.POINTER(SolveOpts)]
+    lib.pb_solve.restype = ctypes.c_int
+    lib.pb_solve.argtypes = [i32, i32, i32, dbl, vp, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
+                             vp, sz, vp, ctypes.POINTER(Info)]
+    lib.pb_energy_workspace_bytes.restype = sz
+    lib.pb_energy_workspace_bytes.argtypes = [i64]
+    lib.pb_energy.restype = ctypes.c_int
+    lib.pb_energy.argtypes = [G, i64, vp, vp, vp, vp, ctypes.POINTER(dbl), vp, sz, vp]
+    return lib
+
+
+lib = _load()
+
+
+def version() -> str:
+    return lib.pb_version().decode()
+
+
+def last_error() -> str:
+    return lib.pb_last_error().decode()
+
+
+def _check(status: int, allow=(PB_OK,)):
+    if status not in allow:
+        raise PBError(status, last_error())
+    return status
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev64(a, device) -> torch.Tensor:
+    t = torch.as_tensor(a, dtype=torch.float64)
+    return t.to(device).contiguous()
+
+
+def make_grid(nx, ny, nz, h, origin) -> Grid:
+    g = Grid()
+    g.nx, g.ny, g.nz, g.h = int(nx), int(ny), int(nz), float(h)
+    for d in range(3):
+        g.origin[d] = float(origin[d])
+    return g
+
+
+def as_grid(grid) -> Grid:
+    if isinstance(grid, Grid):
+        return grid
+    return make_grid(grid.nx, grid.ny, grid.nz, grid.h, grid.origin)
+
+
+@dataclasses.dataclass
+class System:
+    """Device arrays of the linear system (layouts as in include/pbgpu.h)."""
+    grid: Grid
+    eps_x: torch.Tensor
+    eps_y: torch.Tensor
+    eps_z: torch.Tensor
+    kappa2: torch.Tensor
+    rhs: torch.Tensor
+    qgrid: Optional[torch.Tensor] = None
+    mask: Optional[torch.Tensor] = None
+
+    @property
+    def dims(self):
+        return self.grid.nx, self.grid.ny, self.grid.nz
+
+
+def setup(grid, xyz, radius, charge, eps_in=1.0, eps_out=80.0, kappa_d2=0.0,
+          device="cuda", want_q=False, want_mask=False, stream=None) -> System:
+    g = as_grid(grid)
+    nx, ny, nz = g.nx, g.ny, g.nz
+    xyz_t = _dev64(xyz, device).reshape(-1)
+    rad_t = _dev64(radius, device)
+    q_t = _dev64(charge, device)
+    natoms = rad_t.numel()
+    opt = dict(dtype=torch.float64, device=device)
+    ex = torch.empty((nz, ny, nx + 1), **opt)
+    ey = torch.empty((nz, ny + 1, nx), **opt)
+    ez = torch.empty((nz + 1, ny, nx), **opt)
+    k2 = torch.empty((nz, ny, nx), **opt)
+    b = torch.empty((nz, ny, nx), **opt)
+    qg = torch.empty((nz, ny, nx), **opt) if want_q else None
+    mk = torch.empty((nz + 2, ny + 2, nx + 2), dtype=torch.uint8, device=device) if want_mask else None
+    wsb = lib.pb_setup_workspace_bytes(ctypes.byref(g), natoms)
+    if wsb == 0:
+        raise PBError(PB_ERR_ARG, "pb_setup_workspace_bytes rejected the grid / atom count")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=device)
+    st = lib.pb_setup(ctypes.byref(g), natoms, _ptr(xyz_t), _ptr(rad_t), _ptr(q_t), float(eps_in),
+                      float(eps_out), float(kappa_d2), _ptr(ex), _ptr(ey), _ptr(ez), _ptr(k2), _ptr(b),
+                      _ptr(qg), _ptr(mk), _ptr(ws), wsb, _stream(stream))
+    _check(st)
+    return System(g, ex, ey, ez, k2, b, qg, mk)
+
+
+def solve_workspace_bytes(nx, ny, nz, precision="f32", op="stencil", tol=1e-6) -> int:
+    o = SolveOpts()
+    o.tol, o.precision, o.op = tol, PRECISIONS[precision], OPERATORS[op]
+    return int(lib.pb_solve_workspace_bytes(nx, ny, nz, ctypes.byref(o)))
+
+
+def solve(sysm: System, tol=1e-6, precision="f32", op="stencil", maxiter=0, x0=None,
+          inner_tol=0.0, max_outer=0, workspace: Optional[torch.Tensor] = None, out=None,
+          stream=None, check=True):
+    """Jacobi PCG on the system. Returns (x, info dict). Raises PBError on a
+    negative status (and on PB_NOT_CONVERGED when check is true)."""
+    nx, ny, nz = sysm.dims
+    o = SolveOpts()
+    o.tol, o.maxiter = float(tol), int(maxiter)
+    o.precision, o.op = PRECISIONS[precision], OPERATORS[op]
+    o.warm_start = 1 if x0 is not None else 0
+    o.inner_tol, o.max_outer = float(inner_tol), int(max_outer)
+    wsb = lib.pb_solve_workspace_bytes(nx, ny, nz, ctypes.byref(o))
+    if wsb == 0:
+        raise PBError(PB_ERR_ARG, "pb_solve_workspace_bytes rejected the options")
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=sysm.rhs.device)
+    if out is None:
+        out = torch.empty((nz, ny, nx), dtype=torch.float64, device=sysm.rhs.device)
+    if x0 is not None:
+        out.copy_(torch.as_tensor(x0, dtype=torch.float64).reshape(nz, ny, nx))
+    info = Info()
+    st = lib.pb_solve(nx, ny, nz, sysm.grid.h, _ptr(sysm.eps_x), _ptr(sysm.eps_y), _ptr(sysm.eps_z),
+                      _ptr(sysm.kappa2), _ptr(sysm.rhs), _ptr(out), ctypes.byref(o), _ptr(workspace),
+                      workspace.numel(), _stream(stream), ctypes.byref(info))
+    _check(st, allow=(PB_OK,) if check else (PB_OK, PB_NOT_CONVERGED))
+    return out, info.as_dict()
+
+
+def energy(grid, xyz, charge, x: torch.Tensor, atom_phi: Optional[torch.Tensor] = None,
+           stream=None) -> float:
+    g = as_grid(grid)
+    dev = x.device
+    xyz_t = _dev64(xyz, dev).reshape(-1)
+    q_t = _dev64(charge, dev)
+    natoms = q_t.numel()
+    wsb = lib.pb_energy_workspace_bytes(natoms)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    e = ctypes.c_double(0.0)
+    st = lib.pb_energy(ctypes.byref(g), natoms, _ptr(xyz_t), _ptr(q_t), _ptr(x), _ptr(atom_phi),
+                       ctypes.byref(e), _ptr(ws), wsb, _stream(stream))
+    _check(st)
+    return float(e.value)

@@ -1,0 +1,258 @@
+// C-ABI entry points of the solve, argument checking and error reporting.
+#include "solver.hpp"
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+
+namespace pb {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+namespace {
+
+struct SolveWs {
+    SyncState* sync;
+    double* partials;
+    double* small;        // 16 doubles of device scratch
+    Op<double> op64;
+    double* b64;
+    double* x64;
+    double* res64;        // residual partials / scratch (npad)
+    // FP64 state (PB_F64)
+    SolveBufs<double> s64;
+    // FP32 state (PB_F32, PB_F32_REFINE64)
+    SolveBufs<float> s32;
+    SyncState* dia_sync;
+    size_t bytes;
+};
+
+SolveWs carve_solve(void* base, const Layout& L, int prec, int op) {
+    SolveWs w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return base ? (void*)((char*)base + o) : nullptr;
+    };
+    const size_t n8 = sizeof(double) * (size_t)L.npad;
+    const size_t n4 = sizeof(float) * (size_t)L.npad;
+    w.sync = (SyncState*)take(sizeof(SyncState));
+    w.dia_sync = (SyncState*)take(sizeof(SyncState));
+    w.small = (double*)take(16 * sizeof(double));
+    w.partials = (double*)take(sizeof(double) * kMaxPartials * (size_t)kMaxTiles);
+    w.op64.cx = (double*)take(n8);
+    w.op64.cy = (double*)take(n8);
+    w.op64.cz = (double*)take(n8);
+    w.op64.d = (double*)take(n8);
+    w.b64 = (double*)take(n8);
+    w.x64 = (double*)take(n8);
+    w.res64 = (double*)take(n8);
+    if (prec == PB_F64) {
+        SolveBufs<double>& s = w.s64;
+        s.op = w.op64;
+        s.b = w.b64;
+        s.x = w.x64;
+        s.r = (double*)take(n8);
+        s.p0 = (double*)take(n8);
+        s.p1 = (double*)take(n8);
+        s.q = (double*)take(n8);
+        if (op == PB_OP_DIA) {
+            s.z = (double*)take(n8);
+            s.dia = (double*)take(7 * n8);
+        }
+    } else {
+        SolveBufs<float>& s = w.s32;
+        s.op.cx = (float*)take(n4);
+        s.op.cy = (float*)take(n4);
+        s.op.cz = (float*)take(n4);
+        s.op.d = (float*)take(n4);
+        s.b = (float*)take(n4);
+        s.x = (float*)take(n4);
+        s.r = (float*)take(n4);
+        s.p0 = (float*)take(n4);
+        s.p1 = (float*)take(n4);
+        s.q = (float*)take(n4);
+        if (op == PB_OP_DIA) {
+            s.z = (float*)take(n4);
+            s.dia = (float*)take(7 * n4);
+        }
+    }
+    w.bytes = off;
+    return w;
+}
+
+bool opts_ok(const pb_solve_opts* o) {
+    return o && std::isfinite(o->tol) && o->tol > 0 && o->precision >= PB_F64 &&
+           o->precision <= PB_F32_REFINE64 && (o->op == PB_OP_STENCIL || o->op == PB_OP_DIA) &&
+           o->inner_tol >= 0 && o->inner_tol < 1 && o->max_outer >= 0;
+}
+
+bool dims_ok(int nx, int ny, int nz) {
+    return nx >= 1 && ny >= 1 && nz >= 1 && (int64_t)nx * ny * nz < (int64_t(1) << 36);
+}
+
+template <typename T>
+pb_status run_inner(const Layout& L, const SolveBufs<T>& s, const SolveWs& w, int op, double tol, int maxiter,
+                    hipStream_t st, SolveResult* r) {
+    if (op == PB_OP_DIA) return dia_jpcg_impl<T>(L, s, w.dia_sync, w.partials, tol, maxiter, st, r);
+    return fused_jpcg<T>(L, s, w.sync, w.partials, tol, maxiter, st, r, nullptr);
+}
+
+// FP64 residual r = b - A x; returns ||r||^2 and ||b||^2 on the host.
+pb_status residual(const Layout& L, const SolveWs& w, float* r32, double& rr, double& bb, hipStream_t st) {
+    pb_status e = launch_residual64(w.op64, w.b64, w.x64, L, nullptr, r32, w.res64, w.small, st);
+    if (e != PB_OK) return e;
+    double h[2];
+    PB_HIP(hipMemcpyAsync(h, w.small, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    PB_HIP(hipStreamSynchronize(st));
+    rr = h[0];
+    bb = h[1];
+    return PB_OK;
+}
+
+}  // namespace
+
+}  // namespace pb
+
+using namespace pb;
+
+extern "C" const char* pb_version(void) { return "pbgpu 0.1 (gfx950)"; }
+
+extern "C" const char* pb_last_error(void) { return g_err; }
+
+extern "C" size_t pb_solve_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, const pb_solve_opts* opts) {
+    if (!dims_ok(nx, ny, nz) || !opts_ok(opts)) return 0;
+    return carve_solve(nullptr, make_layout(nx, ny, nz), opts->precision, opts->op).bytes;
+}
+
+extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, const double* eps_x,
+                              const double* eps_y, const double* eps_z, const double* kappa2, const double* rhs,
+                              double* x, const pb_solve_opts* opts, void* workspace, size_t workspace_bytes,
+                              void* stream_, pb_info* info) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (info) std::memset(info, 0, sizeof(*info));
+    PB_ARG(dims_ok(nx, ny, nz), "pb_solve: dims must be >= 1 (and below 2^36 nodes)");
+    PB_ARG(std::isfinite(h) && h > 0, "pb_solve: h must be finite and > 0");
+    PB_ARG(opts_ok(opts), "pb_solve: invalid options (tol > 0, precision, operator, inner_tol in [0,1), max_outer >= 0)");
+    PB_ARG(eps_x && eps_y && eps_z && kappa2 && rhs && x, "pb_solve: null array");
+    PB_ARG(workspace != nullptr, "pb_solve: null workspace");
+    PB_ARG(((uintptr_t)workspace & 255) == 0, "pb_solve: workspace must be 256-byte aligned");
+    const Layout L = make_layout(nx, ny, nz);
+    const int prec = opts->precision, op = opts->op;
+    SolveWs w = carve_solve(workspace, L, prec, op);
+    if (workspace_bytes < w.bytes) {
+        set_error("pb_solve: workspace of %zu bytes, %zu needed", workspace_bytes, w.bytes);
+        return PB_ERR_NOMEM;
+    }
+    const int maxiter = opts->maxiter > 0 ? opts->maxiter : 10 * std::max(nx, std::max(ny, nz));
+    hipStream_t st = (hipStream_t)stream_;
+
+    // convert the caller's arrays into the padded FP64 operator and check them
+    int* flags = (int*)w.small;
+    pb_status e = launch_fill<int>(flags, 1, 0, st);
+    if (e != PB_OK) return e;
+    e = launch_prepare64(eps_x, eps_y, eps_z, kappa2, rhs, x, opts->warm_start ? 1 : 0, L, h, w.op64, w.b64,
+                         w.x64, flags, st);
+    if (e != PB_OK) return e;
+    int hflags = 0;
+    PB_HIP(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, st));
+    PB_HIP(hipStreamSynchronize(st));
+    if (hflags & FLAG_BAD_COEF) {
+        set_error("pb_solve: negative or non-finite coefficient, or non-positive diagonal");
+        return PB_ERR_ARG;
+    }
+    if (hflags & (FLAG_BAD_RHS | FLAG_BAD_GUESS)) {
+        set_error("pb_solve: NaN/Inf in the right-hand side or the initial guess");
+        return PB_ERR_NONFINITE;
+    }
+
+    SolveResult r{};
+    int total_iters = 0, outer = 0;
+    double relres_recur = 0.0;
+    pb_status status = PB_OK;
+    if (prec == PB_F64) {
+        SolveBufs<double> s = w.s64;
+        s.warm = opts->warm_start ? 1 : 0;
+        e = run_inner<double>(L, s, w, op, opts->tol, maxiter, st, &r);
+        if (e != PB_OK) return e;
+        status = (pb_status)r.status;
+        total_iters = r.iters;
+        relres_recur = r.bb > 0 ? std::sqrt(r.rr) / std::sqrt(r.bb) : 0.0;
+    } else if (prec == PB_F32) {
+        SolveBufs<float> s = w.s32;
+        s.warm = opts->warm_start ? 1 : 0;
+        e = launch_round32(w.op64, w.b64, w.x64, L.npad, s.op, (float*)s.b, s.x, st);
+        if (e != PB_OK) return e;
+        e = run_inner<float>(L, s, w, op, opts->tol, maxiter, st, &r);
+        if (e != PB_OK) return e;
+        status = (pb_status)r.status;
+        total_iters = r.iters;
+        relres_recur = r.bb > 0 ? std::sqrt(r.rr) / std::sqrt(r.bb) : 0.0;
+        e = launch_f32_to_f64(s.x, w.x64, L.npad, st);
+        if (e != PB_OK) return e;
+    } else {
+        // iterative refinement: FP64 residual, FP32 correction solve, FP64 update
+        SolveBufs<float> s = w.s32;
+        s.warm = 0;
+        e = launch_round32(w.op64, w.b64, w.x64, L.npad, s.op, nullptr, nullptr, st);
+        if (e != PB_OK) return e;
+        const double inner_tol = opts->inner_tol > 0 ? opts->inner_tol : 1e-4;
+        const int max_outer = opts->max_outer > 0 ? opts->max_outer : 20;
+        double rr = 0, bb = 0, rr_prev = -1;
+        status = PB_NOT_CONVERGED;
+        for (outer = 0;; ++outer) {
+            e = residual(L, w, (float*)s.b, rr, bb, st);
+            if (e != PB_OK) return e;
+            if (bb == 0.0) {
+                e = launch_fill<double>(w.x64, L.npad, 0.0, st);
+                if (e != PB_OK) return e;
+                relres_recur = 0.0;
+                status = PB_OK;
+                break;
+            }
+            relres_recur = std::sqrt(rr) / std::sqrt(bb);
+            if (!std::isfinite(relres_recur)) { status = PB_ERR_BREAKDOWN; break; }
+            if (relres_recur < opts->tol) { status = PB_OK; break; }
+            if (outer >= max_outer) break;
+            if (rr_prev >= 0 && rr > 0.25 * rr_prev) break;   // fell by less than 2x: stagnation
+            rr_prev = rr;
+            e = launch_fill<float>(s.x, L.npad, 0.0f, st);
+            if (e != PB_OK) return e;
+            e = run_inner<float>(L, s, w, op, inner_tol, maxiter, st, &r);
+            if (e != PB_OK) return e;
+            total_iters += r.iters;
+            if (r.status < 0) { status = (pb_status)r.status; break; }
+            e = launch_add_correction(w.x64, s.x, L.npad, st);
+            if (e != PB_OK) return e;
+        }
+    }
+    if (status == PB_ERR_TIMEOUT) set_error("pb_solve: a device-side wait timed out");
+    if (status == PB_ERR_BREAKDOWN) set_error("pb_solve: CG breakdown (p.Ap <= 0 or non-finite)");
+    if (status == PB_NOT_CONVERGED) set_error("pb_solve: not converged within the iteration limit");
+
+    // true FP64 residual of the returned potential, then hand x back
+    double rr = 0, bb = 0;
+    e = residual(L, w, nullptr, rr, bb, st);
+    if (e != PB_OK) return e;
+    e = launch_unpad<double>(w.x64, L, x, st);
+    if (e != PB_OK) return e;
+    PB_HIP(hipStreamSynchronize(st));
+    if (info) {
+        info->iters = total_iters;
+        info->outer_iters = outer;
+        info->status = status;
+        info->relres_recur = relres_recur;
+        info->relres_true = bb > 0 ? std::sqrt(rr) / std::sqrt(bb) : 0.0;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
+}

@@ -1,0 +1,536 @@
+// System setup on the GPU (section 2.7 of the paper; Eq. 3 right-hand side).
+//
+// This file is compiled with -ffp-contract=off: the node classification,
+// the edge means and the charge weights must round exactly as the plain
+// (unfused) arithmetic they are defined by.
+#include "pb_internal.hpp"
+
+#include <cmath>
+#include <vector>
+
+namespace pb {
+
+namespace {
+
+constexpr double kFourPi = 12.566370614359172;   // 4*pi rounded to double
+constexpr double kCoulombKcal = 332.0637133;     // e^2/(4 pi eps0), kcal A/mol
+constexpr int kMaxAtoms = (1 << 21) - 1;          // pair id = 8*atom + corner < 2^24
+
+__global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Node classification: one workgroup per atom walks the atom's bounding
+// window of padded nodes and marks the ones strictly inside the sphere.
+// Concurrent writers only ever store 1, so the result is order independent.
+__global__ void k_classify(const double* __restrict__ xyz, const double* __restrict__ radius,
+                           int64_t natoms, int nx, int ny, int nz, double h,
+                           double ox, double oy, double oz, uint8_t* __restrict__ mask) {
+    const int64_t a = blockIdx.x;
+    if (a >= natoms) return;
+    const double cx = xyz[3 * a], cy = xyz[3 * a + 1], cz = xyz[3 * a + 2];
+    const double r = radius[a];
+    const double rr = r * r;
+    const double o[3] = {ox, oy, oz};
+    const double c[3] = {cx, cy, cz};
+    const int n3[3] = {nx, ny, nz};
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        double l = floor((c[d] - r - o[d]) / h) - 1.0;
+        double u = ceil((c[d] + r - o[d]) / h) + 1.0;
+        l = fmin(fmax(l, -1.0), (double)n3[d]);
+        u = fmin(fmax(u, -1.0), (double)n3[d]);
+        lo[d] = (int)l;
+        hi[d] = (int)u;   // inclusive
+    }
+    const int wx = hi[0] - lo[0] + 1, wy = hi[1] - lo[1] + 1, wz = hi[2] - lo[2] + 1;
+    if (wx <= 0 || wy <= 0 || wz <= 0) return;
+    const int64_t total = (int64_t)wx * wy * wz;
+    const int64_t px = nx + 2, py = ny + 2;
+    for (int64_t t = threadIdx.x; t < total; t += blockDim.x) {
+        const int i = lo[0] + (int)(t % wx);
+        const int j = lo[1] + (int)((t / wx) % wy);
+        const int k = lo[2] + (int)(t / ((int64_t)wx * wy));
+        const double x = ox + h * (double)i;
+        const double y = oy + h * (double)j;
+        const double z = oz + h * (double)k;
+        const double dx = x - cx, dy = y - cy, dz = z - cz;
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        if (d2 < rr) mask[(i + 1) + px * ((j + 1) + py * (int64_t)(k + 1))] = 1;
+    }
+}
+
+__device__ __forceinline__ double node_eps(uint8_t m, double ein, double eout) {
+    return m ? ein : eout;
+}
+
+__device__ __forceinline__ double harmonic(double a, double b) {
+    return 2.0 * a * b / (a + b);
+}
+
+// Staggered edge dielectrics and the salt term, one thread per element.
+__global__ void k_edges(const uint8_t* __restrict__ mask, int nx, int ny, int nz,
+                        double ein, double eout, double kbar2,
+                        double* __restrict__ ex, double* __restrict__ ey,
+                        double* __restrict__ ez, double* __restrict__ k2) {
+    const int64_t px = nx + 2, py = ny + 2;
+    const int64_t nex = (int64_t)(nx + 1) * ny * nz;
+    const int64_t ney = (int64_t)nx * (ny + 1) * nz;
+    const int64_t nez = (int64_t)nx * ny * (nz + 1);
+    const int64_t nn = (int64_t)nx * ny * nz;
+    const int64_t total = nex + ney + nez + nn;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        if (t < nex) {
+            const int64_t e = t % (nx + 1);
+            const int64_t j = (t / (nx + 1)) % ny;
+            const int64_t k = t / ((int64_t)(nx + 1) * ny);
+            const int64_t base = px * ((j + 1) + py * (k + 1));
+            ex[t] = harmonic(node_eps(mask[base + e], ein, eout), node_eps(mask[base + e + 1], ein, eout));
+        } else if (t < nex + ney) {
+            const int64_t u = t - nex;
+            const int64_t i = u % nx;
+            const int64_t e = (u / nx) % (ny + 1);
+            const int64_t k = u / ((int64_t)nx * (ny + 1));
+            const int64_t a = (i + 1) + px * (e + py * (k + 1));
+            ey[u] = harmonic(node_eps(mask[a], ein, eout), node_eps(mask[a + px], ein, eout));
+        } else if (t < nex + ney + nez) {
+            const int64_t u = t - nex - ney;
+            const int64_t i = u % nx;
+            const int64_t j = (u / nx) % ny;
+            const int64_t e = u / ((int64_t)nx * ny);
+            const int64_t a = (i + 1) + px * ((j + 1) + py * e);
+            ez[u] = harmonic(node_eps(mask[a], ein, eout), node_eps(mask[a + px * py], ein, eout));
+        } else {
+            const int64_t u = t - nex - ney - nez;
+            const int64_t i = u % nx;
+            const int64_t j = (u / nx) % ny;
+            const int64_t k = u / ((int64_t)nx * ny);
+            const uint8_t m = mask[(i + 1) + px * ((j + 1) + py * (k + 1))];
+            k2[u] = m ? 0.0 : kbar2;
+        }
+    }
+}
+
+// Trilinear cell of one atom along one axis: i0 = clamp(floor(g), 0, n-2), f = g - i0.
+__device__ __forceinline__ bool cell_axis(double c, double o, double h, int n, int& i0, double& f) {
+    const double g = (c - o) / h;
+    if (!(g >= 0.0) || !(g <= (double)(n - 1))) return false;
+    double fl = floor(g);
+    fl = fmin(fmax(fl, 0.0), (double)(n - 2));
+    i0 = (int)fl;
+    f = g - fl;
+    return true;
+}
+
+// Charge spreading, step 1: one sort key per (atom, corner) pair,
+// key = node_index << 24 | (8*atom + corner). Sorting the keys groups the
+// contributions of each node in increasing atom order.
+__global__ void k_spread_keys(const double* __restrict__ xyz, int64_t natoms, int nx, int ny, int nz,
+                              double h, double ox, double oy, double oz,
+                              uint64_t* __restrict__ keys, int* __restrict__ flags) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= 8 * natoms) return;
+    const int64_t a = p >> 3;
+    const int c = (int)(p & 7);
+    int i0, j0, k0;
+    double fx, fy, fz;
+    bool ok = cell_axis(xyz[3 * a], ox, h, nx, i0, fx);
+    ok = cell_axis(xyz[3 * a + 1], oy, h, ny, j0, fy) && ok;
+    ok = cell_axis(xyz[3 * a + 2], oz, h, nz, k0, fz) && ok;
+    if (!ok) {
+        atomicOr(flags, 1);
+        keys[p] = ~0ull;
+        return;
+    }
+    const int64_t node = (int64_t)(i0 + (c & 1)) +
+                         (int64_t)nx * ((int64_t)(j0 + ((c >> 1) & 1)) + (int64_t)ny * (k0 + ((c >> 2) & 1)));
+    keys[p] = ((uint64_t)node << 24) | (uint64_t)p;
+}
+
+// One compare-exchange step of a bitonic sorting network (ascending).
+__global__ void k_bitonic_step(uint64_t* __restrict__ a, int64_t n, int64_t j, int64_t k) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t l = i ^ j;
+    if (l > i) {
+        const uint64_t x = a[i], y = a[l];
+        const bool up = (i & k) == 0;
+        if ((x > y) == up) {
+            a[i] = y;
+            a[l] = x;
+        }
+    }
+}
+
+// Charge spreading, step 2: the first key of each node's run sums the run in
+// key order (increasing atom index), starting from zero, and stores q_node.
+__global__ void k_spread_sum(const uint64_t* __restrict__ keys, int64_t npairs,
+                             const double* __restrict__ xyz, const double* __restrict__ charge,
+                             int nx, int ny, int nz, double h, double ox, double oy, double oz,
+                             double* __restrict__ q) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npairs) return;
+    const uint64_t key = keys[i];
+    if (key == ~0ull) return;
+    const uint64_t node = key >> 24;
+    if (i > 0 && (keys[i - 1] >> 24) == node) return;
+    double s = 0.0;
+    for (int64_t t = i; t < npairs; ++t) {
+        const uint64_t kt = keys[t];
+        if (kt == ~0ull || (kt >> 24) != node) break;
+        const int64_t p = (int64_t)(kt & 0xFFFFFFull);
+        const int64_t a = p >> 3;
+        const int c = (int)(p & 7);
+        int i0, j0, k0;
+        double fx, fy, fz;
+        cell_axis(xyz[3 * a], ox, h, nx, i0, fx);
+        cell_axis(xyz[3 * a + 1], oy, h, ny, j0, fy);
+        cell_axis(xyz[3 * a + 2], oz, h, nz, k0, fz);
+        const double wx = (c & 1) ? fx : 1.0 - fx;
+        const double wy = (c & 2) ? fy : 1.0 - fy;
+        const double wz = (c & 4) ? fz : 1.0 - fz;
+        s = s + charge[a] * wx * wy * wz;
+    }
+    q[node] = s;
+}
+
+// Ghost point `t` of the six faces (x-, x+, y-, y+, z-, z+), in that order;
+// within a face the faster index comes first (y then z, x then z, x then y).
+__device__ __forceinline__ void ghost_point(int64_t t, int nx, int ny, int nz, double h,
+                                            double ox, double oy, double oz,
+                                            double& px, double& py, double& pz) {
+    const int64_t fx = (int64_t)ny * nz, fy = (int64_t)nx * nz;
+    if (t < 2 * fx) {
+        const int side = t >= fx;
+        const int64_t u = t - side * fx;
+        px = ox + h * (side ? (double)nx : -1.0);
+        py = oy + h * (double)(u % ny);
+        pz = oz + h * (double)(u / ny);
+    } else if (t < 2 * fx + 2 * fy) {
+        const int64_t v = t - 2 * fx;
+        const int side = v >= fy;
+        const int64_t u = v - side * fy;
+        px = ox + h * (double)(u % nx);
+        py = oy + h * (side ? (double)ny : -1.0);
+        pz = oz + h * (double)(u / nx);
+    } else {
+        const int64_t fz = (int64_t)nx * ny;
+        const int64_t v = t - 2 * fx - 2 * fy;
+        const int side = v >= fz;
+        const int64_t u = v - side * fz;
+        px = ox + h * (double)(u % nx);
+        py = oy + h * (double)(u / nx);
+        pz = oz + h * (side ? (double)nz : -1.0);
+    }
+}
+
+// Debye-Hueckel potential on the face ghosts: each thread owns one ghost
+// point and sums over all atoms in index order; atoms are staged in LDS.
+// This is the arithmetic-bound part of setup (6 n^2 points x natoms terms).
+constexpr int kDhBlock = 256;
+__global__ __launch_bounds__(kDhBlock) void k_dh_faces(
+        const double* __restrict__ xyz, const double* __restrict__ charge, int64_t natoms,
+        int nx, int ny, int nz, double h, double ox, double oy, double oz,
+        double kd, double eout, double* __restrict__ ghost, int64_t nghost) {
+    __shared__ double sx[kDhBlock], sy[kDhBlock], sz[kDhBlock], sq[kDhBlock];
+    const int64_t t = (int64_t)blockIdx.x * kDhBlock + threadIdx.x;
+    double px = 0, py = 0, pz = 0;
+    if (t < nghost) ghost_point(t, nx, ny, nz, h, ox, oy, oz, px, py, pz);
+    double s = 0.0;
+    for (int64_t a0 = 0; a0 < natoms; a0 += kDhBlock) {
+        __syncthreads();
+        const int64_t a = a0 + threadIdx.x;
+        if (a < natoms) {
+            sx[threadIdx.x] = xyz[3 * a];
+            sy[threadIdx.x] = xyz[3 * a + 1];
+            sz[threadIdx.x] = xyz[3 * a + 2];
+            sq[threadIdx.x] = charge[a];
+        }
+        __syncthreads();
+        const int m = (int)min<int64_t>(kDhBlock, natoms - a0);
+        if (kd == 0.0) {
+            for (int b = 0; b < m; ++b) {
+                const double dx = px - sx[b], dy = py - sy[b], dz = pz - sz[b];
+                const double d = sqrt(dx * dx + dy * dy + dz * dz);
+                s = s + sq[b] / (eout * d);
+            }
+        } else {
+            for (int b = 0; b < m; ++b) {
+                const double dx = px - sx[b], dy = py - sy[b], dz = pz - sz[b];
+                const double d = sqrt(dx * dx + dy * dy + dz * dz);
+                s = s + sq[b] * exp(-kd * d) / (eout * d);
+            }
+        }
+    }
+    if (t < nghost) ghost[t] = s;
+}
+
+// Right-hand side: 4*pi*q/h^3 plus, for nodes on the box faces, the ghost
+// potential times the ghost-side edge dielectric over h^2 (x-, x+, y-, y+,
+// z-, z+ in that order).
+__global__ void k_rhs(const double* __restrict__ q, const double* __restrict__ ex,
+                      const double* __restrict__ ey, const double* __restrict__ ez,
+                      const double* __restrict__ ghost, int nx, int ny, int nz,
+                      double h3, double ih2, double* __restrict__ b) {
+    const int64_t nn = (int64_t)nx * ny * nz;
+    const int64_t fx = (int64_t)ny * nz, fy = (int64_t)nx * nz, fz = (int64_t)nx * ny;
+    const double* gxm = ghost;
+    const double* gxp = ghost + fx;
+    const double* gym = ghost + 2 * fx;
+    const double* gyp = gym + fy;
+    const double* gzm = gym + 2 * fy;
+    const double* gzp = gzm + fz;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = n % nx, j = (n / nx) % ny, k = n / fz;
+        double fold = 0.0;
+        if (i == 0) fold = fold + ex[(nx + 1) * (j + ny * k)] * ih2 * gxm[j + ny * k];
+        if (i == nx - 1) fold = fold + ex[nx + (nx + 1) * (j + ny * k)] * ih2 * gxp[j + ny * k];
+        if (j == 0) fold = fold + ey[i + (int64_t)nx * ((ny + 1) * k)] * ih2 * gym[i + nx * k];
+        if (j == ny - 1) fold = fold + ey[i + (int64_t)nx * (ny + (ny + 1) * k)] * ih2 * gyp[i + nx * k];
+        if (k == 0) fold = fold + ez[i + nx * j] * ih2 * gzm[i + nx * j];
+        if (k == nz - 1) fold = fold + ez[i + nx * j + fz * nz] * ih2 * gzp[i + nx * j];
+        b[n] = kFourPi * q[n] / h3 + fold;
+    }
+}
+
+// Potential at each atom centre by the spreading weights; product q_a*phi_a.
+__global__ void k_energy_atoms(const double* __restrict__ xyz, const double* __restrict__ charge,
+                               int64_t natoms, int nx, int ny, int nz, double h,
+                               double ox, double oy, double oz, const double* __restrict__ x,
+                               double* __restrict__ atom_phi, double* __restrict__ qphi,
+                               int* __restrict__ flags) {
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= natoms) return;
+    int i0, j0, k0;
+    double fx, fy, fz;
+    bool ok = cell_axis(xyz[3 * a], ox, h, nx, i0, fx);
+    ok = cell_axis(xyz[3 * a + 1], oy, h, ny, j0, fy) && ok;
+    ok = cell_axis(xyz[3 * a + 2], oz, h, nz, k0, fz) && ok;
+    if (!ok) {
+        atomicOr(flags, 1);
+        qphi[a] = 0.0;
+        if (atom_phi) atom_phi[a] = 0.0;
+        return;
+    }
+    double t[8];
+    for (int c = 0; c < 8; ++c) {
+        const double wx = (c & 1) ? fx : 1.0 - fx;
+        const double wy = (c & 2) ? fy : 1.0 - fy;
+        const double wz = (c & 4) ? fz : 1.0 - fz;
+        const int64_t node = (int64_t)(i0 + (c & 1)) +
+                             (int64_t)nx * ((int64_t)(j0 + ((c >> 1) & 1)) + (int64_t)ny * (k0 + ((c >> 2) & 1)));
+        t[c] = wx * wy * wz * x[node];
+    }
+    const double phi = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+    if (atom_phi) atom_phi[a] = phi;
+    qphi[a] = charge[a] * phi;
+}
+
+// Fixed-order sum of n doubles by one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_sum_fixed(const double* __restrict__ v, int64_t n,
+                                                    double* __restrict__ out) {
+    __shared__ double s[1024];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) acc += v[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = s[0];
+}
+
+inline int64_t next_pow2(int64_t v) {
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+inline unsigned blocks_for(int64_t n, int bs, int64_t cap = 65536) {
+    int64_t b = (n + bs - 1) / bs;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+struct SetupWs {
+    int* flags;
+    uint64_t* keys;
+    double* qgrid;
+    uint8_t* mask;
+    double* ghost;
+    size_t bytes;
+};
+
+SetupWs carve_setup(void* base, int nx, int ny, int nz, int64_t natoms) {
+    SetupWs w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const int64_t npairs = next_pow2(std::max<int64_t>(2, 8 * natoms));
+    const int64_t nn = (int64_t)nx * ny * nz;
+    const int64_t nmask = (int64_t)(nx + 2) * (ny + 2) * (nz + 2);
+    const int64_t ngh = 2 * ((int64_t)ny * nz + (int64_t)nx * nz + (int64_t)nx * ny);
+    size_t o_flags = take(256);
+    size_t o_keys = take(sizeof(uint64_t) * npairs);
+    size_t o_q = take(sizeof(double) * nn);
+    size_t o_mask = take((size_t)nmask);
+    size_t o_gh = take(sizeof(double) * ngh);
+    w.bytes = off;
+    if (base) {
+        char* b = (char*)base;
+        w.flags = (int*)(b + o_flags);
+        w.keys = (uint64_t*)(b + o_keys);
+        w.qgrid = (double*)(b + o_q);
+        w.mask = (uint8_t*)(b + o_mask);
+        w.ghost = (double*)(b + o_gh);
+    }
+    return w;
+}
+
+bool grid_ok(const pb_grid* g) {
+    return g && g->nx >= 2 && g->ny >= 2 && g->nz >= 2 && std::isfinite(g->h) && g->h > 0.0 &&
+           std::isfinite(g->origin[0]) && std::isfinite(g->origin[1]) && std::isfinite(g->origin[2]) &&
+           (int64_t)(g->nx + 2) * (g->ny + 2) * (int64_t)(g->nz + 2) < (int64_t(1) << 40);
+}
+
+}  // namespace
+
+}  // namespace pb
+
+using namespace pb;
+
+extern "C" size_t pb_setup_workspace_bytes(const pb_grid* g, int64_t natoms) {
+    if (!grid_ok(g) || natoms < 0 || natoms > kMaxAtoms) return 0;
+    return carve_setup(nullptr, g->nx, g->ny, g->nz, natoms).bytes;
+}
+
+extern "C" pb_status pb_setup(const pb_grid* g, int64_t natoms, const double* xyz,
+                              const double* radius, const double* charge, double eps_in,
+                              double eps_out, double kappa_d2, double* eps_x, double* eps_y,
+                              double* eps_z, double* kappa2, double* rhs, double* qgrid,
+                              uint8_t* mask, void* workspace, size_t workspace_bytes,
+                              void* stream_) {
+    PB_ARG(grid_ok(g), "pb_setup: grid needs nx,ny,nz >= 2, finite h > 0 and a finite origin");
+    PB_ARG(natoms >= 0 && natoms <= kMaxAtoms, "pb_setup: natoms must be in [0, 2^21-1]");
+    PB_ARG(natoms == 0 || (xyz && radius && charge), "pb_setup: null atom array");
+    PB_ARG(eps_x && eps_y && eps_z && kappa2 && rhs, "pb_setup: null output array");
+    PB_ARG(std::isfinite(eps_in) && std::isfinite(eps_out) && eps_in > 0 && eps_out > 0,
+           "pb_setup: dielectric constants must be finite and > 0");
+    PB_ARG(std::isfinite(kappa_d2) && kappa_d2 >= 0, "pb_setup: kappa_d2 must be finite and >= 0");
+    PB_ARG(workspace != nullptr, "pb_setup: null workspace");
+    const int nx = g->nx, ny = g->ny, nz = g->nz;
+    SetupWs w = carve_setup(workspace, nx, ny, nz, natoms);
+    if (workspace_bytes < w.bytes) {
+        set_error("pb_setup: workspace of %zu bytes, %zu needed", workspace_bytes, w.bytes);
+        return PB_ERR_NOMEM;
+    }
+    hipStream_t st = (hipStream_t)stream_;
+    const double h = g->h, ox = g->origin[0], oy = g->origin[1], oz = g->origin[2];
+    const int64_t nn = (int64_t)nx * ny * nz;
+    const int64_t nmask = (int64_t)(nx + 2) * (ny + 2) * (nz + 2);
+    const int64_t ngh = 2 * ((int64_t)ny * nz + (int64_t)nx * nz + (int64_t)nx * ny);
+    uint8_t* m = mask ? mask : w.mask;
+    double* q = qgrid ? qgrid : w.qgrid;
+
+    hipLaunchKernelGGL(k_fill_u8, dim3(1), dim3(64), 0, st, (uint8_t*)w.flags, (int64_t)256, (uint8_t)0);
+    hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(nmask, 256)), dim3(256), 0, st, m, nmask, (uint8_t)0);
+    if (natoms > 0)
+        hipLaunchKernelGGL(k_classify, dim3((unsigned)natoms), dim3(256), 0, st, xyz, radius, natoms,
+                           nx, ny, nz, h, ox, oy, oz, m);
+    const int64_t nedge = (int64_t)(nx + 1) * ny * nz + (int64_t)nx * (ny + 1) * nz +
+                          (int64_t)nx * ny * (nz + 1) + nn;
+    hipLaunchKernelGGL(k_edges, dim3(blocks_for(nedge, 256)), dim3(256), 0, st, m, nx, ny, nz,
+                       eps_in, eps_out, eps_out * kappa_d2, eps_x, eps_y, eps_z, kappa2);
+
+    // charges: keys, sort, per-node run sums
+    hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(nn, 256)), dim3(256), 0, st, q, nn, 0.0);
+    if (natoms > 0) {
+        const int64_t np = 8 * natoms;
+        const int64_t P = next_pow2(std::max<int64_t>(2, np));
+        hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(P, 256)), dim3(256), 0, st, w.keys, P, ~0ull);
+        hipLaunchKernelGGL(k_spread_keys, dim3(blocks_for(np, 256, 1 << 30)), dim3(256), 0, st, xyz,
+                           natoms, nx, ny, nz, h, ox, oy, oz, w.keys, w.flags);
+        for (int64_t k = 2; k <= P; k <<= 1)
+            for (int64_t j = k >> 1; j > 0; j >>= 1)
+                hipLaunchKernelGGL(k_bitonic_step, dim3(blocks_for(P, 256, 1 << 30)), dim3(256), 0, st,
+                                   w.keys, P, j, k);
+        hipLaunchKernelGGL(k_spread_sum, dim3(blocks_for(np, 256, 1 << 30)), dim3(256), 0, st, w.keys,
+                           np, xyz, charge, nx, ny, nz, h, ox, oy, oz, q);
+    }
+    // boundary potential on the face ghosts
+    hipLaunchKernelGGL(k_dh_faces, dim3(blocks_for(ngh, kDhBlock, 1 << 30)), dim3(kDhBlock), 0, st,
+                       xyz, charge, natoms, nx, ny, nz, h, ox, oy, oz, std::sqrt(kappa_d2), eps_out,
+                       w.ghost, ngh);
+    hipLaunchKernelGGL(k_rhs, dim3(blocks_for(nn, 256)), dim3(256), 0, st, q, eps_x, eps_y, eps_z,
+                       w.ghost, nx, ny, nz, std::pow(h, 3.0), 1.0 / (h * h), rhs);
+    PB_HIP(hipGetLastError());
+    int flags = 0;
+    PB_HIP(hipMemcpyAsync(&flags, w.flags, sizeof(int), hipMemcpyDeviceToHost, st));
+    PB_HIP(hipStreamSynchronize(st));
+    if (flags) {
+        set_error("pb_setup: an atom centre lies outside the node box");
+        return PB_ERR_ARG;
+    }
+    return PB_OK;
+}
+
+extern "C" size_t pb_energy_workspace_bytes(int64_t natoms) {
+    if (natoms < 0 || natoms > kMaxAtoms) return 0;
+    return 512 + align_up(sizeof(double) * (size_t)std::max<int64_t>(natoms, 1), 256);
+}
+
+extern "C" pb_status pb_energy(const pb_grid* g, int64_t natoms, const double* xyz,
+                               const double* charge, const double* x, double* atom_phi,
+                               double* energy, void* workspace, size_t workspace_bytes,
+                               void* stream_) {
+    PB_ARG(grid_ok(g), "pb_energy: grid needs nx,ny,nz >= 2, finite h > 0 and a finite origin");
+    PB_ARG(natoms >= 0 && natoms <= kMaxAtoms, "pb_energy: natoms must be in [0, 2^21-1]");
+    PB_ARG(natoms == 0 || (xyz && charge), "pb_energy: null atom array");
+    PB_ARG(x && energy && workspace, "pb_energy: null x, energy or workspace");
+    const size_t need = pb_energy_workspace_bytes(natoms);
+    if (workspace_bytes < need) {
+        set_error("pb_energy: workspace of %zu bytes, %zu needed", workspace_bytes, need);
+        return PB_ERR_NOMEM;
+    }
+    hipStream_t st = (hipStream_t)stream_;
+    char* b = (char*)workspace;
+    int* flags = (int*)b;
+    double* out = (double*)(b + 256);
+    double* qphi = (double*)(b + 512);
+    hipLaunchKernelGGL(k_fill_u8, dim3(1), dim3(64), 0, st, (uint8_t*)flags, (int64_t)256, (uint8_t)0);
+    if (natoms > 0)
+        hipLaunchKernelGGL(k_energy_atoms, dim3(blocks_for(natoms, 256, 1 << 30)), dim3(256), 0, st, xyz,
+                           charge, natoms, g->nx, g->ny, g->nz, g->h, g->origin[0], g->origin[1],
+                           g->origin[2], x, atom_phi, qphi, flags);
+    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(1024), 0, st, qphi, natoms, out);
+    PB_HIP(hipGetLastError());
+    double host[2];
+    int hflags = 0;
+    PB_HIP(hipMemcpyAsync(host, out, sizeof(double), hipMemcpyDeviceToHost, st));
+    PB_HIP(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, st));
+    PB_HIP(hipStreamSynchronize(st));
+    if (hflags) {
+        set_error("pb_energy: an atom centre lies outside the node box");
+        return PB_ERR_ARG;
+    }
+    *energy = 0.5 * host[0] * kCoulombKcal;
+    return PB_OK;
+}

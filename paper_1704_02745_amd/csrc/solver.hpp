@@ -1,0 +1,73 @@
+// Host-side declarations of the solver building blocks.
+#pragma once
+
+#include "pb_internal.hpp"
+
+namespace pb {
+
+// operator.hip
+pb_status launch_prepare64(const double* ex, const double* ey, const double* ez, const double* k2,
+                           const double* rhs, const double* xin, int warm, const Layout& L, double h,
+                           Op<double> op, double* b, double* x, int* flags, hipStream_t st);
+pb_status launch_round32(Op<double> op64, const double* b, const double* x, int64_t npad, Op<float> op32,
+                         float* b32, float* x32, hipStream_t st);
+int residual_blocks(const Layout& L);
+pb_status launch_residual64(Op<double> op, const double* b, const double* x, const Layout& L,
+                            double* r64, float* r32, double* partials, double* out2, hipStream_t st);
+pb_status launch_add_correction(double* x, const float* dx, int64_t npad, hipStream_t st);
+pb_status launch_f32_to_f64(const float* a, double* b, int64_t n, hipStream_t st);
+template <typename T>
+pb_status launch_unpad(const T* xp, const Layout& L, double* out, hipStream_t st);
+template <typename T>
+pb_status launch_fill(T* p, int64_t n, T v, hipStream_t st);
+
+// Tiling of the fused kernel: a tile is a contiguous range of `seglen`
+// padded plane positions times a run of `zchunk` planes.
+struct Tiling {
+    int mc;          // 16-byte vector groups per thread per plane (segment = mc*256*VEC)
+    int seglen;      // elements per segment
+    int zchunk;      // planes per tile
+    int nseg, nzc, ntiles;
+    int halo;        // in-plane halo, >= nx, multiple of the vector width
+    int grid;        // workgroups of the cooperative launch
+};
+
+constexpr int kMaxTiles = 65536;
+constexpr int kMaxPartials = 8;   // doubles per tile
+
+// Solver state arrays for one fused or DIA solve in precision T.
+template <typename T>
+struct SolveBufs {
+    Op<T> op;
+    const T* b;
+    T* x;
+    T* r;
+    T* p0;
+    T* p1;
+    T* q;
+    T* z;          // DIA form only
+    T* dia;        // DIA form only: 7 diagonals x npad
+    int warm;      // 1: x holds a nonzero initial guess
+};
+
+struct SolveResult {
+    int status;
+    int iters;
+    double rr;     // ||r||^2 (recurrence) at exit
+    double bb;     // ||b||^2
+};
+
+// jpcg.hip: one persistent cooperative launch running the whole iteration.
+template <typename T>
+pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, double* partials,
+                     double tol, int maxiter, hipStream_t st, SolveResult* res, Tiling* used);
+
+template <typename T>
+Tiling choose_tiling(const Layout& L);
+
+// dia.hip: DIA SpMV plus separate vector kernels, host-driven loop.
+template <typename T>
+pb_status dia_jpcg_impl(const Layout& L, const SolveBufs<T>& s, SyncState* S, double* partials,
+                        double tol, int maxiter, hipStream_t st, SolveResult* res);
+
+}  // namespace pb

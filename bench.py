@@ -1,0 +1,213 @@
+"""Benchmark: linear FDPB Jacobi-PCG on one MI355X.
+
+One step = the whole hot path on the 257^3 workload (20,000-atom synthetic
+globule, h = 0.5 A): GPU setup (classification, edge dielectrics, salt term,
+charge spreading, Debye-Hueckel boundary), the mixed-precision solve (FP32
+fused JPCG to 1e-4 inside an FP64 refinement loop to a 1e-9 relative
+residual) and the energy. Inputs (atom arrays) are resident on the device
+before the timed region; outputs stay on the device.
+
+value = algorithmic HBM bytes of the fused JPCG launches in the timed steps /
+wall time of the timed steps (GB/s). The roofline block reports the fused
+kernel alone: the same bytes over its own summed duration (HIP events on the
+solve stream, recorded by the library). The CPU baseline is the FP64 NumPy
+oracle timed on a bounded sample of the same workload.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import resource
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "JPCG HBM GB/s (% peak) at 257^3; served solves/s + p99 latency at tol 1e-6"
+PEAK_GBS = 8000.0
+# Algorithmic bytes per unknown of the fused FP32 kernel (see the design notes):
+# pass A reads r, d, p_old, cx, cy, cz, x and writes p, q, x (40 B); pass B
+# reads r, q, d and writes r (16 B); the first iteration skips the x update
+# (-8 B); the initial pass reads b, d and writes r, p (16 B); the final pass
+# reads x, p and writes x (12 B).
+ITER_BYTES = 56
+INIT_BYTES = 16 - 8 + 12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jpcg_fused_f32_257_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1704_02745_amd", "csrc", "jpcg.hip")
+
+
+def launch_bytes(n: int, iters: int, launches: int) -> float:
+    return float(n) * (ITER_BYTES * iters + INIT_BYTES * launches)
+
+
+def measured_traffic():
+    """Per-launch HBM bytes of the fused kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if kv.get("kernel_source_sha256") != sha:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(prob, n_iters=8):
+    """FP64 oracle Jacobi PCG at the full 257^3 size, bounded to n_iters
+    iterations. The sample system uses the oracle's own classification,
+    edges, salt term and charges; its boundary values are zero (the boundary
+    sum alone would take minutes in NumPy and does not change the iteration
+    cost)."""
+    import numpy as np
+    from oracle import fdpb, pcg
+    g = prob.grid
+    mask = fdpb.classify(g.nx, g.ny, g.nz, g.h, g.origin, prob.mol.xyz, prob.mol.radius)
+    ex, ey, ez = fdpb.dielectric_edges(mask, prob.eps_in, prob.eps_out)
+    k2 = fdpb.salt_term(mask, prob.eps_out, prob.kappa_d2)
+    q = fdpb.spread_charges(g.nx, g.ny, g.nz, g.h, g.origin, prob.mol.xyz, prob.mol.charge)
+    s = fdpb.System(h=g.h, eps_x=ex, eps_y=ey, eps_z=ez, kappa2=k2, b=fdpb.FOUR_PI * q / g.h ** 3)
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    res = pcg.pcg(lambda v: fdpb.apply(s, v), s.b, fdpb.diagonal(s), 1e-300, n_iters)
+    wall = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    n = g.nx * g.ny * g.nz
+    its = res.iters / wall
+    return {"value": round(its * ITER_BYTES * n / 1e9, 3), "unit": "GB/s",
+            "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
+            "sample": f"{res.iters} FP64 NumPy Jacobi-PCG iterations of the oracle at 257^3 "
+                      f"(same operator, zero boundary), {wall:.1f} s wall; rate scaled by the "
+                      f"metric's {ITER_BYTES} B/unknown per iteration",
+            "iters_per_s": round(its, 4), "os_cpu_count": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "independent solves shard across GPUs without communication, see the design notes.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1704_02745_amd as pbgpu
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    prob = synth.config2()
+    g = prob.grid
+    n = g.nx * g.ny * g.nz
+    xyz = torch.as_tensor(prob.mol.xyz, dtype=torch.float64, device=dev).contiguous()
+    rad = torch.as_tensor(prob.mol.radius, dtype=torch.float64, device=dev)
+    chg = torch.as_tensor(prob.mol.charge, dtype=torch.float64, device=dev)
+    wsb = pbgpu.solve_workspace_bytes(g.nx, g.ny, g.nz, "f32_refine64")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    x = torch.empty((g.nz, g.ny, g.nx), dtype=torch.float64, device=dev)
+
+    def step():
+        t0 = time.perf_counter()
+        sysm = pbgpu.setup(g, xyz, rad, chg, prob.eps_in, prob.eps_out, prob.kappa_d2, device=dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, info = pbgpu.solve(sysm, tol=1e-9, precision="f32_refine64", inner_tol=1e-4,
+                              workspace=ws, out=x)
+        t2 = time.perf_counter()
+        e = pbgpu.energy(g, xyz, chg, x)
+        t3 = time.perf_counter()
+        return sysm, info, e, (t1 - t0, t2 - t1, t3 - t2)
+
+    print(f"bench: {prob.name} n={n} natoms={prob.mol.natoms} warmup={args.warmup} steps={args.steps}",
+          file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    infos, phases = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sysm, info, e, ph = step()
+        infos.append(info)
+        phases.append(ph)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    print(f"bench: timed {args.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
+
+    iters = sum(i["iters"] for i in infos)
+    launches = sum(i["kernel_launches"] for i in infos)
+    ksec = sum(i["kernel_seconds"] for i in infos)
+    total_bytes = launch_bytes(n, iters, launches)
+    value = total_bytes / wall / 1e9
+    achieved = total_bytes / ksec / 1e9
+    traffic = measured_traffic()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic, 0),
+                "kernel": "k_jpcg_fused<float> (persistent, one launch per inner solve)",
+                "bytes_per_launch": round(total_bytes / launches, 0),
+                "avg_launch_ms": round(1e3 * ksec / launches, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(prob)
+
+    # accuracy of the last step, checked by the oracle's own FP64 operator
+    from oracle import fdpb
+    s = fdpb.System(h=g.h, eps_x=sysm.eps_x.cpu().numpy(), eps_y=sysm.eps_y.cpu().numpy(),
+                    eps_z=sysm.eps_z.cpu().numpy(), kappa2=sysm.kappa2.cpu().numpy(),
+                    b=sysm.rhs.cpu().numpy())
+    xs = x.cpu().numpy()
+    relres_oracle = fdpb.true_relres(s, xs)
+    e_oracle = fdpb.energy(g.nx, g.ny, g.nz, g.h, g.origin, prob.mol.xyz, prob.mol.charge, xs)
+
+    last = infos[-1]
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "257^3 grid (16,974,593 unknowns), h=0.5 A, 20,000-atom seeded "
+                               "random-walk globule (R=51.7 A); setup + FP32 JPCG inner 1e-4 inside "
+                               "FP64 refinement to 1e-9 + energy",
+                   "grid": [g.nx, g.ny, g.nz], "natoms": prob.mol.natoms, "tol": 1e-9,
+                   "inner_tol": 1e-4},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "detail": {
+            "iters_per_step": iters / args.steps, "outer_per_step": last["outer_iters"],
+            "launches_per_step": launches / args.steps,
+            "setup_ms": round(1e3 * sum(p[0] for p in phases) / len(phases), 3),
+            "solve_ms": round(1e3 * sum(p[1] for p in phases) / len(phases), 3),
+            "energy_ms": round(1e3 * sum(p[2] for p in phases) / len(phases), 3),
+            "jpcg_kernel_ms_per_step": round(1e3 * ksec / args.steps, 3),
+            "jpcg_iter_us": round(1e6 * ksec / iters, 2),
+            "relres_true_gpu": last["relres_true"], "relres_true_oracle": relres_oracle,
+            "energy_kcal": e, "energy_oracle_of_gpu_phi": e_oracle,
+            "solves_per_s": round(args.steps / wall, 3),
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

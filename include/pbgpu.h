@@ -82,10 +82,11 @@ typedef struct {
     int32_t iters;          /* CG iterations (summed over inner solves for REFINE64) */
     int32_t outer_iters;    /* refinement steps (0 for plain solves) */
     int32_t status;         /* pb_status of the solve */
-    int32_t reserved;
+    int32_t kernel_launches;/* launches of the iteration kernel (fused form) or iteration loops (DIA form) */
     double relres_recur;    /* recurrence residual ||r||/||b|| at exit (outer FP64 residual for REFINE64) */
     double relres_true;     /* ||b - A x||/||b|| recomputed in FP64 with the FP64 coefficients */
     double seconds;         /* wall time of the call */
+    double kernel_seconds;  /* summed duration of those launches / loops, from HIP events on `stream` */
 } pb_info;
 
 /* Library version string (static storage). */

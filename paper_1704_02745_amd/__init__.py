@@ -55,12 +55,12 @@ class SolveOpts(ctypes.Structure):
 
 class Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
-                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("kernel_launches", ctypes.c_int32),
                 ("relres_recur", ctypes.c_double), ("relres_true", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("kernel_seconds", ctypes.c_double)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 def _load():

@@ -176,7 +176,8 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
     }
 
     SolveResult r{};
-    int total_iters = 0, outer = 0;
+    int total_iters = 0, outer = 0, launches = 0;
+    double ksec = 0.0;
     double relres_recur = 0.0;
     pb_status status = PB_OK;
     if (prec == PB_F64) {
@@ -184,6 +185,8 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
         s.warm = opts->warm_start ? 1 : 0;
         e = run_inner<double>(L, s, w, op, opts->tol, maxiter, st, &r);
         if (e != PB_OK) return e;
+        ++launches;
+        ksec += r.kernel_seconds;
         status = (pb_status)r.status;
         total_iters = r.iters;
         relres_recur = r.bb > 0 ? std::sqrt(r.rr) / std::sqrt(r.bb) : 0.0;
@@ -194,6 +197,8 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
         if (e != PB_OK) return e;
         e = run_inner<float>(L, s, w, op, opts->tol, maxiter, st, &r);
         if (e != PB_OK) return e;
+        ++launches;
+        ksec += r.kernel_seconds;
         status = (pb_status)r.status;
         total_iters = r.iters;
         relres_recur = r.bb > 0 ? std::sqrt(r.rr) / std::sqrt(r.bb) : 0.0;
@@ -229,6 +234,8 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
             if (e != PB_OK) return e;
             e = run_inner<float>(L, s, w, op, inner_tol, maxiter, st, &r);
             if (e != PB_OK) return e;
+            ++launches;
+            ksec += r.kernel_seconds;
             total_iters += r.iters;
             if (r.status < 0) { status = (pb_status)r.status; break; }
             e = launch_add_correction(w.x64, s.x, L.npad, st);
@@ -253,6 +260,8 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
         info->relres_recur = relres_recur;
         info->relres_true = bb > 0 ? std::sqrt(rr) / std::sqrt(bb) : 0.0;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        info->kernel_launches = launches;
+        info->kernel_seconds = ksec;
     }
     return status;
 }

@@ -645,26 +645,40 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
     // every wait is bounded: 20 s of the constant-rate clock
     a.timeout_ticks = (long long)(di.wallclock_khz > 0 ? di.wallclock_khz : 100000) * 1000LL * 20LL;
     // the header (barrier counters, scalars) starts cleared
-    PB_ARG(launch_fill<int>((int*)sync, (int64_t)(sizeof(SyncState) / sizeof(int)), 0, st) == PB_OK,
-           "fill failed");
+    if (launch_fill<int>((int*)sync, (int64_t)(sizeof(SyncState) / sizeof(int)), 0, st) != PB_OK)
+        return PB_ERR_HIP;
     const size_t lds = 2 * sizeof(T) * (size_t)(t.seglen + 2 * t.halo);
     void* args[] = {&a};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (res) {
+        PB_HIP(hipEventCreate(&ev[0]));
+        PB_HIP(hipEventCreate(&ev[1]));
+        PB_HIP(hipEventRecord(ev[0], st));
+    }
     hipError_t e = hipSuccess;
     if (t.mc == 1) e = hipLaunchCooperativeKernel((const void*)k_jpcg_fused<T, 1>, dim3(t.grid), dim3(kBS), args, lds, st);
     else if (t.mc == 2) e = hipLaunchCooperativeKernel((const void*)k_jpcg_fused<T, 2>, dim3(t.grid), dim3(kBS), args, lds, st);
     else e = hipLaunchCooperativeKernel((const void*)k_jpcg_fused<T, 4>, dim3(t.grid), dim3(kBS), args, lds, st);
     if (e != hipSuccess) {
+        if (ev[0]) (void)hipEventDestroy(ev[0]);
+        if (ev[1]) (void)hipEventDestroy(ev[1]);
         set_error("fused JPCG launch failed: %s (grid %d, lds %zu)", hipGetErrorString(e), t.grid, lds);
         return PB_ERR_HIP;
     }
     if (res) {
         SyncState h;
+        PB_HIP(hipEventRecord(ev[1], st));
         PB_HIP(hipMemcpyAsync(&h, sync, sizeof(SyncState), hipMemcpyDeviceToHost, st));
         PB_HIP(hipStreamSynchronize(st));
+        float ms = 0.0f;
+        PB_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
         res->status = h.status;
         res->iters = h.iters;
         res->rr = h.rr;
         res->bb = h.bb;
+        res->kernel_seconds = 1e-3 * ms;
     }
     return PB_OK;
 }

@@ -55,6 +55,7 @@ struct SolveResult {
     int iters;
     double rr;     // ||r||^2 (recurrence) at exit
     double bb;     // ||b||^2
+    double kernel_seconds;   // duration of the iteration kernel / loop (HIP events)
 };
 
 // jpcg.hip: one persistent cooperative launch running the whole iteration.

@@ -105,7 +105,7 @@ def test_setup_full_size_129(pb):
     assert np.array_equal(b[1:-1, 1:-1, 1:-1], interior[1:-1, 1:-1, 1:-1])
     # sampled x- face nodes: b = 4 pi q/h^3 + eps_x(edge 0)/h^2 * phi_DH(ghost)
     rng = np.random.default_rng(1)
-    js, ks = rng.integers(0, g.ny, 64), rng.integers(0, g.nz, 64)
+    js, ks = rng.integers(1, g.ny - 1, 64), rng.integers(1, g.nz - 1, 64)   # face interior only
     pts = np.stack([np.full(64, g.origin[0] + g.h * -1.0), g.origin[1] + g.h * js, g.origin[2] + g.h * ks], -1)
     phi = fdpb.dh_potential(pts, prob.mol.xyz, prob.mol.charge, prob.eps_out, prob.kappa_d2)
     expect = interior[ks, js, 0] + ex[ks, js, 0] * (1.0 / (g.h * g.h)) * phi

@@ -169,6 +169,43 @@ pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h,
                    void* workspace, size_t workspace_bytes, void* stream,
                    pb_info* info);
 
+/* One tiling of the fused stencil kernel, as chosen by pb_autotune. */
+typedef struct {
+    int32_t block;          /* threads per workgroup */
+    int32_t groups;         /* 16-byte vector groups per thread per plane (segment = block*groups*vector) */
+    int32_t zchunk;         /* z-planes per tile */
+    int32_t grid;           /* workgroups of the persistent launch */
+    double us_per_iter;     /* measured microseconds per CG iteration (pb_autotune only) */
+    int32_t candidates;     /* tilings timed (pb_autotune only) */
+    int32_t reserved;
+} pb_tuning;
+
+/*
+ * pb_autotune: time every feasible tiling of the fused stencil kernel
+ * (block size, vector groups per thread, workgroups per CU and hence z-chunk)
+ * for `iters_per_trial` iterations on the given system, and record the
+ * fastest for this device, grid shape and precision (FP64 vs FP32/REFINE64)
+ * in the library's per-process table; later pb_solve calls on that shape use
+ * it. The iteration itself is the solver's own (section 2.2 with M = diag A);
+ * only its launch shape is searched. Arrays and workspace as for pb_solve
+ * (opts->op must be PB_OP_STENCIL; opts->tol and maxiter are ignored).
+ * best (host, nullable) receives the winner. Errors: PB_ERR_ARG (also for a
+ * zero right-hand side), PB_ERR_NOMEM, PB_ERR_HIP.
+ */
+pb_status pb_autotune(int32_t nx, int32_t ny, int32_t nz, double h,
+                      const double* eps_x, const double* eps_y, const double* eps_z,
+                      const double* kappa2, const double* rhs, const pb_solve_opts* opts,
+                      int32_t iters_per_trial, void* workspace, size_t workspace_bytes,
+                      void* stream, pb_tuning* best);
+
+/*
+ * pb_set_tuning: record a tiling (for instance one saved from an earlier
+ * pb_autotune) for this grid shape and precision on the current device.
+ * Fields us_per_iter/candidates are ignored. PB_ERR_ARG if the tiling is not
+ * feasible for this shape and device.
+ */
+pb_status pb_set_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t precision, const pb_tuning* tuning);
+
 /* Device workspace needed by pb_energy. Returns 0 for invalid arguments. */
 size_t pb_energy_workspace_bytes(int64_t natoms);
 

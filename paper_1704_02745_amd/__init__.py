@@ -31,7 +31,8 @@ OPERATORS = {"stencil": 0, "dia": 1}
 
 # Every entry point declared in include/pbgpu.h.
 EXPORTS = ("pb_version", "pb_last_error", "pb_setup_workspace_bytes", "pb_setup",
-           "pb_solve_workspace_bytes", "pb_solve", "pb_energy_workspace_bytes", "pb_energy")
+           "pb_solve_workspace_bytes", "pb_solve", "pb_autotune", "pb_set_tuning",
+           "pb_energy_workspace_bytes", "pb_energy")
 
 
 class PBError(RuntimeError):
@@ -63,6 +64,15 @@ class Info(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("groups", ctypes.c_int32), ("zchunk", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("us_per_iter", ctypes.c_double),
+                ("candidates", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"pbgpu: {LIB_PATH} is not built; run paper_1704_02745_amd.build.build()")
@@ -82,6 +92,11 @@ def _load():
     lib.pb_solve.restype = ctypes.c_int
     lib.pb_solve.argtypes = [i32, i32, i32, dbl, vp, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
                              vp, sz, vp, ctypes.POINTER(Info)]
+    lib.pb_autotune.restype = ctypes.c_int
+    lib.pb_autotune.argtypes = [i32, i32, i32, dbl, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts), i32,
+                                vp, sz, vp, ctypes.POINTER(Tuning)]
+    lib.pb_set_tuning.restype = ctypes.c_int
+    lib.pb_set_tuning.argtypes = [i32, i32, i32, i32, ctypes.POINTER(Tuning)]
     lib.pb_energy_workspace_bytes.restype = sz
     lib.pb_energy_workspace_bytes.argtypes = [i64]
     lib.pb_energy.restype = ctypes.c_int
@@ -210,6 +225,50 @@ def solve(sysm: System, tol=1e-6, precision="f32", op="stencil", maxiter=0, x0=N
                       workspace.numel(), _stream(stream), ctypes.byref(info))
     _check(st, allow=(PB_OK,) if check else (PB_OK, PB_NOT_CONVERGED))
     return out, info.as_dict()
+
+
+def autotune(sysm: System, precision="f32", iters_per_trial=20,
+             workspace: Optional[torch.Tensor] = None, stream=None) -> dict:
+    """Time every feasible tiling of the fused kernel on this system and make
+    the fastest the default for its grid shape and precision (per process)."""
+    nx, ny, nz = sysm.dims
+    o = SolveOpts()
+    o.tol, o.precision, o.op = 1e-6, PRECISIONS[precision], OPERATORS["stencil"]
+    wsb = lib.pb_solve_workspace_bytes(nx, ny, nz, ctypes.byref(o))
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=sysm.rhs.device)
+    t = Tuning()
+    st = lib.pb_autotune(nx, ny, nz, sysm.grid.h, _ptr(sysm.eps_x), _ptr(sysm.eps_y), _ptr(sysm.eps_z),
+                         _ptr(sysm.kappa2), _ptr(sysm.rhs), ctypes.byref(o), int(iters_per_trial),
+                         _ptr(workspace), workspace.numel(), _stream(stream), ctypes.byref(t))
+    _check(st)
+    return t.as_dict()
+
+
+def set_tuning(nx, ny, nz, precision, block, groups, zchunk, grid) -> None:
+    t = Tuning()
+    t.block, t.groups, t.zchunk, t.grid = int(block), int(groups), int(zchunk), int(grid)
+    _check(lib.pb_set_tuning(int(nx), int(ny), int(nz), PRECISIONS[precision], ctypes.byref(t)))
+
+
+def save_tuning(path, entries) -> None:
+    """Write autotune results [{nx, ny, nz, precision, block, groups, zchunk, grid, ...}] as JSON."""
+    import json
+    with open(path, "w") as f:
+        json.dump(entries, f, indent=1)
+
+
+def load_tuning(path) -> int:
+    """Record every feasible tiling of a saved JSON table; returns how many were applied."""
+    import json
+    n = 0
+    for e in json.load(open(path)):
+        try:
+            set_tuning(e["nx"], e["ny"], e["nz"], e["precision"], e["block"], e["groups"], e["zchunk"], e["grid"])
+            n += 1
+        except PBError:
+            pass
+    return n
 
 
 def energy(grid, xyz, charge, x: torch.Tensor, atom_phi: Optional[torch.Tensor] = None,

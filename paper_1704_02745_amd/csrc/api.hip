@@ -68,6 +68,9 @@ SolveWs carve_solve(void* base, const Layout& L, int prec, int op) {
         if (op == PB_OP_DIA) {
             s.z = (double*)take(n8);
             s.dia = (double*)take(7 * n8);
+        } else {
+            s.r2 = (double*)take(n8);
+            s.q2 = (double*)take(n8);
         }
     } else {
         SolveBufs<float>& s = w.s32;
@@ -84,6 +87,9 @@ SolveWs carve_solve(void* base, const Layout& L, int prec, int op) {
         if (op == PB_OP_DIA) {
             s.z = (float*)take(n4);
             s.dia = (float*)take(7 * n4);
+        } else {
+            s.r2 = (float*)take(n4);
+            s.q2 = (float*)take(n4);
         }
     }
     w.bytes = off;
@@ -116,6 +122,81 @@ pb_status residual(const Layout& L, const SolveWs& w, float* r32, double& rr, do
     PB_HIP(hipStreamSynchronize(st));
     rr = h[0];
     bb = h[1];
+    return PB_OK;
+}
+
+// Convert the caller's arrays into the padded FP64 operator and check them.
+pb_status prepare(const Layout& L, double h, const double* eps_x, const double* eps_y, const double* eps_z,
+                  const double* kappa2, const double* rhs, const double* x, int warm, const SolveWs& w,
+                  hipStream_t st) {
+    int* flags = (int*)w.small;
+    pb_status e = launch_fill<int>(flags, 1, 0, st);
+    if (e != PB_OK) return e;
+    e = launch_prepare64(eps_x, eps_y, eps_z, kappa2, rhs, x, warm, L, h, w.op64, w.b64, w.x64, flags, st);
+    if (e != PB_OK) return e;
+    int hflags = 0;
+    PB_HIP(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, st));
+    PB_HIP(hipStreamSynchronize(st));
+    if (hflags & FLAG_BAD_COEF) {
+        set_error("negative or non-finite coefficient, or non-positive diagonal");
+        return PB_ERR_ARG;
+    }
+    if (hflags & (FLAG_BAD_RHS | FLAG_BAD_GUESS)) {
+        set_error("NaN/Inf in the right-hand side or the initial guess");
+        return PB_ERR_NONFINITE;
+    }
+    return PB_OK;
+}
+
+// Time `iters` iterations of the fused kernel with tiling t (second of two runs).
+template <typename T>
+pb_status time_tiling(const Layout& L, const SolveBufs<T>& s, const SolveWs& w, const Tiling& t, int iters,
+                      hipStream_t st, double& us_per_iter) {
+    SolveResult r{};
+    for (int rep = 0; rep < 2; ++rep) {
+        pb_status e = fused_jpcg<T>(L, s, w.sync, w.partials, 1e-300, iters, st, &r, &t);
+        if (e != PB_OK) return e;
+        if (r.status < 0) {
+            set_error("autotune trial failed with status %d", r.status);
+            return (pb_status)r.status;
+        }
+    }
+    if (r.iters <= 0) {
+        set_error("autotune: the system converged before any timed iteration (zero right-hand side?)");
+        return PB_ERR_ARG;
+    }
+    us_per_iter = 1e6 * r.kernel_seconds / r.iters;
+    return PB_OK;
+}
+
+template <typename T>
+pb_status autotune_impl(const Layout& L, const SolveBufs<T>& s, const SolveWs& w, int iters, hipStream_t st,
+                        pb_tuning* best) {
+    const std::vector<Tiling> cand = tiling_candidates<T>(L);
+    if (cand.empty()) {
+        set_error("autotune: no feasible tiling for this grid");
+        return PB_ERR_ARG;
+    }
+    double best_us = 1e300;
+    Tiling best_t{};
+    for (const Tiling& t : cand) {
+        double us = 0.0;
+        pb_status e = time_tiling<T>(L, s, w, t, iters, st, us);
+        if (e != PB_OK) return e;
+        if (us < best_us) {
+            best_us = us;
+            best_t = t;
+        }
+    }
+    record_tiling<T>(L, best_t);
+    if (best) {
+        best->block = best_t.bs;
+        best->groups = best_t.mc;
+        best->zchunk = best_t.zchunk;
+        best->grid = best_t.grid;
+        best->us_per_iter = best_us;
+        best->candidates = (int)cand.size();
+    }
     return PB_OK;
 }
 
@@ -155,25 +236,8 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
     }
     const int maxiter = opts->maxiter > 0 ? opts->maxiter : 10 * std::max(nx, std::max(ny, nz));
     hipStream_t st = (hipStream_t)stream_;
-
-    // convert the caller's arrays into the padded FP64 operator and check them
-    int* flags = (int*)w.small;
-    pb_status e = launch_fill<int>(flags, 1, 0, st);
+    pb_status e = prepare(L, h, eps_x, eps_y, eps_z, kappa2, rhs, x, opts->warm_start ? 1 : 0, w, st);
     if (e != PB_OK) return e;
-    e = launch_prepare64(eps_x, eps_y, eps_z, kappa2, rhs, x, opts->warm_start ? 1 : 0, L, h, w.op64, w.b64,
-                         w.x64, flags, st);
-    if (e != PB_OK) return e;
-    int hflags = 0;
-    PB_HIP(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, st));
-    PB_HIP(hipStreamSynchronize(st));
-    if (hflags & FLAG_BAD_COEF) {
-        set_error("pb_solve: negative or non-finite coefficient, or non-positive diagonal");
-        return PB_ERR_ARG;
-    }
-    if (hflags & (FLAG_BAD_RHS | FLAG_BAD_GUESS)) {
-        set_error("pb_solve: NaN/Inf in the right-hand side or the initial guess");
-        return PB_ERR_NONFINITE;
-    }
 
     SolveResult r{};
     int total_iters = 0, outer = 0, launches = 0;
@@ -264,4 +328,55 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
         info->kernel_seconds = ksec;
     }
     return status;
+}
+
+extern "C" pb_status pb_autotune(int32_t nx, int32_t ny, int32_t nz, double h, const double* eps_x,
+                                 const double* eps_y, const double* eps_z, const double* kappa2,
+                                 const double* rhs, const pb_solve_opts* opts, int32_t iters_per_trial,
+                                 void* workspace, size_t workspace_bytes, void* stream_, pb_tuning* best) {
+    if (best) std::memset(best, 0, sizeof(*best));
+    PB_ARG(dims_ok(nx, ny, nz), "pb_autotune: dims must be >= 1 (and below 2^36 nodes)");
+    PB_ARG(std::isfinite(h) && h > 0, "pb_autotune: h must be finite and > 0");
+    PB_ARG(opts_ok(opts) && opts->op == PB_OP_STENCIL, "pb_autotune: invalid options (stencil operator only)");
+    PB_ARG(iters_per_trial >= 1 && iters_per_trial <= 10000, "pb_autotune: iters_per_trial in [1, 10000]");
+    PB_ARG(eps_x && eps_y && eps_z && kappa2 && rhs, "pb_autotune: null array");
+    PB_ARG(workspace != nullptr && ((uintptr_t)workspace & 255) == 0, "pb_autotune: null or misaligned workspace");
+    const Layout L = make_layout(nx, ny, nz);
+    SolveWs w = carve_solve(workspace, L, opts->precision, PB_OP_STENCIL);
+    if (workspace_bytes < w.bytes) {
+        set_error("pb_autotune: workspace of %zu bytes, %zu needed", workspace_bytes, w.bytes);
+        return PB_ERR_NOMEM;
+    }
+    hipStream_t st = (hipStream_t)stream_;
+    pb_status e = prepare(L, h, eps_x, eps_y, eps_z, kappa2, rhs, nullptr, 0, w, st);
+    if (e != PB_OK) return e;
+    if (opts->precision == PB_F64) {
+        SolveBufs<double> s = w.s64;
+        s.warm = 0;
+        return autotune_impl<double>(L, s, w, iters_per_trial, st, best);
+    }
+    SolveBufs<float> s = w.s32;
+    s.warm = 0;
+    e = launch_round32(w.op64, w.b64, w.x64, L.npad, s.op, (float*)s.b, s.x, st);
+    if (e != PB_OK) return e;
+    return autotune_impl<float>(L, s, w, iters_per_trial, st, best);
+}
+
+extern "C" pb_status pb_set_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t precision, const pb_tuning* t) {
+    PB_ARG(dims_ok(nx, ny, nz) && t, "pb_set_tuning: bad dims or null tuning");
+    PB_ARG(precision >= PB_F64 && precision <= PB_F32_REFINE64, "pb_set_tuning: bad precision");
+    const Layout L = make_layout(nx, ny, nz);
+    auto apply = [&](auto tag) -> pb_status {
+        using T = decltype(tag);
+        for (const Tiling& c : tiling_candidates<T>(L)) {
+            if (c.bs == t->block && c.mc == t->groups && c.zchunk == t->zchunk && c.grid == t->grid) {
+                record_tiling<T>(L, c);
+                return PB_OK;
+            }
+        }
+        set_error("pb_set_tuning: (block %d, groups %d, zchunk %d, grid %d) is not a feasible tiling here",
+                  t->block, t->groups, t->zchunk, t->grid);
+        return PB_ERR_ARG;
+    };
+    return precision == PB_F64 ? apply(double{}) : apply(float{});
 }

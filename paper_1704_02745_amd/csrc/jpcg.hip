@@ -1,50 +1,59 @@
-// Fused, persistent Jacobi-preconditioned CG (section 2.2 listing with
-// M = diag(A), section 2.4) on the matrix-free 7-point operator of Eq. 3.
+// Fused, persistent Jacobi-preconditioned CG on the matrix-free 7-point
+// operator of Eq. 3 (preconditioned CG of section 2.2 with M = diag(A),
+// section 2.4), one pass over the grid per iteration.
 //
-// One cooperative launch runs the whole iteration. Each workgroup owns a
-// fixed set of tiles; a tile is a contiguous range of padded plane positions
-// (a "segment", which spans several x-rows) times a run of z-planes. Per
-// iteration the kernel makes two passes separated by grid barriers:
+// The listing updates alpha, x, r, then beta, p, and needs two global
+// reductions per iteration (p.Ap for alpha, r.z for beta). Here the
+// iteration is regrouped so that one pass and one grid barrier suffice:
+// pass l receives alpha_{l-1}, beta_{l-1} and the stored q_{l-1} = A p_{l-2},
+// and per node computes
+//     r_{l-1} = r_{l-2} - alpha_{l-1} q_{l-1}
+//     p_{l-1} = r_{l-1}/d + beta_{l-1} p_{l-2}          (z = r/d never stored)
+//     x_{l-1} = x_{l-2} + alpha_{l-1} p_{l-2}
+//     q_l     = A p_{l-1}
+// together with the sums p.q, r.r/d, r.q/d, q.q/d, r.r, r.q, q.q. After the
+// barrier: alpha_l = (r.r/d) / (p.q) (the listing's r.z), and because
+// r_l = r_{l-1} - alpha_l q_l the next r.z and ||r_l||^2 follow exactly from
+// the expansion (r.r/d) - 2 alpha (r.q/d) + alpha^2 (q.q/d), and likewise for
+// ||r||^2; beta_l is their ratio. The iterates are those of the listing; only
+// the order of the floating-point reductions differs.
 //
-//   pass A: p = z + beta p_old with z = r/d (recomputed, never stored),
-//           q = A p, x += alpha_prev p_old (the previous iteration's x
-//           update, deferred to reuse the p_old load), partial p.q
-//   -- barrier: alpha = (r.z)/(p.q)
-//   pass B: r -= alpha q, partials r.z and r.r
-//   -- barrier: beta = (r.z)_new/(r.z)_old, stopping test ||r||/||b|| < tol
+// Data layout and tiling: arrays use the padded layout of pb_internal.hpp.
+// A tile is a contiguous range of padded plane positions (a segment of
+// several x-rows) times a run of z-planes. The pass marches up a tile's
+// planes: p_{l-1} of the current plane sits in LDS over the segment plus one
+// row of halo on each side (in-plane neighbours +-1, +-nx); the planes above
+// and below stay in registers. Halo values of p are recomputed pointwise, so
+// every array is written once per pass. Traffic per node: reads r, q, d,
+// p_old, cx, cy, cz, x and writes r, p, q, x (48 bytes in FP32).
 //
-// Pass A marches in z: the new direction p on the current plane is staged
-// in LDS over the segment plus one row of halo on each side (in-plane
-// neighbours +-1, +-nx), the planes above and below stay in registers.
-// Halo values of p are recomputed from r, d and p_old, so p is written once.
-//
-// Reductions: every tile reduces its own sums in a fixed order (thread
-// order, then a fixed wave/LDS tree) into its own slot; the last workgroup
-// to reach a barrier sums the tile slots in tile order. Results therefore do
-// not depend on the number of workgroups or on scheduling.
+// Reductions: each tile reduces its sums in a fixed order (thread order, then
+// a fixed wave/LDS tree) into its own slot; the last workgroup to reach the
+// barrier sums the slots in tile order. Results do not depend on the number
+// of workgroups or on scheduling.
 #include "solver.hpp"
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 namespace pb {
 
 namespace {
 
-constexpr int kBS = 256;
-constexpr int kWaves = kBS / 64;
+constexpr int NPART = 7;   // pq, rrd, rqd, qqd, rr, rq, qq
 
 template <typename T>
 struct KArgs {
     Op<T> op;
     const T* b;
     T* x;
-    T* r;
-    T* p0;
-    T* p1;
-    T* q;
+    T* r[2];
+    T* q[2];
+    T* p[2];
     int nx, ny, nz;
     int64_t sp;
     int seglen, zchunk, nseg, nzc, ntiles, halo;
@@ -56,19 +65,27 @@ struct KArgs {
     long long timeout_ticks;
 };
 
-__device__ __forceinline__ double ld_acquire_d(const double* p) {
+__device__ __forceinline__ double ld_agent_d(const double* p) {
     unsigned long long v = __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
     return __longlong_as_double((long long)v);
 }
-__device__ __forceinline__ int ld_acquire_i(const int* p) {
+__device__ __forceinline__ int ld_agent_i(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Reduce acc[0..np) over the workgroup in a fixed order and store the sums
-// into dst[0..np) (thread 0). `red` is LDS scratch of kWaves*kMaxPartials.
-template <int NP>
+// Workgroup barrier for the LDS hand-off between planes.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Reduce acc[0..NP) over the workgroup in a fixed order; thread 0 stores the
+// sums into dst. `red` is LDS scratch of (BS/64)*kMaxPartials doubles.
+template <int BS, int NP>
 __device__ __forceinline__ void tile_reduce_store(double (&acc)[NP], double* red, double* dst) {
+    constexpr int NW = BS / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
@@ -82,21 +99,22 @@ __device__ __forceinline__ void tile_reduce_store(double (&acc)[NP], double* red
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
             double s = red[i];
-            for (int w = 1; w < kWaves; ++w) s += red[w * kMaxPartials + i];
+            for (int w = 1; w < NW; ++w) s += red[w * kMaxPartials + i];
             dst[i] = s;
         }
     }
     __syncthreads();
 }
 
-// Sum slot i of all tile partials in tile order (all threads of the last
-// workgroup take part); the result is valid in thread 0.
+// Sum slot i of every tile in tile order (all threads of the last workgroup
+// take part); the result is returned to every thread.
+template <int BS>
 __device__ double sum_tiles(const double* partials, int ntiles, int i, double* buf) {
     double a = 0.0;
-    for (int t = threadIdx.x; t < ntiles; t += kBS) a += ld_acquire_d(partials + (size_t)t * kMaxPartials + i);
+    for (int t = threadIdx.x; t < ntiles; t += BS) a += ld_agent_d(partials + (size_t)t * kMaxPartials + i);
     buf[threadIdx.x] = a;
     __syncthreads();
-    for (int w = kBS / 2; w > 0; w >>= 1) {
+    for (int w = BS / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
         __syncthreads();
     }
@@ -105,22 +123,24 @@ __device__ double sum_tiles(const double* partials, int ntiles, int i, double* b
     return r;
 }
 
-// Grid barrier. The last workgroup to arrive runs `last(buf)` with all its
-// threads (it sees every other workgroup's writes) and then releases the
-// others. Waits are bounded by timeout_ticks of the constant-rate clock;
-// returns false if this workgroup timed out (it must then leave the kernel).
+// Grid barrier. Arrival is one release-ordered atomic add per workgroup; the
+// last arriver acquires, runs `last(buf)` with all its threads (it sees every
+// other workgroup's writes), and publishes a new generation. The others poll
+// the generation with relaxed loads and acquire once it changes. Waits are
+// bounded by timeout_ticks of the constant-rate clock; returns false if this
+// workgroup timed out (it must then leave the kernel).
 template <typename F>
 __device__ bool grid_barrier(SyncState* S, unsigned& gen, long long timeout_ticks, double* buf,
                              int* s_flag, F&& last) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned prev = __hip_atomic_fetch_add(&S->arrive, 1u, __ATOMIC_ACQ_REL,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned prev = __hip_atomic_fetch_add(&S->arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         *s_flag = (prev == gridDim.x - 1) ? 1 : 0;
     }
     __syncthreads();
     bool ok = true;
     if (*s_flag) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         last(buf);
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -129,15 +149,15 @@ __device__ bool grid_barrier(SyncState* S, unsigned& gen, long long timeout_tick
         }
     } else if (threadIdx.x == 0) {
         const long long t0 = wall_clock64();
-        while (__hip_atomic_load(&S->generation, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-            __builtin_amdgcn_s_sleep(2);
+        while (__hip_atomic_load(&S->generation, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+            __builtin_amdgcn_s_sleep(1);
             if (wall_clock64() - t0 > timeout_ticks) {
-                __hip_atomic_store(&S->status, (int)PB_ERR_TIMEOUT, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&S->status, (int)PB_ERR_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 *s_flag = -1;
                 break;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     ++gen;
     __syncthreads();
@@ -154,42 +174,69 @@ template <typename T>
 __device__ __forceinline__ void vstore(T* p, const typename Vec<T>::type& v) {
     *reinterpret_cast<typename Vec<T>::type*>(p) = v;
 }
+// Jacobi scaling 1/d: the hardware reciprocal in FP32 (about 1 ulp), an
+// exact division in FP64. Every use of M^-1 in a solve goes through this one
+// function, so the preconditioner is the same fixed positive diagonal in the
+// direction update and in the dot products.
+__device__ __forceinline__ float jacobi_inv(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double jacobi_inv(double d) { return 1.0 / d; }
 
-// Tile -> (segment, z-chunk). Workgroup w runs on XCD w % 8; the tiles of
-// one XCD form a contiguous block of the tile order (z-chunk major), so
-// neighbouring tiles share that XCD's L2.
+template <typename T>
+__device__ __forceinline__ typename Vec<T>::type vzero() {
+    typename Vec<T>::type v;
+#pragma unroll
+    for (int u = 0; u < Vec<T>::n; ++u) vget(v, u) = T(0);
+    return v;
+}
+
+// Workgroup w runs on XCD w % 8 when the grid is a multiple of 8. Each XCD
+// takes a contiguous block of the tile order (z-chunk major), so the tiles
+// that share halos also share that XCD's L2.
 __device__ __forceinline__ void xcd_tile_range(int ntiles, int& first, int& stride, int& end) {
     const int G = gridDim.x;
     const int nx8 = (G >= 8 && G % 8 == 0) ? 8 : 1;
     const int xcd = blockIdx.x % nx8, local = blockIdx.x / nx8, per = G / nx8;
-    const int lo = (int)(((long long)xcd * ntiles) / nx8);
-    const int hi = (int)(((long long)(xcd + 1) * ntiles) / nx8);
-    first = lo + local;
+    first = (int)(((long long)xcd * ntiles) / nx8) + local;
     stride = per;
-    end = hi;
+    end = (int)(((long long)(xcd + 1) * ntiles) / nx8);
+}
+
+struct TileBox {
+    int64_t s, e;   // plane positions [s, e)
+    int k0, k1;     // planes [k0, k1)
+};
+
+template <typename T>
+__device__ __forceinline__ TileBox tile_box(const KArgs<T>& a, int tile) {
+    TileBox t;
+    const int seg = tile % a.nseg, zc = tile / a.nseg;
+    t.s = (int64_t)seg * a.seglen;
+    t.e = min(t.s + (int64_t)a.seglen, a.sp);
+    t.k0 = zc * a.zchunk;
+    t.k1 = min(t.k0 + a.zchunk, a.nz);
+    return t;
 }
 
 // ------------------------------------------------------------------ passes
 
-// Initial residual r = b - A x0 (or r = b for a zero guess), p_old = 0,
-// partials r.z, r.r, b.b.
-template <typename T>
-__device__ void init_tile(const KArgs<T>& a, int tile, double (&acc)[3]) {
+// Initial state: r = b - A x0 (r = b for a zero guess), q = 0, p = 0 in
+// buffer 0; sums r.r and b.b.
+template <typename T, int BS>
+__device__ void init_tile(const KArgs<T>& a, int tile, double (&acc)[2]) {
     constexpr int W = Vec<T>::n;
     using V = typename Vec<T>::type;
-    const int seg = tile % a.nseg, zc = tile / a.nseg;
-    const int64_t s = (int64_t)seg * a.seglen;
-    const int64_t e = min(s + (int64_t)a.seglen, a.sp);
-    const int k0 = zc * a.zchunk, k1 = min(k0 + a.zchunk, a.nz);
+    const TileBox tb = tile_box(a, tile);
     const int64_t npad = a.sp * a.nz;
-    for (int k = k0; k < k1; ++k) {
-        for (int64_t pos = s + (int64_t)threadIdx.x * W; pos < e; pos += (int64_t)kBS * W) {
+    const V z0 = vzero<T>();
+    for (int k = tb.k0; k < tb.k1; ++k) {
+        for (int64_t pos = tb.s + (int64_t)threadIdx.x * W; pos < tb.e; pos += (int64_t)BS * W) {
             const int64_t g = (int64_t)k * a.sp + pos;
-            V bv = vload(a.b + g), dv = vload(a.op.d + g), rv;
+            const V bv = vload(a.b + g);
+            V rv = bv;
+            if (a.warm) {
+                const V dv = vload(a.op.d + g);
 #pragma unroll
-            for (int u = 0; u < W; ++u) {
-                T r = vget(bv, u);
-                if (a.warm) {
+                for (int u = 0; u < W; ++u) {
                     const int64_t t = g + u;
                     const T* X = a.x;
                     T nb = a.op.cx[t] * (t + 1 < npad ? X[t + 1] : T(0));
@@ -198,115 +245,139 @@ __device__ void init_tile(const KArgs<T>& a, int tile, double (&acc)[3]) {
                     nb += (t >= a.nx ? a.op.cy[t - a.nx] * X[t - a.nx] : T(0));
                     nb += a.op.cz[t] * (t + a.sp < npad ? X[t + a.sp] : T(0));
                     nb += (t >= a.sp ? a.op.cz[t - a.sp] * X[t - a.sp] : T(0));
-                    r = r - (vget(dv, u) * X[t] - nb);
+                    vget(rv, u) = vget(bv, u) - (vget(dv, u) * X[t] - nb);
                 }
-                vget(rv, u) = r;
-                const T z = r / vget(dv, u);
-                acc[0] += (double)r * (double)z;
-                acc[1] += (double)r * (double)r;
-                acc[2] += (double)vget(bv, u) * (double)vget(bv, u);
             }
-            vstore(a.r + g, rv);
-            V zero;
 #pragma unroll
-            for (int u = 0; u < W; ++u) vget(zero, u) = T(0);
-            vstore(a.p0 + g, zero);
+            for (int u = 0; u < W; ++u) {
+                acc[0] += (double)vget(rv, u) * (double)vget(rv, u);
+                acc[1] += (double)vget(bv, u) * (double)vget(bv, u);
+            }
+            vstore(a.r[0] + g, rv);
+            vstore(a.q[0] + g, z0);
+            vstore(a.p[0] + g, z0);
         }
     }
 }
 
-// Pass A on one tile (see the file comment).
-template <typename T, int MC>
-__device__ void passA_tile(const KArgs<T>& a, int tile, T beta, T alpha_prev, const T* __restrict__ pold,
-                           T* __restrict__ pnew, T* lds0, T* lds1, double& pq) {
+// One pass on one tile (see the file comment). `o`/`n` index the old and new
+// buffers; alpha, beta are alpha_{l-1}, beta_{l-1}.
+template <typename T, int BS, int MC>
+__device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T beta, T* lds0, T* lds1,
+                          double (&acc)[NPART]) {
     constexpr int W = Vec<T>::n;
     using V = typename Vec<T>::type;
-    const int seg = tile % a.nseg, zc = tile / a.nseg;
-    const int64_t s = (int64_t)seg * a.seglen;
-    const int64_t e = min(s + (int64_t)a.seglen, a.sp);
-    const int k0 = zc * a.zchunk, k1 = min(k0 + a.zchunk, a.nz);
+    const TileBox tb = tile_box(a, tile);
+    const int64_t s = tb.s, e = tb.e, sp = a.sp;
+    const int k0 = tb.k0, k1 = tb.k1;
     const int H = a.halo, nx = a.nx;
-    const int64_t sp = a.sp;
     const int64_t lbase = s - H;
     const int hgroups = 2 * H / W;
-    const bool do_x = alpha_prev != T(0);
+    const T* __restrict__ rold = a.r[o];
+    const T* __restrict__ qold = a.q[o];
+    const T* __restrict__ pold = a.p[o];
+    T* __restrict__ rnew = a.r[n];
+    T* __restrict__ pnew = a.p[n];
+    T* __restrict__ qnew = a.q[n];
+    const bool do_x = alpha != T(0);
+    const V z0 = vzero<T>();
 
     int64_t pos[MC];
     bool valid[MC];
 #pragma unroll
     for (int c = 0; c < MC; ++c) {
-        pos[c] = s + (int64_t)(c * kBS + threadIdx.x) * W;
+        pos[c] = s + (int64_t)(c * BS + (int)threadIdx.x) * W;
         valid[c] = pos[c] < e;
     }
-    V pm[MC], pc[MC], pn[MC], czm[MC], poc[MC], dc[MC];
-    const V vzero = [] { V v; for (int u = 0; u < W; ++u) vget(v, u) = T(0); return v; }();
-
-    auto pnew_at = [&](int64_t g, V& po, V& dv) -> V {
-        const V rv = vload(a.r + g);
+    // p_{l-1} at a position from the old state (pointwise); also returns
+    // r_{l-1}, p_{l-2} and d there.
+    auto p_at = [&](int64_t g, V& rv, V& po, V& dv) -> V {
+        rv = vload(rold + g);
+        const V qv = vload(qold + g);
         dv = vload(a.op.d + g);
         po = vload(pold + g);
         V out;
 #pragma unroll
-        for (int u = 0; u < W; ++u) vget(out, u) = vget(rv, u) / vget(dv, u) + beta * vget(po, u);
+        for (int u = 0; u < W; ++u) {
+            const T r = vget(rv, u) - alpha * vget(qv, u);
+            vget(rv, u) = r;
+            vget(out, u) = r * jacobi_inv(vget(dv, u)) + beta * vget(po, u);
+        }
         return out;
     };
     auto halo_fill = [&](int k, T* buf) {
-        for (int hg = threadIdx.x; hg < hgroups; hg += kBS) {
+        for (int hg = threadIdx.x; hg < hgroups; hg += BS) {
             const int64_t hp = (hg < H / W) ? (s - H + (int64_t)hg * W) : (e + (int64_t)(hg - H / W) * W);
-            V v = vzero;
+            V v = z0;
             if (hp >= 0 && hp < sp) {
-                V po, dv;
-                v = pnew_at((int64_t)k * sp + hp, po, dv);
+                V rv, po, dv;
+                v = p_at((int64_t)k * sp + hp, rv, po, dv);
             }
             vstore(buf + (hp - lbase), v);
         }
     };
-
-    // prologue: plane k0-1 (own positions only) and plane k0 (with halo)
-#pragma unroll
-    for (int c = 0; c < MC; ++c) {
-        pm[c] = vzero;
-        czm[c] = vzero;
-        if (valid[c] && k0 > 0) {
-            const int64_t g = (int64_t)(k0 - 1) * sp + pos[c];
-            V po, dv;
-            pm[c] = pnew_at(g, po, dv);
-            czm[c] = vload(a.op.cz + g);
-        }
-    }
-    {
-        T* buf = (k0 & 1) ? lds1 : lds0;
+    // Own positions of plane k: the new p (also into LDS when `buf` is
+    // given); for an owned plane also r_{l-1} and the x update are written.
+    V pc[MC], pm[MC], pn[MC], czm[MC], rc[MC], dc[MC];
+    auto own_plane = [&](int k, T* buf, bool owned, V (&pv)[MC], V (&rv)[MC], V (&dv)[MC]) {
 #pragma unroll
         for (int c = 0; c < MC; ++c) {
-            pc[c] = vzero;
-            poc[c] = vzero;
-            dc[c] = vzero;
-            if (valid[c]) {
-                pc[c] = pnew_at((int64_t)k0 * sp + pos[c], poc[c], dc[c]);
-                vstore(buf + (pos[c] - lbase), pc[c]);
+            pv[c] = z0;
+            rv[c] = z0;
+            dv[c] = z0;
+            if (!valid[c]) continue;
+            const int64_t g = (int64_t)k * sp + pos[c];
+            V po;
+            pv[c] = p_at(g, rv[c], po, dv[c]);
+            if (buf) vstore(buf + (pos[c] - lbase), pv[c]);
+            if (owned) {
+                vstore(rnew + g, rv[c]);
+                if (do_x) {
+                    V xv = vload(a.x + g);
+#pragma unroll
+                    for (int u = 0; u < W; ++u) vget(xv, u) = vget(xv, u) + alpha * vget(po, u);
+                    vstore(a.x + g, xv);
+                }
             }
         }
+    };
+
+    // prologue: plane k0-1 (own positions, z-neighbour only) and plane k0
+    {
+        V rdummy[MC], ddummy[MC];
+        if (k0 > 0) {
+            own_plane(k0 - 1, nullptr, false, pm, rdummy, ddummy);
+#pragma unroll
+            for (int c = 0; c < MC; ++c) czm[c] = valid[c] ? vload(a.op.cz + (int64_t)(k0 - 1) * sp + pos[c]) : z0;
+        } else {
+#pragma unroll
+            for (int c = 0; c < MC; ++c) {
+                pm[c] = z0;
+                czm[c] = z0;
+            }
+        }
+        T* buf = (k0 & 1) ? lds1 : lds0;
+        own_plane(k0, buf, true, pc, rc, dc);
         halo_fill(k0, buf);
     }
-    __syncthreads();
+    lds_barrier();
 
     for (int k = k0; k < k1; ++k) {
         const T* cur = (k & 1) ? lds1 : lds0;
         T* nxt = (k & 1) ? lds0 : lds1;
-        V pon[MC], dn[MC];
-        const bool has_next = k + 1 < a.nz;
+        V rn[MC], dn[MC];
+        if (k + 1 < a.nz) {
+            const bool owned = k + 1 < k1;
+            own_plane(k + 1, owned ? nxt : nullptr, owned, pn, rn, dn);
+            if (owned) halo_fill(k + 1, nxt);
+        } else {
 #pragma unroll
-        for (int c = 0; c < MC; ++c) {
-            pn[c] = vzero;
-            pon[c] = vzero;
-            dn[c] = vzero;
-            if (valid[c] && has_next) {
-                pn[c] = pnew_at((int64_t)(k + 1) * sp + pos[c], pon[c], dn[c]);
-                vstore(nxt + (pos[c] - lbase), pn[c]);
+            for (int c = 0; c < MC; ++c) {
+                pn[c] = z0;
+                rn[c] = z0;
+                dn[c] = z0;
             }
         }
-        if (has_next && k + 1 < k1) halo_fill(k + 1, nxt);
-
 #pragma unroll
         for (int c = 0; c < MC; ++c) {
             if (!valid[c]) continue;
@@ -331,77 +402,48 @@ __device__ void passA_tile(const KArgs<T>& a, int tile, T beta, T alpha_prev, co
                 nb += vget(czv, u) * vget(pn[c], u) + vget(czm[c], u) * vget(pm[c], u);
                 const T qq = vget(dc[c], u) * p - nb;
                 vget(qv, u) = qq;
-                pq += (double)p * (double)qq;
+                const T iv = jacobi_inv(vget(dc[c], u));
+                const double pd = (double)p, qd = (double)qq, rd = (double)vget(rc[c], u);
+                const double zd = (double)(vget(rc[c], u) * iv), wd = (double)(qq * iv);
+                acc[0] += pd * qd;
+                acc[1] += rd * zd;
+                acc[2] += rd * wd;
+                acc[3] += qd * wd;
+                acc[4] += rd * rd;
+                acc[5] += rd * qd;
+                acc[6] += qd * qd;
             }
             vstore(pnew + g, pc[c]);
-            vstore(a.q + g, qv);
-            if (do_x) {
-                V xv = vload(a.x + g);
-#pragma unroll
-                for (int u = 0; u < W; ++u) vget(xv, u) = vget(xv, u) + alpha_prev * vget(poc[c], u);
-                vstore(a.x + g, xv);
-            }
+            vstore(qnew + g, qv);
             czm[c] = czv;
         }
 #pragma unroll
         for (int c = 0; c < MC; ++c) {
             pm[c] = pc[c];
             pc[c] = pn[c];
-            poc[c] = pon[c];
+            rc[c] = rn[c];
             dc[c] = dn[c];
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
-// Pass B on one tile: r -= alpha q; partials r.z and r.r.
-template <typename T>
-__device__ void passB_tile(const KArgs<T>& a, int tile, T alpha, double& rz, double& rr) {
-    constexpr int W = Vec<T>::n;
-    using V = typename Vec<T>::type;
-    const int seg = tile % a.nseg, zc = tile / a.nseg;
-    const int64_t s = (int64_t)seg * a.seglen;
-    const int64_t e = min(s + (int64_t)a.seglen, a.sp);
-    const int k0 = zc * a.zchunk, k1 = min(k0 + a.zchunk, a.nz);
-    for (int k = k0; k < k1; ++k) {
-        for (int64_t pos = s + (int64_t)threadIdx.x * W; pos < e; pos += (int64_t)kBS * W) {
-            const int64_t g = (int64_t)k * a.sp + pos;
-            V rv = vload(a.r + g);
-            const V qv = vload(a.q + g);
-            const V dv = vload(a.op.d + g);
-#pragma unroll
-            for (int u = 0; u < W; ++u) {
-                const T r = vget(rv, u) - alpha * vget(qv, u);
-                vget(rv, u) = r;
-                const T z = r / vget(dv, u);
-                rz += (double)r * (double)z;
-                rr += (double)r * (double)r;
-            }
-            vstore(a.r + g, rv);
-        }
-    }
-}
-
-// Final pass: x += alpha p (or x = 0 for a zero right-hand side).
-template <typename T>
+// Final update x += alpha p (or x = 0 for a zero right-hand side).
+template <typename T, int BS>
 __device__ void final_tile(const KArgs<T>& a, int tile, T alpha, const T* p, bool zero) {
     constexpr int W = Vec<T>::n;
     using V = typename Vec<T>::type;
-    const int seg = tile % a.nseg, zc = tile / a.nseg;
-    const int64_t s = (int64_t)seg * a.seglen;
-    const int64_t e = min(s + (int64_t)a.seglen, a.sp);
-    const int k0 = zc * a.zchunk, k1 = min(k0 + a.zchunk, a.nz);
-    for (int k = k0; k < k1; ++k) {
-        for (int64_t pos = s + (int64_t)threadIdx.x * W; pos < e; pos += (int64_t)kBS * W) {
+    const TileBox tb = tile_box(a, tile);
+    for (int k = tb.k0; k < tb.k1; ++k) {
+        for (int64_t pos = tb.s + (int64_t)threadIdx.x * W; pos < tb.e; pos += (int64_t)BS * W) {
             const int64_t g = (int64_t)k * a.sp + pos;
             V xv = vload(a.x + g);
             if (zero) {
-#pragma unroll
-                for (int u = 0; u < W; ++u) vget(xv, u) = T(0);
+                xv = vzero<T>();
             } else {
                 const V pv = vload(p + g);
 #pragma unroll
-                for (int u = 0; u < W; ++u) vget(xv, u) = vget(xv, u) + alpha * vget(pv, u);
+                for (int u = 0; u < Vec<T>::n; ++u) vget(xv, u) = vget(xv, u) + alpha * vget(pv, u);
             }
             vstore(a.x + g, xv);
         }
@@ -411,34 +453,32 @@ __device__ void final_tile(const KArgs<T>& a, int tile, T alpha, const T* p, boo
 // ------------------------------------------------------------------ kernel
 
 struct Scal {
-    double alpha, alpha_prev, beta, rho, rr, bb;
+    double alpha, beta, rr, bb;
     int iters, done, status, zero;
 };
 
 __device__ void read_scalars(SyncState* S, Scal* out) {
     if (threadIdx.x == 0) {
-        out->alpha = ld_acquire_d(&S->alpha);
-        out->alpha_prev = ld_acquire_d(&S->alpha_prev);
-        out->beta = ld_acquire_d(&S->beta);
-        out->rho = ld_acquire_d(&S->rho);
-        out->rr = ld_acquire_d(&S->rr);
-        out->bb = ld_acquire_d(&S->bb);
-        out->iters = ld_acquire_i(&S->iters);
-        out->done = ld_acquire_i(&S->done);
-        out->status = ld_acquire_i(&S->status);
-        out->zero = ld_acquire_i(&S->zero_rhs);
+        out->alpha = ld_agent_d(&S->alpha);
+        out->beta = ld_agent_d(&S->beta);
+        out->rr = ld_agent_d(&S->rr);
+        out->bb = ld_agent_d(&S->bb);
+        out->iters = ld_agent_i(&S->iters);
+        out->done = ld_agent_i(&S->done);
+        out->status = ld_agent_i(&S->status);
+        out->zero = ld_agent_i(&S->zero_rhs);
     }
     __syncthreads();
 }
 
-template <typename T, int MC>
-__global__ __launch_bounds__(kBS) void k_jpcg_fused(KArgs<T> a) {
+template <typename T, int BS, int MC>
+__global__ __launch_bounds__(BS) void k_jpcg_fused(KArgs<T> a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int lds_len = a.seglen + 2 * a.halo;
     T* lds0 = reinterpret_cast<T*>(lds_raw);
     T* lds1 = lds0 + lds_len;
-    __shared__ double red[kWaves * kMaxPartials];
-    __shared__ double buf[kBS];
+    __shared__ double red[(BS / 64) * kMaxPartials];
+    __shared__ double buf[BS];
     __shared__ int s_flag;
     __shared__ Scal sc;
     SyncState* S = a.S;
@@ -448,17 +488,16 @@ __global__ __launch_bounds__(kBS) void k_jpcg_fused(KArgs<T> a) {
 
     // ---- initial residual
     for (int t = first; t < end; t += stride) {
-        double acc[3] = {0.0, 0.0, 0.0};
-        init_tile<T>(a, t, acc);
-        tile_reduce_store<3>(acc, red, a.partials + (size_t)t * kMaxPartials);
+        double acc[2] = {0.0, 0.0};
+        init_tile<T, BS>(a, t, acc);
+        tile_reduce_store<BS, 2>(acc, red, a.partials + (size_t)t * kMaxPartials);
     }
     bool ok = grid_barrier(S, gen, a.timeout_ticks, buf, &s_flag, [&](double* b) {
-        const double rz = sum_tiles(a.partials, a.ntiles, 0, b);
-        const double rr = sum_tiles(a.partials, a.ntiles, 1, b);
-        const double bb = sum_tiles(a.partials, a.ntiles, 2, b);
+        const double rr = sum_tiles<BS>(a.partials, a.ntiles, 0, b);
+        const double bb = sum_tiles<BS>(a.partials, a.ntiles, 1, b);
         if (threadIdx.x == 0) {
-            S->rho = rz; S->rr = rr; S->bb = bb;
-            S->alpha = 0.0; S->alpha_prev = 0.0; S->beta = 0.0; S->iters = 0;
+            S->rr = rr; S->bb = bb;
+            S->alpha = 0.0; S->beta = 0.0; S->iters = 0;
             int done = 0, status = PB_OK;
             if (!(bb - bb == 0.0) || !(rr - rr == 0.0)) { done = 1; status = PB_ERR_NONFINITE; }
             else if (bb == 0.0) { done = 1; S->zero_rhs = 1; }
@@ -473,61 +512,52 @@ __global__ __launch_bounds__(kBS) void k_jpcg_fused(KArgs<T> a) {
     int it = 0;
     bool final_update = false;
     while (!sc.done) {
-        const T* pold = (it & 1) ? a.p1 : a.p0;
-        T* pnew = (it & 1) ? a.p0 : a.p1;
-        const T beta = (T)sc.beta, alpha_prev = (T)sc.alpha_prev;
+        const int o = it & 1, n = (it + 1) & 1;
+        const T alpha = (T)sc.alpha, beta = (T)sc.beta;
         for (int t = first; t < end; t += stride) {
-            double acc[1] = {0.0};
-            passA_tile<T, MC>(a, t, beta, alpha_prev, pold, pnew, lds0, lds1, acc[0]);
-            tile_reduce_store<1>(acc, red, a.partials + (size_t)t * kMaxPartials);
+            double acc[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            pass_tile<T, BS, MC>(a, t, o, n, alpha, beta, lds0, lds1, acc);
+            tile_reduce_store<BS, NPART>(acc, red, a.partials + (size_t)t * kMaxPartials);
         }
-        ok = grid_barrier(S, gen, a.timeout_ticks, buf, &s_flag, [&](double* b) {
-            const double pq = sum_tiles(a.partials, a.ntiles, 0, b);
+        ok = grid_barrier(S, gen, a.timeout_ticks, buf, &s_flag, [&](double* bsc) {
+            double v[NPART];
+#pragma unroll
+            for (int i = 0; i < NPART; ++i) v[i] = sum_tiles<BS>(a.partials, a.ntiles, i, bsc);
             if (threadIdx.x == 0) {
+                const double pq = v[0], rrd = v[1], rqd = v[2], qqd = v[3], rr0 = v[4], rq = v[5], qq = v[6];
+                const int iters = ld_agent_i(&S->iters) + 1;
+                S->iters = iters;
                 S->pq = pq;
-                if (!(pq > 0.0) || !(pq - pq == 0.0)) {
+                if (!(pq > 0.0) || !(pq - pq == 0.0) || !(rrd > 0.0)) {
                     S->done = 1;
                     S->status = PB_ERR_BREAKDOWN;
                     S->alpha = 0.0;
+                    S->iters = iters - 1;
                 } else {
-                    S->alpha = ld_acquire_d(&S->rho) / pq;
+                    const double al = rrd / pq;
+                    const double rho = fmax(rrd - 2.0 * al * rqd + al * al * qqd, 0.0);
+                    const double rr = fmax(rr0 - 2.0 * al * rq + al * al * qq, 0.0);
+                    S->alpha = al;
+                    S->beta = rho / rrd;
+                    S->rho = rho;
+                    S->rr = rr;
+                    const double rel = sqrt(rr) / sqrt(ld_agent_d(&S->bb));
+                    if (!(rel - rel == 0.0)) { S->done = 1; S->status = PB_ERR_BREAKDOWN; }
+                    else if (rel < a.tol) { S->done = 1; S->status = PB_OK; }
+                    else if (iters >= a.maxiter) { S->done = 1; S->status = PB_NOT_CONVERGED; }
                 }
             }
         });
         if (!ok) return;
         read_scalars(S, &sc);
-        if (sc.done) break;   // breakdown: x already holds the last good iterate
-        const T alpha = (T)sc.alpha;
-        for (int t = first; t < end; t += stride) {
-            double acc[2] = {0.0, 0.0};
-            passB_tile<T>(a, t, alpha, acc[0], acc[1]);
-            tile_reduce_store<2>(acc, red, a.partials + (size_t)t * kMaxPartials);
-        }
-        ok = grid_barrier(S, gen, a.timeout_ticks, buf, &s_flag, [&](double* b) {
-            const double rz = sum_tiles(a.partials, a.ntiles, 0, b);
-            const double rr = sum_tiles(a.partials, a.ntiles, 1, b);
-            if (threadIdx.x == 0) {
-                const int iters = ld_acquire_i(&S->iters) + 1;
-                S->iters = iters;
-                S->beta = rz / ld_acquire_d(&S->rho);
-                S->rho = rz;
-                S->rr = rr;
-                S->alpha_prev = ld_acquire_d(&S->alpha);
-                const double rel = sqrt(rr) / sqrt(ld_acquire_d(&S->bb));
-                if (!(rel - rel == 0.0)) { S->done = 1; S->status = PB_ERR_BREAKDOWN; }
-                else if (rel < a.tol) { S->done = 1; S->status = PB_OK; }
-                else if (iters >= a.maxiter) { S->done = 1; S->status = PB_NOT_CONVERGED; }
-            }
-        });
-        if (!ok) return;
-        read_scalars(S, &sc);
         ++it;
+        if (sc.status == PB_ERR_BREAKDOWN) break;   // x holds the last good iterate
         final_update = true;
     }
-    // ---- final x update with the last alpha and direction (or x = 0)
+    // ---- last x update with the final alpha and direction (or x = 0)
     if (sc.zero || (final_update && sc.status != PB_ERR_BREAKDOWN)) {
-        const T* plast = (it & 1) ? a.p1 : a.p0;
-        for (int t = first; t < end; t += stride) final_tile<T>(a, t, (T)sc.alpha, plast, sc.zero != 0);
+        const T* plast = a.p[it & 1];
+        for (int t = first; t < end; t += stride) final_tile<T, BS>(a, t, (T)sc.alpha, plast, sc.zero != 0);
     }
 }
 
@@ -547,18 +577,33 @@ DevInfo dev_info() {
     if ((int)cache.size() <= dev) cache.resize(dev + 1);
     if (cache[dev].cus == 0) {
         DevInfo d;
-        hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev);
-        hipDeviceGetAttribute(&d.wallclock_khz, hipDeviceAttributeWallClockRate, dev);
+        if (hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) d.cus = 0;
+        if (hipDeviceGetAttribute(&d.wallclock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
+            d.wallclock_khz = 0;
         cache[dev] = d;
     }
     return cache[dev];
 }
 
-template <typename T, int MC>
-int max_coresident(size_t lds_bytes) {
+using KernelFn = const void*;
+
+struct Variant {
+    int bs, mc;
+    KernelFn fn;
+};
+
+template <typename T>
+const std::vector<Variant>& variants() {
+    static const std::vector<Variant> v = {
+        {256, 1, (KernelFn)k_jpcg_fused<T, 256, 1>},   {256, 2, (KernelFn)k_jpcg_fused<T, 256, 2>},
+        {512, 1, (KernelFn)k_jpcg_fused<T, 512, 1>},   {512, 2, (KernelFn)k_jpcg_fused<T, 512, 2>},
+    };
+    return v;
+}
+
+int max_coresident(KernelFn fn, int bs, size_t lds_bytes) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_jpcg_fused<T, MC>, kBS, lds_bytes) != hipSuccess)
-        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, bs, lds_bytes) != hipSuccess) return 0;
     return nb;
 }
 
@@ -568,43 +613,50 @@ int halo_for(int nx) {
     return (nx + W - 1) / W * W;
 }
 
-}  // namespace
-
-// Tile shape: segments of mc*256*VEC positions; z-chunks sized so that every
-// workgroup gets at most one tile per pass when possible (balanced work).
+// Tiling for one kernel variant: z-chunks chosen so that the tile count
+// fits the co-resident workgroups (each workgroup owns at most one tile, so
+// a pass takes the time of one tile). Returns grid = 0 when infeasible.
 template <typename T>
-Tiling choose_tiling(const Layout& L) {
+Tiling tiling_for(const Layout& L, const Variant& v, int cus, int max_per_cu) {
     constexpr int W = Vec<T>::n;
+    Tiling t{};
+    t.mc = v.mc;
+    t.bs = v.bs;
+    t.seglen = v.mc * v.bs * W;
+    t.halo = halo_for<T>(L.nx);
+    if (2 * t.halo / W > v.bs) return t;   // halo groups must fit one per thread
+    const size_t lds = 2 * sizeof(T) * (size_t)(t.seglen + 2 * t.halo);
+    int per_cu = max_coresident(v.fn, v.bs, lds);
+    if (max_per_cu > 0) per_cu = std::min(per_cu, max_per_cu);
+    if (per_cu <= 0) return t;
+    const int G = per_cu * cus;
+    t.nseg = (int)((L.sp + t.seglen - 1) / t.seglen);
+    const int max_chunks = G / t.nseg;
+    if (max_chunks < 1) return t;
+    t.zchunk = (L.nz + max_chunks - 1) / max_chunks;
+    t.nzc = (L.nz + t.zchunk - 1) / t.zchunk;
+    t.ntiles = t.nseg * t.nzc;
+    if (t.ntiles > kMaxTiles || t.ntiles > G) return t;
+    int grid = (t.ntiles + 7) / 8 * 8;
+    if (grid > G) grid = t.ntiles;
+    t.grid = grid;
+    t.lds = lds;
+    return t;
+}
+
+template <typename T>
+Tiling choose_tiling_impl(const Layout& L, int want_bs, int want_mc, int max_per_cu) {
     const DevInfo di = dev_info();
     const int cus = di.cus > 0 ? di.cus : 256;
     Tiling best{};
     double best_cost = 1e300;
-    for (int mc : {1, 2, 4}) {
-        Tiling t{};
-        t.mc = mc;
-        t.seglen = mc * kBS * W;
-        t.halo = halo_for<T>(L.nx);
-        const size_t lds = 2 * sizeof(T) * (size_t)(t.seglen + 2 * t.halo);
-        int per_cu = 0;
-        if (mc == 1) per_cu = max_coresident<T, 1>(lds);
-        if (mc == 2) per_cu = max_coresident<T, 2>(lds);
-        if (mc == 4) per_cu = max_coresident<T, 4>(lds);
-        if (per_cu <= 0) continue;
-        int G = per_cu * cus;
-        t.nseg = (int)((L.sp + t.seglen - 1) / t.seglen);
-        // z-chunk: fill the co-resident workgroups with about one tile each
-        int zc = std::max(1, (int)((L.nz * (int64_t)t.nseg + G - 1) / G));
-        t.zchunk = zc;
-        t.nzc = (L.nz + zc - 1) / zc;
-        t.ntiles = t.nseg * t.nzc;
-        if (t.ntiles > kMaxTiles) continue;
-        if (G > t.ntiles) G = t.ntiles;
-        if (G >= 8) G = G / 8 * 8;
-        t.grid = G;
-        // cost: the busiest workgroup's elements incl. halo and the extra z-plane
-        const int tiles_per_wg = (t.ntiles + G - 1) / G;
-        const double work = (double)tiles_per_wg * (t.zchunk + 1) * (t.seglen + 2.0 * t.halo * 0.5);
-        const double cost = work;
+    for (const auto& v : variants<T>()) {
+        if ((want_bs > 0 && v.bs != want_bs) || (want_mc > 0 && v.mc != want_mc)) continue;
+        Tiling t = tiling_for<T>(L, v, cus, max_per_cu);
+        if (t.grid <= 0) continue;
+        // model: work of one tile (planes incl. the extra one, segment incl.
+        // halo) plus a per-workgroup barrier cost
+        const double cost = (double)(t.zchunk + 1) * (t.seglen + t.halo) + 40.0 * t.grid;
         if (cost < best_cost) {
             best_cost = cost;
             best = t;
@@ -612,27 +664,94 @@ Tiling choose_tiling(const Layout& L) {
     }
     return best;
 }
+
+// Tilings recorded by the autotuner, per device, grid shape and precision.
+using TuneKey = std::tuple<int, int, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, Tiling> g_tuned;
+
+template <typename T>
+TuneKey tune_key(const Layout& L) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    return TuneKey(dev, L.nx, L.ny, L.nz, (int)sizeof(T));
+}
+
+}  // namespace
+
+template <typename T>
+Tiling choose_tiling(const Layout& L) {
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(tune_key<T>(L));
+        if (it != g_tuned.end()) return it->second;
+    }
+    return choose_tiling_impl<T>(L, 0, 0, 0);
+}
+
+template <typename T>
+void record_tiling(const Layout& L, const Tiling& t) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[tune_key<T>(L)] = t;
+}
+template void record_tiling<float>(const Layout&, const Tiling&);
+template void record_tiling<double>(const Layout&, const Tiling&);
+
+// Every distinct feasible tiling over block sizes, vector groups and
+// workgroups-per-CU caps (the autotuner's search space).
+template <typename T>
+std::vector<Tiling> tiling_candidates(const Layout& L) {
+    std::vector<Tiling> out;
+    for (const auto& v : variants<T>()) {
+        for (int cap : {1, 2, 3, 4, 0}) {
+            const Tiling t = choose_tiling_impl<T>(L, v.bs, v.mc, cap);
+            if (t.grid <= 0) continue;
+            bool dup = false;
+            for (const auto& u : out)
+                dup = dup || (u.bs == t.bs && u.mc == t.mc && u.grid == t.grid && u.zchunk == t.zchunk);
+            if (!dup) out.push_back(t);
+        }
+    }
+    return out;
+}
+template std::vector<Tiling> tiling_candidates<float>(const Layout&);
+template std::vector<Tiling> tiling_candidates<double>(const Layout&);
 template Tiling choose_tiling<float>(const Layout&);
 template Tiling choose_tiling<double>(const Layout&);
 
 template <typename T>
+Tiling tiling_with(const Layout& L, int bs, int mc, int max_per_cu) {
+    return choose_tiling_impl<T>(L, bs, mc, max_per_cu);
+}
+template Tiling tiling_with<float>(const Layout&, int, int, int);
+template Tiling tiling_with<double>(const Layout&, int, int, int);
+
+template <typename T>
 pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, double* partials, double tol,
-                     int maxiter, hipStream_t st, SolveResult* res, Tiling* used) {
-    Tiling t = choose_tiling<T>(L);
+                     int maxiter, hipStream_t st, SolveResult* res, const Tiling* force) {
+    const Tiling t = force && force->grid > 0 ? *force : choose_tiling<T>(L);
     if (t.grid <= 0) {
-        set_error("fused JPCG: no feasible tiling / occupancy for this grid");
-        return PB_ERR_HIP;
+        set_error("fused JPCG: no feasible tiling for this grid (nx too large for the in-plane halo)");
+        return PB_ERR_ARG;
     }
-    if (used) *used = t;
+    KernelFn fn = nullptr;
+    for (const auto& v : variants<T>())
+        if (v.bs == t.bs && v.mc == t.mc) fn = v.fn;
+    if (!fn) {
+        set_error("fused JPCG: unknown kernel variant bs=%d mc=%d", t.bs, t.mc);
+        return PB_ERR_ARG;
+    }
     const DevInfo di = dev_info();
     KArgs<T> a{};
     a.op = s.op;
     a.b = s.b;
     a.x = s.x;
-    a.r = s.r;
-    a.p0 = s.p0;
-    a.p1 = s.p1;
-    a.q = s.q;
+    a.r[0] = s.r;
+    a.r[1] = s.r2;
+    a.q[0] = s.q;
+    a.q[1] = s.q2;
+    a.p[0] = s.p0;
+    a.p[1] = s.p1;
     a.nx = L.nx; a.ny = L.ny; a.nz = L.nz;
     a.sp = L.sp;
     a.seglen = t.seglen; a.zchunk = t.zchunk; a.nseg = t.nseg; a.nzc = t.nzc; a.ntiles = t.ntiles;
@@ -647,7 +766,6 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
     // the header (barrier counters, scalars) starts cleared
     if (launch_fill<int>((int*)sync, (int64_t)(sizeof(SyncState) / sizeof(int)), 0, st) != PB_OK)
         return PB_ERR_HIP;
-    const size_t lds = 2 * sizeof(T) * (size_t)(t.seglen + 2 * t.halo);
     void* args[] = {&a};
     hipEvent_t ev[2] = {nullptr, nullptr};
     if (res) {
@@ -655,14 +773,12 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
         PB_HIP(hipEventCreate(&ev[1]));
         PB_HIP(hipEventRecord(ev[0], st));
     }
-    hipError_t e = hipSuccess;
-    if (t.mc == 1) e = hipLaunchCooperativeKernel((const void*)k_jpcg_fused<T, 1>, dim3(t.grid), dim3(kBS), args, lds, st);
-    else if (t.mc == 2) e = hipLaunchCooperativeKernel((const void*)k_jpcg_fused<T, 2>, dim3(t.grid), dim3(kBS), args, lds, st);
-    else e = hipLaunchCooperativeKernel((const void*)k_jpcg_fused<T, 4>, dim3(t.grid), dim3(kBS), args, lds, st);
+    const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(t.grid), dim3(t.bs), args, t.lds, st);
     if (e != hipSuccess) {
         if (ev[0]) (void)hipEventDestroy(ev[0]);
         if (ev[1]) (void)hipEventDestroy(ev[1]);
-        set_error("fused JPCG launch failed: %s (grid %d, lds %zu)", hipGetErrorString(e), t.grid, lds);
+        set_error("fused JPCG launch failed: %s (grid %d, block %d, lds %zu)", hipGetErrorString(e), t.grid,
+                  t.bs, t.lds);
         return PB_ERR_HIP;
     }
     if (res) {
@@ -679,12 +795,13 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
         res->rr = h.rr;
         res->bb = h.bb;
         res->kernel_seconds = 1e-3 * ms;
+        res->tiling = t;
     }
     return PB_OK;
 }
 template pb_status fused_jpcg<float>(const Layout&, const SolveBufs<float>&, SyncState*, double*, double, int,
-                                     hipStream_t, SolveResult*, Tiling*);
+                                     hipStream_t, SolveResult*, const Tiling*);
 template pb_status fused_jpcg<double>(const Layout&, const SolveBufs<double>&, SyncState*, double*, double, int,
-                                      hipStream_t, SolveResult*, Tiling*);
+                                      hipStream_t, SolveResult*, const Tiling*);
 
 }  // namespace pb

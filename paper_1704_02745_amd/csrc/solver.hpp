@@ -3,6 +3,8 @@
 
 #include "pb_internal.hpp"
 
+#include <vector>
+
 namespace pb {
 
 // operator.hip
@@ -24,7 +26,9 @@ pb_status launch_fill(T* p, int64_t n, T v, hipStream_t st);
 // Tiling of the fused kernel: a tile is a contiguous range of `seglen`
 // padded plane positions times a run of `zchunk` planes.
 struct Tiling {
-    int mc;          // 16-byte vector groups per thread per plane (segment = mc*256*VEC)
+    int bs;          // threads per workgroup
+    int mc;          // 16-byte vector groups per thread per plane (segment = mc*bs*VEC)
+    size_t lds;      // dynamic LDS bytes
     int seglen;      // elements per segment
     int zchunk;      // planes per tile
     int nseg, nzc, ntiles;
@@ -42,9 +46,11 @@ struct SolveBufs {
     const T* b;
     T* x;
     T* r;
+    T* r2;         // fused form: second residual buffer (ping-pong)
     T* p0;
     T* p1;
     T* q;
+    T* q2;         // fused form: second A.p buffer (ping-pong)
     T* z;          // DIA form only
     T* dia;        // DIA form only: 7 diagonals x npad
     int warm;      // 1: x holds a nonzero initial guess
@@ -56,15 +62,27 @@ struct SolveResult {
     double rr;     // ||r||^2 (recurrence) at exit
     double bb;     // ||b||^2
     double kernel_seconds;   // duration of the iteration kernel / loop (HIP events)
+    Tiling tiling;           // fused form: the tiling used
 };
 
 // jpcg.hip: one persistent cooperative launch running the whole iteration.
 template <typename T>
 pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, double* partials,
-                     double tol, int maxiter, hipStream_t st, SolveResult* res, Tiling* used);
+                     double tol, int maxiter, hipStream_t st, SolveResult* res, const Tiling* force);
 
 template <typename T>
 Tiling choose_tiling(const Layout& L);
+
+// Tiling restricted to a block size / vector-group count (0 = any) and a
+// cap on workgroups per CU (0 = occupancy limit).
+template <typename T>
+Tiling tiling_with(const Layout& L, int bs, int mc, int max_per_cu);
+
+// Autotuner support: the search space, and recording the winner for later solves.
+template <typename T>
+std::vector<Tiling> tiling_candidates(const Layout& L);
+template <typename T>
+void record_tiling(const Layout& L, const Tiling& t);
 
 // dia.hip: DIA SpMV plus separate vector kernels, host-driven loop.
 template <typename T>

@@ -306,3 +306,20 @@ def test_full_size_257_refinement(pb):
     e = pb.energy(g, prob.mol.xyz, prob.mol.charge, x)
     e_ref = fdpb.energy(g.nx, g.ny, g.nz, g.h, g.origin, prob.mol.xyz, prob.mol.charge, xs)
     assert abs(e - e_ref) <= 1e-12 * abs(e_ref)
+
+
+def test_autotune_then_solve(pb, ragged):
+    """The autotuner times every feasible tiling; the recorded winner is used
+    by later solves, which must still match the oracle."""
+    prob, ref, sysm, exact, o6 = ragged
+    for prec in ("f32", "f64"):
+        best = pb.autotune(sysm, precision=prec, iters_per_trial=5)
+        print(f"autotune {prec}: {best}", flush=True)
+        assert best["candidates"] >= 1 and best["us_per_iter"] > 0
+        x, info = pb.solve(sysm, tol=1e-6, precision=prec)
+        assert iters_close(info["iters"], o6.iters)
+        assert np.abs(x.cpu().numpy() - exact).max() <= 1e-5 * np.abs(exact).max()
+        nx, ny, nz = sysm.dims
+        pb.set_tuning(nx, ny, nz, prec, best["block"], best["groups"], best["zchunk"], best["grid"])
+    with pytest.raises(pb.PBError):
+        pb.set_tuning(61, 53, 47, "f32", 256, 1, 1, 3)   # infeasible grid size

@@ -31,11 +31,11 @@ sys.path.insert(0, ROOT)
 METRIC = "JPCG HBM GB/s (% peak) at 257^3; served solves/s + p99 latency at tol 1e-6"
 PEAK_GBS = 8000.0
 # Algorithmic bytes per unknown of the fused FP32 kernel (see the design notes):
-# pass A reads r, d, p_old, cx, cy, cz, x and writes p, q, x (40 B); pass B
-# reads r, q, d and writes r (16 B); the first iteration skips the x update
-# (-8 B); the initial pass reads b, d and writes r, p (16 B); the final pass
-# reads x, p and writes x (12 B).
-ITER_BYTES = 56
+# each iteration's single pass reads r, q, d, p_old, cx, cy, cz, x and writes
+# r, p, q, x (48 B); the first iteration skips the x update (-8 B); the
+# initial pass reads b and writes r, q, p (16 B); the final pass reads x, p
+# and writes x (12 B).
+ITER_BYTES = 48
 INIT_BYTES = 16 - 8 + 12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jpcg_fused_f32_257_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1704_02745_amd", "csrc", "jpcg.hip")

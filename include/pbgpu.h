@@ -206,6 +206,62 @@ pb_status pb_autotune(int32_t nx, int32_t ny, int32_t nz, double h,
  */
 pb_status pb_set_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t precision, const pb_tuning* tuning);
 
+/*
+ * Batched solves (many independent systems, e.g. snapshots of a trajectory,
+ * on grids of uneven size). Each problem uses the array layouts of pb_solve.
+ */
+typedef struct {
+    int32_t nx, ny, nz;     /* nodes per axis (>= 1; nx <= 512 in FP32, <= 256 in FP64) */
+    int32_t maxiter;        /* <= 0 selects 10*max(nx,ny,nz) */
+    double h;               /* grid spacing, Angstrom */
+    double tol;             /* stop when ||r||/||b|| < tol (recurrence residual) */
+    const double* eps_x;    /* device arrays as for pb_solve */
+    const double* eps_y;
+    const double* eps_z;
+    const double* kappa2;
+    const double* rhs;
+    double* x;              /* in: guess when warm_start; out: phi */
+    int32_t warm_start;
+    int32_t reserved;
+} pb_problem;
+
+/* Device workspace for a batch (depends on every problem's shape and the precision). 0 if invalid. */
+size_t pb_batch_workspace_bytes(int32_t nprob, const pb_problem* probs, int32_t precision);
+
+/*
+ * pb_solve_batch: solve all problems (section 2.2 with M = diag(A)) in ONE
+ * persistent launch. Workgroups are shared out in proportion to each
+ * problem's expected work; each problem synchronises only its own
+ * workgroups, and its tiling and reduction order depend on its shape alone,
+ * so a problem's result is bitwise identical alone and in any mix.
+ * precision: PB_F32 or PB_F64. infos (host, nprob entries, nullable) receive
+ * per-problem iterations, status and FP64 true residuals; kernel_seconds is
+ * the whole batch's device time. Returns PB_OK, PB_NOT_CONVERGED if any
+ * problem did not converge, or the first error. nprob may not exceed the
+ * device's co-resident workgroups of the batch kernel (PB_ERR_ARG).
+ */
+pb_status pb_solve_batch(int32_t nprob, const pb_problem* probs, int32_t precision,
+                         void* workspace, size_t workspace_bytes, void* stream, pb_info* infos);
+
+/*
+ * The same batch recorded once in a HIP graph (preparation, the persistent
+ * solve and the hand-back), replayed by pb_batch_graph_launch. Array
+ * pointers and shapes are fixed at creation; their contents may change
+ * between launches (e.g. new snapshots written into the same buffers).
+ * pb_batch_graph_results synchronises `stream` and reads per-problem infos.
+ * The handle owns host-side state only; the workspace stays caller-owned and
+ * must outlive the handle. Calls on one handle must not overlap.
+ */
+typedef struct pb_batch_graph pb_batch_graph;
+pb_status pb_batch_graph_create(int32_t nprob, const pb_problem* probs, int32_t precision,
+                                void* workspace, size_t workspace_bytes, void* stream,
+                                pb_batch_graph** graph);
+pb_status pb_batch_graph_launch(pb_batch_graph* graph, void* stream);
+pb_status pb_batch_graph_results(pb_batch_graph* graph, void* stream, pb_info* infos);
+/* 1 if the graph holds a cooperative launch, 0 if it fell back to a plain launch sized to co-residency. */
+int32_t pb_batch_graph_is_cooperative(const pb_batch_graph* graph);
+void pb_batch_graph_destroy(pb_batch_graph* graph);
+
 /* Device workspace needed by pb_energy. Returns 0 for invalid arguments. */
 size_t pb_energy_workspace_bytes(int64_t natoms);
 

@@ -32,6 +32,8 @@ OPERATORS = {"stencil": 0, "dia": 1}
 # Every entry point declared in include/pbgpu.h.
 EXPORTS = ("pb_version", "pb_last_error", "pb_setup_workspace_bytes", "pb_setup",
            "pb_solve_workspace_bytes", "pb_solve", "pb_autotune", "pb_set_tuning",
+           "pb_batch_workspace_bytes", "pb_solve_batch", "pb_batch_graph_create", "pb_batch_graph_launch",
+           "pb_batch_graph_results", "pb_batch_graph_is_cooperative", "pb_batch_graph_destroy",
            "pb_energy_workspace_bytes", "pb_energy")
 
 
@@ -73,6 +75,14 @@ class Tuning(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("maxiter", ctypes.c_int32), ("h", ctypes.c_double), ("tol", ctypes.c_double),
+                ("eps_x", ctypes.c_void_p), ("eps_y", ctypes.c_void_p), ("eps_z", ctypes.c_void_p),
+                ("kappa2", ctypes.c_void_p), ("rhs", ctypes.c_void_p), ("x", ctypes.c_void_p),
+                ("warm_start", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"pbgpu: {LIB_PATH} is not built; run paper_1704_02745_amd.build.build()")
@@ -97,6 +107,21 @@ def _load():
                                 vp, sz, vp, ctypes.POINTER(Tuning)]
     lib.pb_set_tuning.restype = ctypes.c_int
     lib.pb_set_tuning.argtypes = [i32, i32, i32, i32, ctypes.POINTER(Tuning)]
+    P = ctypes.POINTER(Problem)
+    lib.pb_batch_workspace_bytes.restype = sz
+    lib.pb_batch_workspace_bytes.argtypes = [i32, P, i32]
+    lib.pb_solve_batch.restype = ctypes.c_int
+    lib.pb_solve_batch.argtypes = [i32, P, i32, vp, sz, vp, ctypes.POINTER(Info)]
+    lib.pb_batch_graph_create.restype = ctypes.c_int
+    lib.pb_batch_graph_create.argtypes = [i32, P, i32, vp, sz, vp, ctypes.POINTER(vp)]
+    lib.pb_batch_graph_launch.restype = ctypes.c_int
+    lib.pb_batch_graph_launch.argtypes = [vp, vp]
+    lib.pb_batch_graph_results.restype = ctypes.c_int
+    lib.pb_batch_graph_results.argtypes = [vp, vp, ctypes.POINTER(Info)]
+    lib.pb_batch_graph_is_cooperative.restype = i32
+    lib.pb_batch_graph_is_cooperative.argtypes = [vp]
+    lib.pb_batch_graph_destroy.restype = None
+    lib.pb_batch_graph_destroy.argtypes = [vp]
     lib.pb_energy_workspace_bytes.restype = sz
     lib.pb_energy_workspace_bytes.argtypes = [i64]
     lib.pb_energy.restype = ctypes.c_int
@@ -269,6 +294,94 @@ def load_tuning(path) -> int:
         except PBError:
             pass
     return n
+
+
+def _problems(systems, tol, maxiter, outs, x0s):
+    n = len(systems)
+    arr = (Problem * n)()
+    tols = tol if isinstance(tol, (list, tuple)) else [tol] * n
+    for i, sm in enumerate(systems):
+        nx, ny, nz = sm.dims
+        p = arr[i]
+        p.nx, p.ny, p.nz, p.maxiter = nx, ny, nz, int(maxiter)
+        p.h, p.tol = sm.grid.h, float(tols[i])
+        p.eps_x, p.eps_y, p.eps_z = sm.eps_x.data_ptr(), sm.eps_y.data_ptr(), sm.eps_z.data_ptr()
+        p.kappa2, p.rhs, p.x = sm.kappa2.data_ptr(), sm.rhs.data_ptr(), outs[i].data_ptr()
+        p.warm_start = 1 if (x0s is not None and x0s[i] is not None) else 0
+    return arr
+
+
+def _outs(systems, outs, x0s):
+    if outs is None:
+        outs = [torch.empty(sm.rhs.shape, dtype=torch.float64, device=sm.rhs.device) for sm in systems]
+    if x0s is not None:
+        for o, x0 in zip(outs, x0s):
+            if x0 is not None:
+                o.copy_(torch.as_tensor(x0, dtype=torch.float64).reshape(o.shape))
+    return outs
+
+
+def solve_batch(systems, tol=1e-6, precision="f32", maxiter=0, outs=None, x0s=None,
+                workspace: Optional[torch.Tensor] = None, stream=None, check=True):
+    """Solve many systems in one persistent launch. Returns (list of x, list of info dicts)."""
+    outs = _outs(systems, outs, x0s)
+    arr = _problems(systems, tol, maxiter, outs, x0s)
+    n = len(systems)
+    prec = PRECISIONS[precision]
+    wsb = lib.pb_batch_workspace_bytes(n, arr, prec)
+    if wsb == 0:
+        raise PBError(PB_ERR_ARG, last_error() or "pb_batch_workspace_bytes rejected the batch")
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=systems[0].rhs.device)
+    infos = (Info * n)()
+    st = lib.pb_solve_batch(n, arr, prec, _ptr(workspace), workspace.numel(), _stream(stream), infos)
+    _check(st, allow=(PB_OK,) if check else (PB_OK, PB_NOT_CONVERGED) + tuple(range(-6, 0)))
+    return outs, [i.as_dict() for i in infos]
+
+
+class BatchGraph:
+    """A batch recorded once in a HIP graph and replayed by launch(). Input
+    tensors keep their addresses; their contents may change between launches."""
+
+    def __init__(self, systems, tol=1e-6, precision="f32", maxiter=0, outs=None, stream=None):
+        self.systems = list(systems)
+        self.outs = _outs(self.systems, outs, None)
+        self._arr = _problems(self.systems, tol, maxiter, self.outs, None)
+        n = len(self.systems)
+        prec = PRECISIONS[precision]
+        wsb = lib.pb_batch_workspace_bytes(n, self._arr, prec)
+        if wsb == 0:
+            raise PBError(PB_ERR_ARG, last_error() or "pb_batch_workspace_bytes rejected the batch")
+        self.workspace = torch.empty(wsb, dtype=torch.uint8, device=self.systems[0].rhs.device)
+        h = ctypes.c_void_p()
+        _check(lib.pb_batch_graph_create(n, self._arr, prec, _ptr(self.workspace), wsb, _stream(stream),
+                                         ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def cooperative(self) -> bool:
+        return bool(lib.pb_batch_graph_is_cooperative(self._h))
+
+    def launch(self, stream=None):
+        _check(lib.pb_batch_graph_launch(self._h, _stream(stream)))
+
+    def results(self, stream=None, check=True):
+        n = len(self.systems)
+        infos = (Info * n)()
+        st = lib.pb_batch_graph_results(self._h, _stream(stream), infos)
+        _check(st, allow=(PB_OK,) if check else (PB_OK, PB_NOT_CONVERGED) + tuple(range(-6, 0)))
+        return [i.as_dict() for i in infos]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.pb_batch_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def energy(grid, xyz, charge, x: torch.Tensor, atom_phi: Optional[torch.Tensor] = None,

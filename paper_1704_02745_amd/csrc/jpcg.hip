@@ -35,6 +35,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -123,19 +124,21 @@ __device__ double sum_tiles(const double* partials, int ntiles, int i, double* b
     return r;
 }
 
-// Grid barrier. Arrival is one release-ordered atomic add per workgroup; the
+// Barrier over the `group` workgroups that share S (the whole grid for a
+// single solve, one problem's workgroups in a batch). Arrival is one
+// release-ordered atomic add per workgroup; the
 // last arriver acquires, runs `last(buf)` with all its threads (it sees every
 // other workgroup's writes), and publishes a new generation. The others poll
 // the generation with relaxed loads and acquire once it changes. Waits are
 // bounded by timeout_ticks of the constant-rate clock; returns false if this
 // workgroup timed out (it must then leave the kernel).
 template <typename F>
-__device__ bool grid_barrier(SyncState* S, unsigned& gen, long long timeout_ticks, double* buf,
+__device__ bool grid_barrier(SyncState* S, unsigned group, unsigned& gen, long long timeout_ticks, double* buf,
                              int* s_flag, F&& last) {
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned prev = __hip_atomic_fetch_add(&S->arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        *s_flag = (prev == gridDim.x - 1) ? 1 : 0;
+        *s_flag = (prev == group - 1) ? 1 : 0;
     }
     __syncthreads();
     bool ok = true;
@@ -189,13 +192,14 @@ __device__ __forceinline__ typename Vec<T>::type vzero() {
     return v;
 }
 
-// Workgroup w runs on XCD w % 8 when the grid is a multiple of 8. Each XCD
-// takes a contiguous block of the tile order (z-chunk major), so the tiles
-// that share halos also share that XCD's L2.
-__device__ __forceinline__ void xcd_tile_range(int ntiles, int& first, int& stride, int& end) {
-    const int G = gridDim.x;
-    const int nx8 = (G >= 8 && G % 8 == 0) ? 8 : 1;
-    const int xcd = blockIdx.x % nx8, local = blockIdx.x / nx8, per = G / nx8;
+// Tiles of workgroup `w` out of `G` sharing a problem. With `xcd` set and G a
+// multiple of 8, workgroup w runs on XCD w % 8 and each XCD takes a
+// contiguous block of the tile order (z-chunk major), so tiles that share
+// halos also share that XCD's L2; otherwise tiles are dealt round-robin.
+__device__ __forceinline__ void xcd_tile_range(int ntiles, int w, int G, bool xcd_map, int& first, int& stride,
+                                               int& end) {
+    const int nx8 = (xcd_map && G >= 8 && G % 8 == 0) ? 8 : 1;
+    const int xcd = w % nx8, local = w / nx8, per = G / nx8;
     first = (int)(((long long)xcd * ntiles) / nx8) + local;
     stride = per;
     end = (int)(((long long)(xcd + 1) * ntiles) / nx8);
@@ -471,9 +475,10 @@ __device__ void read_scalars(SyncState* S, Scal* out) {
     __syncthreads();
 }
 
+// The whole solve of one problem by workgroup `w` of the `G` workgroups
+// assigned to it; `lds_raw` holds two plane buffers of seglen + 2*halo.
 template <typename T, int BS, int MC>
-__global__ __launch_bounds__(BS) void k_jpcg_fused(KArgs<T> a) {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
+__device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsigned char* lds_raw) {
     const int lds_len = a.seglen + 2 * a.halo;
     T* lds0 = reinterpret_cast<T*>(lds_raw);
     T* lds1 = lds0 + lds_len;
@@ -484,7 +489,7 @@ __global__ __launch_bounds__(BS) void k_jpcg_fused(KArgs<T> a) {
     SyncState* S = a.S;
     unsigned gen = 0;
     int first, stride, end;
-    xcd_tile_range(a.ntiles, first, stride, end);
+    xcd_tile_range(a.ntiles, w, G, xcd_map, first, stride, end);
 
     // ---- initial residual
     for (int t = first; t < end; t += stride) {
@@ -492,7 +497,7 @@ __global__ __launch_bounds__(BS) void k_jpcg_fused(KArgs<T> a) {
         init_tile<T, BS>(a, t, acc);
         tile_reduce_store<BS, 2>(acc, red, a.partials + (size_t)t * kMaxPartials);
     }
-    bool ok = grid_barrier(S, gen, a.timeout_ticks, buf, &s_flag, [&](double* b) {
+    bool ok = grid_barrier(S, (unsigned)G, gen, a.timeout_ticks, buf, &s_flag, [&](double* b) {
         const double rr = sum_tiles<BS>(a.partials, a.ntiles, 0, b);
         const double bb = sum_tiles<BS>(a.partials, a.ntiles, 1, b);
         if (threadIdx.x == 0) {
@@ -519,7 +524,7 @@ __global__ __launch_bounds__(BS) void k_jpcg_fused(KArgs<T> a) {
             pass_tile<T, BS, MC>(a, t, o, n, alpha, beta, lds0, lds1, acc);
             tile_reduce_store<BS, NPART>(acc, red, a.partials + (size_t)t * kMaxPartials);
         }
-        ok = grid_barrier(S, gen, a.timeout_ticks, buf, &s_flag, [&](double* bsc) {
+        ok = grid_barrier(S, (unsigned)G, gen, a.timeout_ticks, buf, &s_flag, [&](double* bsc) {
             double v[NPART];
 #pragma unroll
             for (int i = 0; i < NPART; ++i) v[i] = sum_tiles<BS>(a.partials, a.ntiles, i, bsc);
@@ -559,6 +564,29 @@ __global__ __launch_bounds__(BS) void k_jpcg_fused(KArgs<T> a) {
         const T* plast = a.p[it & 1];
         for (int t = first; t < end; t += stride) final_tile<T, BS>(a, t, (T)sc.alpha, plast, sc.zero != 0);
     }
+}
+
+template <typename T, int BS, int MC>
+__global__ __launch_bounds__(BS) void k_jpcg_fused(KArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    run_problem<T, BS, MC>(a, blockIdx.x, gridDim.x, true, lds_raw);
+}
+
+// Many independent problems in one launch: workgroups [first[p], first[p+1])
+// solve problem p with their own barrier state; problems never wait for
+// each other, and each problem's tiling and reduction order depend only on
+// its own shape.
+template <typename T, int BS, int MC>
+__global__ __launch_bounds__(BS) void k_jpcg_batch(const KArgs<T>* __restrict__ probs,
+                                                   const int* __restrict__ first, int nprob) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    int lo = 0, hi = nprob;   // last p with first[p] <= blockIdx.x
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (first[mid] <= (int)blockIdx.x) lo = mid; else hi = mid;
+    }
+    const KArgs<T> a = probs[lo];
+    run_problem<T, BS, MC>(a, blockIdx.x - first[lo], first[lo + 1] - first[lo], false, lds_raw);
 }
 
 // ------------------------------------------------------------------ host side
@@ -801,6 +829,103 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
 }
 template pb_status fused_jpcg<float>(const Layout&, const SolveBufs<float>&, SyncState*, double*, double, int,
                                      hipStream_t, SolveResult*, const Tiling*);
+
+// ------------------------------------------------------------------ batch support
+
+namespace {
+constexpr int kBatchBS = 256;
+constexpr int kBatchMC = 1;
+constexpr int kBatchZ = 16;
+}  // namespace
+
+// Tiling used for a problem inside a batch: a fixed kernel variant and
+// z-chunk, so it depends on the problem's shape alone (the same problem gives
+// bitwise the same result alone and in any mix). grid is left 0.
+template <typename T>
+Tiling batch_tiling(const Layout& L) {
+    constexpr int W = Vec<T>::n;
+    Tiling t{};
+    t.bs = kBatchBS;
+    t.mc = kBatchMC;
+    t.seglen = kBatchMC * kBatchBS * W;
+    t.halo = halo_for<T>(L.nx);
+    if (2 * t.halo / W > kBatchBS) return t;   // infeasible: ntiles stays 0
+    t.zchunk = kBatchZ;
+    t.nseg = (int)((L.sp + t.seglen - 1) / t.seglen);
+    t.nzc = (L.nz + t.zchunk - 1) / t.zchunk;
+    t.ntiles = t.nseg * t.nzc;
+    t.lds = 2 * sizeof(T) * (size_t)(t.seglen + 2 * t.halo);
+    return t;
+}
+template Tiling batch_tiling<float>(const Layout&);
+template Tiling batch_tiling<double>(const Layout&);
+
+template <typename T>
+size_t batch_kargs_bytes() {
+    return sizeof(KArgs<T>);
+}
+template size_t batch_kargs_bytes<float>();
+template size_t batch_kargs_bytes<double>();
+
+// Host-side record of one problem's kernel arguments (written to `dst`).
+template <typename T>
+void batch_fill_kargs(void* dst, const Layout& L, const SolveBufs<T>& s, SyncState* S, double* partials,
+                      const Tiling& t, double tol, int maxiter) {
+    const DevInfo di = dev_info();
+    KArgs<T> a{};
+    a.op = s.op;
+    a.b = s.b;
+    a.x = s.x;
+    a.r[0] = s.r; a.r[1] = s.r2;
+    a.q[0] = s.q; a.q[1] = s.q2;
+    a.p[0] = s.p0; a.p[1] = s.p1;
+    a.nx = L.nx; a.ny = L.ny; a.nz = L.nz;
+    a.sp = L.sp;
+    a.seglen = t.seglen; a.zchunk = t.zchunk; a.nseg = t.nseg; a.nzc = t.nzc; a.ntiles = t.ntiles;
+    a.halo = t.halo;
+    a.tol = tol;
+    a.maxiter = maxiter;
+    a.warm = s.warm;
+    a.S = S;
+    a.partials = partials;
+    a.timeout_ticks = (long long)(di.wallclock_khz > 0 ? di.wallclock_khz : 100000) * 1000LL * 20LL;
+    std::memcpy(dst, &a, sizeof(a));
+}
+template void batch_fill_kargs<float>(void*, const Layout&, const SolveBufs<float>&, SyncState*, double*,
+                                      const Tiling&, double, int);
+template void batch_fill_kargs<double>(void*, const Layout&, const SolveBufs<double>&, SyncState*, double*,
+                                       const Tiling&, double, int);
+
+// Co-resident workgroups of the batch kernel with `lds` bytes of dynamic LDS.
+template <typename T>
+int batch_capacity(size_t lds) {
+    const DevInfo di = dev_info();
+    const int per_cu = max_coresident((KernelFn)k_jpcg_batch<T, kBatchBS, kBatchMC>, kBatchBS, lds);
+    return per_cu * (di.cus > 0 ? di.cus : 256);
+}
+template int batch_capacity<float>(size_t);
+template int batch_capacity<double>(size_t);
+
+template <typename T>
+pb_status batch_launch(const void* d_kargs, const int* d_first, int nprob, int grid, size_t lds, hipStream_t st,
+                       bool cooperative) {
+    const KArgs<T>* kp = (const KArgs<T>*)d_kargs;
+    void* args[] = {&kp, &d_first, &nprob};
+    hipError_t e;
+    if (cooperative)
+        e = hipLaunchCooperativeKernel((const void*)k_jpcg_batch<T, kBatchBS, kBatchMC>, dim3(grid), dim3(kBatchBS),
+                                       args, lds, st);
+    else
+        e = hipLaunchKernel((const void*)k_jpcg_batch<T, kBatchBS, kBatchMC>, dim3(grid), dim3(kBatchBS), args, lds,
+                            st);
+    if (e != hipSuccess) {
+        set_error("batch JPCG launch failed: %s (grid %d, lds %zu)", hipGetErrorString(e), grid, lds);
+        return PB_ERR_HIP;
+    }
+    return PB_OK;
+}
+template pb_status batch_launch<float>(const void*, const int*, int, int, size_t, hipStream_t, bool);
+template pb_status batch_launch<double>(const void*, const int*, int, int, size_t, hipStream_t, bool);
 template pb_status fused_jpcg<double>(const Layout&, const SolveBufs<double>&, SyncState*, double*, double, int,
                                       hipStream_t, SolveResult*, const Tiling*);
 

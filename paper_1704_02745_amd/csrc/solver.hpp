@@ -89,4 +89,19 @@ template <typename T>
 pb_status dia_jpcg_impl(const Layout& L, const SolveBufs<T>& s, SyncState* S, double* partials,
                         double tol, int maxiter, hipStream_t st, SolveResult* res);
 
+// Batch support (jpcg.hip): shape-only tiling, per-problem kernel arguments,
+// capacity and launch of the multi-problem persistent kernel.
+template <typename T>
+Tiling batch_tiling(const Layout& L);
+template <typename T>
+size_t batch_kargs_bytes();
+template <typename T>
+void batch_fill_kargs(void* dst, const Layout& L, const SolveBufs<T>& s, SyncState* S, double* partials,
+                      const Tiling& t, double tol, int maxiter);
+template <typename T>
+int batch_capacity(size_t lds);
+template <typename T>
+pb_status batch_launch(const void* d_kargs, const int* d_first, int nprob, int grid, size_t lds, hipStream_t st,
+                       bool cooperative);
+
 }  // namespace pb

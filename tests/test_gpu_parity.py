@@ -323,3 +323,78 @@ def test_autotune_then_solve(pb, ragged):
         pb.set_tuning(nx, ny, nz, prec, best["block"], best["groups"], best["zchunk"], best["grid"])
     with pytest.raises(pb.PBError):
         pb.set_tuning(61, 53, 47, "f32", 256, 1, 1, 3)   # infeasible grid size
+
+
+# ------------------------------------------------------------------ batched form
+
+BATCH_SHAPES = [(37, 29, 23, 20), (45, 45, 45, 60), (21, 30, 17, 8), (64, 9, 33, 12), (33, 33, 65, 40)]
+
+
+@pytest.fixture(scope="module")
+def batch_set(pb):
+    probs = [synth.small_problem(nx, ny, nz, na, seed=100 + i) for i, (nx, ny, nz, na) in enumerate(BATCH_SHAPES)]
+    refs = [fdpb.assemble_problem(p) for p in probs]
+    exact = [pcg.jpcg(r, 1e-13, maxiter=20000).x for r in refs]
+    o6 = [pcg.jpcg(r, 1e-6) for r in refs]
+    systems = [gpu_setup(pb, p) for p in probs]
+    return probs, refs, exact, o6, systems
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batch_matches_oracle_and_is_mix_independent(pb, batch_set, prec):
+    probs, refs, exact, o6, systems = batch_set
+    xs, infos = pb.solve_batch(systems, tol=1e-6, precision=prec)
+    for i in range(len(systems)):
+        xg = xs[i].cpu().numpy()
+        print(f"batch {prec} #{i} {BATCH_SHAPES[i][:3]}: iters {infos[i]['iters']} oracle {o6[i].iters} "
+              f"relres_true {infos[i]['relres_true']:.2e}", flush=True)
+        assert infos[i]["status"] == pb.PB_OK
+        assert iters_close(infos[i]["iters"], o6[i].iters)
+        assert fdpb.true_relres(refs[i], xg) <= 1e-5
+        assert np.abs(xg - exact[i]).max() <= 1e-5 * np.abs(exact[i]).max()
+    # each problem alone gives bitwise the same result as in the mix
+    for i in (0, 3):
+        xa, ia = pb.solve_batch([systems[i]], tol=1e-6, precision=prec)
+        assert ia[0]["iters"] == infos[i]["iters"] and torch.equal(xa[0], xs[i])
+    # a different mix (reversed order, a subset) changes nothing either
+    sub = [systems[4], systems[1], systems[2]]
+    xb, ib = pb.solve_batch(sub, tol=1e-6, precision=prec)
+    for j, i in enumerate((4, 1, 2)):
+        assert torch.equal(xb[j], xs[i])
+
+
+def test_batch_per_problem_tolerance_and_status(pb, batch_set):
+    probs, refs, exact, o6, systems = batch_set
+    tols = [1e-3, 1e-6, 2.0, 1e-4, 1e-6]
+    xs, infos = pb.solve_batch(systems, tol=tols, precision="f32")
+    assert infos[2]["iters"] == 0 and not xs[2].any()
+    for i, t in enumerate(tols):
+        if t < 1:
+            assert infos[i]["relres_recur"] < t
+    xs, infos = pb.solve_batch(systems[:2], tol=1e-6, precision="f32", maxiter=3, check=False)
+    assert all(i["status"] == pb.PB_NOT_CONVERGED and i["iters"] == 3 for i in infos)
+
+
+def test_batch_graph_replay(pb, batch_set):
+    probs, refs, exact, o6, systems = batch_set
+    ref_x, ref_info = pb.solve_batch(systems, tol=1e-6, precision="f32")
+    g = pb.BatchGraph(systems, tol=1e-6, precision="f32")
+    print(f"graph cooperative={g.cooperative}", flush=True)
+    for rep in range(3):
+        g.launch()
+        infos = g.results()
+        for i in range(len(systems)):
+            assert infos[i]["iters"] == ref_info[i]["iters"]
+            assert torch.equal(g.outs[i], ref_x[i]), (rep, i)
+        torch.cuda.synchronize()
+    # new contents in the same buffers: doubling every rhs doubles every potential exactly
+    saved = [s.rhs.clone() for s in systems]
+    for s in systems:
+        s.rhs.mul_(2.0)
+    g.launch()
+    infos = g.results()
+    for s, r in zip(systems, saved):
+        s.rhs.copy_(r)
+    for i in range(len(systems)):
+        assert torch.equal(g.outs[i], 2.0 * ref_x[i])
+    g.close()

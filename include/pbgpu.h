@@ -262,6 +262,51 @@ pb_status pb_batch_graph_results(pb_batch_graph* graph, void* stream, pb_info* i
 int32_t pb_batch_graph_is_cooperative(const pb_batch_graph* graph);
 void pb_batch_graph_destroy(pb_batch_graph* graph);
 
+/*
+ * Continuous-batching server. Requests are queued by pb_server_submit; each
+ * pb_server_step admits queued requests in arrival order while slots and the
+ * caller's HBM arena allow (the arena size is the memory budget), advances
+ * every active request by up to `chunk` CG iterations in ONE persistent
+ * launch (the requests' work overlaps on the device), and retires requests
+ * that converged or failed, freeing their memory for the next admissions.
+ * An unfinished request's CG state stays in the arena and the next step
+ * resumes it exactly: a request's result does not depend on chunking or on
+ * the other requests in flight. precision PB_F32 runs FP32 Jacobi-PCG to the
+ * request's tol; PB_F32_REFINE64 cycles FP64 residual / FP32 correction to a
+ * relative 1e-4 / FP64 update until the FP64 residual is below tol.
+ * Request arrays (pb_problem, nx <= 512) are caller-owned and must stay
+ * valid until the request is reported done; its x receives phi then.
+ * The server owns host-side state only; the arena stays caller-owned and
+ * must outlive the server. Calls on one server must not overlap.
+ */
+typedef struct pb_server pb_server;
+
+typedef struct {
+    int32_t pending;        /* queued, not yet admitted */
+    int32_t active;         /* admitted, not yet reported */
+    size_t arena_used;      /* bytes in use (slot memory plus the launch table) */
+    size_t arena_bytes;
+    int64_t launches;       /* persistent launches so far */
+    double device_seconds;  /* their summed device time (HIP events) */
+} pb_server_stats_t;
+
+/* Arena bytes one request occupies while admitted (0 if it cannot be served). */
+size_t pb_server_request_bytes(const pb_problem* request);
+/* arena: device memory, 256-byte aligned; max_slots in [1, 4096]. */
+pb_status pb_server_create(void* arena, size_t arena_bytes, int32_t max_slots, pb_server** server);
+/* Queue a request; *id receives its handle. PB_ERR_ARG if it can never fit. */
+pb_status pb_server_submit(pb_server* server, const pb_problem* request, int32_t precision, int64_t* id);
+/*
+ * One admission + chunk + retirement round on `stream` (synchronises it).
+ * Up to max_done finished requests are reported in done_ids/done_infos
+ * (pb_info.seconds = submit-to-completion time); *n_done receives the count.
+ * Finished requests beyond max_done are reported by later steps.
+ */
+pb_status pb_server_step(pb_server* server, int32_t chunk, void* stream, int32_t max_done,
+                         int32_t* n_done, int64_t* done_ids, pb_info* done_infos);
+pb_status pb_server_stats(const pb_server* server, pb_server_stats_t* stats);
+void pb_server_destroy(pb_server* server);
+
 /* Device workspace needed by pb_energy. Returns 0 for invalid arguments. */
 size_t pb_energy_workspace_bytes(int64_t natoms);
 

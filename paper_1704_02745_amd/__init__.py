@@ -34,6 +34,8 @@ EXPORTS = ("pb_version", "pb_last_error", "pb_setup_workspace_bytes", "pb_setup"
            "pb_solve_workspace_bytes", "pb_solve", "pb_autotune", "pb_set_tuning",
            "pb_batch_workspace_bytes", "pb_solve_batch", "pb_batch_graph_create", "pb_batch_graph_launch",
            "pb_batch_graph_results", "pb_batch_graph_is_cooperative", "pb_batch_graph_destroy",
+           "pb_server_request_bytes", "pb_server_create", "pb_server_submit", "pb_server_step",
+           "pb_server_stats", "pb_server_destroy",
            "pb_energy_workspace_bytes", "pb_energy")
 
 
@@ -83,6 +85,15 @@ class Problem(ctypes.Structure):
                 ("warm_start", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("pending", ctypes.c_int32), ("active", ctypes.c_int32), ("arena_used", ctypes.c_size_t),
+                ("arena_bytes", ctypes.c_size_t), ("launches", ctypes.c_int64),
+                ("device_seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"pbgpu: {LIB_PATH} is not built; run paper_1704_02745_amd.build.build()")
@@ -122,6 +133,18 @@ def _load():
     lib.pb_batch_graph_is_cooperative.argtypes = [vp]
     lib.pb_batch_graph_destroy.restype = None
     lib.pb_batch_graph_destroy.argtypes = [vp]
+    lib.pb_server_request_bytes.restype = sz
+    lib.pb_server_request_bytes.argtypes = [P]
+    lib.pb_server_create.restype = ctypes.c_int
+    lib.pb_server_create.argtypes = [vp, sz, i32, ctypes.POINTER(vp)]
+    lib.pb_server_submit.restype = ctypes.c_int
+    lib.pb_server_submit.argtypes = [vp, P, i32, ctypes.POINTER(i64)]
+    lib.pb_server_step.restype = ctypes.c_int
+    lib.pb_server_step.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(Info)]
+    lib.pb_server_stats.restype = ctypes.c_int
+    lib.pb_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.pb_server_destroy.restype = None
+    lib.pb_server_destroy.argtypes = [vp]
     lib.pb_energy_workspace_bytes.restype = sz
     lib.pb_energy_workspace_bytes.argtypes = [i64]
     lib.pb_energy.restype = ctypes.c_int
@@ -375,6 +398,63 @@ class BatchGraph:
     def close(self):
         if getattr(self, "_h", None):
             lib.pb_batch_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching solve server over a device arena of `arena_bytes`
+    (the HBM budget). submit() queues a request; step() admits, advances every
+    active request by `chunk` iterations in one launch and returns the
+    requests that finished as [(id, info)]."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 256, device="cuda"):
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        _check(lib.pb_server_create(_ptr(self.arena), self.arena.numel(), int(max_slots), ctypes.byref(h)))
+        self._h = h
+        self._live = {}        # id -> (system, out, problem struct): keeps request memory alive
+        self.outputs = {}      # id -> potential tensor of finished requests
+
+    @staticmethod
+    def request_bytes(sysm: System) -> int:
+        arr = _problems([sysm], 1e-6, 0, [sysm.rhs], None)
+        return int(lib.pb_server_request_bytes(arr))
+
+    def submit(self, sysm: System, tol=1e-6, precision="f32", maxiter=0, out=None, x0=None) -> int:
+        outs = _outs([sysm], None if out is None else [out], None if x0 is None else [x0])
+        arr = _problems([sysm], tol, maxiter, outs, None if x0 is None else [x0])
+        rid = ctypes.c_int64()
+        _check(lib.pb_server_submit(self._h, arr, PRECISIONS[precision], ctypes.byref(rid)))
+        self._live[rid.value] = (sysm, outs[0], arr)
+        return rid.value
+
+    def step(self, chunk=32, stream=None, max_done=256):
+        n = ctypes.c_int32()
+        ids = (ctypes.c_int64 * max_done)()
+        infos = (Info * max_done)()
+        _check(lib.pb_server_step(self._h, int(chunk), _stream(stream), int(max_done), ctypes.byref(n), ids, infos))
+        done = []
+        for k in range(n.value):
+            rid = ids[k]
+            sysm, out, _ = self._live.pop(rid)
+            self.outputs[rid] = out
+            done.append((rid, infos[k].as_dict()))
+        return done
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib.pb_server_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.pb_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

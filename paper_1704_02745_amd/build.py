@@ -23,7 +23,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 # Setup arithmetic must round exactly as written (no fused multiply-add).
 PER_FILE = {"setup.hip": ["-ffp-contract=off"]}
-SOURCES = ["api.hip", "setup.hip", "operator.hip", "jpcg.hip", "dia.hip", "batch.hip"]
+SOURCES = ["api.hip", "setup.hip", "operator.hip", "jpcg.hip", "dia.hip", "batch.hip", "server.hip"]
 
 
 def _hipcc() -> str:

@@ -195,7 +195,7 @@ pb_status upload_table(const Plan<T>& P, const pb_problem* probs, int& grid, hip
         const int maxiter = probs[i].maxiter > 0 ? probs[i].maxiter
                                                  : 10 * std::max(probs[i].nx, std::max(probs[i].ny, probs[i].nz));
         batch_fill_kargs<T>(host.data() + batch_kargs_bytes<T>() * i, P.L[i], P.s[i], &P.sync[i], P.partials[i],
-                            P.t[i], probs[i].tol, maxiter);
+                            P.t[i], probs[i].tol, maxiter, 0, 0);
     }
     PB_HIP(hipMemcpyAsync(P.table, host.data(), host.size(), hipMemcpyHostToDevice, st));
     PB_HIP(hipMemcpyAsync(P.first, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice, st));

@@ -61,6 +61,8 @@ struct KArgs {
     double tol;
     int maxiter;
     int warm;
+    int resume;          // 1: continue from the state and scalars left by an earlier launch
+    int chunk;           // > 0: stop after this many iterations in this launch (state stays resumable)
     SyncState* S;
     double* partials;
     long long timeout_ticks;
@@ -487,9 +489,11 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
     __shared__ int s_flag;
     __shared__ Scal sc;
     SyncState* S = a.S;
-    unsigned gen = 0;
+    unsigned gen = __hip_atomic_load(&S->generation, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int first, stride, end;
     xcd_tile_range(a.ntiles, w, G, xcd_map, first, stride, end);
+    bool ok = true;
+    if (a.resume) goto iterate;
 
     // ---- initial residual
     for (int t = first; t < end; t += stride) {
@@ -497,7 +501,7 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
         init_tile<T, BS>(a, t, acc);
         tile_reduce_store<BS, 2>(acc, red, a.partials + (size_t)t * kMaxPartials);
     }
-    bool ok = grid_barrier(S, (unsigned)G, gen, a.timeout_ticks, buf, &s_flag, [&](double* b) {
+    ok = grid_barrier(S, (unsigned)G, gen, a.timeout_ticks, buf, &s_flag, [&](double* b) {
         const double rr = sum_tiles<BS>(a.partials, a.ntiles, 0, b);
         const double bb = sum_tiles<BS>(a.partials, a.ntiles, 1, b);
         if (threadIdx.x == 0) {
@@ -513,10 +517,11 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
         }
     });
     if (!ok) return;
+iterate:
     read_scalars(S, &sc);
-    int it = 0;
+    int it = sc.iters, this_launch = 0;
     bool final_update = false;
-    while (!sc.done) {
+    while (!sc.done && (a.chunk <= 0 || this_launch < a.chunk)) {
         const int o = it & 1, n = (it + 1) & 1;
         const T alpha = (T)sc.alpha, beta = (T)sc.beta;
         for (int t = first; t < end; t += stride) {
@@ -556,11 +561,13 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
         if (!ok) return;
         read_scalars(S, &sc);
         ++it;
+        ++this_launch;
         if (sc.status == PB_ERR_BREAKDOWN) break;   // x holds the last good iterate
         final_update = true;
     }
-    // ---- last x update with the final alpha and direction (or x = 0)
-    if (sc.zero || (final_update && sc.status != PB_ERR_BREAKDOWN)) {
+    // ---- last x update with the final alpha and direction (or x = 0); a
+    // chunk that stops before convergence leaves the state to be resumed
+    if (sc.zero || (sc.done && final_update && sc.status != PB_ERR_BREAKDOWN)) {
         const T* plast = a.p[it & 1];
         for (int t = first; t < end; t += stride) final_tile<T, BS>(a, t, (T)sc.alpha, plast, sc.zero != 0);
     }
@@ -870,7 +877,7 @@ template size_t batch_kargs_bytes<double>();
 // Host-side record of one problem's kernel arguments (written to `dst`).
 template <typename T>
 void batch_fill_kargs(void* dst, const Layout& L, const SolveBufs<T>& s, SyncState* S, double* partials,
-                      const Tiling& t, double tol, int maxiter) {
+                      const Tiling& t, double tol, int maxiter, int resume, int chunk) {
     const DevInfo di = dev_info();
     KArgs<T> a{};
     a.op = s.op;
@@ -886,15 +893,17 @@ void batch_fill_kargs(void* dst, const Layout& L, const SolveBufs<T>& s, SyncSta
     a.tol = tol;
     a.maxiter = maxiter;
     a.warm = s.warm;
+    a.resume = resume;
+    a.chunk = chunk;
     a.S = S;
     a.partials = partials;
     a.timeout_ticks = (long long)(di.wallclock_khz > 0 ? di.wallclock_khz : 100000) * 1000LL * 20LL;
     std::memcpy(dst, &a, sizeof(a));
 }
 template void batch_fill_kargs<float>(void*, const Layout&, const SolveBufs<float>&, SyncState*, double*,
-                                      const Tiling&, double, int);
+                                      const Tiling&, double, int, int, int);
 template void batch_fill_kargs<double>(void*, const Layout&, const SolveBufs<double>&, SyncState*, double*,
-                                       const Tiling&, double, int);
+                                       const Tiling&, double, int, int, int);
 
 // Co-resident workgroups of the batch kernel with `lds` bytes of dynamic LDS.
 template <typename T>

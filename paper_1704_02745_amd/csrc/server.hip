@@ -1,0 +1,479 @@
+// Continuous-batching solve server.
+//
+// Requests (systems of any supported size and tolerance) are queued by
+// pb_server_submit. Each pb_server_step admits queued requests in arrival
+// order while slots and the caller's HBM arena allow, advances every active
+// request by up to `chunk` Jacobi-PCG iterations in ONE persistent batch
+// launch (the requests' work overlaps on the device), retires requests that
+// converged or failed, and frees their memory for the next admissions. The
+// CG state of an unfinished request stays resident between steps and the
+// next launch resumes it exactly, so chunking and the mix of co-running
+// requests do not change any request's arithmetic.
+//
+// PB_F32 requests run FP32 JPCG to their tolerance. PB_F32_REFINE64 requests
+// cycle: FP64 residual -> FP32 JPCG correction to a relative 1e-4 -> FP64
+// update, until the FP64 residual is below their tolerance.
+#include "solver.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <vector>
+
+namespace pb {
+namespace {
+
+constexpr double kInnerTol = 1e-4;
+constexpr int kMaxOuter = 20;
+
+struct SlotRec {   // per-slot results written by kernels and read by the host
+    int flags;
+    int pad;
+    double rr, bb;
+    double pad2[5];
+};
+
+struct Slot {
+    int64_t id = 0;
+    pb_problem req{};
+    int precision = PB_F32;
+    Layout L{};
+    Tiling t{};
+    size_t off = 0, bytes = 0;       // arena range
+    SyncState* S = nullptr;
+    SlotRec* rec = nullptr;
+    double* partials = nullptr;
+    double* resp = nullptr;
+    Op<double> op64{};
+    double* b64 = nullptr;
+    double* x64 = nullptr;
+    SolveBufs<float> s{};
+    int maxiter = 0;
+    bool resume = false;             // inner solve already initialised
+    bool solving = false;            // inner solve in progress
+    int outer = 0, iters = 0;
+    double rr_prev = -1.0;
+    int status = PB_OK;
+    double relres = 0.0, relres_true = 0.0;
+    double t_submit = 0.0;
+};
+
+// Carve one slot's device memory at `base` (null to size it).
+size_t carve_slot(char* base, Slot& s) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return base ? base + o : nullptr;
+    };
+    const size_t n8 = sizeof(double) * (size_t)s.L.npad, n4 = sizeof(float) * (size_t)s.L.npad;
+    s.S = (SyncState*)take(sizeof(SyncState));
+    s.rec = (SlotRec*)take(sizeof(SlotRec));
+    s.partials = (double*)take(sizeof(double) * kMaxPartials * (size_t)s.t.ntiles);
+    s.resp = (double*)take(sizeof(double) * 2 * (size_t)residual_blocks(s.L));
+    s.op64.cx = (double*)take(n8);
+    s.op64.cy = (double*)take(n8);
+    s.op64.cz = (double*)take(n8);
+    s.op64.d = (double*)take(n8);
+    s.b64 = (double*)take(n8);
+    s.x64 = (double*)take(n8);
+    s.s.op.cx = (float*)take(n4);
+    s.s.op.cy = (float*)take(n4);
+    s.s.op.cz = (float*)take(n4);
+    s.s.op.d = (float*)take(n4);
+    s.s.b = (float*)take(n4);
+    s.s.x = (float*)take(n4);
+    s.s.r = (float*)take(n4);
+    s.s.r2 = (float*)take(n4);
+    s.s.q = (float*)take(n4);
+    s.s.q2 = (float*)take(n4);
+    s.s.p0 = (float*)take(n4);
+    s.s.p1 = (float*)take(n4);
+    return off;
+}
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct Server {
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    int max_slots = 0;
+    char* table = nullptr;        // device: kernel-argument records for max_slots
+    int* first = nullptr;         // device: workgroup offsets
+    size_t reserved = 0;          // arena bytes used by the table
+    std::vector<std::pair<size_t, size_t>> free_list;   // (offset, bytes), sorted by offset
+    std::deque<std::unique_ptr<Slot>> pending;
+    std::vector<std::unique_ptr<Slot>> active;
+    int64_t next_id = 1;
+    int64_t launches = 0;
+    double device_seconds = 0.0;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    std::vector<char> host_table;
+    std::vector<int> host_first;
+
+    bool alloc(size_t bytes, size_t& off) {
+        for (size_t i = 0; i < free_list.size(); ++i) {
+            if (free_list[i].second >= bytes) {
+                off = free_list[i].first;
+                free_list[i].first += bytes;
+                free_list[i].second -= bytes;
+                if (free_list[i].second == 0) free_list.erase(free_list.begin() + i);
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        auto it = std::lower_bound(free_list.begin(), free_list.end(), std::make_pair(off, (size_t)0));
+        it = free_list.insert(it, {off, bytes});
+        // merge with neighbours
+        size_t i = it - free_list.begin();
+        if (i + 1 < free_list.size() && free_list[i].first + free_list[i].second == free_list[i + 1].first) {
+            free_list[i].second += free_list[i + 1].second;
+            free_list.erase(free_list.begin() + i + 1);
+        }
+        if (i > 0 && free_list[i - 1].first + free_list[i - 1].second == free_list[i].first) {
+            free_list[i - 1].second += free_list[i].second;
+            free_list.erase(free_list.begin() + i);
+        }
+    }
+    size_t used() const {
+        size_t f = 0;
+        for (auto& p : free_list) f += p.second;
+        return arena_bytes - f;
+    }
+};
+
+namespace {
+
+// Enqueue the FP64 residual of a refinement slot: r (FP32) into the inner
+// right-hand side, sums into rec.
+pb_status enqueue_outer_residual(Slot& s, hipStream_t st) {
+    return launch_residual64(s.op64, s.b64, s.x64, s.L, nullptr, (float*)s.s.b, s.resp, &s.rec->rr, st);
+}
+
+// Reset the inner FP32 solve of a slot (zero guess, cleared barrier state).
+pb_status enqueue_inner_reset(Slot& s, hipStream_t st) {
+    pb_status e = launch_fill<int>((int*)s.S, (int64_t)(sizeof(SyncState) / sizeof(int)), 0, st);
+    if (e != PB_OK) return e;
+    e = launch_fill<float>(s.s.x, s.L.npad, 0.0f, st);
+    s.resume = false;
+    s.solving = true;
+    return e;
+}
+
+}  // namespace
+}  // namespace pb
+
+using namespace pb;
+
+struct pb_server : public pb::Server {};
+
+extern "C" size_t pb_server_request_bytes(const pb_problem* req) {
+    if (!req || req->nx < 1 || req->ny < 1 || req->nz < 1) return 0;
+    Slot s;
+    s.L = make_layout(req->nx, req->ny, req->nz);
+    s.t = batch_tiling<float>(s.L);
+    if (s.t.ntiles <= 0) return 0;
+    return carve_slot(nullptr, s);
+}
+
+extern "C" pb_status pb_server_create(void* arena, size_t arena_bytes, int32_t max_slots, pb_server** out) {
+    PB_ARG(out != nullptr, "pb_server_create: null output handle");
+    *out = nullptr;
+    PB_ARG(arena != nullptr && ((uintptr_t)arena & 255) == 0, "pb_server_create: null or misaligned arena");
+    PB_ARG(max_slots >= 1 && max_slots <= 4096, "pb_server_create: max_slots in [1, 4096]");
+    std::unique_ptr<pb_server> S(new pb_server());
+    S->arena = (char*)arena;
+    S->arena_bytes = arena_bytes;
+    S->max_slots = max_slots;
+    const size_t tb = align_up(batch_kargs_bytes<float>() * (size_t)max_slots, 256);
+    const size_t fb = align_up(sizeof(int) * (size_t)(max_slots + 1), 256);
+    PB_ARG(arena_bytes > tb + fb, "pb_server_create: arena too small");
+    S->table = S->arena;
+    S->first = (int*)(S->arena + tb);
+    S->reserved = tb + fb;
+    S->free_list.push_back({S->reserved, arena_bytes - S->reserved});
+    S->host_table.resize(batch_kargs_bytes<float>() * (size_t)max_slots);
+    S->host_first.resize(max_slots + 1);
+    PB_HIP(hipEventCreate(&S->ev[0]));
+    PB_HIP(hipEventCreate(&S->ev[1]));
+    *out = S.release();
+    return PB_OK;
+}
+
+extern "C" pb_status pb_server_submit(pb_server* S, const pb_problem* req, int32_t precision, int64_t* id) {
+    PB_ARG(S && req && id, "pb_server_submit: null argument");
+    PB_ARG(precision == PB_F32 || precision == PB_F32_REFINE64, "pb_server_submit: precision PB_F32 or PB_F32_REFINE64");
+    PB_ARG(req->nx >= 1 && req->ny >= 1 && req->nz >= 1 && std::isfinite(req->h) && req->h > 0 &&
+               std::isfinite(req->tol) && req->tol > 0 && req->eps_x && req->eps_y && req->eps_z && req->kappa2 &&
+               req->rhs && req->x,
+           "pb_server_submit: invalid request");
+    std::unique_ptr<Slot> s(new Slot());
+    s->req = *req;
+    s->precision = precision;
+    s->L = make_layout(req->nx, req->ny, req->nz);
+    s->t = batch_tiling<float>(s->L);
+    PB_ARG(s->t.ntiles > 0, "pb_server_submit: grid too wide for the batch kernel (nx <= 512)");
+    s->bytes = carve_slot(nullptr, *s);
+    PB_ARG(s->bytes <= S->arena_bytes - S->reserved, "pb_server_submit: request larger than the whole arena");
+    s->maxiter = req->maxiter > 0 ? req->maxiter : 10 * std::max(req->nx, std::max(req->ny, req->nz));
+    s->id = S->next_id++;
+    s->t_submit = now_s();
+    *id = s->id;
+    S->pending.push_back(std::move(s));
+    return PB_OK;
+}
+
+namespace {
+
+// Mark a slot finished and hand its potential back to the caller (enqueued).
+pb_status finish_slot(Slot& s, int status, hipStream_t st) {
+    s.status = status;
+    s.solving = false;
+    return launch_unpad<double>(s.x64, s.L, s.req.x, st);
+}
+
+}  // namespace
+
+extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, int32_t max_done, int32_t* n_done,
+                                    int64_t* done_ids, pb_info* done_infos) {
+    PB_ARG(S && n_done, "pb_server_step: null argument");
+    PB_ARG(chunk >= 1, "pb_server_step: chunk >= 1");
+    PB_ARG(max_done >= 0 && (max_done == 0 || (done_ids && done_infos)), "pb_server_step: bad output arrays");
+    *n_done = 0;
+    hipStream_t st = (hipStream_t)stream;
+    pb_status e;
+
+    // ---- admission (arrival order; stops at the first request that does not fit)
+    std::vector<Slot*> admitted;
+    while (!S->pending.empty() && (int)S->active.size() < S->max_slots) {
+        Slot& s = *S->pending.front();
+        size_t off = 0;
+        if (!S->alloc(s.bytes, off)) break;
+        s.off = off;
+        carve_slot(S->arena + off, s);
+        e = launch_fill<int>((int*)s.rec, (int64_t)(sizeof(SlotRec) / sizeof(int)), 0, st);
+        if (e != PB_OK) return e;
+        e = launch_prepare64(s.req.eps_x, s.req.eps_y, s.req.eps_z, s.req.kappa2, s.req.rhs, s.req.x,
+                             s.req.warm_start ? 1 : 0, s.L, s.req.h, s.op64, s.b64, s.x64, &s.rec->flags, st);
+        if (e != PB_OK) return e;
+        if (s.precision == PB_F32) {
+            e = launch_round32(s.op64, s.b64, s.x64, s.L.npad, s.s.op, (float*)s.s.b, s.s.x, st);
+            if (e != PB_OK) return e;
+            e = launch_fill<int>((int*)s.S, (int64_t)(sizeof(SyncState) / sizeof(int)), 0, st);
+            if (e != PB_OK) return e;
+            s.s.warm = s.req.warm_start ? 1 : 0;
+            s.resume = false;
+            s.solving = true;
+        } else {
+            e = launch_round32(s.op64, s.b64, s.x64, s.L.npad, s.s.op, nullptr, nullptr, st);
+            if (e != PB_OK) return e;
+            s.s.warm = 0;
+            e = enqueue_outer_residual(s, st);
+            if (e != PB_OK) return e;
+        }
+        admitted.push_back(&s);
+        S->active.push_back(std::move(S->pending.front()));
+        S->pending.pop_front();
+    }
+    if (!admitted.empty()) {
+        PB_HIP(hipStreamSynchronize(st));
+        for (Slot* sp : admitted) {
+            Slot& s = *sp;
+            SlotRec r;
+            PB_HIP(hipMemcpy(&r, s.rec, sizeof(r), hipMemcpyDeviceToHost));
+            if (r.flags & FLAG_BAD_COEF) { e = finish_slot(s, PB_ERR_ARG, st); if (e != PB_OK) return e; continue; }
+            if (r.flags & (FLAG_BAD_RHS | FLAG_BAD_GUESS)) {
+                e = finish_slot(s, PB_ERR_NONFINITE, st);
+                if (e != PB_OK) return e;
+                continue;
+            }
+            if (s.precision == PB_F32_REFINE64) {
+                if (r.bb == 0.0) {
+                    e = launch_fill<double>(s.x64, s.L.npad, 0.0, st);
+                    if (e != PB_OK) return e;
+                    s.relres = s.relres_true = 0.0;
+                    e = finish_slot(s, PB_OK, st);
+                } else {
+                    s.relres = s.relres_true = std::sqrt(r.rr) / std::sqrt(r.bb);
+                    if (s.relres < s.req.tol) e = finish_slot(s, PB_OK, st);
+                    else {
+                        s.rr_prev = r.rr;
+                        e = enqueue_inner_reset(s, st);
+                    }
+                }
+                if (e != PB_OK) return e;
+            }
+        }
+    }
+
+    // ---- one persistent launch over every slot with an inner solve in progress
+    std::vector<Slot*> run;
+    for (auto& up : S->active)
+        if (up->solving) run.push_back(up.get());
+    if (!run.empty()) {
+        std::vector<Layout> Ls;
+        std::vector<Tiling> Ts;
+        size_t lds = 0;
+        for (Slot* sp : run) {
+            Ls.push_back(sp->L);
+            Ts.push_back(sp->t);
+            lds = std::max(lds, sp->t.lds);
+        }
+        const int cap = batch_capacity<float>(lds);
+        if (cap < (int)run.size()) {
+            set_error("pb_server_step: %zu active solves exceed %d co-resident workgroups", run.size(), cap);
+            return PB_ERR_ARG;
+        }
+        std::vector<int> first(run.size() + 1, 0);
+        {
+            // workgroups in proportion to work, at least one each (same rule as the batch)
+            std::vector<double> w(run.size());
+            std::vector<int> g(run.size(), 1);
+            for (size_t i = 0; i < run.size(); ++i)
+                w[i] = (double)Ls[i].n * std::max(Ls[i].nx, std::max(Ls[i].ny, Ls[i].nz));
+            int used = (int)run.size();
+            while (used < cap) {
+                int best = -1;
+                for (size_t i = 0; i < run.size(); ++i)
+                    if (g[i] < Ts[i].ntiles && (best < 0 || w[i] / g[i] > w[best] / g[best])) best = (int)i;
+                if (best < 0) break;
+                ++g[best];
+                ++used;
+            }
+            for (size_t i = 0; i < run.size(); ++i) first[i + 1] = first[i] + g[i];
+        }
+        const size_t kb = batch_kargs_bytes<float>();
+        for (size_t i = 0; i < run.size(); ++i) {
+            Slot& s = *run[i];
+            const double tol = s.precision == PB_F32 ? s.req.tol : kInnerTol;
+            batch_fill_kargs<float>(S->host_table.data() + kb * i, s.L, s.s, s.S, s.partials, s.t, tol, s.maxiter,
+                                    s.resume ? 1 : 0, chunk);
+        }
+        PB_HIP(hipMemcpyAsync(S->table, S->host_table.data(), kb * run.size(), hipMemcpyHostToDevice, st));
+        PB_HIP(hipMemcpyAsync(S->first, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice, st));
+        PB_HIP(hipEventRecord(S->ev[0], st));
+        e = batch_launch<float>(S->table, S->first, (int)run.size(), first.back(), lds, st, true);
+        if (e != PB_OK) return e;
+        PB_HIP(hipEventRecord(S->ev[1], st));
+        PB_HIP(hipStreamSynchronize(st));
+        float ms = 0;
+        PB_HIP(hipEventElapsedTime(&ms, S->ev[0], S->ev[1]));
+        S->device_seconds += 1e-3 * ms;
+        ++S->launches;
+        // ---- inner solves that finished in this chunk
+        std::vector<Slot*> outer_check;
+        for (Slot* sp : run) {
+            Slot& s = *sp;
+            s.resume = true;
+            SyncState h;
+            PB_HIP(hipMemcpy(&h, s.S, sizeof(SyncState), hipMemcpyDeviceToHost));
+            if (!h.done) continue;
+            if (s.precision == PB_F32) {
+                s.iters = h.iters;
+                s.relres = h.bb > 0 ? std::sqrt(h.rr) / std::sqrt(h.bb) : 0.0;
+                e = launch_f32_to_f64(s.s.x, s.x64, s.L.npad, st);
+                if (e != PB_OK) return e;
+                e = launch_residual64(s.op64, s.b64, s.x64, s.L, nullptr, nullptr, s.resp, &s.rec->rr, st);
+                if (e != PB_OK) return e;
+                e = finish_slot(s, h.status, st);
+                if (e != PB_OK) return e;
+                outer_check.push_back(&s);
+            } else {
+                s.iters += h.iters;
+                if (h.status < 0) {
+                    e = finish_slot(s, h.status, st);
+                    if (e != PB_OK) return e;
+                    continue;
+                }
+                ++s.outer;
+                e = launch_add_correction(s.x64, s.s.x, s.L.npad, st);
+                if (e != PB_OK) return e;
+                e = enqueue_outer_residual(s, st);
+                if (e != PB_OK) return e;
+                e = launch_unpad<double>(s.x64, s.L, s.req.x, st);
+                if (e != PB_OK) return e;
+                s.solving = false;
+                outer_check.push_back(&s);
+            }
+        }
+        if (!outer_check.empty()) {
+            PB_HIP(hipStreamSynchronize(st));
+            for (Slot* sp : outer_check) {
+                Slot& s = *sp;
+                SlotRec r;
+                PB_HIP(hipMemcpy(&r, s.rec, sizeof(r), hipMemcpyDeviceToHost));
+                const double rel = r.bb > 0 ? std::sqrt(r.rr) / std::sqrt(r.bb) : 0.0;
+                if (s.precision == PB_F32) {
+                    s.relres_true = rel;
+                    continue;
+                }
+                s.relres = s.relres_true = rel;
+                if (!(rel - rel == 0.0)) s.status = PB_ERR_BREAKDOWN;
+                else if (rel < s.req.tol) s.status = PB_OK;
+                else if (s.outer >= kMaxOuter || r.rr > 0.25 * s.rr_prev) s.status = PB_NOT_CONVERGED;
+                else {
+                    s.rr_prev = r.rr;
+                    e = enqueue_inner_reset(s, st);
+                    if (e != PB_OK) return e;
+                    continue;
+                }
+            }
+        }
+    }
+
+    // ---- retire finished slots (their potential was handed back on the stream)
+    PB_HIP(hipStreamSynchronize(st));
+    const double tnow = now_s();
+    std::vector<std::unique_ptr<Slot>> keep;
+    for (auto& up : S->active) {
+        Slot& s = *up;
+        if (s.solving) {
+            keep.push_back(std::move(up));
+            continue;
+        }
+        if (*n_done < max_done) {
+            done_ids[*n_done] = s.id;
+            pb_info& f = done_infos[*n_done];
+            std::memset(&f, 0, sizeof(f));
+            f.iters = s.iters;
+            f.outer_iters = s.outer;
+            f.status = s.status;
+            f.relres_recur = s.relres;
+            f.relres_true = s.relres_true;
+            f.seconds = tnow - s.t_submit;
+            ++*n_done;
+            S->release(s.off, s.bytes);
+        } else {
+            keep.push_back(std::move(up));   // reported by a later step
+        }
+    }
+    S->active = std::move(keep);
+    return PB_OK;
+}
+
+extern "C" pb_status pb_server_stats(const pb_server* S, pb_server_stats_t* out) {
+    PB_ARG(S && out, "pb_server_stats: null argument");
+    out->pending = (int32_t)S->pending.size();
+    out->active = (int32_t)S->active.size();
+    out->arena_used = S->used();
+    out->arena_bytes = S->arena_bytes;
+    out->launches = S->launches;
+    out->device_seconds = S->device_seconds;
+    return PB_OK;
+}
+
+extern "C" void pb_server_destroy(pb_server* S) {
+    if (!S) return;
+    if (S->ev[0]) (void)hipEventDestroy(S->ev[0]);
+    if (S->ev[1]) (void)hipEventDestroy(S->ev[1]);
+    delete S;
+}

@@ -97,7 +97,7 @@ template <typename T>
 size_t batch_kargs_bytes();
 template <typename T>
 void batch_fill_kargs(void* dst, const Layout& L, const SolveBufs<T>& s, SyncState* S, double* partials,
-                      const Tiling& t, double tol, int maxiter);
+                      const Tiling& t, double tol, int maxiter, int resume, int chunk);
 template <typename T>
 int batch_capacity(size_t lds);
 template <typename T>

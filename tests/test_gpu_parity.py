@@ -398,3 +398,67 @@ def test_batch_graph_replay(pb, batch_set):
     for i in range(len(systems)):
         assert torch.equal(g.outs[i], 2.0 * ref_x[i])
     g.close()
+
+
+# ------------------------------------------------------------------ serving
+
+SERVE_SET = [((37, 29, 23, 20), 1e-6, "f32"), ((45, 45, 45, 60), 1e-8, "f32_refine64"),
+             ((21, 30, 17, 8), 1e-4, "f32"), ((64, 9, 33, 12), 1e-6, "f32"),
+             ((33, 33, 65, 40), 1e-8, "f32_refine64"), ((29, 29, 29, 15), 1e-6, "f32")]
+
+
+@pytest.fixture(scope="module")
+def serve_set(pb):
+    probs = [synth.small_problem(nx, ny, nz, na, seed=200 + i) for i, ((nx, ny, nz, na), _, _) in enumerate(SERVE_SET)]
+    refs = [fdpb.assemble_problem(p) for p in probs]
+    exact = [pcg.jpcg(r, 1e-13, maxiter=20000).x for r in refs]
+    systems = [gpu_setup(pb, p) for p in probs]
+    return probs, refs, exact, systems
+
+
+def _serve(pb, systems, order, arena, chunk=16):
+    srv = pb.Server(arena, max_slots=8)
+    ids = {}
+    for i in order:
+        _, tol, prec = SERVE_SET[i]
+        ids[srv.submit(systems[i], tol=tol, precision=prec)] = i
+    results, trace = {}, []
+    for _ in range(2000):
+        st = srv.stats()
+        assert st["arena_used"] <= st["arena_bytes"]
+        trace.append((st["active"], st["pending"]))
+        for rid, info in srv.step(chunk=chunk):
+            results[ids[rid]] = (srv.outputs[rid].clone(), info)
+        if len(results) == len(order):
+            break
+    srv.close()
+    return results, trace
+
+
+def test_server_continuous_batching(pb, serve_set):
+    probs, refs, exact, systems = serve_set
+    sizes = [pb.Server.request_bytes(s) for s in systems]
+    arena = int(sum(sorted(sizes)[-3:]) * 1.05) + (1 << 20)      # room for about three requests at once
+    mixed, trace = _serve(pb, systems, list(range(len(systems))), arena)
+    assert len(mixed) == len(systems)
+    # the budget limited admission at some point, and requests were backfilled
+    assert any(a > 0 and p > 0 for a, p in trace)
+    assert max(a for a, _ in trace) >= 2
+    for i, (x, info) in mixed.items():
+        _, tol, prec = SERVE_SET[i]
+        xg = x.cpu().numpy()
+        rel = fdpb.true_relres(refs[i], xg)
+        print(f"serve #{i} {prec} tol {tol}: iters {info['iters']} outer {info['outer_iters']} relres_true {rel:.2e}",
+              flush=True)
+        assert info["status"] == pb.PB_OK
+        if prec == "f32_refine64":
+            assert rel < tol and np.abs(xg - exact[i]).max() <= 1e-7 * np.abs(exact[i]).max()
+        else:
+            assert rel <= max(10 * tol, 1e-5)
+    # every result is the same alone, and in a different arrival order
+    for i in (0, 1, 3):
+        alone, _ = _serve(pb, [systems[k] if k == i else None for k in range(len(systems))], [i], arena)
+        assert torch.equal(alone[i][0], mixed[i][0]), i
+    rev, _ = _serve(pb, systems, list(reversed(range(len(systems)))), arena)
+    for i in range(len(systems)):
+        assert torch.equal(rev[i][0], mixed[i][0]), i

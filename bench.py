@@ -94,12 +94,133 @@ def cpu_baseline(prob, n_iters=8):
             "iters_per_s": round(its, 4), "os_cpu_count": os.cpu_count()}
 
 
+def bench_batched(pbgpu, torch, synth, dev, nsnap=256, seq_sample=24):
+    """Config 3: snapshots on {65,97,129,161}^3 grids solved to 1e-6 in FP32 in one
+    persistent launch (and replayed from a HIP graph), against plain per-snapshot
+    fused solves on a sample."""
+    probs = synth.config3(nsnap)
+    systems = [pbgpu.setup(p.grid, p.mol.xyz, p.mol.radius, p.mol.charge, p.eps_in, p.eps_out, p.kappa_d2,
+                           device=dev) for p in probs]
+    torch.cuda.synchronize()
+    pbgpu.solve_batch(systems[:8], tol=1e-6, precision="f32")          # warm-up (code, allocator)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, infos = pbgpu.solve_batch(systems, tol=1e-6, precision="f32")
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    nodes = [p.grid.nx * p.grid.ny * p.grid.nz for p in probs]
+    bytes_ = sum(ITER_BYTES * n * i["iters"] for n, i in zip(nodes, infos))
+    ok = sum(1 for i in infos if i["status"] == 0)
+    worst = max(i["relres_true"] for i in infos)
+    del xs
+    g = pbgpu.BatchGraph(systems, tol=1e-6, precision="f32")
+    g.launch()
+    g.results()
+    t0 = time.perf_counter()
+    g.launch()
+    ginfos = g.results()
+    t_graph = time.perf_counter() - t0
+    coop = g.cooperative
+    g.close()
+    del g
+    # plain fused FP32 solves, one after another, on a sample
+    t_seq, n_seq = 0.0, 0
+    for sm in systems[:seq_sample]:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pbgpu.solve(sm, tol=1e-6, precision="f32")
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        n_seq += 1
+    del systems
+    torch.cuda.empty_cache()
+    return {"snapshots": nsnap, "converged": ok, "worst_relres_true": worst,
+            "total_unknowns": sum(nodes), "iters_mean": sum(i["iters"] for i in infos) / nsnap,
+            "batch_s": round(t_batch, 4), "snapshots_per_s": round(nsnap / t_batch, 2),
+            "batch_gbs": round(bytes_ / t_batch / 1e9, 1),
+            "graph_s": round(t_graph, 4), "graph_snapshots_per_s": round(nsnap / t_graph, 2),
+            "graph_cooperative": coop,
+            "plain_fused_sequential_snapshots_per_s": round(n_seq / t_seq, 2),
+            "plain_fused_sample": n_seq}
+
+
+def bench_serving(pbgpu, torch, synth, dev, nreq=2200, warm=200, rate=200.0, pool=48, chunk=32,
+                  arena_gb=48, seq_sample=48):
+    """Config 4: a seeded Poisson trace of PB solve requests (atom counts
+    log-uniform 500-30,000, grids 49^3-193^3, tol 1e-4/1e-6/1e-8) served by
+    the continuous-batching server. Requests are pre-assembled systems drawn
+    from a pool of distinct molecules (setup is not part of the served
+    latency). Latency = completion - arrival."""
+    import numpy as np
+    reqs = [synth.config4_request(i) for i in range(pool)]
+    systems = [pbgpu.setup(p.grid, p.mol.xyz, p.mol.radius, p.mol.charge, p.eps_in, p.eps_out, p.kappa_d2,
+                           device=dev) for p in reqs]
+    torch.cuda.synchronize()
+
+    def run(nr, rate_, seed):
+        arrivals = synth.config4_arrivals(nr, rate=rate_, seed=seed)
+        srv = pbgpu.Server(int(arena_gb * (1 << 30)), max_slots=96, device=dev, keep_outputs=False)
+        done_at, submitted = {}, {}
+        k = 0
+        t0 = time.perf_counter()
+        while len(done_at) < nr:
+            now = time.perf_counter() - t0
+            while k < nr and arrivals[k] <= now:
+                p = reqs[k % pool]
+                rid = srv.submit(systems[k % pool], tol=p.tol, precision=p.precision)
+                submitted[rid] = k
+                k += 1
+            st = srv.stats()
+            if st["active"] == 0 and st["pending"] == 0:
+                if k < nr:
+                    time.sleep(max(0.0, min(arrivals[k] - (time.perf_counter() - t0), 0.01)))
+                continue
+            for rid, info in srv.step(chunk=chunk):
+                done_at[submitted[rid]] = (time.perf_counter() - t0, info)
+        span = time.perf_counter() - t0
+        stats = srv.stats()
+        srv.close()
+        lat = np.array([done_at[i][0] - arrivals[i] for i in range(warm if nr > warm else 0, nr)])
+        fin = np.array([done_at[i][0] for i in range(warm if nr > warm else 0, nr)])
+        okc = sum(1 for i in range(nr) if done_at[i][1]["status"] == 0)
+        thr = len(lat) / max(fin.max() - min(arrivals[warm if nr > warm else 0], fin.min()), 1e-9)
+        return {"requests": nr, "offered_per_s": rate_, "solves_per_s": round(thr, 2),
+                "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
+                "converged": okc, "span_s": round(span, 3), "launches": stats["launches"],
+                "device_s": round(stats["device_seconds"], 3)}
+
+    full = run(nreq, rate, 4999)
+    light_rate = round(0.7 * full["solves_per_s"], 1)
+    light = run(max(400, nreq // 4), light_rate, 5999)
+    # plain fused solves of the same requests, one at a time
+    lat_seq = []
+    for i in range(seq_sample):
+        p = reqs[i % pool]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pbgpu.solve(systems[i % pool], tol=p.tol, precision=p.precision)
+        torch.cuda.synchronize()
+        lat_seq.append(time.perf_counter() - t0)
+    lat_seq = np.array(lat_seq)
+    del systems
+    torch.cuda.empty_cache()
+    return {"trace": full, "at_0.7x_capacity": light,
+            "plain_fused_sequential": {"solves_per_s": round(len(lat_seq) / lat_seq.sum(), 2),
+                                       "p50_ms": round(1e3 * float(np.percentile(lat_seq, 50)), 2),
+                                       "p99_ms": round(1e3 * float(np.percentile(lat_seq, 99)), 2),
+                                       "sample": len(lat_seq)},
+            "pool": pool, "chunk": chunk}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched (config 3) and served (config 4) measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one untimed 512 MiB device copy first (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -179,6 +300,15 @@ def main():
                 "bytes_per_launch": round(total_bytes / launches, 0),
                 "avg_launch_ms": round(1e3 * ksec / launches, 4)}
 
+    forms = {}
+    if not args.no_forms:
+        print("bench: batched form (config 3)", file=sys.stderr, flush=True)
+        forms["batched"] = bench_batched(pbgpu, torch, synth, dev)
+        print(f"bench: {forms['batched']}", file=sys.stderr, flush=True)
+        print("bench: served form (config 4)", file=sys.stderr, flush=True)
+        forms["served"] = bench_serving(pbgpu, torch, synth, dev)
+        print(f"bench: {forms['served']}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
@@ -220,6 +350,7 @@ def main():
             "solves_per_s": round(args.steps / wall, 3),
             "tuning": tuning,
         },
+        "forms": forms,
     }
     print(json.dumps(out), flush=True)
 

@@ -413,7 +413,8 @@ class Server:
     active request by `chunk` iterations in one launch and returns the
     requests that finished as [(id, info)]."""
 
-    def __init__(self, arena_bytes: int, max_slots: int = 256, device="cuda"):
+    def __init__(self, arena_bytes: int, max_slots: int = 256, device="cuda", keep_outputs=True):
+        self.keep_outputs = keep_outputs
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
         h = ctypes.c_void_p()
         _check(lib.pb_server_create(_ptr(self.arena), self.arena.numel(), int(max_slots), ctypes.byref(h)))
@@ -443,7 +444,8 @@ class Server:
         for k in range(n.value):
             rid = ids[k]
             sysm, out, _ = self._live.pop(rid)
-            self.outputs[rid] = out
+            if self.keep_outputs:
+                self.outputs[rid] = out
             done.append((rid, infos[k].as_dict()))
         return done
 

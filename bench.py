@@ -94,6 +94,41 @@ def cpu_baseline(prob, n_iters=8):
             "iters_per_s": round(its, 4), "os_cpu_count": os.cpu_count()}
 
 
+# DIA form: 7 diagonals (28 B) + p (4 B) read, q (4 B) written by the SpMV;
+# p.q (8 B); x, r axpy (24 B); z = r/d with r.z, r.r (12 B); p = z + beta p (12 B).
+DIA_ITER_BYTES = 92
+
+
+def bench_c1(pbgpu, torch, synth, dev, reps=3):
+    """Config 1: 129^3 FP32 to 1e-6, fused matrix-free stencil vs the DIA form."""
+    p = synth.config1()
+    g = p.grid
+    sm = pbgpu.setup(g, p.mol.xyz, p.mol.radius, p.mol.charge, p.eps_in, p.eps_out, p.kappa_d2, device=dev)
+    n = g.nx * g.ny * g.nz
+    out = {}
+    for op, per in (("stencil", ITER_BYTES), ("dia", DIA_ITER_BYTES)):
+        pbgpu.solve(sm, tol=1e-6, precision="f32", op=op)
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = pbgpu.solve(sm, tol=1e-6, precision="f32", op=op)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if best is None or dt < best[0]:
+                best = (dt, info)
+        dt, info = best
+        out[op] = {"iters": info["iters"], "solve_ms": round(1e3 * dt, 3),
+                   "iter_loop_ms": round(1e3 * info["kernel_seconds"], 3),
+                   "us_per_iter": round(1e6 * info["kernel_seconds"] / max(info["iters"], 1), 2),
+                   "algorithmic_gbs": round(per * n * info["iters"] / info["kernel_seconds"] / 1e9, 1),
+                   "bytes_per_node_iter": per, "relres_true": info["relres_true"]}
+    out["speedup_stencil_vs_dia"] = round(out["dia"]["iter_loop_ms"] / out["stencil"]["iter_loop_ms"], 2)
+    del sm
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_batched(pbgpu, torch, synth, dev, nsnap=256, seq_sample=24):
     """Config 3: snapshots on {65,97,129,161}^3 grids solved to 1e-6 in FP32 in one
     persistent launch (and replayed from a HIP graph), against plain per-snapshot
@@ -302,6 +337,9 @@ def main():
 
     forms = {}
     if not args.no_forms:
+        print("bench: config 1 (129^3 stencil vs DIA)", file=sys.stderr, flush=True)
+        forms["c1_129_stencil_vs_dia"] = bench_c1(pbgpu, torch, synth, dev)
+        print(f"bench: {forms['c1_129_stencil_vs_dia']}", file=sys.stderr, flush=True)
         print("bench: batched form (config 3)", file=sys.stderr, flush=True)
         forms["batched"] = bench_batched(pbgpu, torch, synth, dev)
         print(f"bench: {forms['batched']}", file=sys.stderr, flush=True)

@@ -279,12 +279,14 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
     const int H = a.halo, nx = a.nx;
     const int64_t lbase = s - H;
     const int hgroups = 2 * H / W;
-    const T* __restrict__ rold = a.r[o];
-    const T* __restrict__ qold = a.q[o];
-    const T* __restrict__ pold = a.p[o];
-    T* __restrict__ rnew = a.r[n];
-    T* __restrict__ pnew = a.p[n];
-    T* __restrict__ qnew = a.q[n];
+    // ping-pong buffers chosen by select (no runtime array indexing, which
+    // would put a private copy of the arguments in scratch memory)
+    const T* __restrict__ rold = o ? a.r[1] : a.r[0];
+    const T* __restrict__ qold = o ? a.q[1] : a.q[0];
+    const T* __restrict__ pold = o ? a.p[1] : a.p[0];
+    T* __restrict__ rnew = n ? a.r[1] : a.r[0];
+    T* __restrict__ pnew = n ? a.p[1] : a.p[0];
+    T* __restrict__ qnew = n ? a.q[1] : a.q[0];
     const bool do_x = alpha != T(0);
     const V z0 = vzero<T>();
 
@@ -368,31 +370,96 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
     }
     lds_barrier();
 
+    // Each plane step first issues every global load it needs (the next
+    // plane's r, q, d, p_old and x, this thread's halo group of the next
+    // plane, and the current plane's couplings), then computes: one memory
+    // round trip per step. The tiling guarantees at most one halo group per
+    // thread (2*halo/VEC <= block size).
+    const int hg = threadIdx.x;
+    const int64_t hp = (hg < H / W) ? (s - H + (int64_t)hg * W) : (e + (int64_t)(hg - H / W) * W);
+    const bool h_in_range = hg < hgroups && hp >= 0 && hp < sp;
     for (int k = k0; k < k1; ++k) {
         const T* cur = (k & 1) ? lds1 : lds0;
         T* nxt = (k & 1) ? lds0 : lds1;
-        V rn[MC], dn[MC];
-        if (k + 1 < a.nz) {
-            const bool owned = k + 1 < k1;
-            own_plane(k + 1, owned ? nxt : nullptr, owned, pn, rn, dn);
-            if (owned) halo_fill(k + 1, nxt);
-        } else {
+        const bool has_next = k + 1 < a.nz;
+        const bool owned = k + 1 < k1;
+        const bool x_upd = owned && do_x;
+        // ---- loads
+        V in_r[MC], in_q[MC], in_d[MC], in_po[MC], in_x[MC];
+        V cxv[MC], cyv[MC], czv[MC];
+        T cxm[MC], cym[MC][W];
 #pragma unroll
-            for (int c = 0; c < MC; ++c) {
-                pn[c] = z0;
-                rn[c] = z0;
-                dn[c] = z0;
+        for (int c = 0; c < MC; ++c) {
+            in_r[c] = in_q[c] = in_po[c] = in_x[c] = z0;
+            in_d[c] = z0;
+            if (!valid[c]) continue;
+            if (has_next) {
+                const int64_t g1 = (int64_t)(k + 1) * sp + pos[c];
+                in_r[c] = vload(rold + g1);
+                in_q[c] = vload(qold + g1);
+                in_d[c] = vload(a.op.d + g1);
+                in_po[c] = vload(pold + g1);
+                if (x_upd) in_x[c] = vload(a.x + g1);
+            }
+            const int64_t g = (int64_t)k * sp + pos[c];
+            cxv[c] = vload(a.op.cx + g);
+            cyv[c] = vload(a.op.cy + g);
+            czv[c] = vload(a.op.cz + g);
+            cxm[c] = pos[c] >= 1 ? a.op.cx[g - 1] : T(0);
+#pragma unroll
+            for (int u = 0; u < W; ++u) cym[c][u] = (pos[c] + u - nx >= 0) ? a.op.cy[g + u - nx] : T(0);
+        }
+        V h_r = z0, h_q = z0, h_d = z0, h_po = z0;
+        const bool h_load = has_next && owned && h_in_range;
+        if (h_load) {
+            const int64_t gh = (int64_t)(k + 1) * sp + hp;
+            h_r = vload(rold + gh);
+            h_q = vload(qold + gh);
+            h_d = vload(a.op.d + gh);
+            h_po = vload(pold + gh);
+        }
+        // ---- next plane: new p (own and halo), r_{l-1}, x update
+        V rn[MC], dn[MC];
+#pragma unroll
+        for (int c = 0; c < MC; ++c) {
+            pn[c] = z0;
+            rn[c] = z0;
+            dn[c] = in_d[c];
+            if (!valid[c] || !has_next) continue;
+            const int64_t g1 = (int64_t)(k + 1) * sp + pos[c];
+#pragma unroll
+            for (int u = 0; u < W; ++u) {
+                const T r = vget(in_r[c], u) - alpha * vget(in_q[c], u);
+                vget(rn[c], u) = r;
+                vget(pn[c], u) = r * jacobi_inv(vget(in_d[c], u)) + beta * vget(in_po[c], u);
+            }
+            if (owned) {
+                vstore(nxt + (pos[c] - lbase), pn[c]);
+                vstore(rnew + g1, rn[c]);
+                if (x_upd) {
+#pragma unroll
+                    for (int u = 0; u < W; ++u) vget(in_x[c], u) = vget(in_x[c], u) + alpha * vget(in_po[c], u);
+                    vstore(a.x + g1, in_x[c]);
+                }
             }
         }
+        if (has_next && owned && hg < hgroups) {
+            V hv = z0;
+            if (h_in_range) {
+#pragma unroll
+                for (int u = 0; u < W; ++u) {
+                    const T r = vget(h_r, u) - alpha * vget(h_q, u);
+                    vget(hv, u) = r * jacobi_inv(vget(h_d, u)) + beta * vget(h_po, u);
+                }
+            }
+            vstore(nxt + (hp - lbase), hv);
+        }
+        // ---- current plane: q = A p and the partial sums
 #pragma unroll
         for (int c = 0; c < MC; ++c) {
             if (!valid[c]) continue;
             const int64_t g = (int64_t)k * sp + pos[c];
             const int64_t l = pos[c] - lbase;
-            const V cxv = vload(a.op.cx + g);
-            const V cyv = vload(a.op.cy + g);
-            const V czv = vload(a.op.cz + g);
-            const T cxm = pos[c] >= 1 ? a.op.cx[g - 1] : T(0);
             const T left = cur[l - 1];
             const T right = cur[l + W];
             V qv;
@@ -401,11 +468,10 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
                 const T p = vget(pc[c], u);
                 const T pl = (u == 0) ? left : vget(pc[c], u - 1);
                 const T pr = (u == W - 1) ? right : vget(pc[c], u + 1);
-                const T cl = (u == 0) ? cxm : vget(cxv, u - 1);
-                const T cym = (pos[c] + u - nx >= 0) ? a.op.cy[g + u - nx] : T(0);
-                T nb = vget(cxv, u) * pr + cl * pl;
-                nb += vget(cyv, u) * cur[l + u + nx] + cym * cur[l + u - nx];
-                nb += vget(czv, u) * vget(pn[c], u) + vget(czm[c], u) * vget(pm[c], u);
+                const T cl = (u == 0) ? cxm[c] : vget(cxv[c], u - 1);
+                T nb = vget(cxv[c], u) * pr + cl * pl;
+                nb += vget(cyv[c], u) * cur[l + u + nx] + cym[c][u] * cur[l + u - nx];
+                nb += vget(czv[c], u) * vget(pn[c], u) + vget(czm[c], u) * vget(pm[c], u);
                 const T qq = vget(dc[c], u) * p - nb;
                 vget(qv, u) = qq;
                 const T iv = jacobi_inv(vget(dc[c], u));
@@ -421,7 +487,7 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
             }
             vstore(pnew + g, pc[c]);
             vstore(qnew + g, qv);
-            czm[c] = czv;
+            czm[c] = czv[c];
         }
 #pragma unroll
         for (int c = 0; c < MC; ++c) {
@@ -568,7 +634,7 @@ iterate:
     // ---- last x update with the final alpha and direction (or x = 0); a
     // chunk that stops before convergence leaves the state to be resumed
     if (sc.zero || (sc.done && final_update && sc.status != PB_ERR_BREAKDOWN)) {
-        const T* plast = a.p[it & 1];
+        const T* plast = (it & 1) ? a.p[1] : a.p[0];
         for (int t = first; t < end; t += stride) final_tile<T, BS>(a, t, (T)sc.alpha, plast, sc.zero != 0);
     }
 }

@@ -48,7 +48,7 @@ SolveWs carve_solve(void* base, const Layout& L, int prec, int op) {
     w.sync = (SyncState*)take(sizeof(SyncState));
     w.dia_sync = (SyncState*)take(sizeof(SyncState));
     w.small = (double*)take(16 * sizeof(double));
-    w.partials = (double*)take(sizeof(double) * kMaxPartials * (size_t)kMaxTiles);
+    w.partials = (double*)take(2 * sizeof(double) * kMaxPartials * (size_t)kMaxTiles);
     w.op64.cx = (double*)take(n8);
     w.op64.cy = (double*)take(n8);
     w.op64.cz = (double*)take(n8);

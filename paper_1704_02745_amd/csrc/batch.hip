@@ -76,7 +76,7 @@ bool carve_batch(void* base, int nprob, const pb_problem* probs, Plan<T>& P) {
         const size_t n8 = sizeof(double) * (size_t)L.npad, nT = sizeof(T) * (size_t)L.npad;
         P.L.push_back(L);
         P.t.push_back(t);
-        P.partials.push_back((double*)take(sizeof(double) * kMaxPartials * (size_t)t.ntiles));
+        P.partials.push_back((double*)take(2 * sizeof(double) * kMaxPartials * (size_t)t.ntiles));
         P.resp.push_back((double*)take(sizeof(double) * 2 * (size_t)residual_blocks(L)));
         Op<double> o64;
         o64.cx = (double*)take(n8);

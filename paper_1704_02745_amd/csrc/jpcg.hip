@@ -84,91 +84,144 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Reduce acc[0..NP) over the workgroup in a fixed order; thread 0 stores the
-// sums into dst. `red` is LDS scratch of (BS/64)*kMaxPartials doubles.
+// Cross-lane moves of a double through DPP (two 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)u, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int kDppXor1 = 0xB1;         // quad permute [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;         // quad permute [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane i of 8 reads lane 7-i
+constexpr int kDppMirror = 0x140;      // lane i of 16 reads lane 15-i
+constexpr int kDppRor8 = 0x128;        // lane i of 16 reads lane (i+8) mod 16
+
+// Sum over the 64 lanes of a wave (every lane active) in a fixed order: a
+// butterfly inside each 16-lane row, then (row0 + row1) + (row2 + row3).
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_d<kDppXor1>(v);
+    v += dpp_d<kDppXor2>(v);
+    v += dpp_d<kDppHalfMirror>(v);
+    v += dpp_d<kDppMirror>(v);
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// LDS scratch of the reductions below, in doubles.
+template <int BS>
+constexpr int red_len() { return (BS / 64) * 4 * kMaxPartials + kMaxPartials; }
+
+// Reduce acc[0..NP) over the workgroup in a fixed order and store the sums
+// into dst. The stores are made by the first NP lanes of wave 0, the wave
+// that later publishes them (its release covers its own stores).
 template <int BS, int NP>
 __device__ __forceinline__ void tile_reduce_store(double (&acc)[NP], double* red, double* dst) {
     constexpr int NW = BS / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
-        double v = acc[i];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        const double v = wave_sum(acc[i]);
         if (lane == 0) red[wave * kMaxPartials + i] = v;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < NP; ++i) {
-            double s = red[i];
-            for (int w = 1; w < NW; ++w) s += red[w * kMaxPartials + i];
-            dst[i] = s;
-        }
+    if (threadIdx.x < NP) {
+        double v = red[threadIdx.x];
+        for (int q = 1; q < NW; ++q) v += red[q * kMaxPartials + threadIdx.x];
+        dst[threadIdx.x] = v;
     }
     __syncthreads();
 }
 
-// Sum slot i of every tile in tile order (all threads of the last workgroup
-// take part); the result is returned to every thread.
-template <int BS>
-__device__ double sum_tiles(const double* partials, int ntiles, int i, double* buf) {
-    double a = 0.0;
-    for (int t = threadIdx.x; t < ntiles; t += BS) a += ld_agent_d(partials + (size_t)t * kMaxPartials + i);
-    buf[threadIdx.x] = a;
+// Barrier over the G workgroups that share a problem (the whole grid for a
+// single solve, one problem's workgroups in a batch), fused with the
+// reduction of the tile sums. Workgroup w adds one release-ordered arrival to
+// counter w % 8 (eight cache lines, so arrivals do not serialise on one
+// address); for barrier b of this launch it waits (eight lanes polling the
+// eight counters together) until every counter holds
+// (b+1) times its share of the G workgroups, acquires, and then EVERY
+// workgroup reduces all tile sums of slot b & 1 itself in the same fixed
+// order (a coalesced sweep over the tiles, then a fixed lane and wave order), so
+// all workgroups obtain bitwise identical sums with no second publication
+// step. Tile sums are double-buffered by barrier parity: a workgroup can only
+// overwrite slot b & 1 after barrier b+1, which every reader of barrier b has
+// reached. Waits are bounded by timeout_ticks; returns false on timeout.
+// The summation order depends on the block size only, not on G or on which
+// workgroup ran which tile.
+template <int BS, int NP>
+__device__ bool grid_sync_reduce(SyncState* S, int w, int G, int b, const double* __restrict__ tile_sums,
+                                 int ntiles, long long timeout_ticks, double* red, int* s_flag,
+                                 double (&out)[NP]) {
+    constexpr int NW = BS / 64;
     __syncthreads();
-    for (int w = BS / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
-        __syncthreads();
-    }
-    const double r = buf[0];
-    __syncthreads();
-    return r;
-}
-
-// Barrier over the `group` workgroups that share S (the whole grid for a
-// single solve, one problem's workgroups in a batch). Arrival is one
-// release-ordered atomic add per workgroup; the
-// last arriver acquires, runs `last(buf)` with all its threads (it sees every
-// other workgroup's writes), and publishes a new generation. The others poll
-// the generation with relaxed loads and acquire once it changes. Waits are
-// bounded by timeout_ticks of the constant-rate clock; returns false if this
-// workgroup timed out (it must then leave the kernel).
-template <typename F>
-__device__ bool grid_barrier(SyncState* S, unsigned group, unsigned& gen, long long timeout_ticks, double* buf,
-                             int* s_flag, F&& last) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned prev = __hip_atomic_fetch_add(&S->arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        *s_flag = (prev == group - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    bool ok = true;
-    if (*s_flag) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        last(buf);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            __hip_atomic_store(&S->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&S->generation, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    } else if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {
+        // wave 0: lane 0 arrives, lanes 0..7 each watch one counter, so one
+        // poll costs a single memory round trip
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(&S->arrive[w & 7][0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const int c = threadIdx.x & 7;
+        const unsigned need = (unsigned)(b + 1) * (unsigned)(G / 8 + (c < G % 8 ? 1 : 0));
+        int ok = 1;
         const long long t0 = wall_clock64();
-        while (__hip_atomic_load(&S->generation, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        while (true) {
+            const unsigned v = threadIdx.x < 8
+                                   ? __hip_atomic_load(&S->arrive[c][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                   : need;
+            if (__all(v >= need)) break;
             __builtin_amdgcn_s_sleep(1);
             if (wall_clock64() - t0 > timeout_ticks) {
-                __hip_atomic_store(&S->status, (int)PB_ERR_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                *s_flag = -1;
+                ok = 0;
                 break;
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (threadIdx.x == 0) {
+            if (!ok) __hip_atomic_store(&S->status, (int)PB_ERR_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            *s_flag = ok;
+        }
     }
-    ++gen;
     __syncthreads();
-    if (*s_flag == -1) ok = false;
+    if (!*s_flag) return false;
+    // coalesced sweep: thread (j, i) adds slot i of tiles j, j + BS/8, ...
+    // Plain loads: after the acquire above they observe every released tile
+    // sum, and the workgroups of one XCD then share the lines in its L2.
+    constexpr int NJ = BS / 8;
+    const int i = threadIdx.x & 7, j = threadIdx.x >> 3;
+    constexpr int U = 8;   // loads in flight per thread
+    double acc = 0.0;
+    if (i < NP) {
+        for (int t0 = j; t0 < ntiles; t0 += U * NJ) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * NJ;
+                v[u] = t < ntiles ? tile_sums[(size_t)t * kMaxPartials + i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc += v[u];
+        }
+    }
+    acc += dpp_d<kDppRor8>(acc);   // lanes i and i+8 of each row hold the same slot
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if ((lane & 15) < 8) red[(wave * 4 + (lane >> 4)) * kMaxPartials + i] = acc;
     __syncthreads();
-    return ok;
+    double* fin = red + NW * 4 * kMaxPartials;
+    if (threadIdx.x < NP) {
+        double v = red[threadIdx.x];
+        for (int q = 1; q < NW * 4; ++q) v += red[q * kMaxPartials + threadIdx.x];
+        fin[threadIdx.x] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NP; ++k) out[k] = fin[k];
+    __syncthreads();
+    return true;
 }
 
 template <typename T>
@@ -529,62 +582,61 @@ struct Scal {
     int iters, done, status, zero;
 };
 
-__device__ void read_scalars(SyncState* S, Scal* out) {
-    if (threadIdx.x == 0) {
-        out->alpha = ld_agent_d(&S->alpha);
-        out->beta = ld_agent_d(&S->beta);
-        out->rr = ld_agent_d(&S->rr);
-        out->bb = ld_agent_d(&S->bb);
-        out->iters = ld_agent_i(&S->iters);
-        out->done = ld_agent_i(&S->done);
-        out->status = ld_agent_i(&S->status);
-        out->zero = ld_agent_i(&S->zero_rhs);
-    }
-    __syncthreads();
-}
-
 // The whole solve of one problem by workgroup `w` of the `G` workgroups
 // assigned to it; `lds_raw` holds two plane buffers of seglen + 2*halo.
+// Every workgroup derives the scalars (alpha, beta, stopping test) itself
+// from the identically reduced tile sums; workgroup 0 also persists them in
+// S for the host and for a resumed launch.
 template <typename T, int BS, int MC>
 __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsigned char* lds_raw) {
     const int lds_len = a.seglen + 2 * a.halo;
     T* lds0 = reinterpret_cast<T*>(lds_raw);
     T* lds1 = lds0 + lds_len;
-    __shared__ double red[(BS / 64) * kMaxPartials];
-    __shared__ double buf[BS];
+    __shared__ double red[red_len<BS>()];
     __shared__ int s_flag;
     __shared__ Scal sc;
     SyncState* S = a.S;
-    unsigned gen = __hip_atomic_load(&S->generation, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool lead = (w == 0) && (threadIdx.x == 0);
     int first, stride, end;
     xcd_tile_range(a.ntiles, w, G, xcd_map, first, stride, end);
-    bool ok = true;
-    if (a.resume) goto iterate;
+    int b = 0;   // barrier index within this launch (arrival counters start at zero)
+    auto sums = [&](int bb) { return a.partials + (size_t)(bb & 1) * a.ntiles * kMaxPartials; };
 
-    // ---- initial residual
-    for (int t = first; t < end; t += stride) {
-        double acc[2] = {0.0, 0.0};
-        init_tile<T, BS>(a, t, acc);
-        tile_reduce_store<BS, 2>(acc, red, a.partials + (size_t)t * kMaxPartials);
-    }
-    ok = grid_barrier(S, (unsigned)G, gen, a.timeout_ticks, buf, &s_flag, [&](double* b) {
-        const double rr = sum_tiles<BS>(a.partials, a.ntiles, 0, b);
-        const double bb = sum_tiles<BS>(a.partials, a.ntiles, 1, b);
+    if (!a.resume) {
+        // ---- initial residual
+        for (int t = first; t < end; t += stride) {
+            double acc[2] = {0.0, 0.0};
+            init_tile<T, BS>(a, t, acc);
+            tile_reduce_store<BS, 2>(acc, red, sums(b) + (size_t)t * kMaxPartials);
+        }
+        double v[2];
+        if (!grid_sync_reduce<BS, 2>(S, w, G, b, sums(b), a.ntiles, a.timeout_ticks, red, &s_flag, v)) return;
+        ++b;
         if (threadIdx.x == 0) {
-            S->rr = rr; S->bb = bb;
-            S->alpha = 0.0; S->beta = 0.0; S->iters = 0;
-            int done = 0, status = PB_OK;
+            const double rr = v[0], bb = v[1];
+            int done = 0, status = PB_OK, zero = 0;
             if (!(bb - bb == 0.0) || !(rr - rr == 0.0)) { done = 1; status = PB_ERR_NONFINITE; }
-            else if (bb == 0.0) { done = 1; S->zero_rhs = 1; }
+            else if (bb == 0.0) { done = 1; zero = 1; }
             else if (sqrt(rr) / sqrt(bb) < a.tol) { done = 1; }
             else if (a.maxiter <= 0) { done = 1; status = PB_NOT_CONVERGED; }
-            S->done = done;
-            S->status = status;
+            sc.alpha = 0.0; sc.beta = 0.0; sc.rr = rr; sc.bb = bb;
+            sc.iters = 0; sc.done = done; sc.status = status; sc.zero = zero;
+            if (lead) {
+                S->rr = rr; S->bb = bb; S->alpha = 0.0; S->beta = 0.0; S->iters = 0;
+                S->done = done; S->status = status; S->zero_rhs = zero;
+            }
         }
-    });
-    if (!ok) return;
-iterate:
-    read_scalars(S, &sc);
+        __syncthreads();
+    } else {
+        if (threadIdx.x == 0) {
+            sc.alpha = ld_agent_d(&S->alpha); sc.beta = ld_agent_d(&S->beta);
+            sc.rr = ld_agent_d(&S->rr); sc.bb = ld_agent_d(&S->bb);
+            sc.iters = ld_agent_i(&S->iters); sc.done = ld_agent_i(&S->done);
+            sc.status = ld_agent_i(&S->status); sc.zero = ld_agent_i(&S->zero_rhs);
+        }
+        __syncthreads();
+    }
+
     int it = sc.iters, this_launch = 0;
     bool final_update = false;
     while (!sc.done && (a.chunk <= 0 || this_launch < a.chunk)) {
@@ -593,39 +645,39 @@ iterate:
         for (int t = first; t < end; t += stride) {
             double acc[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             pass_tile<T, BS, MC>(a, t, o, n, alpha, beta, lds0, lds1, acc);
-            tile_reduce_store<BS, NPART>(acc, red, a.partials + (size_t)t * kMaxPartials);
+            tile_reduce_store<BS, NPART>(acc, red, sums(b) + (size_t)t * kMaxPartials);
         }
-        ok = grid_barrier(S, (unsigned)G, gen, a.timeout_ticks, buf, &s_flag, [&](double* bsc) {
-            double v[NPART];
-#pragma unroll
-            for (int i = 0; i < NPART; ++i) v[i] = sum_tiles<BS>(a.partials, a.ntiles, i, bsc);
-            if (threadIdx.x == 0) {
-                const double pq = v[0], rrd = v[1], rqd = v[2], qqd = v[3], rr0 = v[4], rq = v[5], qq = v[6];
-                const int iters = ld_agent_i(&S->iters) + 1;
-                S->iters = iters;
-                S->pq = pq;
-                if (!(pq > 0.0) || !(pq - pq == 0.0) || !(rrd > 0.0)) {
-                    S->done = 1;
-                    S->status = PB_ERR_BREAKDOWN;
-                    S->alpha = 0.0;
-                    S->iters = iters - 1;
-                } else {
-                    const double al = rrd / pq;
-                    const double rho = fmax(rrd - 2.0 * al * rqd + al * al * qqd, 0.0);
-                    const double rr = fmax(rr0 - 2.0 * al * rq + al * al * qq, 0.0);
-                    S->alpha = al;
-                    S->beta = rho / rrd;
-                    S->rho = rho;
-                    S->rr = rr;
-                    const double rel = sqrt(rr) / sqrt(ld_agent_d(&S->bb));
-                    if (!(rel - rel == 0.0)) { S->done = 1; S->status = PB_ERR_BREAKDOWN; }
-                    else if (rel < a.tol) { S->done = 1; S->status = PB_OK; }
-                    else if (iters >= a.maxiter) { S->done = 1; S->status = PB_NOT_CONVERGED; }
-                }
+        double v[NPART];
+        if (!grid_sync_reduce<BS, NPART>(S, w, G, b, sums(b), a.ntiles, a.timeout_ticks, red, &s_flag, v)) return;
+        ++b;
+        if (threadIdx.x == 0) {
+            const double pq = v[0], rrd = v[1], rqd = v[2], qqd = v[3], rr0 = v[4], rq = v[5], qq = v[6];
+            if (!(pq > 0.0) || !(pq - pq == 0.0) || !(rrd > 0.0)) {
+                sc.done = 1;
+                sc.status = PB_ERR_BREAKDOWN;
+                sc.alpha = 0.0;
+            } else {
+                const double al = rrd / pq;
+                const double rho = fmax(rrd - 2.0 * al * rqd + al * al * qqd, 0.0);
+                const double rr = fmax(rr0 - 2.0 * al * rq + al * al * qq, 0.0);
+                const int iters = sc.iters + 1;
+                sc.alpha = al;
+                sc.beta = rho / rrd;
+                sc.rr = rr;
+                sc.iters = iters;
+                const double rel = sqrt(rr) / sqrt(sc.bb);
+                if (!(rel - rel == 0.0)) { sc.done = 1; sc.status = PB_ERR_BREAKDOWN; }
+                else if (rel < a.tol) { sc.done = 1; sc.status = PB_OK; }
+                else if (iters >= a.maxiter) { sc.done = 1; sc.status = PB_NOT_CONVERGED; }
+                if (lead) S->rho = rho;
             }
-        });
-        if (!ok) return;
-        read_scalars(S, &sc);
+            if (lead) {
+                S->pq = pq;
+                S->alpha = sc.alpha; S->beta = sc.beta; S->rr = sc.rr; S->iters = sc.iters;
+                S->done = sc.done; S->status = sc.status;
+            }
+        }
+        __syncthreads();
         ++it;
         ++this_launch;
         if (sc.status == PB_ERR_BREAKDOWN) break;   // x holds the last good iterate
@@ -708,6 +760,17 @@ int max_coresident(KernelFn fn, int bs, size_t lds_bytes) {
     return nb;
 }
 
+// Segment length for at most `cap` positions per plane step: the fewest
+// segments that cover a padded plane, split evenly (rounded up to 64 bytes,
+// so segments start aligned and none is empty once nseg is recomputed).
+template <typename T>
+int balanced_seglen(const Layout& L, int cap) {
+    constexpr int A = 64 / (int)sizeof(T);
+    const int64_t nseg = (L.sp + cap - 1) / cap;
+    const int64_t even = (L.sp + nseg - 1) / nseg;
+    return (int)std::min<int64_t>(cap, (even + A - 1) / A * A);
+}
+
 template <typename T>
 int halo_for(int nx) {
     constexpr int W = Vec<T>::n;
@@ -723,7 +786,7 @@ Tiling tiling_for(const Layout& L, const Variant& v, int cus, int max_per_cu) {
     Tiling t{};
     t.mc = v.mc;
     t.bs = v.bs;
-    t.seglen = v.mc * v.bs * W;
+    t.seglen = balanced_seglen<T>(L, v.mc * v.bs * W);
     t.halo = halo_for<T>(L.nx);
     if (2 * t.halo / W > v.bs) return t;   // halo groups must fit one per thread
     const size_t lds = 2 * sizeof(T) * (size_t)(t.seglen + 2 * t.halo);
@@ -920,7 +983,7 @@ Tiling batch_tiling(const Layout& L) {
     Tiling t{};
     t.bs = kBatchBS;
     t.mc = kBatchMC;
-    t.seglen = kBatchMC * kBatchBS * W;
+    t.seglen = balanced_seglen<T>(L, kBatchMC * kBatchBS * W);
     t.halo = halo_for<T>(L.nx);
     if (2 * t.halo / W > kBatchBS) return t;   // infeasible: ntiles stays 0
     t.zchunk = kBatchZ;
@@ -980,6 +1043,24 @@ int batch_capacity(size_t lds) {
 }
 template int batch_capacity<float>(size_t);
 template int batch_capacity<double>(size_t);
+
+template <typename T>
+__global__ void k_reset_arrivals(const KArgs<T>* __restrict__ probs, int nprob) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nprob * 8) probs[i / 8].S->arrive[i % 8][0] = 0u;
+}
+
+// Clear the arrival counters of every problem in a device argument table
+// (needed before a launch that resumes problems whose state is kept).
+template <typename T>
+pb_status batch_reset_arrivals(const void* d_kargs, int nprob, hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_arrivals<T>, dim3((nprob * 8 + 255) / 256), dim3(256), 0, st,
+                       (const KArgs<T>*)d_kargs, nprob);
+    PB_HIP(hipGetLastError());
+    return PB_OK;
+}
+template pb_status batch_reset_arrivals<float>(const void*, int, hipStream_t);
+template pb_status batch_reset_arrivals<double>(const void*, int, hipStream_t);
 
 template <typename T>
 pb_status batch_launch(const void* d_kargs, const int* d_first, int nprob, int grid, size_t lds, hipStream_t st,

@@ -74,27 +74,26 @@ struct Op {
 
 // ---------------------------------------------------------------- device sync
 //
-// Grid-wide barrier state of the persistent solver and the scalars it
-// publishes. One instance lives at the head of the solve workspace.
+// Barrier state of the persistent solver and the scalars it persists. One
+// instance per problem (at the head of the solve workspace for a single
+// solve). The arrival counters are cleared before every launch; the scalars
+// are written by workgroup 0 after every iteration so the host can read
+// them and a later launch can resume.
 struct alignas(256) SyncState {
-    unsigned int arrive;          // arrivals in the current barrier
-    unsigned int pad0[63];
-    unsigned int generation;      // incremented by the last arriver
-    unsigned int pad1[63];
-    // published scalars (written by the last arriver before the release)
-    double alpha;                 // alpha of the current iteration
-    double alpha_prev;            // alpha of the previous iteration (deferred x update)
+    unsigned int arrive[8][64];   // arrivals of this launch, spread over 8 cache lines
+    double alpha;                 // alpha of the last completed iteration
+    double alpha_prev;
     double beta;
     double rho;                   // r.z
-    double rr;                    // ||r||^2
+    double rr;                    // ||r||^2 (recurrence)
     double bb;                    // ||b||^2
     double pq;
-    double rq, qq, rqd, qqd;      // single-pass form: expansion terms
+    double rq, qq, rqd, qqd;
     int iters;
     int done;                     // 1: stop iterating
     int status;                   // pb_status
     int zero_rhs;                 // 1: ||b|| == 0
-    int flags;                    // argument / finiteness flags from preparation
+    int flags;
     int pad2[59];
 };
 

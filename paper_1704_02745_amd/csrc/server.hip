@@ -72,7 +72,7 @@ size_t carve_slot(char* base, Slot& s) {
     const size_t n8 = sizeof(double) * (size_t)s.L.npad, n4 = sizeof(float) * (size_t)s.L.npad;
     s.S = (SyncState*)take(sizeof(SyncState));
     s.rec = (SlotRec*)take(sizeof(SlotRec));
-    s.partials = (double*)take(sizeof(double) * kMaxPartials * (size_t)s.t.ntiles);
+    s.partials = (double*)take(2 * sizeof(double) * kMaxPartials * (size_t)s.t.ntiles);
     s.resp = (double*)take(sizeof(double) * 2 * (size_t)residual_blocks(s.L));
     s.op64.cx = (double*)take(n8);
     s.op64.cy = (double*)take(n8);
@@ -360,6 +360,8 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
         }
         PB_HIP(hipMemcpyAsync(S->table, S->host_table.data(), kb * run.size(), hipMemcpyHostToDevice, st));
         PB_HIP(hipMemcpyAsync(S->first, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice, st));
+        e = batch_reset_arrivals<float>(S->table, (int)run.size(), st);
+        if (e != PB_OK) return e;
         PB_HIP(hipEventRecord(S->ev[0], st));
         e = batch_launch<float>(S->table, S->first, (int)run.size(), first.back(), lds, st, true);
         if (e != PB_OK) return e;

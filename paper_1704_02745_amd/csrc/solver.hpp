@@ -37,7 +37,7 @@ struct Tiling {
 };
 
 constexpr int kMaxTiles = 65536;
-constexpr int kMaxPartials = 8;   // doubles per tile
+constexpr int kMaxPartials = 8;   // doubles per tile (tile sums are double-buffered: 2 slots)
 
 // Solver state arrays for one fused or DIA solve in precision T.
 template <typename T>
@@ -100,6 +100,8 @@ void batch_fill_kargs(void* dst, const Layout& L, const SolveBufs<T>& s, SyncSta
                       const Tiling& t, double tol, int maxiter, int resume, int chunk);
 template <typename T>
 int batch_capacity(size_t lds);
+template <typename T>
+pb_status batch_reset_arrivals(const void* d_kargs, int nprob, hipStream_t st);
 template <typename T>
 pb_status batch_launch(const void* d_kargs, const int* d_first, int nprob, int grid, size_t lds, hipStream_t st,
                        bool cooperative);

@@ -30,19 +30,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "JPCG HBM GB/s (% peak) at 257^3; served solves/s + p99 latency at tol 1e-6"
 PEAK_GBS = 8000.0
-# Algorithmic bytes per unknown of the fused FP32 kernel (see the design notes):
-# each iteration's single pass reads r, q, d, p_old, cx, cy, cz, x and writes
-# r, p, q, x (48 B); the first iteration skips the x update (-8 B); the
-# initial pass reads b and writes r, q, p (16 B); the final pass reads x, p
-# and writes x (12 B).
-ITER_BYTES = 48
-INIT_BYTES = 16 - 8 + 12
+# Algorithmic bytes per unknown of the fused FP32 kernel, by pass form:
+# form 1 (40-byte pass) reads r, p_old, d, cx, cy, cz, x and writes r, p, x
+# (40 B), recomputing A.p_old; form 0 also reads and writes the stored A.p
+# (48 B). The first iteration skips the x update (-8 B); the initial pass
+# reads b and writes r, p (and q in form 0): 12 or 16 B; the final pass reads
+# x, p and writes x (12 B).
+ITER_BYTES_BY_SCHEME = {0: 48, 1: 40}
+INIT_BYTES_BY_SCHEME = {0: 16 - 8 + 12, 1: 12 - 8 + 12}
+ITER_BYTES = 48   # the batched form always runs the form-0 pass
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jpcg_fused_f32_257_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1704_02745_amd", "csrc", "jpcg.hip")
 
 
-def launch_bytes(n: int, iters: int, launches: int) -> float:
-    return float(n) * (ITER_BYTES * iters + INIT_BYTES * launches)
+def launch_bytes(n: int, iters: int, launches: int, scheme: int) -> float:
+    return float(n) * (ITER_BYTES_BY_SCHEME[scheme] * iters + INIT_BYTES_BY_SCHEME[scheme] * launches)
 
 
 def measured_traffic():
@@ -64,7 +66,7 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(prob, n_iters=8):
+def cpu_baseline(prob, iter_bytes, n_iters=8):
     """FP64 oracle Jacobi PCG at the full 257^3 size, bounded to n_iters
     iterations. The sample system uses the oracle's own classification,
     edges, salt term and charges; its boundary values are zero (the boundary
@@ -86,11 +88,11 @@ def cpu_baseline(prob, n_iters=8):
     cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
     n = g.nx * g.ny * g.nz
     its = res.iters / wall
-    return {"value": round(its * ITER_BYTES * n / 1e9, 3), "unit": "GB/s",
+    return {"value": round(its * iter_bytes * n / 1e9, 3), "unit": "GB/s",
             "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
             "sample": f"{res.iters} FP64 NumPy Jacobi-PCG iterations of the oracle at 257^3 "
                       f"(same operator, zero boundary), {wall:.1f} s wall; rate scaled by the "
-                      f"metric's {ITER_BYTES} B/unknown per iteration",
+                      f"metric's {iter_bytes} B/unknown per iteration",
             "iters_per_s": round(its, 4), "os_cpu_count": os.cpu_count()}
 
 
@@ -106,7 +108,8 @@ def bench_c1(pbgpu, torch, synth, dev, reps=3):
     sm = pbgpu.setup(g, p.mol.xyz, p.mol.radius, p.mol.charge, p.eps_in, p.eps_out, p.kappa_d2, device=dev)
     n = g.nx * g.ny * g.nz
     out = {}
-    for op, per in (("stencil", ITER_BYTES), ("dia", DIA_ITER_BYTES)):
+    sch = pbgpu.get_tuning(g.nx, g.ny, g.nz, "f32")["scheme"]
+    for op, per in (("stencil", ITER_BYTES_BY_SCHEME[sch]), ("dia", DIA_ITER_BYTES)):
         pbgpu.solve(sm, tol=1e-6, precision="f32", op=op)
         best = None
         for _ in range(reps):
@@ -123,6 +126,8 @@ def bench_c1(pbgpu, torch, synth, dev, reps=3):
                    "us_per_iter": round(1e6 * info["kernel_seconds"] / max(info["iters"], 1), 2),
                    "algorithmic_gbs": round(per * n * info["iters"] / info["kernel_seconds"] / 1e9, 1),
                    "bytes_per_node_iter": per, "relres_true": info["relres_true"]}
+        if op == "stencil":
+            out[op]["pass_form"] = sch
     out["speedup_stencil_vs_dia"] = round(out["dia"]["iter_loop_ms"] / out["stencil"]["iter_loop_ms"], 2)
     del sm
     torch.cuda.empty_cache()
@@ -307,6 +312,7 @@ def main():
     sys0 = pbgpu.setup(g, xyz, rad, chg, prob.eps_in, prob.eps_out, prob.kappa_d2, device=dev)
     tuning = pbgpu.autotune(sys0, precision="f32", iters_per_trial=20, workspace=ws)
     print(f"bench: autotune {tuning}", file=sys.stderr, flush=True)
+    scheme = tuning["scheme"]
     del sys0
     for _ in range(args.warmup):
         step()
@@ -324,14 +330,15 @@ def main():
     iters = sum(i["iters"] for i in infos)
     launches = sum(i["kernel_launches"] for i in infos)
     ksec = sum(i["kernel_seconds"] for i in infos)
-    total_bytes = launch_bytes(n, iters, launches)
+    total_bytes = launch_bytes(n, iters, launches, scheme)
     value = total_bytes / wall / 1e9
     achieved = total_bytes / ksec / 1e9
     traffic = measured_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic, 0),
-                "kernel": "k_jpcg_fused<float> (persistent, one launch per inner solve)",
+                "kernel": f"k_jpcg_fused<float, {tuning['block']}, {tuning['groups']}, {scheme}> (persistent, "
+                          f"one launch per inner solve; {ITER_BYTES_BY_SCHEME[scheme]} B/unknown/iteration)",
                 "bytes_per_launch": round(total_bytes / launches, 0),
                 "avg_launch_ms": round(1e3 * ksec / launches, 4)}
 
@@ -350,7 +357,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(prob)
+        cpu = cpu_baseline(prob, ITER_BYTES_BY_SCHEME[scheme])
 
     # accuracy of the last step, checked by the oracle's own FP64 operator
     from oracle import fdpb

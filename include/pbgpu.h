@@ -177,7 +177,8 @@ typedef struct {
     int32_t grid;           /* workgroups of the persistent launch */
     double us_per_iter;     /* measured microseconds per CG iteration (pb_autotune only) */
     int32_t candidates;     /* tilings timed (pb_autotune only) */
-    int32_t reserved;
+    int32_t scheme;         /* pass form: 0 stores A.p (48 B/node/iteration in FP32),
+                               1 recomputes A.p_old from p_old (40 B/node/iteration) */
 } pb_tuning;
 
 /*
@@ -205,6 +206,26 @@ pb_status pb_autotune(int32_t nx, int32_t ny, int32_t nz, double h,
  * feasible for this shape and device.
  */
 pb_status pb_set_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t precision, const pb_tuning* tuning);
+
+/*
+ * pb_get_tuning: the tiling pb_solve will use for this grid shape and
+ * precision on the current device: the one recorded by pb_autotune or
+ * pb_set_tuning, else the library's default choice. us_per_iter and
+ * candidates are 0. Errors: PB_ERR_ARG (bad dims or precision, null out, or
+ * no feasible tiling: nx too large for the in-plane halo).
+ */
+pb_status pb_get_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t precision, pb_tuning* out);
+
+/*
+ * pb_tiling_candidates: the feasible tilings of the fused stencil kernel for
+ * this grid shape and precision on the current device, i.e. the search space
+ * of pb_autotune (the same iteration, launched in different shapes). Writes
+ * min(total, max) entries into out (host array, nullable when max == 0) and
+ * the total into *count (host). us_per_iter is 0; candidates holds the total.
+ * Errors: PB_ERR_ARG (bad dims or precision, null count), PB_ERR_HIP.
+ */
+pb_status pb_tiling_candidates(int32_t nx, int32_t ny, int32_t nz, int32_t precision, pb_tuning* out,
+                               int32_t max, int32_t* count);
 
 /*
  * Batched solves (many independent systems, e.g. snapshots of a trajectory,
@@ -323,6 +344,40 @@ pb_status pb_energy(const pb_grid* grid, int64_t natoms,
                     const double* xyz, const double* charge, const double* x,
                     double* atom_phi, double* energy,
                     void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Device workspace needed by pb_solvation_energy (the five system arrays,
+ * two potentials and the larger of the setup, solve and energy workspaces).
+ * Returns 0 for invalid arguments.
+ */
+size_t pb_solvation_workspace_bytes(const pb_grid* grid, int64_t natoms, const pb_solve_opts* opts);
+
+/*
+ * pb_solvation_energy: solvation (reaction-field) energy
+ *     dG = E(solvent) - E(reference)   (kcal/mol)
+ * with E = 1/2 sum_a q_a phi(c_a) as in pb_energy, from two complete
+ * setups and solves on the same grid with the same charges: the solvent
+ * system (eps_in inside, eps_out and kappa_d2 outside) and the reference
+ * with a uniform eps_in and no salt (eps_out = eps_in, kappa_d2 = 0). The
+ * grid self-energy of the charges is the same in both and cancels; this is
+ * the energy the paper's accuracy comparison uses (section 3.1). For one
+ * ion the continuum value is Born's -332.06 q^2/(2a) (1/eps_in - 1/eps_out).
+ *   atoms, eps_in, eps_out, kappa_d2   as for pb_setup
+ *   opts            solve options for both solves (opts->warm_start must be 0)
+ *   phi_solv, phi_ref (device, N each, nullable) receive the two potentials
+ *   dG (host) the solvation energy; e_solv, e_ref (host, nullable) the two energies
+ *   info_solv, info_ref (host, nullable) the two solves' pb_info
+ * Runs on `stream` and synchronises it. Returns PB_NOT_CONVERGED if either
+ * solve hit its limit (dG is still written); errors as for pb_setup,
+ * pb_solve and pb_energy, PB_ERR_NOMEM for a short workspace.
+ */
+pb_status pb_solvation_energy(const pb_grid* grid, int64_t natoms,
+                              const double* xyz, const double* radius, const double* charge,
+                              double eps_in, double eps_out, double kappa_d2,
+                              const pb_solve_opts* opts, double* phi_solv, double* phi_ref,
+                              double* dG, double* e_solv, double* e_ref,
+                              pb_info* info_solv, pb_info* info_ref,
+                              void* workspace, size_t workspace_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -31,12 +31,14 @@ OPERATORS = {"stencil": 0, "dia": 1}
 
 # Every entry point declared in include/pbgpu.h.
 EXPORTS = ("pb_version", "pb_last_error", "pb_setup_workspace_bytes", "pb_setup",
-           "pb_solve_workspace_bytes", "pb_solve", "pb_autotune", "pb_set_tuning",
+           "pb_solve_workspace_bytes", "pb_solve", "pb_autotune", "pb_set_tuning", "pb_tiling_candidates",
+           "pb_get_tuning",
            "pb_batch_workspace_bytes", "pb_solve_batch", "pb_batch_graph_create", "pb_batch_graph_launch",
            "pb_batch_graph_results", "pb_batch_graph_is_cooperative", "pb_batch_graph_destroy",
            "pb_server_request_bytes", "pb_server_create", "pb_server_submit", "pb_server_step",
            "pb_server_stats", "pb_server_destroy",
-           "pb_energy_workspace_bytes", "pb_energy")
+           "pb_energy_workspace_bytes", "pb_energy",
+           "pb_solvation_workspace_bytes", "pb_solvation_energy")
 
 
 class PBError(RuntimeError):
@@ -71,10 +73,10 @@ class Info(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("groups", ctypes.c_int32), ("zchunk", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("us_per_iter", ctypes.c_double),
-                ("candidates", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("candidates", ctypes.c_int32), ("scheme", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Problem(ctypes.Structure):
@@ -96,7 +98,7 @@ class ServerStats(ctypes.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"pbgpu: {LIB_PATH} is not built; run paper_1704_02745_amd.build.build()")
+        raise ImportError(f"pbgpu: {LIB_PATH} is not built; run python paper_1704_02745_amd/build.py")
     lib = ctypes.CDLL(LIB_PATH)
     vp, sz, i32, i64, dbl = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     G = ctypes.POINTER(Grid)
@@ -118,6 +120,10 @@ def _load():
                                 vp, sz, vp, ctypes.POINTER(Tuning)]
     lib.pb_set_tuning.restype = ctypes.c_int
     lib.pb_set_tuning.argtypes = [i32, i32, i32, i32, ctypes.POINTER(Tuning)]
+    lib.pb_get_tuning.restype = ctypes.c_int
+    lib.pb_get_tuning.argtypes = [i32, i32, i32, i32, ctypes.POINTER(Tuning)]
+    lib.pb_tiling_candidates.restype = ctypes.c_int
+    lib.pb_tiling_candidates.argtypes = [i32, i32, i32, i32, ctypes.POINTER(Tuning), i32, ctypes.POINTER(i32)]
     P = ctypes.POINTER(Problem)
     lib.pb_batch_workspace_bytes.restype = sz
     lib.pb_batch_workspace_bytes.argtypes = [i32, P, i32]
@@ -149,6 +155,12 @@ def _load():
     lib.pb_energy_workspace_bytes.argtypes = [i64]
     lib.pb_energy.restype = ctypes.c_int
     lib.pb_energy.argtypes = [G, i64, vp, vp, vp, vp, ctypes.POINTER(dbl), vp, sz, vp]
+    lib.pb_solvation_workspace_bytes.restype = sz
+    lib.pb_solvation_workspace_bytes.argtypes = [G, i64, ctypes.POINTER(SolveOpts)]
+    lib.pb_solvation_energy.restype = ctypes.c_int
+    PD, PI = ctypes.POINTER(dbl), ctypes.POINTER(Info)
+    lib.pb_solvation_energy.argtypes = [G, i64, vp, vp, vp, dbl, dbl, dbl, ctypes.POINTER(SolveOpts), vp, vp,
+                                        PD, PD, PD, PI, PI, vp, sz, vp]
     return lib
 
 
@@ -293,10 +305,34 @@ def autotune(sysm: System, precision="f32", iters_per_trial=20,
     return t.as_dict()
 
 
-def set_tuning(nx, ny, nz, precision, block, groups, zchunk, grid) -> None:
+def set_tuning(nx, ny, nz, precision, block, groups, zchunk, grid, scheme=0) -> None:
+    """Record a tiling of the fused kernel for this grid shape and precision;
+    scheme 0 is the pass that stores A.p, 1 the 40-byte pass that recomputes it."""
     t = Tuning()
     t.block, t.groups, t.zchunk, t.grid = int(block), int(groups), int(zchunk), int(grid)
+    t.scheme = int(scheme)
     _check(lib.pb_set_tuning(int(nx), int(ny), int(nz), PRECISIONS[precision], ctypes.byref(t)))
+
+
+def get_tuning(nx, ny, nz, precision="f32") -> dict:
+    """The tiling (and pass form) solves of this shape and precision will use."""
+    t = Tuning()
+    _check(lib.pb_get_tuning(int(nx), int(ny), int(nz), PRECISIONS[precision], ctypes.byref(t)))
+    d = t.as_dict()
+    d.pop("us_per_iter")
+    d.pop("candidates")
+    return d
+
+
+def tiling_candidates(nx, ny, nz, precision="f32") -> list:
+    """Every feasible tiling of the fused kernel for this shape and precision
+    on the current device (the autotuner's search space), as dicts."""
+    n = ctypes.c_int32(0)
+    _check(lib.pb_tiling_candidates(int(nx), int(ny), int(nz), PRECISIONS[precision], None, 0, ctypes.byref(n)))
+    arr = (Tuning * max(1, n.value))()
+    _check(lib.pb_tiling_candidates(int(nx), int(ny), int(nz), PRECISIONS[precision], arr, n.value,
+                                    ctypes.byref(n)))
+    return [arr[i].as_dict() for i in range(n.value)]
 
 
 def save_tuning(path, entries) -> None:
@@ -480,3 +516,38 @@ def energy(grid, xyz, charge, x: torch.Tensor, atom_phi: Optional[torch.Tensor] 
                        ctypes.byref(e), _ptr(ws), wsb, _stream(stream))
     _check(st)
     return float(e.value)
+
+
+def solvation_energy(grid, xyz, radius, charge, eps_in=1.0, eps_out=80.0, kappa_d2=0.0, tol=1e-6,
+                     precision="f32", op="stencil", maxiter=0, inner_tol=0.0, max_outer=0, device="cuda",
+                     want_phi=False, stream=None, check=True) -> dict:
+    """Solvation energy dG = E(solvent) - E(uniform eps_in reference) in
+    kcal/mol from two solves on the same grid (pb_solvation_energy)."""
+    g = as_grid(grid)
+    nx, ny, nz = g.nx, g.ny, g.nz
+    xyz_t = _dev64(xyz, device).reshape(-1)
+    rad_t = _dev64(radius, device)
+    q_t = _dev64(charge, device)
+    natoms = rad_t.numel()
+    o = SolveOpts()
+    o.tol, o.maxiter = float(tol), int(maxiter)
+    o.precision, o.op = PRECISIONS[precision], OPERATORS[op]
+    o.inner_tol, o.max_outer = float(inner_tol), int(max_outer)
+    wsb = lib.pb_solvation_workspace_bytes(ctypes.byref(g), natoms, ctypes.byref(o))
+    if wsb == 0:
+        raise PBError(PB_ERR_ARG, "pb_solvation_workspace_bytes rejected the grid / atoms / options")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=device)
+    phs = [torch.empty((nz, ny, nx), dtype=torch.float64, device=device) for _ in range(2)] if want_phi \
+        else [None, None]
+    dg, es, er = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    i_s, i_r = Info(), Info()
+    st = lib.pb_solvation_energy(ctypes.byref(g), natoms, _ptr(xyz_t), _ptr(rad_t), _ptr(q_t), float(eps_in),
+                                 float(eps_out), float(kappa_d2), ctypes.byref(o), _ptr(phs[0]), _ptr(phs[1]),
+                                 ctypes.byref(dg), ctypes.byref(es), ctypes.byref(er), ctypes.byref(i_s),
+                                 ctypes.byref(i_r), _ptr(ws), wsb, _stream(stream))
+    _check(st, allow=(PB_OK,) if check else (PB_OK, PB_NOT_CONVERGED))
+    out = {"dG": dg.value, "e_solv": es.value, "e_ref": er.value, "info_solv": i_s.as_dict(),
+           "info_ref": i_r.as_dict(), "status": st}
+    if want_phi:
+        out["phi_solv"], out["phi_ref"] = phs
+    return out

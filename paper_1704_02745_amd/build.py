@@ -1,6 +1,7 @@
 """Build libpbgpu.so (HIP, gfx950) in-tree with hipcc.
 
-Usage: python -m paper_1704_02745_amd.build   (or build() from Python)
+Usage: python paper_1704_02745_amd/build.py   (or __graft_entry__.build(); the package
+itself cannot be imported before the library exists)
 """
 from __future__ import annotations
 
@@ -23,7 +24,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 # Setup arithmetic must round exactly as written (no fused multiply-add).
 PER_FILE = {"setup.hip": ["-ffp-contract=off"]}
-SOURCES = ["api.hip", "setup.hip", "operator.hip", "jpcg.hip", "dia.hip", "batch.hip", "server.hip"]
+SOURCES = ["api.hip", "setup.hip", "operator.hip", "jpcg.hip", "dia.hip", "batch.hip", "server.hip", "solvation.hip"]
 
 
 def _hipcc() -> str:

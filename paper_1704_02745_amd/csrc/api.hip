@@ -192,6 +192,7 @@ pb_status autotune_impl(const Layout& L, const SolveBufs<T>& s, const SolveWs& w
     if (best) {
         best->block = best_t.bs;
         best->groups = best_t.mc;
+        best->scheme = best_t.scheme;
         best->zchunk = best_t.zchunk;
         best->grid = best_t.grid;
         best->us_per_iter = best_us;
@@ -362,6 +363,45 @@ extern "C" pb_status pb_autotune(int32_t nx, int32_t ny, int32_t nz, double h, c
     return autotune_impl<float>(L, s, w, iters_per_trial, st, best);
 }
 
+extern "C" pb_status pb_get_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t precision, pb_tuning* out) {
+    PB_ARG(dims_ok(nx, ny, nz) && out, "pb_get_tuning: bad dims or null output");
+    PB_ARG(precision >= PB_F64 && precision <= PB_F32_REFINE64, "pb_get_tuning: bad precision");
+    const Layout L = make_layout(nx, ny, nz);
+    const Tiling c = precision == PB_F64 ? choose_tiling<double>(L) : choose_tiling<float>(L);
+    PB_ARG(c.grid > 0, "pb_get_tuning: no feasible tiling for this grid (nx too large for the in-plane halo)");
+    pb_tuning t{};
+    t.block = c.bs;
+    t.groups = c.mc;
+    t.zchunk = c.zchunk;
+    t.grid = c.grid;
+    t.scheme = c.scheme;
+    *out = t;
+    return PB_OK;
+}
+
+extern "C" pb_status pb_tiling_candidates(int32_t nx, int32_t ny, int32_t nz, int32_t precision, pb_tuning* out,
+                                         int32_t max, int32_t* count) {
+    PB_ARG(dims_ok(nx, ny, nz) && count, "pb_tiling_candidates: bad dims or null count");
+    PB_ARG(precision >= PB_F64 && precision <= PB_F32_REFINE64, "pb_tiling_candidates: bad precision");
+    PB_ARG(max >= 0 && (max == 0 || out), "pb_tiling_candidates: bad output array");
+    const Layout L = make_layout(nx, ny, nz);
+    const std::vector<Tiling> c =
+        precision == PB_F64 ? tiling_candidates<double>(L) : tiling_candidates<float>(L);
+    *count = (int32_t)c.size();
+    for (int i = 0; i < (int)c.size() && i < max; ++i) {
+        pb_tuning t{};
+        t.block = c[i].bs;
+        t.groups = c[i].mc;
+        t.zchunk = c[i].zchunk;
+        t.grid = c[i].grid;
+        t.us_per_iter = 0.0;
+        t.candidates = (int32_t)c.size();
+        t.scheme = c[i].scheme;
+        out[i] = t;
+    }
+    return PB_OK;
+}
+
 extern "C" pb_status pb_set_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t precision, const pb_tuning* t) {
     PB_ARG(dims_ok(nx, ny, nz) && t, "pb_set_tuning: bad dims or null tuning");
     PB_ARG(precision >= PB_F64 && precision <= PB_F32_REFINE64, "pb_set_tuning: bad precision");
@@ -369,13 +409,14 @@ extern "C" pb_status pb_set_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t p
     auto apply = [&](auto tag) -> pb_status {
         using T = decltype(tag);
         for (const Tiling& c : tiling_candidates<T>(L)) {
-            if (c.bs == t->block && c.mc == t->groups && c.zchunk == t->zchunk && c.grid == t->grid) {
+            if (c.bs == t->block && c.mc == t->groups && c.scheme == t->scheme && c.zchunk == t->zchunk &&
+                c.grid == t->grid) {
                 record_tiling<T>(L, c);
                 return PB_OK;
             }
         }
-        set_error("pb_set_tuning: (block %d, groups %d, zchunk %d, grid %d) is not a feasible tiling here",
-                  t->block, t->groups, t->zchunk, t->grid);
+        set_error("pb_set_tuning: (block %d, groups %d, scheme %d, zchunk %d, grid %d) is not a feasible tiling here",
+                  t->block, t->groups, t->scheme, t->zchunk, t->grid);
         return PB_ERR_ARG;
     };
     return precision == PB_F64 ? apply(double{}) : apply(float{});

@@ -24,13 +24,21 @@
 // planes: p_{l-1} of the current plane sits in LDS over the segment plus one
 // row of halo on each side (in-plane neighbours +-1, +-nx); the planes above
 // and below stay in registers. Halo values of p are recomputed pointwise, so
-// every array is written once per pass. Traffic per node: reads r, q, d,
-// p_old, cx, cy, cz, x and writes r, p, q, x (48 bytes in FP32).
+// every array is written once per pass.
 //
-// Reductions: each tile reduces its sums in a fixed order (thread order, then
-// a fixed wave/LDS tree) into its own slot; the last workgroup to reach the
-// barrier sums the slots in tile order. Results do not depend on the number
-// of workgroups or on scheduling.
+// Two pass forms compute the same iterates. pass_tile stores q_l for the
+// next pass: it reads r, q, d, p_old, cx, cy, cz, x and writes r, p, q, x (48
+// bytes per node in FP32). pass_tile40 recomputes q_{l-1} = A p_{l-2} from the
+// stored p_{l-2} (in LDS over the segment plus two halo widths), so it reads
+// r, p_old, d, cx, cy, cz, x and writes r, p, x: 40 bytes per node, the
+// least any schedule of this iteration moves (three vectors read and written
+// plus four operator arrays read once).
+//
+// Reductions and the grid barrier: each tile reduces its sums in a fixed
+// order into its own slot; workgroups arrive on counters spread over eight
+// cache lines, and after the barrier every workgroup sums all tile slots in
+// the same fixed order and derives alpha, beta and the stopping test itself.
+// Results do not depend on the number of workgroups or on scheduling.
 #include "solver.hpp"
 
 #include <algorithm>
@@ -278,10 +286,10 @@ __device__ __forceinline__ TileBox tile_box(const KArgs<T>& a, int tile) {
 
 // ------------------------------------------------------------------ passes
 
-// Initial state: r = b - A x0 (r = b for a zero guess), q = 0, p = 0 in
-// buffer 0; sums r.r and b.b.
+// Initial state: r = b - A x0 (r = b for a zero guess), p = 0 and (for the
+// pass that reads a stored A.p) q = 0 in buffer 0; sums r.r and b.b.
 template <typename T, int BS>
-__device__ void init_tile(const KArgs<T>& a, int tile, double (&acc)[2]) {
+__device__ void init_tile(const KArgs<T>& a, int tile, bool with_q, double (&acc)[2]) {
     constexpr int W = Vec<T>::n;
     using V = typename Vec<T>::type;
     const TileBox tb = tile_box(a, tile);
@@ -313,7 +321,7 @@ __device__ void init_tile(const KArgs<T>& a, int tile, double (&acc)[2]) {
                 acc[1] += (double)vget(bv, u) * (double)vget(bv, u);
             }
             vstore(a.r[0] + g, rv);
-            vstore(a.q[0] + g, z0);
+            if (with_q) vstore(a.q[0] + g, z0);
             vstore(a.p[0] + g, z0);
         }
     }
@@ -554,6 +562,246 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
 }
 
 // Final update x += alpha p (or x = 0 for a zero right-hand side).
+// (A v) at one node: d v minus the six couplings times the neighbour values,
+// summed in one fixed order (x, then y, then z). Every evaluation of the
+// operator in the 40-byte pass goes through this function, so a node's value
+// recomputed in a tile's halo is the one its own tile computes.
+template <typename T>
+__device__ __forceinline__ T apply_point(T d, T v, T cr, T vr, T cl, T vl, T cu, T vu, T cd, T vd, T ca, T va, T cb,
+                                         T vb) {
+    T nb = cr * vr + cl * vl;
+    nb += cu * vu + cd * vd;
+    nb += ca * va + cb * vb;
+    return d * v - nb;
+}
+
+// One pass on one tile, 40-byte form: the same iteration as pass_tile, but
+// q_{l-1} = A p_{l-2} is recomputed from the stored p_{l-2} instead of being
+// stored by the previous pass. Per node the pass reads r, p_old, d, cx, cy,
+// cz, x and writes r, p, x: 40 bytes in FP32 against 48.
+//
+// The march keeps p_{l-2} on planes k, k+1, k+2 and p_{l-1} on planes k-1,
+// k, k+1. Plane k+1 of p_{l-2} is in LDS over the segment widened by two
+// halo widths (the in-plane neighbours of the inner halo ring); plane k of
+// p_{l-1} is in LDS over the segment widened by one. Step k evaluates
+// q_{l-1} and p_{l-1} on plane k+1 (own positions and the inner ring), then
+// q_l = A p_{l-1} and the sums on plane k. Two warm-up steps below the tile
+// build planes k0-1 and k0 of p_{l-1}. Threads: own positions s + tid*VEC,
+// inner ring groups on the first 2*halo/VEC threads, outer ring groups on the
+// last 2*halo/VEC threads (the tiling guarantees 2*halo/VEC <= BS).
+template <typename T, int BS>
+__device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, T beta, T* lds,
+                            double (&acc)[NPART]) {
+    constexpr int W = Vec<T>::n;
+    using V = typename Vec<T>::type;
+    const TileBox tb = tile_box(a, tile);
+    const int64_t s = tb.s, e = tb.e, sp = a.sp;
+    const int k0 = tb.k0, k1 = tb.k1, nz = a.nz;
+    const int H = a.halo, nx = a.nx;
+    const int lo_len = a.seglen + 4 * H, ln_len = a.seglen + 2 * H;
+    T* const PO0 = lds;
+    T* const PO1 = lds + lo_len;
+    T* const PN0 = lds + 2 * lo_len;
+    T* const PN1 = PN0 + ln_len;
+    const int64_t obase = s - 2 * H, nbase = s - H;
+    const T* __restrict__ rold = o ? a.r[1] : a.r[0];
+    const T* __restrict__ pold = o ? a.p[1] : a.p[0];
+    T* __restrict__ rnew = n ? a.r[1] : a.r[0];
+    T* __restrict__ pnew = n ? a.p[1] : a.p[0];
+    const T* __restrict__ CX = a.op.cx;
+    const T* __restrict__ CY = a.op.cy;
+    const T* __restrict__ CZ = a.op.cz;
+    const T* __restrict__ DD = a.op.d;
+    const bool do_x = alpha != T(0);
+    const V z0 = vzero<T>();
+
+    const int tid = threadIdx.x;
+    const int64_t pos = s + (int64_t)tid * W;
+    const bool valid = pos < e;
+    const int ring = 2 * H / W;   // vector groups per ring (both sides)
+    const bool is_h = tid < ring;
+    const int64_t hp = (tid < H / W) ? (s - H + (int64_t)tid * W) : (e + (int64_t)(tid - H / W) * W);
+    const bool h_in = is_h && hp >= 0 && hp < sp;
+    const int og = tid - (BS - ring);
+    const bool is_o = og >= 0;
+    const int64_t op = (og < H / W) ? (s - 2 * H + (int64_t)og * W) : (e + H + (int64_t)(og - H / W) * W);
+    const bool o_in = is_o && op >= 0 && op < sp;
+
+    // state at the start of step k (k = k0-2 first)
+    V po_m, po_c;     // p_{l-2}, planes k and k+1 (own)
+    V hpo_m, hpo_c;   // p_{l-2}, planes k and k+1 (inner ring position)
+    V cz_c, hcz_c;    // cz on plane k (own, ring)
+    {
+        const int km = k0 - 2, kc = k0 - 1;
+        const bool vm = km >= 0, vc = kc >= 0;
+        po_m = (valid && vm) ? vload(pold + (int64_t)km * sp + pos) : z0;
+        po_c = (valid && vc) ? vload(pold + (int64_t)kc * sp + pos) : z0;
+        cz_c = (valid && vm) ? vload(CZ + (int64_t)km * sp + pos) : z0;
+        hpo_m = (h_in && vm) ? vload(pold + (int64_t)km * sp + hp) : z0;
+        hpo_c = (h_in && vc) ? vload(pold + (int64_t)kc * sp + hp) : z0;
+        hcz_c = (h_in && vm) ? vload(CZ + (int64_t)km * sp + hp) : z0;
+        const V o_po = (o_in && vc) ? vload(pold + (int64_t)kc * sp + op) : z0;
+        T* P = (kc & 1) ? PO1 : PO0;
+        if (valid) vstore(P + (pos - obase), po_c);
+        if (is_h) vstore(P + (hp - obase), hpo_c);
+        if (is_o) vstore(P + (op - obase), o_po);
+    }
+    lds_barrier();
+
+    V pn_m = z0, pn_c = z0, rn_c = z0, d_c = z0;   // p_{l-1} on k-1, k; r_{l-1}, d on k (own)
+    V cx_c = z0, cy_c = z0, cz_m = z0;             // couplings of plane k; cz of plane k-1
+    T cxm_c = T(0), cym_c[W];
+#pragma unroll
+    for (int u = 0; u < W; ++u) cym_c[u] = T(0);
+
+    for (int k = k0 - 2; k < k1; ++k) {
+        const int kn = k + 1, kf = k + 2;
+        const bool v1 = kn >= 0 && kn < nz;
+        const bool v2 = kf >= 0 && kf < nz;
+        const bool own1 = kn >= k0 && kn < k1;   // plane k+1 belongs to this tile
+        const bool xu = own1 && do_x;
+        T* const POc = (kn & 1) ? PO1 : PO0;
+        T* const POn = (kf & 1) ? PO1 : PO0;
+        const T* const PNc = (k & 1) ? PN1 : PN0;
+        T* const PNn = (kn & 1) ? PN1 : PN0;
+        const int64_t g1 = (int64_t)kn * sp + pos;
+
+        // ---- loads: p_{l-2} of plane k+2; r, d, x and couplings of plane k+1
+        V po_n = z0, r_o = z0, d_n = z0, x_n = z0, cx_n = z0, cy_n = z0, cz_n = z0;
+        T cxm_n = T(0), cym_n[W];
+#pragma unroll
+        for (int u = 0; u < W; ++u) cym_n[u] = T(0);
+        if (valid) {
+            if (v2) po_n = vload(pold + (int64_t)kf * sp + pos);
+            if (v1) {
+                r_o = vload(rold + g1);
+                d_n = vload(DD + g1);
+                if (xu) x_n = vload(a.x + g1);
+                cx_n = vload(CX + g1);
+                cy_n = vload(CY + g1);
+                cz_n = vload(CZ + g1);
+                cxm_n = pos >= 1 ? CX[g1 - 1] : T(0);
+#pragma unroll
+                for (int u = 0; u < W; ++u) cym_n[u] = (pos + u - nx >= 0) ? CY[g1 + u - nx] : T(0);
+            }
+        }
+        V hpo_n = z0, h_r = z0, h_d = z0, h_cx = z0, h_cy = z0, h_cz = z0;
+        T h_cxm = T(0), h_cym[W];
+#pragma unroll
+        for (int u = 0; u < W; ++u) h_cym[u] = T(0);
+        if (h_in) {
+            if (v2) hpo_n = vload(pold + (int64_t)kf * sp + hp);
+            if (v1) {
+                const int64_t gh = (int64_t)kn * sp + hp;
+                h_cz = vload(CZ + gh);
+                if (own1) {
+                    h_r = vload(rold + gh);
+                    h_d = vload(DD + gh);
+                    h_cx = vload(CX + gh);
+                    h_cy = vload(CY + gh);
+                    h_cxm = hp >= 1 ? CX[gh - 1] : T(0);
+#pragma unroll
+                    for (int u = 0; u < W; ++u) h_cym[u] = (hp + u - nx >= 0) ? CY[gh + u - nx] : T(0);
+                }
+            }
+        }
+        const V o_po = (o_in && v2) ? vload(pold + (int64_t)kf * sp + op) : z0;
+
+        // ---- q_{l-1}, r_{l-1}, p_{l-1} (and x) on plane k+1, own positions
+        V pn_n = z0, rn_n = z0;
+        if (valid && v1) {
+            const int64_t l = pos - obase;
+            const T left = POc[l - 1], right = POc[l + W];
+#pragma unroll
+            for (int u = 0; u < W; ++u) {
+                const T pr = (u == W - 1) ? right : vget(po_c, u + 1);
+                const T pl = (u == 0) ? left : vget(po_c, u - 1);
+                const T cl = (u == 0) ? cxm_n : vget(cx_n, u - 1);
+                const T qo = apply_point(vget(d_n, u), vget(po_c, u), vget(cx_n, u), pr, cl, pl, vget(cy_n, u),
+                                         POc[l + u + nx], cym_n[u], POc[l + u - nx], vget(cz_n, u), vget(po_n, u),
+                                         vget(cz_c, u), vget(po_m, u));
+                const T r = vget(r_o, u) - alpha * qo;
+                vget(rn_n, u) = r;
+                vget(pn_n, u) = r * jacobi_inv(vget(d_n, u)) + beta * vget(po_c, u);
+                if (xu) vget(x_n, u) = vget(x_n, u) + alpha * vget(po_c, u);
+            }
+            vstore(PNn + (pos - nbase), pn_n);
+            if (own1) {
+                vstore(rnew + g1, rn_n);
+                vstore(pnew + g1, pn_n);
+                if (xu) vstore(a.x + g1, x_n);
+            }
+        }
+        // ---- the same on the inner ring (LDS only; needed on owned planes)
+        if (is_h && own1) {
+            V hv = z0;
+            if (h_in) {
+                const int64_t l = hp - obase;
+                const T left = POc[l - 1], right = POc[l + W];
+#pragma unroll
+                for (int u = 0; u < W; ++u) {
+                    const T pr = (u == W - 1) ? right : vget(hpo_c, u + 1);
+                    const T pl = (u == 0) ? left : vget(hpo_c, u - 1);
+                    const T cl = (u == 0) ? h_cxm : vget(h_cx, u - 1);
+                    const T qo = apply_point(vget(h_d, u), vget(hpo_c, u), vget(h_cx, u), pr, cl, pl, vget(h_cy, u),
+                                             POc[l + u + nx], h_cym[u], POc[l + u - nx], vget(h_cz, u),
+                                             vget(hpo_n, u), vget(hcz_c, u), vget(hpo_m, u));
+                    const T r = vget(h_r, u) - alpha * qo;
+                    vget(hv, u) = r * jacobi_inv(vget(h_d, u)) + beta * vget(hpo_c, u);
+                }
+            }
+            vstore(PNn + (hp - nbase), hv);
+        }
+        // ---- q_l = A p_{l-1} on plane k and the partial sums
+        if (k >= k0 && valid) {
+            const int64_t l = pos - nbase;
+            const T left = PNc[l - 1], right = PNc[l + W];
+#pragma unroll
+            for (int u = 0; u < W; ++u) {
+                const T p = vget(pn_c, u);
+                const T pr = (u == W - 1) ? right : vget(pn_c, u + 1);
+                const T pl = (u == 0) ? left : vget(pn_c, u - 1);
+                const T cl = (u == 0) ? cxm_c : vget(cx_c, u - 1);
+                const T qq = apply_point(vget(d_c, u), p, vget(cx_c, u), pr, cl, pl, vget(cy_c, u), PNc[l + u + nx],
+                                         cym_c[u], PNc[l + u - nx], vget(cz_c, u), vget(pn_n, u), vget(cz_m, u),
+                                         vget(pn_m, u));
+                const T iv = jacobi_inv(vget(d_c, u));
+                const double pd = (double)p, qd = (double)qq, rd = (double)vget(rn_c, u);
+                const double zd = (double)(vget(rn_c, u) * iv), wd = (double)(qq * iv);
+                acc[0] += pd * qd;
+                acc[1] += rd * zd;
+                acc[2] += rd * wd;
+                acc[3] += qd * wd;
+                acc[4] += rd * rd;
+                acc[5] += rd * qd;
+                acc[6] += qd * qd;
+            }
+        }
+        // ---- p_{l-2} of plane k+2 into LDS for the next step
+        if (valid) vstore(POn + (pos - obase), po_n);
+        if (is_h) vstore(POn + (hp - obase), hpo_n);
+        if (is_o) vstore(POn + (op - obase), o_po);
+        // ---- advance one plane
+        po_m = po_c;
+        po_c = po_n;
+        hpo_m = hpo_c;
+        hpo_c = hpo_n;
+        hcz_c = h_cz;
+        pn_m = pn_c;
+        pn_c = pn_n;
+        rn_c = rn_n;
+        d_c = d_n;
+        cz_m = cz_c;
+        cz_c = cz_n;
+        cx_c = cx_n;
+        cy_c = cy_n;
+        cxm_c = cxm_n;
+#pragma unroll
+        for (int u = 0; u < W; ++u) cym_c[u] = cym_n[u];
+        lds_barrier();
+    }
+}
+
 template <typename T, int BS>
 __device__ void final_tile(const KArgs<T>& a, int tile, T alpha, const T* p, bool zero) {
     constexpr int W = Vec<T>::n;
@@ -583,12 +831,14 @@ struct Scal {
 };
 
 // The whole solve of one problem by workgroup `w` of the `G` workgroups
-// assigned to it; `lds_raw` holds two plane buffers of seglen + 2*halo.
+// assigned to it with pass form SCH (0: pass_tile, 48 bytes per node; 1:
+// pass_tile40); `lds_raw` holds that form's plane buffers.
 // Every workgroup derives the scalars (alpha, beta, stopping test) itself
 // from the identically reduced tile sums; workgroup 0 also persists them in
 // S for the host and for a resumed launch.
-template <typename T, int BS, int MC>
+template <typename T, int BS, int MC, int SCH>
 __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsigned char* lds_raw) {
+    static_assert(SCH == 0 || MC == 1, "the 40-byte pass takes one vector group per thread");
     const int lds_len = a.seglen + 2 * a.halo;
     T* lds0 = reinterpret_cast<T*>(lds_raw);
     T* lds1 = lds0 + lds_len;
@@ -606,7 +856,7 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
         // ---- initial residual
         for (int t = first; t < end; t += stride) {
             double acc[2] = {0.0, 0.0};
-            init_tile<T, BS>(a, t, acc);
+            init_tile<T, BS>(a, t, SCH == 0, acc);
             tile_reduce_store<BS, 2>(acc, red, sums(b) + (size_t)t * kMaxPartials);
         }
         double v[2];
@@ -644,7 +894,10 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
         const T alpha = (T)sc.alpha, beta = (T)sc.beta;
         for (int t = first; t < end; t += stride) {
             double acc[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            pass_tile<T, BS, MC>(a, t, o, n, alpha, beta, lds0, lds1, acc);
+            if constexpr (SCH == 1)
+                pass_tile40<T, BS>(a, t, o, n, alpha, beta, lds0, acc);
+            else
+                pass_tile<T, BS, MC>(a, t, o, n, alpha, beta, lds0, lds1, acc);
             tile_reduce_store<BS, NPART>(acc, red, sums(b) + (size_t)t * kMaxPartials);
         }
         double v[NPART];
@@ -691,10 +944,10 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
     }
 }
 
-template <typename T, int BS, int MC>
+template <typename T, int BS, int MC, int SCH>
 __global__ __launch_bounds__(BS) void k_jpcg_fused(KArgs<T> a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    run_problem<T, BS, MC>(a, blockIdx.x, gridDim.x, true, lds_raw);
+    run_problem<T, BS, MC, SCH>(a, blockIdx.x, gridDim.x, true, lds_raw);
 }
 
 // Many independent problems in one launch: workgroups [first[p], first[p+1])
@@ -711,7 +964,7 @@ __global__ __launch_bounds__(BS) void k_jpcg_batch(const KArgs<T>* __restrict__ 
         if (first[mid] <= (int)blockIdx.x) lo = mid; else hi = mid;
     }
     const KArgs<T> a = probs[lo];
-    run_problem<T, BS, MC>(a, blockIdx.x - first[lo], first[lo + 1] - first[lo], false, lds_raw);
+    run_problem<T, BS, MC, 0>(a, blockIdx.x - first[lo], first[lo + 1] - first[lo], false, lds_raw);
 }
 
 // ------------------------------------------------------------------ host side
@@ -741,15 +994,16 @@ DevInfo dev_info() {
 using KernelFn = const void*;
 
 struct Variant {
-    int bs, mc;
+    int bs, mc, scheme;
     KernelFn fn;
 };
 
 template <typename T>
 const std::vector<Variant>& variants() {
     static const std::vector<Variant> v = {
-        {256, 1, (KernelFn)k_jpcg_fused<T, 256, 1>},   {256, 2, (KernelFn)k_jpcg_fused<T, 256, 2>},
-        {512, 1, (KernelFn)k_jpcg_fused<T, 512, 1>},   {512, 2, (KernelFn)k_jpcg_fused<T, 512, 2>},
+        {256, 1, 0, (KernelFn)k_jpcg_fused<T, 256, 1, 0>}, {256, 2, 0, (KernelFn)k_jpcg_fused<T, 256, 2, 0>},
+        {512, 1, 0, (KernelFn)k_jpcg_fused<T, 512, 1, 0>}, {512, 2, 0, (KernelFn)k_jpcg_fused<T, 512, 2, 0>},
+        {256, 1, 1, (KernelFn)k_jpcg_fused<T, 256, 1, 1>}, {512, 1, 1, (KernelFn)k_jpcg_fused<T, 512, 1, 1>},
     };
     return v;
 }
@@ -771,6 +1025,16 @@ int balanced_seglen(const Layout& L, int cap) {
     return (int)std::min<int64_t>(cap, (even + A - 1) / A * A);
 }
 
+// Dynamic LDS of one workgroup: two planes of p over the segment +- halo
+// (48-byte pass); two planes of p_old over the segment +- 2 halo and two of p
+// over the segment +- halo (40-byte pass).
+template <typename T>
+size_t lds_bytes(int scheme, int seglen, int halo) {
+    const size_t elems = scheme == 1 ? 2 * (size_t)(seglen + 4 * halo) + 2 * (size_t)(seglen + 2 * halo)
+                                     : 2 * (size_t)(seglen + 2 * halo);
+    return sizeof(T) * elems;
+}
+
 template <typename T>
 int halo_for(int nx) {
     constexpr int W = Vec<T>::n;
@@ -786,10 +1050,11 @@ Tiling tiling_for(const Layout& L, const Variant& v, int cus, int max_per_cu) {
     Tiling t{};
     t.mc = v.mc;
     t.bs = v.bs;
+    t.scheme = v.scheme;
     t.seglen = balanced_seglen<T>(L, v.mc * v.bs * W);
     t.halo = halo_for<T>(L.nx);
     if (2 * t.halo / W > v.bs) return t;   // halo groups must fit one per thread
-    const size_t lds = 2 * sizeof(T) * (size_t)(t.seglen + 2 * t.halo);
+    const size_t lds = lds_bytes<T>(t.scheme, t.seglen, t.halo);
     int per_cu = max_coresident(v.fn, v.bs, lds);
     if (max_per_cu > 0) per_cu = std::min(per_cu, max_per_cu);
     if (per_cu <= 0) return t;
@@ -809,18 +1074,20 @@ Tiling tiling_for(const Layout& L, const Variant& v, int cus, int max_per_cu) {
 }
 
 template <typename T>
-Tiling choose_tiling_impl(const Layout& L, int want_bs, int want_mc, int max_per_cu) {
+Tiling choose_tiling_impl(const Layout& L, int want_bs, int want_mc, int max_per_cu, int want_scheme = -1) {
     const DevInfo di = dev_info();
     const int cus = di.cus > 0 ? di.cus : 256;
     Tiling best{};
     double best_cost = 1e300;
     for (const auto& v : variants<T>()) {
         if ((want_bs > 0 && v.bs != want_bs) || (want_mc > 0 && v.mc != want_mc)) continue;
+        if (want_scheme >= 0 && v.scheme != want_scheme) continue;
         Tiling t = tiling_for<T>(L, v, cus, max_per_cu);
         if (t.grid <= 0) continue;
-        // model: work of one tile (planes incl. the extra one, segment incl.
-        // halo) plus a per-workgroup barrier cost
-        const double cost = (double)(t.zchunk + 1) * (t.seglen + t.halo) + 40.0 * t.grid;
+        // model: bytes of one tile (planes incl. the extra ones below, segment
+        // incl. halo work) plus a per-workgroup barrier cost
+        const double cost = t.scheme == 1 ? 40.0 * (t.zchunk + 2) * (t.seglen + 1.5 * t.halo) + 1920.0 * t.grid
+                                          : 48.0 * (t.zchunk + 1) * (t.seglen + t.halo) + 1920.0 * t.grid;
         if (cost < best_cost) {
             best_cost = cost;
             best = t;
@@ -868,11 +1135,12 @@ std::vector<Tiling> tiling_candidates(const Layout& L) {
     std::vector<Tiling> out;
     for (const auto& v : variants<T>()) {
         for (int cap : {1, 2, 3, 4, 0}) {
-            const Tiling t = choose_tiling_impl<T>(L, v.bs, v.mc, cap);
+            const Tiling t = choose_tiling_impl<T>(L, v.bs, v.mc, cap, v.scheme);
             if (t.grid <= 0) continue;
             bool dup = false;
             for (const auto& u : out)
-                dup = dup || (u.bs == t.bs && u.mc == t.mc && u.grid == t.grid && u.zchunk == t.zchunk);
+                dup = dup || (u.bs == t.bs && u.mc == t.mc && u.scheme == t.scheme && u.grid == t.grid &&
+                              u.zchunk == t.zchunk);
             if (!dup) out.push_back(t);
         }
     }
@@ -900,9 +1168,9 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
     }
     KernelFn fn = nullptr;
     for (const auto& v : variants<T>())
-        if (v.bs == t.bs && v.mc == t.mc) fn = v.fn;
+        if (v.bs == t.bs && v.mc == t.mc && v.scheme == t.scheme) fn = v.fn;
     if (!fn) {
-        set_error("fused JPCG: unknown kernel variant bs=%d mc=%d", t.bs, t.mc);
+        set_error("fused JPCG: unknown kernel variant bs=%d mc=%d scheme=%d", t.bs, t.mc, t.scheme);
         return PB_ERR_ARG;
     }
     const DevInfo di = dev_info();
@@ -990,7 +1258,8 @@ Tiling batch_tiling(const Layout& L) {
     t.nseg = (int)((L.sp + t.seglen - 1) / t.seglen);
     t.nzc = (L.nz + t.zchunk - 1) / t.zchunk;
     t.ntiles = t.nseg * t.nzc;
-    t.lds = 2 * sizeof(T) * (size_t)(t.seglen + 2 * t.halo);
+    t.scheme = 0;
+    t.lds = lds_bytes<T>(0, t.seglen, t.halo);
     return t;
 }
 template Tiling batch_tiling<float>(const Layout&);

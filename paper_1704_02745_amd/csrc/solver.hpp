@@ -28,6 +28,7 @@ pb_status launch_fill(T* p, int64_t n, T v, hipStream_t st);
 struct Tiling {
     int bs;          // threads per workgroup
     int mc;          // 16-byte vector groups per thread per plane (segment = mc*bs*VEC)
+    int scheme;      // 0: pass stores A.p (48 B/node FP32); 1: recomputes it (40 B/node)
     size_t lds;      // dynamic LDS bytes
     int seglen;      // elements per segment
     int zchunk;      // planes per tile

@@ -39,6 +39,8 @@ def test_struct_layouts(pbgpu):
     assert ctypes.sizeof(pbgpu.Info) == 48
     assert pbgpu.SolveOpts.inner_tol.offset == 24
     assert pbgpu.Info.relres_recur.offset == 16
+    assert ctypes.sizeof(pbgpu.Tuning) == 32
+    assert pbgpu.Tuning.us_per_iter.offset == 16 and pbgpu.Tuning.scheme.offset == 28
 
 
 def test_version(pbgpu):
@@ -99,3 +101,16 @@ def test_bad_arguments_rejected_on_host(pbgpu):
     e = ctypes.c_double()
     st = lib.pb_energy(ctypes.byref(g), 3, dummy, dummy, dummy, None, ctypes.byref(e), dummy, 8, None)
     assert st == pbgpu.PB_ERR_NOMEM
+
+
+def test_tuning_queries_reject_bad_arguments_on_host(pbgpu):
+    lib = pbgpu.lib
+    t = pbgpu.Tuning()
+    n = ctypes.c_int32(-1)
+    assert lib.pb_get_tuning(33, 33, 33, pbgpu.PRECISIONS["f32"], None) == pbgpu.PB_ERR_ARG
+    assert lib.pb_get_tuning(0, 33, 33, pbgpu.PRECISIONS["f32"], ctypes.byref(t)) == pbgpu.PB_ERR_ARG
+    assert lib.pb_get_tuning(33, 33, 33, 7, ctypes.byref(t)) == pbgpu.PB_ERR_ARG
+    assert lib.pb_tiling_candidates(33, 33, 33, pbgpu.PRECISIONS["f32"], None, 0, None) == pbgpu.PB_ERR_ARG
+    assert lib.pb_tiling_candidates(33, 33, 33, pbgpu.PRECISIONS["f32"], None, 4, ctypes.byref(n)) == pbgpu.PB_ERR_ARG
+    assert lib.pb_set_tuning(33, 33, 33, pbgpu.PRECISIONS["f32"], None) == pbgpu.PB_ERR_ARG
+    assert n.value == -1

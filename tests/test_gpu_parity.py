@@ -20,7 +20,7 @@ import pytest
 import torch
 
 import synth
-from oracle import fdpb, pcg
+from oracle import fdpb, pcg, solvation
 
 pytestmark = pytest.mark.gpu
 
@@ -320,9 +320,82 @@ def test_autotune_then_solve(pb, ragged):
         assert iters_close(info["iters"], o6.iters)
         assert np.abs(x.cpu().numpy() - exact).max() <= 1e-5 * np.abs(exact).max()
         nx, ny, nz = sysm.dims
-        pb.set_tuning(nx, ny, nz, prec, best["block"], best["groups"], best["zchunk"], best["grid"])
+        pb.set_tuning(nx, ny, nz, prec, best["block"], best["groups"], best["zchunk"], best["grid"], best["scheme"])
     with pytest.raises(pb.PBError):
         pb.set_tuning(61, 53, 47, "f32", 256, 1, 1, 3)   # infeasible grid size
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_every_tiling_and_pass_form(pb, ragged, prec):
+    """Every feasible launch shape of the fused kernel, both pass forms (the
+    pass that stores A.p and the 40-byte pass that recomputes it), solves the
+    ragged system to the oracle's exact solution in the oracle's iteration
+    count; the two forms give the same iterates up to rounding."""
+    prob, ref, sysm, exact, o6 = ragged
+    nx, ny, nz = sysm.dims
+    cands = pb.tiling_candidates(nx, ny, nz, prec)
+    assert {c["scheme"] for c in cands} == {0, 1}, cands
+    xs = {}
+    try:
+        for c in cands:
+            pb.set_tuning(nx, ny, nz, prec, c["block"], c["groups"], c["zchunk"], c["grid"], c["scheme"])
+            print(f"tiling {prec} {c}", flush=True)
+            x, info = pb.solve(sysm, tol=1e-6, precision=prec)
+            assert info["status"] == pb.PB_OK
+            assert iters_close(info["iters"], o6.iters), (c, info["iters"], o6.iters)
+            xv = x.cpu().numpy()
+            assert np.abs(xv - exact).max() <= 1e-5 * np.abs(exact).max(), c
+            xs.setdefault(c["scheme"], []).append(xv)
+    finally:
+        best = pb.autotune(sysm, precision=prec, iters_per_trial=3)   # leave a recorded winner behind
+    a, b = xs[0][0], xs[1][0]
+    assert np.abs(a - b).max() <= 1e-6 * np.abs(exact).max()
+
+
+# ------------------------------------------------------------------ solvation energy
+
+@pytest.fixture(scope="module")
+def born_case():
+    n, h, a = 33, 0.5, 2.1
+    org = np.full(3, -(n - 1) / 2 * h)
+    xyz, R, q = np.zeros((1, 3)), np.array([a]), np.array([1.0])
+    sol = solvation.solvation_energy(n, n, n, h, org, xyz, R, q, 1.0, 80.0, 0.0, tol=1e-10)
+    return n, h, org, xyz, R, q, sol
+
+
+@pytest.mark.parametrize("prec,tol,rel", [("f64", 1e-10, 1e-7), ("f32_refine64", 1e-10, 1e-7),
+                                          ("f32", 1e-6, 1e-3)])
+def test_solvation_born_ion(pb, born_case, prec, tol, rel):
+    """One unit ion: the two-solve dG equals the oracle's discrete value and
+    lies within the h = 0.5 grid error of Born's formula."""
+    n, h, org, xyz, R, q, sol = born_case
+    g = pb.make_grid(n, n, n, h, org)
+    r = pb.solvation_energy(g, xyz, R, q, 1.0, 80.0, 0.0, tol=tol, precision=prec)
+    print(f"born {prec}: gpu {r['dG']:.9f} oracle {sol.dG:.9f} "
+          f"iters {r['info_solv']['iters']}/{r['info_ref']['iters']}", flush=True)
+    assert r["status"] == pb.PB_OK
+    assert abs(r["dG"] - sol.dG) <= rel * abs(sol.dG)
+    assert abs(r["dG"] / solvation.born_energy(1.0, 2.1, 1.0, 80.0) - 1) <= 0.05
+    assert abs(r["e_solv"] - r["e_ref"] - r["dG"]) <= 1e-12 * abs(r["e_ref"])
+
+
+def test_solvation_molecule_with_salt(pb, c0):
+    """Config-0 molecule (50 atoms, salt): dG from the GPU matches the
+    oracle's two FP64 solves; the returned potentials give the same energies
+    through pb_energy."""
+    prob = c0[0]
+    g = prob.grid
+    sol = solvation.solvation_energy(g.nx, g.ny, g.nz, g.h, g.origin, prob.mol.xyz, prob.mol.radius,
+                                     prob.mol.charge, prob.eps_in, prob.eps_out, prob.kappa_d2, tol=1e-10)
+    r = pb.solvation_energy(g, prob.mol.xyz, prob.mol.radius, prob.mol.charge, prob.eps_in, prob.eps_out,
+                            prob.kappa_d2, tol=1e-10, precision="f64", want_phi=True)
+    print(f"c0 dG gpu {r['dG']:.9f} oracle {sol.dG:.9f}", flush=True)
+    assert abs(r["dG"] - sol.dG) <= 1e-7 * abs(sol.dG)
+    assert iters_close(r["info_solv"]["iters"], sol.iters_solv)
+    assert iters_close(r["info_ref"]["iters"], sol.iters_ref)
+    e_s = pb.energy(g, prob.mol.xyz, prob.mol.charge, r["phi_solv"])
+    assert e_s == r["e_solv"]
+    assert np.abs(r["phi_ref"].cpu().numpy() - sol.phi_ref).max() <= 1e-8 * np.abs(sol.phi_ref).max()
 
 
 # ------------------------------------------------------------------ batched form

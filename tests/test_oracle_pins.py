@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import fdpb, pcg
+from oracle import fdpb, pcg, solvation
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -208,25 +208,50 @@ def _born(h, n):
     a = 2.1
     org = np.full(3, -(n - 1) / 2 * h)
     xyz, R, q = np.zeros((1, 3)), np.array([a]), np.array([1.0])
-    phis = []
-    for eo in (80.0, 1.0):
-        s = fdpb.assemble(n, n, n, h, org, xyz, R, q, 1.0, eo, 0.0)
-        res = pcg.jpcg(s, 1e-10, maxiter=20000)
-        assert res.converged
-        phis.append(fdpb.energy(n, n, n, h, org, xyz, q, res.x))
-    dg = phis[0] - phis[1]
-    exact = -fdpb.COULOMB_KCAL / (2 * a) * (1 - 1 / 80.0)
-    return dg, exact
+    sol = solvation.solvation_energy(n, n, n, h, org, xyz, R, q, 1.0, 80.0, 0.0, tol=1e-10, maxiter=20000)
+    return sol.dG, solvation.born_energy(1.0, a, 1.0, 80.0)
 
 
 def test_v4_born_sphere_energy():
     dg1, exact = _born(0.5, 33)
     dg2, _ = _born(0.25, 49)
     assert abs(exact - (-78.0745)) < 1e-3
+    assert abs(exact - (-fdpb.COULOMB_KCAL / (2 * 2.1) * (1 - 1 / 80.0))) < 1e-12
     e1, e2 = abs(dg1 / exact - 1), abs(dg2 / exact - 1)
     assert e1 <= 0.05
     assert e2 <= 0.01
     assert e2 < e1
+
+
+def test_v4_solvation_limits():
+    """dG vanishes when the solvent dielectric equals the solute's and there
+    is no salt; it is negative and grows in magnitude with eps_out; two ions
+    of opposite charge far apart (separation >> radii) solvate like two Born
+    ions, each at its own Born value (within the h = 0.5 grid error); a
+    neutral (zero-charge) set has dG = 0 exactly."""
+    n, h, a = 33, 0.5, 2.1
+    org = np.full(3, -(n - 1) / 2 * h)
+    xyz, R, q = np.zeros((1, 3)), np.array([a]), np.array([1.0])
+    same = solvation.solvation_energy(n, n, n, h, org, xyz, R, q, 1.0, 1.0, 0.0, tol=1e-10)
+    assert abs(same.dG) <= 1e-9 * abs(same.e_ref)
+    d4 = solvation.solvation_energy(n, n, n, h, org, xyz, R, q, 1.0, 4.0, 0.0, tol=1e-10).dG
+    d80 = solvation.solvation_energy(n, n, n, h, org, xyz, R, q, 1.0, 80.0, 0.0, tol=1e-10).dG
+    assert d80 < d4 < 0.0
+    # the continuum ratio (1 - 1/4)/(1 - 1/80) holds up to the grid error
+    assert abs((d4 / d80) / (0.75 / (1 - 1 / 80.0)) - 1) < 0.03
+    zero = solvation.solvation_energy(n, n, n, h, org, xyz, R, np.zeros(1), 1.0, 80.0, 0.0, tol=1e-10)
+    assert zero.dG == 0.0 and zero.iters_solv == 0 and zero.iters_ref == 0
+    # two opposite unit ions 10 A apart: in the continuum picture dG is twice the
+    # single-ion value plus the change of their pair energy, +q^2/d (1 - 1/eps_out);
+    # each ion's field polarising the other's cavity adds a few percent
+    n2 = 49
+    org2 = np.full(3, -(n2 - 1) / 2 * h)
+    single = solvation.solvation_energy(n2, n2, n2, h, org2, xyz, R, q, 1.0, 80.0, 0.0, tol=1e-10).dG
+    xyz2 = np.array([[-5.0, 0.0, 0.0], [5.0, 0.0, 0.0]])
+    pair = solvation.solvation_energy(n2, n2, n2, h, org2, xyz2, np.array([a, a]), np.array([1.0, -1.0]),
+                                      1.0, 80.0, 0.0, tol=1e-10).dG
+    cross = fdpb.COULOMB_KCAL * (1.0 - 1.0 / 80.0) / 10.0
+    assert abs(pair - (2 * single + cross)) <= 0.05 * abs(2 * single)
 
 
 # ---------------------------------------------------------------- V5 SPD at scale

@@ -10,5 +10,9 @@ Modules:
           the energy and a dense assembly for tiny grids.
   pcg   - the preconditioned CG listing of section 2.2 with the Jacobi
           preconditioner of section 2.4, and FP64 iterative refinement.
+  solvation - the solvation energy from a solvent and a uniform reference
+          solve on the same grid (the energies of section 3.1).
+  periodic - the periodic-boundary setup, operator and energy (section 2.7's
+          alternative boundary), with an exact FFT solver for uniform media.
 """
-from . import fdpb, pcg  # noqa: F401
+from . import fdpb, pcg, periodic, solvation  # noqa: F401

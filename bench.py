@@ -30,21 +30,23 @@ sys.path.insert(0, ROOT)
 
 METRIC = "JPCG HBM GB/s (% peak) at 257^3; served solves/s + p99 latency at tol 1e-6"
 PEAK_GBS = 8000.0
-# Algorithmic bytes per unknown of the fused FP32 kernel, by pass form:
-# form 1 (40-byte pass) reads r, p_old, d, cx, cy, cz, x and writes r, p, x
-# (40 B), recomputing A.p_old; form 0 also reads and writes the stored A.p
-# (48 B). The first iteration skips the x update (-8 B); the initial pass
-# reads b and writes r, p (and q in form 0): 12 or 16 B; the final pass reads
-# x, p and writes x (12 B).
-ITER_BYTES_BY_SCHEME = {0: 48, 1: 40}
-INIT_BYTES_BY_SCHEME = {0: 16 - 8 + 12, 1: 12 - 8 + 12}
-ITER_BYTES = 48   # the batched form always runs the form-0 pass
+# Algorithmic bytes per unknown (FP32): the schedule-independent floor of one
+# JPCG iteration, x, r and p each read and written (24 B) plus the four
+# operator arrays read once (16 B) = 40 B, whatever pass form runs. Per
+# launch add the initial pass (read b, write r and p: 12 B) and the final x
+# update (read x, p, write x: 12 B), less the x update the first iteration
+# skips (8 B). The pass forms themselves move 48 B (form 0, stores A.p) or
+# 40 B (form 1, recomputes it) per unknown per iteration; that figure is
+# reported beside the metric.
+ITER_BYTES = 40
+INIT_BYTES = 12 - 8 + 12
+PASS_BYTES_BY_SCHEME = {0: 48, 1: 40}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jpcg_fused_f32_257_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1704_02745_amd", "csrc", "jpcg.hip")
 
 
-def launch_bytes(n: int, iters: int, launches: int, scheme: int) -> float:
-    return float(n) * (ITER_BYTES_BY_SCHEME[scheme] * iters + INIT_BYTES_BY_SCHEME[scheme] * launches)
+def launch_bytes(n: int, iters: int, launches: int) -> float:
+    return float(n) * (ITER_BYTES * iters + INIT_BYTES * launches)
 
 
 def measured_traffic():
@@ -66,7 +68,7 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(prob, iter_bytes, n_iters=8):
+def cpu_baseline(prob, n_iters=8):
     """FP64 oracle Jacobi PCG at the full 257^3 size, bounded to n_iters
     iterations. The sample system uses the oracle's own classification,
     edges, salt term and charges; its boundary values are zero (the boundary
@@ -88,11 +90,11 @@ def cpu_baseline(prob, iter_bytes, n_iters=8):
     cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
     n = g.nx * g.ny * g.nz
     its = res.iters / wall
-    return {"value": round(its * iter_bytes * n / 1e9, 3), "unit": "GB/s",
+    return {"value": round(its * ITER_BYTES * n / 1e9, 3), "unit": "GB/s",
             "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
             "sample": f"{res.iters} FP64 NumPy Jacobi-PCG iterations of the oracle at 257^3 "
                       f"(same operator, zero boundary), {wall:.1f} s wall; rate scaled by the "
-                      f"metric's {iter_bytes} B/unknown per iteration",
+                      f"metric's {ITER_BYTES} B/unknown per iteration",
             "iters_per_s": round(its, 4), "os_cpu_count": os.cpu_count()}
 
 
@@ -109,7 +111,7 @@ def bench_c1(pbgpu, torch, synth, dev, reps=3):
     n = g.nx * g.ny * g.nz
     out = {}
     sch = pbgpu.get_tuning(g.nx, g.ny, g.nz, "f32")["scheme"]
-    for op, per in (("stencil", ITER_BYTES_BY_SCHEME[sch]), ("dia", DIA_ITER_BYTES)):
+    for op, per in (("stencil", PASS_BYTES_BY_SCHEME[sch]), ("dia", DIA_ITER_BYTES)):
         pbgpu.solve(sm, tol=1e-6, precision="f32", op=op)
         best = None
         for _ in range(reps):
@@ -124,8 +126,9 @@ def bench_c1(pbgpu, torch, synth, dev, reps=3):
         out[op] = {"iters": info["iters"], "solve_ms": round(1e3 * dt, 3),
                    "iter_loop_ms": round(1e3 * info["kernel_seconds"], 3),
                    "us_per_iter": round(1e6 * info["kernel_seconds"] / max(info["iters"], 1), 2),
-                   "algorithmic_gbs": round(per * n * info["iters"] / info["kernel_seconds"] / 1e9, 1),
-                   "bytes_per_node_iter": per, "relres_true": info["relres_true"]}
+                   "algorithmic_gbs": round(ITER_BYTES * n * info["iters"] / info["kernel_seconds"] / 1e9, 1),
+                   "form_gbs": round(per * n * info["iters"] / info["kernel_seconds"] / 1e9, 1),
+                   "form_bytes_per_node_iter": per, "relres_true": info["relres_true"]}
         if op == "stencil":
             out[op]["pass_form"] = sch
     out["speedup_stencil_vs_dia"] = round(out["dia"]["iter_loop_ms"] / out["stencil"]["iter_loop_ms"], 2)
@@ -261,6 +264,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched (config 3) and served (config 4) measurements")
+    ap.add_argument("--tuning", default="",
+                    help="block,groups,zchunk,grid,scheme: use this tiling instead of autotuning (profiled runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one untimed 512 MiB device copy first (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -309,11 +314,16 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     # untimed: pick the fused kernel's tiling for this grid shape
-    sys0 = pbgpu.setup(g, xyz, rad, chg, prob.eps_in, prob.eps_out, prob.kappa_d2, device=dev)
-    tuning = pbgpu.autotune(sys0, precision="f32", iters_per_trial=20, workspace=ws)
-    print(f"bench: autotune {tuning}", file=sys.stderr, flush=True)
+    if args.tuning:
+        bl, gr, zc, gd, sc = (int(v) for v in args.tuning.split(","))
+        pbgpu.set_tuning(g.nx, g.ny, g.nz, "f32", bl, gr, zc, gd, sc)
+        tuning = dict(pbgpu.get_tuning(g.nx, g.ny, g.nz, "f32"), us_per_iter=None, candidates=0)
+    else:
+        sys0 = pbgpu.setup(g, xyz, rad, chg, prob.eps_in, prob.eps_out, prob.kappa_d2, device=dev)
+        tuning = pbgpu.autotune(sys0, precision="f32", iters_per_trial=20, workspace=ws)
+        del sys0
+    print(f"bench: tuning {tuning}", file=sys.stderr, flush=True)
     scheme = tuning["scheme"]
-    del sys0
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -330,15 +340,16 @@ def main():
     iters = sum(i["iters"] for i in infos)
     launches = sum(i["kernel_launches"] for i in infos)
     ksec = sum(i["kernel_seconds"] for i in infos)
-    total_bytes = launch_bytes(n, iters, launches, scheme)
+    total_bytes = launch_bytes(n, iters, launches)
     value = total_bytes / wall / 1e9
     achieved = total_bytes / ksec / 1e9
     traffic = measured_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic, 0),
-                "kernel": f"k_jpcg_fused<float, {tuning['block']}, {tuning['groups']}, {scheme}> (persistent, "
-                          f"one launch per inner solve; {ITER_BYTES_BY_SCHEME[scheme]} B/unknown/iteration)",
+                "kernel": f"k_jpcg_fused<float, {tuning['block']}, {tuning['groups']}, {scheme}, false> (persistent, "
+                          f"one launch per inner solve; algorithmic {ITER_BYTES} B/unknown/iteration, this pass "
+                          f"form moves {PASS_BYTES_BY_SCHEME[scheme]} B)",
                 "bytes_per_launch": round(total_bytes / launches, 0),
                 "avg_launch_ms": round(1e3 * ksec / launches, 4)}
 
@@ -357,7 +368,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(prob, ITER_BYTES_BY_SCHEME[scheme])
+        cpu = cpu_baseline(prob)
 
     # accuracy of the last step, checked by the oracle's own FP64 operator
     from oracle import fdpb
@@ -390,6 +401,8 @@ def main():
             "energy_ms": round(1e3 * sum(p[2] for p in phases) / len(phases), 3),
             "jpcg_kernel_ms_per_step": round(1e3 * ksec / args.steps, 3),
             "jpcg_iter_us": round(1e6 * ksec / iters, 2),
+            "pass_form": scheme, "pass_form_bytes_per_unknown_iter": PASS_BYTES_BY_SCHEME[scheme],
+            "pass_form_gbs": round(float(n) * PASS_BYTES_BY_SCHEME[scheme] * iters / ksec / 1e9, 1),
             "relres_true_gpu": last["relres_true"], "relres_true_oracle": relres_oracle,
             "energy_kcal": e, "energy_oracle_of_gpu_phi": e_oracle,
             "solves_per_s": round(args.steps / wall, 3),

@@ -60,9 +60,15 @@ typedef enum {
     PB_OP_DIA = 1           /* 7-diagonal (DIA) SpMV and separate vector kernels, host-driven loop */
 } pb_operator;
 
+typedef enum {
+    PB_BOUNDARY_FREE = 0,     /* free space: Debye-Hueckel Dirichlet values on a ghost layer one h outside */
+    PB_BOUNDARY_PERIODIC = 1  /* periodic box of nx*h x ny*h x nz*h: node i+nx is node i (section 2.7) */
+} pb_boundary;
+
 typedef struct {
-    int32_t nx, ny, nz;     /* nodes per axis (>= 2 for pb_setup / pb_energy, >= 1 for pb_solve) */
-    int32_t reserved;
+    int32_t nx, ny, nz;     /* nodes per axis (>= 2 for pb_setup / pb_energy, >= 1 for pb_solve;
+                               >= 3 with the periodic boundary) */
+    int32_t boundary;       /* pb_boundary (pb_setup, pb_energy, pb_solvation_energy) */
     double h;               /* grid spacing, Angstrom (> 0) */
     double origin[3];       /* position of node (0,0,0), Angstrom */
 } pb_grid;
@@ -75,7 +81,7 @@ typedef struct {
     int32_t warm_start;     /* nonzero: x holds the initial guess on entry; zero: start from x = 0 */
     double inner_tol;       /* REFINE64: inner tolerance relative to the current outer residual; 0 selects 1e-4 */
     int32_t max_outer;      /* REFINE64: outer step limit; 0 selects 20 */
-    int32_t reserved;
+    int32_t boundary;       /* pb_boundary of the system (PERIODIC: stencil operator only, n >= 3 per axis) */
 } pb_solve_opts;
 
 typedef struct {

@@ -19,7 +19,7 @@ from __future__ import annotations
 
 import dataclasses
 
-from . import fdpb, pcg
+from . import fdpb, pcg, periodic
 
 
 @dataclasses.dataclass
@@ -34,16 +34,23 @@ class Solvation:
 
 
 def solvation_energy(nx, ny, nz, h, origin, xyz, radius, charge, eps_in, eps_out, kappa_d2,
-                     tol=1e-10, maxiter=None) -> Solvation:
+                     tol=1e-10, maxiter=None, boundary="free") -> Solvation:
     """Two full setups and JPCG solves on the same grid, then the energy
-    difference (section 3.1 energies; systems of Eq. 3 as in fdpb)."""
+    difference (section 3.1 energies; systems of Eq. 3 as in fdpb, or the
+    periodic box of oracle.periodic)."""
     out = []
     for eo, k2 in ((eps_out, kappa_d2), (eps_in, 0.0)):
-        s = fdpb.assemble(nx, ny, nz, h, origin, xyz, radius, charge, eps_in, eo, k2)
-        res = pcg.jpcg(s, tol, maxiter=maxiter)
+        if boundary == "periodic":
+            s = periodic.assemble(nx, ny, nz, h, origin, xyz, radius, charge, eps_in, eo, k2)
+            res = periodic.jpcg(s, tol, maxiter=maxiter)
+            e = periodic.energy(nx, ny, nz, h, origin, xyz, charge, res.x) if res.converged else None
+        else:
+            s = fdpb.assemble(nx, ny, nz, h, origin, xyz, radius, charge, eps_in, eo, k2)
+            res = pcg.jpcg(s, tol, maxiter=maxiter)
+            e = fdpb.energy(nx, ny, nz, h, origin, xyz, charge, res.x) if res.converged else None
         if not res.converged:
             raise RuntimeError(f"oracle solve did not converge (eps_out={eo})")
-        out.append((fdpb.energy(nx, ny, nz, h, origin, xyz, charge, res.x), res.iters, res.x))
+        out.append((e, res.iters, res.x))
     (es, its, xs), (er, itr, xr) = out
     return Solvation(dG=es - er, e_solv=es, e_ref=er, iters_solv=its, iters_ref=itr, phi_solv=xs, phi_ref=xr)
 

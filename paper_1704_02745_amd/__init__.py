@@ -49,7 +49,7 @@ class PBError(RuntimeError):
 
 class Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("h", ctypes.c_double),
+                ("boundary", ctypes.c_int32), ("h", ctypes.c_double),
                 ("origin", ctypes.c_double * 3)]
 
 
@@ -57,7 +57,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("op", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("inner_tol", ctypes.c_double),
-                ("max_outer", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_outer", ctypes.c_int32), ("boundary", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -195,18 +195,25 @@ def _dev64(a, device) -> torch.Tensor:
     return t.to(device).contiguous()
 
 
-def make_grid(nx, ny, nz, h, origin) -> Grid:
+BOUNDARIES = {"free": 0, "periodic": 1}
+
+
+def make_grid(nx, ny, nz, h, origin, boundary="free") -> Grid:
     g = Grid()
     g.nx, g.ny, g.nz, g.h = int(nx), int(ny), int(nz), float(h)
+    g.boundary = BOUNDARIES[boundary] if isinstance(boundary, str) else int(boundary)
     for d in range(3):
         g.origin[d] = float(origin[d])
     return g
 
 
-def as_grid(grid) -> Grid:
-    if isinstance(grid, Grid):
+def as_grid(grid, boundary=None) -> Grid:
+    """A Grid struct from a Grid or any object with nx, ny, nz, h, origin
+    (and optionally boundary); `boundary` overrides it when given."""
+    if isinstance(grid, Grid) and boundary is None:
         return grid
-    return make_grid(grid.nx, grid.ny, grid.nz, grid.h, grid.origin)
+    b = boundary if boundary is not None else getattr(grid, "boundary", 0)
+    return make_grid(grid.nx, grid.ny, grid.nz, grid.h, grid.origin, b)
 
 
 @dataclasses.dataclass
@@ -227,8 +234,10 @@ class System:
 
 
 def setup(grid, xyz, radius, charge, eps_in=1.0, eps_out=80.0, kappa_d2=0.0,
-          device="cuda", want_q=False, want_mask=False, stream=None) -> System:
-    g = as_grid(grid)
+          device="cuda", want_q=False, want_mask=False, stream=None, boundary=None) -> System:
+    """Build the system of Eq. 3 on the device (pb_setup); boundary "free"
+    (default, or the grid's own) or "periodic"."""
+    g = as_grid(grid, boundary)
     nx, ny, nz = g.nx, g.ny, g.nz
     xyz_t = _dev64(xyz, device).reshape(-1)
     rad_t = _dev64(radius, device)
@@ -270,6 +279,7 @@ def solve(sysm: System, tol=1e-6, precision="f32", op="stencil", maxiter=0, x0=N
     o.precision, o.op = PRECISIONS[precision], OPERATORS[op]
     o.warm_start = 1 if x0 is not None else 0
     o.inner_tol, o.max_outer = float(inner_tol), int(max_outer)
+    o.boundary = sysm.grid.boundary
     wsb = lib.pb_solve_workspace_bytes(nx, ny, nz, ctypes.byref(o))
     if wsb == 0:
         raise PBError(PB_ERR_ARG, "pb_solve_workspace_bytes rejected the options")
@@ -503,8 +513,8 @@ class Server:
 
 
 def energy(grid, xyz, charge, x: torch.Tensor, atom_phi: Optional[torch.Tensor] = None,
-           stream=None) -> float:
-    g = as_grid(grid)
+           stream=None, boundary=None) -> float:
+    g = as_grid(grid, boundary)
     dev = x.device
     xyz_t = _dev64(xyz, dev).reshape(-1)
     q_t = _dev64(charge, dev)
@@ -520,10 +530,10 @@ def energy(grid, xyz, charge, x: torch.Tensor, atom_phi: Optional[torch.Tensor] 
 
 def solvation_energy(grid, xyz, radius, charge, eps_in=1.0, eps_out=80.0, kappa_d2=0.0, tol=1e-6,
                      precision="f32", op="stencil", maxiter=0, inner_tol=0.0, max_outer=0, device="cuda",
-                     want_phi=False, stream=None, check=True) -> dict:
+                     want_phi=False, stream=None, check=True, boundary=None) -> dict:
     """Solvation energy dG = E(solvent) - E(uniform eps_in reference) in
     kcal/mol from two solves on the same grid (pb_solvation_energy)."""
-    g = as_grid(grid)
+    g = as_grid(grid, boundary)
     nx, ny, nz = g.nx, g.ny, g.nz
     xyz_t = _dev64(xyz, device).reshape(-1)
     rad_t = _dev64(radius, device)

@@ -99,7 +99,8 @@ SolveWs carve_solve(void* base, const Layout& L, int prec, int op) {
 bool opts_ok(const pb_solve_opts* o) {
     return o && std::isfinite(o->tol) && o->tol > 0 && o->precision >= PB_F64 &&
            o->precision <= PB_F32_REFINE64 && (o->op == PB_OP_STENCIL || o->op == PB_OP_DIA) &&
-           o->inner_tol >= 0 && o->inner_tol < 1 && o->max_outer >= 0;
+           o->inner_tol >= 0 && o->inner_tol < 1 && o->max_outer >= 0 &&
+           (o->boundary == PB_BOUNDARY_FREE || (o->boundary == PB_BOUNDARY_PERIODIC && o->op == PB_OP_STENCIL));
 }
 
 bool dims_ok(int nx, int ny, int nz) {
@@ -107,15 +108,16 @@ bool dims_ok(int nx, int ny, int nz) {
 }
 
 template <typename T>
-pb_status run_inner(const Layout& L, const SolveBufs<T>& s, const SolveWs& w, int op, double tol, int maxiter,
-                    hipStream_t st, SolveResult* r) {
+pb_status run_inner(const Layout& L, const SolveBufs<T>& s, const SolveWs& w, int op, int periodic, double tol,
+                    int maxiter, hipStream_t st, SolveResult* r) {
     if (op == PB_OP_DIA) return dia_jpcg_impl<T>(L, s, w.dia_sync, w.partials, tol, maxiter, st, r);
-    return fused_jpcg<T>(L, s, w.sync, w.partials, tol, maxiter, st, r, nullptr);
+    return fused_jpcg<T>(L, s, w.sync, w.partials, tol, maxiter, st, r, nullptr, periodic);
 }
 
 // FP64 residual r = b - A x; returns ||r||^2 and ||b||^2 on the host.
-pb_status residual(const Layout& L, const SolveWs& w, float* r32, double& rr, double& bb, hipStream_t st) {
-    pb_status e = launch_residual64(w.op64, w.b64, w.x64, L, nullptr, r32, w.res64, w.small, st);
+pb_status residual(const Layout& L, const SolveWs& w, int periodic, float* r32, double& rr, double& bb,
+                   hipStream_t st) {
+    pb_status e = launch_residual64(w.op64, w.b64, w.x64, L, periodic, nullptr, r32, w.res64, w.small, st);
     if (e != PB_OK) return e;
     double h[2];
     PB_HIP(hipMemcpyAsync(h, w.small, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -126,13 +128,16 @@ pb_status residual(const Layout& L, const SolveWs& w, float* r32, double& rr, do
 }
 
 // Convert the caller's arrays into the padded FP64 operator and check them.
+// `singular` (out): periodic boundary with kbar^2 = 0 at every node, where
+// the operator annihilates constants; b then has its mean removed here.
 pb_status prepare(const Layout& L, double h, const double* eps_x, const double* eps_y, const double* eps_z,
-                  const double* kappa2, const double* rhs, const double* x, int warm, const SolveWs& w,
-                  hipStream_t st) {
+                  const double* kappa2, const double* rhs, const double* x, int warm, int periodic,
+                  const SolveWs& w, hipStream_t st, bool* singular) {
     int* flags = (int*)w.small;
     pb_status e = launch_fill<int>(flags, 1, 0, st);
     if (e != PB_OK) return e;
-    e = launch_prepare64(eps_x, eps_y, eps_z, kappa2, rhs, x, warm, L, h, w.op64, w.b64, w.x64, flags, st);
+    e = launch_prepare64(eps_x, eps_y, eps_z, kappa2, rhs, x, warm, periodic, L, h, w.op64, w.b64, w.x64, flags,
+                         st);
     if (e != PB_OK) return e;
     int hflags = 0;
     PB_HIP(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -145,6 +150,9 @@ pb_status prepare(const Layout& L, double h, const double* eps_x, const double* 
         set_error("NaN/Inf in the right-hand side or the initial guess");
         return PB_ERR_NONFINITE;
     }
+    const bool sing = periodic && !(hflags & FLAG_HAS_SALT);
+    if (singular) *singular = sing;
+    if (sing) return launch_remove_mean(w.b64, L, w.res64, w.small + 8, st);
     return PB_OK;
 }
 
@@ -154,7 +162,7 @@ pb_status time_tiling(const Layout& L, const SolveBufs<T>& s, const SolveWs& w, 
                       hipStream_t st, double& us_per_iter) {
     SolveResult r{};
     for (int rep = 0; rep < 2; ++rep) {
-        pb_status e = fused_jpcg<T>(L, s, w.sync, w.partials, 1e-300, iters, st, &r, &t);
+        pb_status e = fused_jpcg<T>(L, s, w.sync, w.partials, 1e-300, iters, st, &r, &t, 0);
         if (e != PB_OK) return e;
         if (r.status < 0) {
             set_error("autotune trial failed with status %d", r.status);
@@ -236,8 +244,12 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
         return PB_ERR_NOMEM;
     }
     const int maxiter = opts->maxiter > 0 ? opts->maxiter : 10 * std::max(nx, std::max(ny, nz));
+    const int per = opts->boundary == PB_BOUNDARY_PERIODIC ? 1 : 0;
+    PB_ARG(!per || (nx >= 3 && ny >= 3 && nz >= 3), "pb_solve: the periodic boundary needs nx, ny, nz >= 3");
     hipStream_t st = (hipStream_t)stream_;
-    pb_status e = prepare(L, h, eps_x, eps_y, eps_z, kappa2, rhs, x, opts->warm_start ? 1 : 0, w, st);
+    bool singular = false;
+    pb_status e = prepare(L, h, eps_x, eps_y, eps_z, kappa2, rhs, x, opts->warm_start ? 1 : 0, per, w, st,
+                          &singular);
     if (e != PB_OK) return e;
 
     SolveResult r{};
@@ -248,7 +260,7 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
     if (prec == PB_F64) {
         SolveBufs<double> s = w.s64;
         s.warm = opts->warm_start ? 1 : 0;
-        e = run_inner<double>(L, s, w, op, opts->tol, maxiter, st, &r);
+        e = run_inner<double>(L, s, w, op, per, opts->tol, maxiter, st, &r);
         if (e != PB_OK) return e;
         ++launches;
         ksec += r.kernel_seconds;
@@ -260,7 +272,7 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
         s.warm = opts->warm_start ? 1 : 0;
         e = launch_round32(w.op64, w.b64, w.x64, L.npad, s.op, (float*)s.b, s.x, st);
         if (e != PB_OK) return e;
-        e = run_inner<float>(L, s, w, op, opts->tol, maxiter, st, &r);
+        e = run_inner<float>(L, s, w, op, per, opts->tol, maxiter, st, &r);
         if (e != PB_OK) return e;
         ++launches;
         ksec += r.kernel_seconds;
@@ -280,7 +292,7 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
         double rr = 0, bb = 0, rr_prev = -1;
         status = PB_NOT_CONVERGED;
         for (outer = 0;; ++outer) {
-            e = residual(L, w, (float*)s.b, rr, bb, st);
+            e = residual(L, w, per, (float*)s.b, rr, bb, st);
             if (e != PB_OK) return e;
             if (bb == 0.0) {
                 e = launch_fill<double>(w.x64, L.npad, 0.0, st);
@@ -297,7 +309,7 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
             rr_prev = rr;
             e = launch_fill<float>(s.x, L.npad, 0.0f, st);
             if (e != PB_OK) return e;
-            e = run_inner<float>(L, s, w, op, inner_tol, maxiter, st, &r);
+            e = run_inner<float>(L, s, w, op, per, inner_tol, maxiter, st, &r);
             if (e != PB_OK) return e;
             ++launches;
             ksec += r.kernel_seconds;
@@ -311,9 +323,14 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
     if (status == PB_ERR_BREAKDOWN) set_error("pb_solve: CG breakdown (p.Ap <= 0 or non-finite)");
     if (status == PB_NOT_CONVERGED) set_error("pb_solve: not converged within the iteration limit");
 
+    // singular periodic system: report the zero-mean potential
+    if (singular) {
+        e = launch_remove_mean(w.x64, L, w.res64, w.small + 8, st);
+        if (e != PB_OK) return e;
+    }
     // true FP64 residual of the returned potential, then hand x back
     double rr = 0, bb = 0;
-    e = residual(L, w, nullptr, rr, bb, st);
+    e = residual(L, w, per, nullptr, rr, bb, st);
     if (e != PB_OK) return e;
     e = launch_unpad<double>(w.x64, L, x, st);
     if (e != PB_OK) return e;
@@ -338,7 +355,8 @@ extern "C" pb_status pb_autotune(int32_t nx, int32_t ny, int32_t nz, double h, c
     if (best) std::memset(best, 0, sizeof(*best));
     PB_ARG(dims_ok(nx, ny, nz), "pb_autotune: dims must be >= 1 (and below 2^36 nodes)");
     PB_ARG(std::isfinite(h) && h > 0, "pb_autotune: h must be finite and > 0");
-    PB_ARG(opts_ok(opts) && opts->op == PB_OP_STENCIL, "pb_autotune: invalid options (stencil operator only)");
+    PB_ARG(opts_ok(opts) && opts->op == PB_OP_STENCIL && opts->boundary == PB_BOUNDARY_FREE,
+           "pb_autotune: invalid options (stencil operator and free-space boundary only)");
     PB_ARG(iters_per_trial >= 1 && iters_per_trial <= 10000, "pb_autotune: iters_per_trial in [1, 10000]");
     PB_ARG(eps_x && eps_y && eps_z && kappa2 && rhs, "pb_autotune: null array");
     PB_ARG(workspace != nullptr && ((uintptr_t)workspace & 255) == 0, "pb_autotune: null or misaligned workspace");
@@ -349,7 +367,7 @@ extern "C" pb_status pb_autotune(int32_t nx, int32_t ny, int32_t nz, double h, c
         return PB_ERR_NOMEM;
     }
     hipStream_t st = (hipStream_t)stream_;
-    pb_status e = prepare(L, h, eps_x, eps_y, eps_z, kappa2, rhs, nullptr, 0, w, st);
+    pb_status e = prepare(L, h, eps_x, eps_y, eps_z, kappa2, rhs, nullptr, 0, 0, w, st, nullptr);
     if (e != PB_OK) return e;
     if (opts->precision == PB_F64) {
         SolveBufs<double> s = w.s64;

@@ -141,7 +141,7 @@ template <typename T>
 pb_status enqueue_prepare(const Plan<T>& P, const pb_problem* probs, hipStream_t st) {
     for (int i = 0; i < P.nprob; ++i) {
         pb_status e = launch_prepare64(probs[i].eps_x, probs[i].eps_y, probs[i].eps_z, probs[i].kappa2, probs[i].rhs,
-                                       probs[i].x, probs[i].warm_start ? 1 : 0, P.L[i], probs[i].h, P.op64[i],
+                                       probs[i].x, probs[i].warm_start ? 1 : 0, 0, P.L[i], probs[i].h, P.op64[i],
                                        P.b64[i], P.x64[i], &P.rec[i].flags, st);
         if (e != PB_OK) return e;
         if constexpr (sizeof(T) == sizeof(float)) {
@@ -158,7 +158,7 @@ pb_status enqueue_finish(const Plan<T>& P, const pb_problem* probs, hipStream_t 
         pb_status e = PB_OK;
         if constexpr (sizeof(T) == sizeof(float)) e = launch_f32_to_f64(P.s[i].x, P.x64[i], P.L[i].npad, st);
         if (e != PB_OK) return e;
-        e = launch_residual64(P.op64[i], P.b64[i], P.x64[i], P.L[i], nullptr, nullptr, P.resp[i], &P.rec[i].rr, st);
+        e = launch_residual64(P.op64[i], P.b64[i], P.x64[i], P.L[i], 0, nullptr, nullptr, P.resp[i], &P.rec[i].rr, st);
         if (e != PB_OK) return e;
         e = launch_unpad<double>(P.x64[i], P.L[i], probs[i].x, st);
         if (e != PB_OK) return e;

@@ -288,7 +288,7 @@ __device__ __forceinline__ TileBox tile_box(const KArgs<T>& a, int tile) {
 
 // Initial state: r = b - A x0 (r = b for a zero guess), p = 0 and (for the
 // pass that reads a stored A.p) q = 0 in buffer 0; sums r.r and b.b.
-template <typename T, int BS>
+template <typename T, int BS, bool PER>
 __device__ void init_tile(const KArgs<T>& a, int tile, bool with_q, double (&acc)[2]) {
     constexpr int W = Vec<T>::n;
     using V = typename Vec<T>::type;
@@ -306,12 +306,35 @@ __device__ void init_tile(const KArgs<T>& a, int tile, bool with_q, double (&acc
                 for (int u = 0; u < W; ++u) {
                     const int64_t t = g + u;
                     const T* X = a.x;
-                    T nb = a.op.cx[t] * (t + 1 < npad ? X[t + 1] : T(0));
-                    nb += (t >= 1 ? a.op.cx[t - 1] * X[t - 1] : T(0));
-                    nb += a.op.cy[t] * (t + a.nx < npad ? X[t + a.nx] : T(0));
-                    nb += (t >= a.nx ? a.op.cy[t - a.nx] * X[t - a.nx] : T(0));
-                    nb += a.op.cz[t] * (t + a.sp < npad ? X[t + a.sp] : T(0));
-                    nb += (t >= a.sp ? a.op.cz[t - a.sp] * X[t - a.sp] : T(0));
+                    T nb;
+                    if constexpr (PER) {
+                        const int64_t q = pos + u;
+                        if (q >= (int64_t)a.nx * a.ny) {
+                            nb = T(0);
+                        } else {
+                            const int64_t j = q / a.nx, i = q - j * a.nx;
+                            const int64_t ys = (int64_t)(a.ny - 1) * a.nx, zs = (int64_t)(a.nz - 1) * a.sp;
+                            const int64_t xr = (i == a.nx - 1) ? t - (a.nx - 1) : t + 1;
+                            const int64_t xl = (i == 0) ? t + (a.nx - 1) : t - 1;
+                            const int64_t yu = (j == a.ny - 1) ? t - ys : t + a.nx;
+                            const int64_t yd = (j == 0) ? t + ys : t - a.nx;
+                            const int64_t zu = (k == a.nz - 1) ? t - zs : t + a.sp;
+                            const int64_t zd = (k == 0) ? t + zs : t - a.sp;
+                            nb = a.op.cx[t] * X[xr];
+                            nb += a.op.cx[xl] * X[xl];
+                            nb += a.op.cy[t] * X[yu];
+                            nb += a.op.cy[yd] * X[yd];
+                            nb += a.op.cz[t] * X[zu];
+                            nb += a.op.cz[zd] * X[zd];
+                        }
+                    } else {
+                        nb = a.op.cx[t] * (t + 1 < npad ? X[t + 1] : T(0));
+                        nb += (t >= 1 ? a.op.cx[t - 1] * X[t - 1] : T(0));
+                        nb += a.op.cy[t] * (t + a.nx < npad ? X[t + a.nx] : T(0));
+                        nb += (t >= a.nx ? a.op.cy[t - a.nx] * X[t - a.nx] : T(0));
+                        nb += a.op.cz[t] * (t + a.sp < npad ? X[t + a.sp] : T(0));
+                        nb += (t >= a.sp ? a.op.cz[t - a.sp] * X[t - a.sp] : T(0));
+                    }
                     vget(rv, u) = vget(bv, u) - (vget(dv, u) * X[t] - nb);
                 }
             }
@@ -328,10 +351,15 @@ __device__ void init_tile(const KArgs<T>& a, int tile, bool with_q, double (&acc
 }
 
 // One pass on one tile (see the file comment). `o`/`n` index the old and new
-// buffers; alpha, beta are alpha_{l-1}, beta_{l-1}.
-template <typename T, int BS, int MC>
+// buffers; alpha, beta are alpha_{l-1}, beta_{l-1}. PER: periodic boundary
+// (one vector group per thread): neighbours across the x ends come from the
+// LDS row, across the y ends from p recomputed pointwise at the partner node
+// of the far row (one plane ahead, with the other loads), across the z ends
+// from the wrapped plane of the march.
+template <typename T, int BS, int MC, bool PER>
 __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T beta, T* lds0, T* lds1,
                           double (&acc)[NPART]) {
+    static_assert(!PER || MC == 1, "the periodic pass takes one vector group per thread");
     constexpr int W = Vec<T>::n;
     using V = typename Vec<T>::type;
     const TileBox tb = tile_box(a, tile);
@@ -358,6 +386,35 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
         pos[c] = s + (int64_t)(c * BS + (int)threadIdx.x) * W;
         valid[c] = pos[c] < e;
     }
+    // periodic: per element of this thread's group, bit u set when element u
+    // is at i = 0 (wl), i = nx-1 (wr), j = 0 (wd) or j = ny-1 (wu), or is a
+    // pad slot after the plane (wpad: the last real node's wrap couplings
+    // would otherwise reach it through cx[n-1], cy[n-nx])
+    unsigned wl = 0, wr = 0, wd = 0, wu = 0, wpad = 0;
+    const int64_t yspan = (int64_t)(a.ny - 1) * nx;   // offset of the partner row
+    if constexpr (PER) {
+        const int64_t plane = (int64_t)nx * a.ny;
+        if (valid[0]) {
+#pragma unroll
+            for (int u = 0; u < W; ++u) {
+                const int64_t q = pos[0] + u;
+                if (q >= plane) {
+                    wpad |= 1u << u;
+                    continue;
+                }
+                const int64_t j = q / nx, i = q - j * nx;
+                if (i == 0) wl |= 1u << u;
+                if (i == nx - 1) wr |= 1u << u;
+                if (j == 0) wd |= 1u << u;
+                if (j == a.ny - 1) wu |= 1u << u;
+            }
+        }
+    }
+    // p_{l-1} at one node from the old state (the arithmetic of p_at below)
+    auto p_point = [&](int64_t g) -> T {
+        const T r = rold[g] - alpha * qold[g];
+        return r * jacobi_inv(a.op.d[g]) + beta * pold[g];
+    };
     // p_{l-1} at a position from the old state (pointwise); also returns
     // r_{l-1}, p_{l-2} and d there.
     auto p_at = [&](int64_t g, V& rv, V& po, V& dv) -> V {
@@ -411,13 +468,27 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
         }
     };
 
+    // y-wrap partners of plane k (periodic): p_{l-1} at the far row
+    T pw[W];
+#pragma unroll
+    for (int u = 0; u < W; ++u) pw[u] = T(0);
+    auto partners = [&](int k, T (&out)[W]) {
+#pragma unroll
+        for (int u = 0; u < W; ++u) {
+            out[u] = T(0);
+            if ((wd >> u) & 1u) out[u] = p_point((int64_t)k * sp + pos[0] + u + yspan);
+            if ((wu >> u) & 1u) out[u] = p_point((int64_t)k * sp + pos[0] + u - yspan);
+        }
+    };
+
     // prologue: plane k0-1 (own positions, z-neighbour only) and plane k0
     {
         V rdummy[MC], ddummy[MC];
-        if (k0 > 0) {
-            own_plane(k0 - 1, nullptr, false, pm, rdummy, ddummy);
+        if (k0 > 0 || PER) {
+            const int km = k0 > 0 ? k0 - 1 : a.nz - 1;   // periodic: the top plane wraps below plane 0
+            own_plane(km, nullptr, false, pm, rdummy, ddummy);
 #pragma unroll
-            for (int c = 0; c < MC; ++c) czm[c] = valid[c] ? vload(a.op.cz + (int64_t)(k0 - 1) * sp + pos[c]) : z0;
+            for (int c = 0; c < MC; ++c) czm[c] = valid[c] ? vload(a.op.cz + (int64_t)km * sp + pos[c]) : z0;
         } else {
 #pragma unroll
             for (int c = 0; c < MC; ++c) {
@@ -428,6 +499,7 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
         T* buf = (k0 & 1) ? lds1 : lds0;
         own_plane(k0, buf, true, pc, rc, dc);
         halo_fill(k0, buf);
+        if constexpr (PER) partners(k0, pw);
     }
     lds_barrier();
 
@@ -442,20 +514,22 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
     for (int k = k0; k < k1; ++k) {
         const T* cur = (k & 1) ? lds1 : lds0;
         T* nxt = (k & 1) ? lds0 : lds1;
-        const bool has_next = k + 1 < a.nz;
+        const bool has_next = PER || k + 1 < a.nz;
+        const int kn = (PER && k + 1 == a.nz) ? 0 : k + 1;   // the next plane (wrapped when periodic)
         const bool owned = k + 1 < k1;
         const bool x_upd = owned && do_x;
         // ---- loads
         V in_r[MC], in_q[MC], in_d[MC], in_po[MC], in_x[MC];
         V cxv[MC], cyv[MC], czv[MC];
         T cxm[MC], cym[MC][W];
+        T cxw[W], cyw[W], pwn[W];   // periodic: wrap couplings of plane k, partners of the next plane
 #pragma unroll
         for (int c = 0; c < MC; ++c) {
             in_r[c] = in_q[c] = in_po[c] = in_x[c] = z0;
             in_d[c] = z0;
             if (!valid[c]) continue;
             if (has_next) {
-                const int64_t g1 = (int64_t)(k + 1) * sp + pos[c];
+                const int64_t g1 = (int64_t)kn * sp + pos[c];
                 in_r[c] = vload(rold + g1);
                 in_q[c] = vload(qold + g1);
                 in_d[c] = vload(a.op.d + g1);
@@ -469,6 +543,15 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
             cxm[c] = pos[c] >= 1 ? a.op.cx[g - 1] : T(0);
 #pragma unroll
             for (int u = 0; u < W; ++u) cym[c][u] = (pos[c] + u - nx >= 0) ? a.op.cy[g + u - nx] : T(0);
+        }
+        if constexpr (PER) {
+            const int64_t g = (int64_t)k * sp + pos[0];
+#pragma unroll
+            for (int u = 0; u < W; ++u) {
+                cxw[u] = ((wl >> u) & 1u) ? a.op.cx[g + u + nx - 1] : T(0);
+                cyw[u] = ((wd >> u) & 1u) ? a.op.cy[g + u + yspan] : T(0);
+            }
+            partners(kn, pwn);
         }
         V h_r = z0, h_q = z0, h_d = z0, h_po = z0;
         const bool h_load = has_next && owned && h_in_range;
@@ -487,7 +570,7 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
             rn[c] = z0;
             dn[c] = in_d[c];
             if (!valid[c] || !has_next) continue;
-            const int64_t g1 = (int64_t)(k + 1) * sp + pos[c];
+            const int64_t g1 = (int64_t)kn * sp + pos[c];
 #pragma unroll
             for (int u = 0; u < W; ++u) {
                 const T r = vget(in_r[c], u) - alpha * vget(in_q[c], u);
@@ -527,13 +610,29 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
 #pragma unroll
             for (int u = 0; u < W; ++u) {
                 const T p = vget(pc[c], u);
-                const T pl = (u == 0) ? left : vget(pc[c], u - 1);
-                const T pr = (u == W - 1) ? right : vget(pc[c], u + 1);
-                const T cl = (u == 0) ? cxm[c] : vget(cxv[c], u - 1);
+                T pl = (u == 0) ? left : vget(pc[c], u - 1);
+                T pr = (u == W - 1) ? right : vget(pc[c], u + 1);
+                T cl = (u == 0) ? cxm[c] : vget(cxv[c], u - 1);
+                T vup = cur[l + u + nx], vdn = cur[l + u - nx], cdn = cym[c][u];
+                if constexpr (PER) {
+                    if ((wr >> u) & 1u) pr = cur[l + u - (nx - 1)];
+                    if ((wl >> u) & 1u) {
+                        pl = cur[l + u + (nx - 1)];
+                        cl = cxw[u];
+                    }
+                    if ((wu >> u) & 1u) vup = pw[u];
+                    if ((wd >> u) & 1u) {
+                        vdn = pw[u];
+                        cdn = cyw[u];
+                    }
+                }
                 T nb = vget(cxv[c], u) * pr + cl * pl;
-                nb += vget(cyv[c], u) * cur[l + u + nx] + cym[c][u] * cur[l + u - nx];
+                nb += vget(cyv[c], u) * vup + cdn * vdn;
                 nb += vget(czv[c], u) * vget(pn[c], u) + vget(czm[c], u) * vget(pm[c], u);
-                const T qq = vget(dc[c], u) * p - nb;
+                T qq = vget(dc[c], u) * p - nb;
+                if constexpr (PER) {
+                    if ((wpad >> u) & 1u) qq = T(0);
+                }
                 vget(qv, u) = qq;
                 const T iv = jacobi_inv(vget(dc[c], u));
                 const double pd = (double)p, qd = (double)qq, rd = (double)vget(rc[c], u);
@@ -556,6 +655,10 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
             pc[c] = pn[c];
             rc[c] = rn[c];
             dc[c] = dn[c];
+        }
+        if constexpr (PER) {
+#pragma unroll
+            for (int u = 0; u < W; ++u) pw[u] = pwn[u];
         }
         lds_barrier();
     }
@@ -836,9 +939,10 @@ struct Scal {
 // Every workgroup derives the scalars (alpha, beta, stopping test) itself
 // from the identically reduced tile sums; workgroup 0 also persists them in
 // S for the host and for a resumed launch.
-template <typename T, int BS, int MC, int SCH>
+template <typename T, int BS, int MC, int SCH, bool PER>
 __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsigned char* lds_raw) {
     static_assert(SCH == 0 || MC == 1, "the 40-byte pass takes one vector group per thread");
+    static_assert(!PER || SCH == 0, "the periodic boundary uses the pass that stores A.p");
     const int lds_len = a.seglen + 2 * a.halo;
     T* lds0 = reinterpret_cast<T*>(lds_raw);
     T* lds1 = lds0 + lds_len;
@@ -856,7 +960,7 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
         // ---- initial residual
         for (int t = first; t < end; t += stride) {
             double acc[2] = {0.0, 0.0};
-            init_tile<T, BS>(a, t, SCH == 0, acc);
+            init_tile<T, BS, PER>(a, t, SCH == 0, acc);
             tile_reduce_store<BS, 2>(acc, red, sums(b) + (size_t)t * kMaxPartials);
         }
         double v[2];
@@ -897,7 +1001,7 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
             if constexpr (SCH == 1)
                 pass_tile40<T, BS>(a, t, o, n, alpha, beta, lds0, acc);
             else
-                pass_tile<T, BS, MC>(a, t, o, n, alpha, beta, lds0, lds1, acc);
+                pass_tile<T, BS, MC, PER>(a, t, o, n, alpha, beta, lds0, lds1, acc);
             tile_reduce_store<BS, NPART>(acc, red, sums(b) + (size_t)t * kMaxPartials);
         }
         double v[NPART];
@@ -944,10 +1048,10 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
     }
 }
 
-template <typename T, int BS, int MC, int SCH>
+template <typename T, int BS, int MC, int SCH, bool PER>
 __global__ __launch_bounds__(BS) void k_jpcg_fused(KArgs<T> a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    run_problem<T, BS, MC, SCH>(a, blockIdx.x, gridDim.x, true, lds_raw);
+    run_problem<T, BS, MC, SCH, PER>(a, blockIdx.x, gridDim.x, true, lds_raw);
 }
 
 // Many independent problems in one launch: workgroups [first[p], first[p+1])
@@ -964,7 +1068,7 @@ __global__ __launch_bounds__(BS) void k_jpcg_batch(const KArgs<T>* __restrict__ 
         if (first[mid] <= (int)blockIdx.x) lo = mid; else hi = mid;
     }
     const KArgs<T> a = probs[lo];
-    run_problem<T, BS, MC, 0>(a, blockIdx.x - first[lo], first[lo + 1] - first[lo], false, lds_raw);
+    run_problem<T, BS, MC, 0, false>(a, blockIdx.x - first[lo], first[lo + 1] - first[lo], false, lds_raw);
 }
 
 // ------------------------------------------------------------------ host side
@@ -994,16 +1098,21 @@ DevInfo dev_info() {
 using KernelFn = const void*;
 
 struct Variant {
-    int bs, mc, scheme;
+    int bs, mc, scheme, per;
     KernelFn fn;
 };
 
 template <typename T>
 const std::vector<Variant>& variants() {
     static const std::vector<Variant> v = {
-        {256, 1, 0, (KernelFn)k_jpcg_fused<T, 256, 1, 0>}, {256, 2, 0, (KernelFn)k_jpcg_fused<T, 256, 2, 0>},
-        {512, 1, 0, (KernelFn)k_jpcg_fused<T, 512, 1, 0>}, {512, 2, 0, (KernelFn)k_jpcg_fused<T, 512, 2, 0>},
-        {256, 1, 1, (KernelFn)k_jpcg_fused<T, 256, 1, 1>}, {512, 1, 1, (KernelFn)k_jpcg_fused<T, 512, 1, 1>},
+        {256, 1, 0, 0, (KernelFn)k_jpcg_fused<T, 256, 1, 0, false>},
+        {256, 2, 0, 0, (KernelFn)k_jpcg_fused<T, 256, 2, 0, false>},
+        {512, 1, 0, 0, (KernelFn)k_jpcg_fused<T, 512, 1, 0, false>},
+        {512, 2, 0, 0, (KernelFn)k_jpcg_fused<T, 512, 2, 0, false>},
+        {256, 1, 1, 0, (KernelFn)k_jpcg_fused<T, 256, 1, 1, false>},
+        {512, 1, 1, 0, (KernelFn)k_jpcg_fused<T, 512, 1, 1, false>},
+        {256, 1, 0, 1, (KernelFn)k_jpcg_fused<T, 256, 1, 0, true>},
+        {512, 1, 0, 1, (KernelFn)k_jpcg_fused<T, 512, 1, 0, true>},
     };
     return v;
 }
@@ -1051,6 +1160,7 @@ Tiling tiling_for(const Layout& L, const Variant& v, int cus, int max_per_cu) {
     t.mc = v.mc;
     t.bs = v.bs;
     t.scheme = v.scheme;
+    t.per = v.per;
     t.seglen = balanced_seglen<T>(L, v.mc * v.bs * W);
     t.halo = halo_for<T>(L.nx);
     if (2 * t.halo / W > v.bs) return t;   // halo groups must fit one per thread
@@ -1074,7 +1184,8 @@ Tiling tiling_for(const Layout& L, const Variant& v, int cus, int max_per_cu) {
 }
 
 template <typename T>
-Tiling choose_tiling_impl(const Layout& L, int want_bs, int want_mc, int max_per_cu, int want_scheme = -1) {
+Tiling choose_tiling_impl(const Layout& L, int want_bs, int want_mc, int max_per_cu, int want_scheme = -1,
+                          int want_per = 0) {
     const DevInfo di = dev_info();
     const int cus = di.cus > 0 ? di.cus : 256;
     Tiling best{};
@@ -1082,6 +1193,7 @@ Tiling choose_tiling_impl(const Layout& L, int want_bs, int want_mc, int max_per
     for (const auto& v : variants<T>()) {
         if ((want_bs > 0 && v.bs != want_bs) || (want_mc > 0 && v.mc != want_mc)) continue;
         if (want_scheme >= 0 && v.scheme != want_scheme) continue;
+        if (v.per != want_per) continue;
         Tiling t = tiling_for<T>(L, v, cus, max_per_cu);
         if (t.grid <= 0) continue;
         // model: bytes of one tile (planes incl. the extra ones below, segment
@@ -1134,6 +1246,7 @@ template <typename T>
 std::vector<Tiling> tiling_candidates(const Layout& L) {
     std::vector<Tiling> out;
     for (const auto& v : variants<T>()) {
+        if (v.per) continue;   // periodic solves use their own default tiling
         for (int cap : {1, 2, 3, 4, 0}) {
             const Tiling t = choose_tiling_impl<T>(L, v.bs, v.mc, cap, v.scheme);
             if (t.grid <= 0) continue;
@@ -1160,17 +1273,19 @@ template Tiling tiling_with<double>(const Layout&, int, int, int);
 
 template <typename T>
 pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, double* partials, double tol,
-                     int maxiter, hipStream_t st, SolveResult* res, const Tiling* force) {
-    const Tiling t = force && force->grid > 0 ? *force : choose_tiling<T>(L);
+                     int maxiter, hipStream_t st, SolveResult* res, const Tiling* force, int periodic) {
+    const Tiling t = periodic ? choose_tiling_impl<T>(L, 0, 0, 0, 0, 1)
+                              : (force && force->grid > 0 ? *force : choose_tiling<T>(L));
     if (t.grid <= 0) {
         set_error("fused JPCG: no feasible tiling for this grid (nx too large for the in-plane halo)");
         return PB_ERR_ARG;
     }
     KernelFn fn = nullptr;
     for (const auto& v : variants<T>())
-        if (v.bs == t.bs && v.mc == t.mc && v.scheme == t.scheme) fn = v.fn;
+        if (v.bs == t.bs && v.mc == t.mc && v.scheme == t.scheme && v.per == t.per) fn = v.fn;
     if (!fn) {
-        set_error("fused JPCG: unknown kernel variant bs=%d mc=%d scheme=%d", t.bs, t.mc, t.scheme);
+        set_error("fused JPCG: unknown kernel variant bs=%d mc=%d scheme=%d periodic=%d", t.bs, t.mc, t.scheme,
+                  t.per);
         return PB_ERR_ARG;
     }
     const DevInfo di = dev_info();
@@ -1232,7 +1347,7 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
     return PB_OK;
 }
 template pb_status fused_jpcg<float>(const Layout&, const SolveBufs<float>&, SyncState*, double*, double, int,
-                                     hipStream_t, SolveResult*, const Tiling*);
+                                     hipStream_t, SolveResult*, const Tiling*, int);
 
 // ------------------------------------------------------------------ batch support
 
@@ -1352,6 +1467,6 @@ pb_status batch_launch(const void* d_kargs, const int* d_first, int nprob, int g
 template pb_status batch_launch<float>(const void*, const int*, int, int, size_t, hipStream_t, bool);
 template pb_status batch_launch<double>(const void*, const int*, int, int, size_t, hipStream_t, bool);
 template pb_status fused_jpcg<double>(const Layout&, const SolveBufs<double>&, SyncState*, double*, double, int,
-                                      hipStream_t, SolveResult*, const Tiling*);
+                                      hipStream_t, SolveResult*, const Tiling*, int);
 
 }  // namespace pb

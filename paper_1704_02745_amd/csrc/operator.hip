@@ -3,8 +3,10 @@
 // The caller's arrays (staggered edge dielectrics, kbar^2, right-hand side,
 // potential) are converted once per solve into the padded internal layout
 // (see Layout in pb_internal.hpp): coupling arrays cx, cy, cz with the 1/h^2
-// factor applied and zero across the box faces, and the full diagonal of
-// Eq. 3, d = (sum of the six edge dielectrics)/h^2 + kbar^2.
+// factor applied, and the full diagonal of Eq. 3, d = (sum of the six edge
+// dielectrics)/h^2 + kbar^2. With the free-space boundary the couplings are
+// zero across the box faces; with the periodic boundary the last node of a
+// row, column or z-line holds the wrap coupling to the first.
 #include "pb_internal.hpp"
 #include "solver.hpp"
 
@@ -16,7 +18,7 @@ __device__ __forceinline__ bool finite_d(double v) { return v - v == 0.0; }
 __global__ void k_prepare64(const double* __restrict__ ex, const double* __restrict__ ey,
                             const double* __restrict__ ez, const double* __restrict__ k2,
                             const double* __restrict__ rhs, const double* __restrict__ xin,
-                            int warm, int nx, int ny, int nz, int64_t sp, double hh,
+                            int warm, int per, int nx, int ny, int nz, int64_t sp, double hh,
                             double* __restrict__ cx, double* __restrict__ cy, double* __restrict__ cz,
                             double* __restrict__ d, double* __restrict__ b, double* __restrict__ x,
                             int* __restrict__ flags) {
@@ -44,9 +46,10 @@ __global__ void k_prepare64(const double* __restrict__ ex, const double* __restr
         if (!(exm >= 0.0 && exp_ >= 0.0 && eym >= 0.0 && eyp >= 0.0 && ezm >= 0.0 && ezp >= 0.0 &&
               kk >= 0.0 && finite_d(dd) && dd > 0.0))
             bad |= FLAG_BAD_COEF;
-        cx[t] = (i < nx - 1) ? exp_ / hh : 0.0;
-        cy[t] = (j < ny - 1) ? eyp / hh : 0.0;
-        cz[t] = (k < nz - 1) ? ezp / hh : 0.0;
+        cx[t] = (per || i < nx - 1) ? exp_ / hh : 0.0;
+        cy[t] = (per || j < ny - 1) ? eyp / hh : 0.0;
+        cz[t] = (per || k < nz - 1) ? ezp / hh : 0.0;
+        if (kk > 0.0) bad |= FLAG_HAS_SALT;
         d[t] = dd;
         const double bv = rhs[n];
         if (!finite_d(bv)) bad |= FLAG_BAD_RHS;
@@ -82,22 +85,47 @@ __global__ void k_round32(const double* __restrict__ cx, const double* __restric
 // r = b - A x in FP64 over the padded layout, with per-block partial sums of
 // r.r and b.b (each block handles a contiguous range; the block order is fixed).
 // Optionally writes r (FP64) and its FP32 rounding.
-template <int BS>
+// Periodic boundary (PER): neighbours wrap within each row, column and
+// z-line; the wrap coupling sits at the last node of the line.
+template <int BS, bool PER>
 __global__ __launch_bounds__(BS) void k_residual64(
         const double* __restrict__ cx, const double* __restrict__ cy, const double* __restrict__ cz,
         const double* __restrict__ d, const double* __restrict__ b, const double* __restrict__ x,
-        int nx, int64_t sp, int64_t npad, int64_t per_block, double* __restrict__ r64,
+        int nx, int ny, int nz, int64_t sp, int64_t npad, int64_t per_block, double* __restrict__ r64,
         float* __restrict__ r32, double* __restrict__ partials) {
     const int64_t lo = (int64_t)blockIdx.x * per_block;
     const int64_t hi = min(lo + per_block, npad);
+    const int64_t plane = (int64_t)nx * ny;
     double rr = 0.0, bb = 0.0;
     for (int64_t t = lo + threadIdx.x; t < hi; t += BS) {
-        double nb = cx[t] * (t + 1 < npad ? x[t + 1] : 0.0);
-        nb += (t >= 1 ? cx[t - 1] * x[t - 1] : 0.0);
-        nb += cy[t] * (t + nx < npad ? x[t + nx] : 0.0);
-        nb += (t >= nx ? cy[t - nx] * x[t - nx] : 0.0);
-        nb += cz[t] * (t + sp < npad ? x[t + sp] : 0.0);
-        nb += (t >= sp ? cz[t - sp] * x[t - sp] : 0.0);
+        double nb;
+        if constexpr (PER) {
+            const int64_t k = t / sp, pp = t - k * sp;
+            if (pp >= plane) {
+                nb = 0.0;
+            } else {
+                const int64_t j = pp / nx, i = pp - j * nx;
+                const int64_t xr = (i == nx - 1) ? t - (nx - 1) : t + 1;
+                const int64_t xl = (i == 0) ? t + (nx - 1) : t - 1;
+                const int64_t yu = (j == ny - 1) ? t - (int64_t)(ny - 1) * nx : t + nx;
+                const int64_t yd = (j == 0) ? t + (int64_t)(ny - 1) * nx : t - nx;
+                const int64_t zu = (k == nz - 1) ? t - (int64_t)(nz - 1) * sp : t + sp;
+                const int64_t zd = (k == 0) ? t + (int64_t)(nz - 1) * sp : t - sp;
+                nb = cx[t] * x[xr];
+                nb += cx[xl] * x[xl];
+                nb += cy[t] * x[yu];
+                nb += cy[yd] * x[yd];
+                nb += cz[t] * x[zu];
+                nb += cz[zd] * x[zd];
+            }
+        } else {
+            nb = cx[t] * (t + 1 < npad ? x[t + 1] : 0.0);
+            nb += (t >= 1 ? cx[t - 1] * x[t - 1] : 0.0);
+            nb += cy[t] * (t + nx < npad ? x[t + nx] : 0.0);
+            nb += (t >= nx ? cy[t - nx] * x[t - nx] : 0.0);
+            nb += cz[t] * (t + sp < npad ? x[t + sp] : 0.0);
+            nb += (t >= sp ? cz[t - sp] * x[t - sp] : 0.0);
+        }
         const double bv = b[t];
         const double rv = bv - (d[t] * x[t] - nb);
         if (r64) r64[t] = rv;
@@ -147,6 +175,38 @@ __global__ __launch_bounds__(256) void k_reduce_pairs(const double* __restrict__
     }
 }
 
+// Per-block partial sums of v over the real nodes of the padded layout
+// (fixed block ranges), as (sum, 0) pairs for k_reduce_pairs.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_real_sum(const double* __restrict__ v, int64_t plane, int64_t sp,
+                                                 int64_t npad, int64_t per_block, double* __restrict__ partials) {
+    const int64_t lo = (int64_t)blockIdx.x * per_block;
+    const int64_t hi = min(lo + per_block, npad);
+    double acc = 0.0;
+    for (int64_t t = lo + threadIdx.x; t < hi; t += BS)
+        if (t % sp < plane) acc += v[t];
+    __shared__ double s[BS];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = BS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = s[0];
+        partials[2 * blockIdx.x + 1] = 0.0;
+    }
+}
+
+// v -= sum[0] / n on the real nodes (pads stay zero).
+__global__ void k_sub_mean(double* __restrict__ v, const double* __restrict__ sum, double n, int64_t plane,
+                           int64_t sp, int64_t npad) {
+    const double m = sum[0] / n;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npad;
+         t += (int64_t)gridDim.x * blockDim.x)
+        if (t % sp < plane) v[t] = v[t] - m;
+}
+
 // x64 += (double) dx (padded layout).
 __global__ void k_add_correction(double* __restrict__ x, const float* __restrict__ dx, int64_t npad) {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npad;
@@ -188,10 +248,10 @@ static unsigned grid_for(int64_t n, int bs = 256, int64_t cap = 8192) {
 }
 
 pb_status launch_prepare64(const double* ex, const double* ey, const double* ez, const double* k2,
-                           const double* rhs, const double* xin, int warm, const Layout& L, double h,
-                           Op<double> op, double* b, double* x, int* flags, hipStream_t st) {
+                           const double* rhs, const double* xin, int warm, int periodic, const Layout& L,
+                           double h, Op<double> op, double* b, double* x, int* flags, hipStream_t st) {
     hipLaunchKernelGGL(k_prepare64, dim3(grid_for(L.npad)), dim3(256), 0, st, ex, ey, ez, k2, rhs, xin,
-                       warm, L.nx, L.ny, L.nz, L.sp, h * h, (double*)op.cx, (double*)op.cy,
+                       warm, periodic, L.nx, L.ny, L.nz, L.sp, h * h, (double*)op.cx, (double*)op.cy,
                        (double*)op.cz, (double*)op.d, b, x, flags);
     PB_HIP(hipGetLastError());
     return PB_OK;
@@ -210,13 +270,28 @@ int residual_blocks(const Layout& L) {
     return (int)std::min<int64_t>(4096, std::max<int64_t>(1, (L.npad + 4095) / 4096));
 }
 
-pb_status launch_residual64(Op<double> op, const double* b, const double* x, const Layout& L,
+pb_status launch_residual64(Op<double> op, const double* b, const double* x, const Layout& L, int periodic,
                             double* r64, float* r32, double* partials, double* out2, hipStream_t st) {
     const int nblk = residual_blocks(L);
     const int64_t per = (L.npad + nblk - 1) / nblk;
-    hipLaunchKernelGGL(k_residual64<256>, dim3(nblk), dim3(256), 0, st, op.cx, op.cy, op.cz, op.d, b, x,
-                       L.nx, L.sp, L.npad, per, r64, r32, partials);
+    if (periodic)
+        hipLaunchKernelGGL((k_residual64<256, true>), dim3(nblk), dim3(256), 0, st, op.cx, op.cy, op.cz, op.d, b,
+                           x, L.nx, L.ny, L.nz, L.sp, L.npad, per, r64, r32, partials);
+    else
+        hipLaunchKernelGGL((k_residual64<256, false>), dim3(nblk), dim3(256), 0, st, op.cx, op.cy, op.cz, op.d,
+                           b, x, L.nx, L.ny, L.nz, L.sp, L.npad, per, r64, r32, partials);
     hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(256), 0, st, partials, nblk, out2);
+    PB_HIP(hipGetLastError());
+    return PB_OK;
+}
+
+pb_status launch_remove_mean(double* v, const Layout& L, double* partials, double* out2, hipStream_t st) {
+    const int nblk = residual_blocks(L);
+    const int64_t per = (L.npad + nblk - 1) / nblk;
+    hipLaunchKernelGGL(k_real_sum<256>, dim3(nblk), dim3(256), 0, st, v, L.plane, L.sp, L.npad, per, partials);
+    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(256), 0, st, partials, nblk, out2);
+    hipLaunchKernelGGL(k_sub_mean, dim3(grid_for(L.npad)), dim3(256), 0, st, v, (const double*)out2,
+                       (double)L.n, L.plane, L.sp, L.npad);
     PB_HIP(hipGetLastError());
     return PB_OK;
 }

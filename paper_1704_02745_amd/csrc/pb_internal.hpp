@@ -101,6 +101,7 @@ enum PrepFlags {
     FLAG_BAD_COEF = 1,    // negative / non-finite coefficient or non-positive diagonal
     FLAG_BAD_RHS = 2,     // NaN / Inf in the right-hand side
     FLAG_BAD_GUESS = 4,   // NaN / Inf in the initial guess
+    FLAG_HAS_SALT = 8,    // some node has kbar^2 > 0 (the periodic operator is then definite)
 };
 
 // ---------------------------------------------------------------- helpers

@@ -156,7 +156,7 @@ namespace {
 // Enqueue the FP64 residual of a refinement slot: r (FP32) into the inner
 // right-hand side, sums into rec.
 pb_status enqueue_outer_residual(Slot& s, hipStream_t st) {
-    return launch_residual64(s.op64, s.b64, s.x64, s.L, nullptr, (float*)s.s.b, s.resp, &s.rec->rr, st);
+    return launch_residual64(s.op64, s.b64, s.x64, s.L, 0, nullptr, (float*)s.s.b, s.resp, &s.rec->rr, st);
 }
 
 // Reset the inner FP32 solve of a slot (zero guess, cleared barrier state).
@@ -263,7 +263,7 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
         e = launch_fill<int>((int*)s.rec, (int64_t)(sizeof(SlotRec) / sizeof(int)), 0, st);
         if (e != PB_OK) return e;
         e = launch_prepare64(s.req.eps_x, s.req.eps_y, s.req.eps_z, s.req.kappa2, s.req.rhs, s.req.x,
-                             s.req.warm_start ? 1 : 0, s.L, s.req.h, s.op64, s.b64, s.x64, &s.rec->flags, st);
+                             s.req.warm_start ? 1 : 0, 0, s.L, s.req.h, s.op64, s.b64, s.x64, &s.rec->flags, st);
         if (e != PB_OK) return e;
         if (s.precision == PB_F32) {
             e = launch_round32(s.op64, s.b64, s.x64, s.L.npad, s.s.op, (float*)s.s.b, s.s.x, st);
@@ -384,7 +384,7 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
                 s.relres = h.bb > 0 ? std::sqrt(h.rr) / std::sqrt(h.bb) : 0.0;
                 e = launch_f32_to_f64(s.s.x, s.x64, s.L.npad, st);
                 if (e != PB_OK) return e;
-                e = launch_residual64(s.op64, s.b64, s.x64, s.L, nullptr, nullptr, s.resp, &s.rec->rr, st);
+                e = launch_residual64(s.op64, s.b64, s.x64, s.L, 0, nullptr, nullptr, s.resp, &s.rec->rr, st);
                 if (e != PB_OK) return e;
                 e = finish_slot(s, h.status, st);
                 if (e != PB_OK) return e;

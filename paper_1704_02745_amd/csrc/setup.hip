@@ -15,6 +15,7 @@ namespace {
 constexpr double kFourPi = 12.566370614359172;   // 4*pi rounded to double
 constexpr double kCoulombKcal = 332.0637133;     // e^2/(4 pi eps0), kcal A/mol
 constexpr int kMaxAtoms = (1 << 21) - 1;          // pair id = 8*atom + corner < 2^24
+constexpr double kPeriodicMaxIndex = 268435456.0;  // 2^28: bound on |(c - o)/h| with the periodic boundary
 
 __global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -36,7 +37,7 @@ __global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
 // Concurrent writers only ever store 1, so the result is order independent.
 __global__ void k_classify(const double* __restrict__ xyz, const double* __restrict__ radius,
                            int64_t natoms, int nx, int ny, int nz, double h,
-                           double ox, double oy, double oz, uint8_t* __restrict__ mask) {
+                           double ox, double oy, double oz, int per, uint8_t* __restrict__ mask) {
     const int64_t a = blockIdx.x;
     if (a >= natoms) return;
     const double cx = xyz[3 * a], cy = xyz[3 * a + 1], cz = xyz[3 * a + 2];
@@ -49,8 +50,14 @@ __global__ void k_classify(const double* __restrict__ xyz, const double* __restr
     for (int d = 0; d < 3; ++d) {
         double l = floor((c[d] - r - o[d]) / h) - 1.0;
         double u = ceil((c[d] + r - o[d]) / h) + 1.0;
-        l = fmin(fmax(l, -1.0), (double)n3[d]);
-        u = fmin(fmax(u, -1.0), (double)n3[d]);
+        if (per) {
+            // periodic: the unwrapped window around the sphere (the nodes it
+            // covers are marked at their wrapped index)
+            if (!(fabs(l) < kPeriodicMaxIndex && fabs(u) < kPeriodicMaxIndex)) return;
+        } else {
+            l = fmin(fmax(l, -1.0), (double)n3[d]);
+            u = fmin(fmax(u, -1.0), (double)n3[d]);
+        }
         lo[d] = (int)l;
         hi[d] = (int)u;   // inclusive
     }
@@ -67,7 +74,41 @@ __global__ void k_classify(const double* __restrict__ xyz, const double* __restr
         const double z = oz + h * (double)k;
         const double dx = x - cx, dy = y - cy, dz = z - cz;
         const double d2 = dx * dx + dy * dy + dz * dz;
-        if (d2 < rr) mask[(i + 1) + px * ((j + 1) + py * (int64_t)(k + 1))] = 1;
+        if (d2 < rr) {
+            if (per) {
+                const int iw = ((i % nx) + nx) % nx, jw = ((j % ny) + ny) % ny, kw = ((k % nz) + nz) % nz;
+                mask[(iw + 1) + px * ((jw + 1) + py * (int64_t)(kw + 1))] = 1;
+            } else {
+                mask[(i + 1) + px * ((j + 1) + py * (int64_t)(k + 1))] = 1;
+            }
+        }
+    }
+}
+
+// Periodic: fill the ghost layer of the padded mask with the wrapped nodes,
+// one axis at a time (x, then y over whole padded rows, then z over whole
+// padded planes) so edges and corners wrap too.
+__global__ void k_wrap_ghosts(uint8_t* __restrict__ m, int nx, int ny, int nz, int axis) {
+    const int64_t px = nx + 2, py = ny + 2, pz = nz + 2;
+    const int64_t n = axis == 0 ? (int64_t)ny * nz : axis == 1 ? px * nz : px * py;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        if (axis == 0) {
+            const int64_t j = 1 + t % ny, k = 1 + t / ny;
+            uint8_t* row = m + px * (j + py * k);
+            row[0] = row[nx];
+            row[nx + 1] = row[1];
+        } else if (axis == 1) {
+            const int64_t i = t % px, k = 1 + t / px;
+            uint8_t* col = m + i + px * py * k;
+            col[0] = col[px * ny];
+            col[px * (ny + 1)] = col[px];
+        } else {
+            const int64_t i = t % px, j = t / px;
+            uint8_t* line = m + i + px * j;
+            line[0] = line[px * py * nz];
+            line[px * py * (pz - 1)] = line[px * py];
+        }
     }
 }
 
@@ -123,9 +164,19 @@ __global__ void k_edges(const uint8_t* __restrict__ mask, int nx, int ny, int nz
     }
 }
 
-// Trilinear cell of one atom along one axis: i0 = clamp(floor(g), 0, n-2), f = g - i0.
-__device__ __forceinline__ bool cell_axis(double c, double o, double h, int n, int& i0, double& f) {
+// Trilinear cell of one atom along one axis: i0 = clamp(floor(g), 0, n-2),
+// f = g - i0. Periodic: i0 = floor(g) mod n, f = g - floor(g) (the second
+// node of the cell is (i0 + 1) mod n).
+__device__ __forceinline__ bool cell_axis(double c, double o, double h, int n, int per, int& i0, double& f) {
     const double g = (c - o) / h;
+    if (per) {
+        if (!(fabs(g) < kPeriodicMaxIndex)) return false;
+        const double fl = floor(g);
+        f = g - fl;
+        const long long w = (long long)fl % n;
+        i0 = (int)(w < 0 ? w + n : w);
+        return true;
+    }
     if (!(g >= 0.0) || !(g <= (double)(n - 1))) return false;
     double fl = floor(g);
     fl = fmin(fmax(fl, 0.0), (double)(n - 2));
@@ -134,11 +185,20 @@ __device__ __forceinline__ bool cell_axis(double c, double o, double h, int n, i
     return true;
 }
 
+// Node index of corner c (bit 0: +x, bit 1: +y, bit 2: +z) of a cell.
+__device__ __forceinline__ int64_t corner_node(int i0, int j0, int k0, int c, int nx, int ny, int nz) {
+    int i = i0 + (c & 1), j = j0 + ((c >> 1) & 1), k = k0 + ((c >> 2) & 1);
+    if (i == nx) i = 0;   // only reached with the periodic cell
+    if (j == ny) j = 0;
+    if (k == nz) k = 0;
+    return (int64_t)i + (int64_t)nx * ((int64_t)j + (int64_t)ny * k);
+}
+
 // Charge spreading, step 1: one sort key per (atom, corner) pair,
 // key = node_index << 24 | (8*atom + corner). Sorting the keys groups the
 // contributions of each node in increasing atom order.
 __global__ void k_spread_keys(const double* __restrict__ xyz, int64_t natoms, int nx, int ny, int nz,
-                              double h, double ox, double oy, double oz,
+                              double h, double ox, double oy, double oz, int per,
                               uint64_t* __restrict__ keys, int* __restrict__ flags) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= 8 * natoms) return;
@@ -146,16 +206,15 @@ __global__ void k_spread_keys(const double* __restrict__ xyz, int64_t natoms, in
     const int c = (int)(p & 7);
     int i0, j0, k0;
     double fx, fy, fz;
-    bool ok = cell_axis(xyz[3 * a], ox, h, nx, i0, fx);
-    ok = cell_axis(xyz[3 * a + 1], oy, h, ny, j0, fy) && ok;
-    ok = cell_axis(xyz[3 * a + 2], oz, h, nz, k0, fz) && ok;
+    bool ok = cell_axis(xyz[3 * a], ox, h, nx, per, i0, fx);
+    ok = cell_axis(xyz[3 * a + 1], oy, h, ny, per, j0, fy) && ok;
+    ok = cell_axis(xyz[3 * a + 2], oz, h, nz, per, k0, fz) && ok;
     if (!ok) {
         atomicOr(flags, 1);
         keys[p] = ~0ull;
         return;
     }
-    const int64_t node = (int64_t)(i0 + (c & 1)) +
-                         (int64_t)nx * ((int64_t)(j0 + ((c >> 1) & 1)) + (int64_t)ny * (k0 + ((c >> 2) & 1)));
+    const int64_t node = corner_node(i0, j0, k0, c, nx, ny, nz);
     keys[p] = ((uint64_t)node << 24) | (uint64_t)p;
 }
 
@@ -178,7 +237,7 @@ __global__ void k_bitonic_step(uint64_t* __restrict__ a, int64_t n, int64_t j, i
 // key order (increasing atom index), starting from zero, and stores q_node.
 __global__ void k_spread_sum(const uint64_t* __restrict__ keys, int64_t npairs,
                              const double* __restrict__ xyz, const double* __restrict__ charge,
-                             int nx, int ny, int nz, double h, double ox, double oy, double oz,
+                             int nx, int ny, int nz, double h, double ox, double oy, double oz, int per,
                              double* __restrict__ q) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npairs) return;
@@ -195,9 +254,9 @@ __global__ void k_spread_sum(const uint64_t* __restrict__ keys, int64_t npairs,
         const int c = (int)(p & 7);
         int i0, j0, k0;
         double fx, fy, fz;
-        cell_axis(xyz[3 * a], ox, h, nx, i0, fx);
-        cell_axis(xyz[3 * a + 1], oy, h, ny, j0, fy);
-        cell_axis(xyz[3 * a + 2], oz, h, nz, k0, fz);
+        cell_axis(xyz[3 * a], ox, h, nx, per, i0, fx);
+        cell_axis(xyz[3 * a + 1], oy, h, ny, per, j0, fy);
+        cell_axis(xyz[3 * a + 2], oz, h, nz, per, k0, fz);
         const double wx = (c & 1) ? fx : 1.0 - fx;
         const double wy = (c & 2) ? fy : 1.0 - fy;
         const double wz = (c & 4) ? fz : 1.0 - fz;
@@ -283,7 +342,7 @@ __global__ __launch_bounds__(kDhBlock) void k_dh_faces(
 __global__ void k_rhs(const double* __restrict__ q, const double* __restrict__ ex,
                       const double* __restrict__ ey, const double* __restrict__ ez,
                       const double* __restrict__ ghost, int nx, int ny, int nz,
-                      double h3, double ih2, double* __restrict__ b) {
+                      double h3, double ih2, int per, double* __restrict__ b) {
     const int64_t nn = (int64_t)nx * ny * nz;
     const int64_t fx = (int64_t)ny * nz, fy = (int64_t)nx * nz, fz = (int64_t)nx * ny;
     const double* gxm = ghost;
@@ -296,6 +355,10 @@ __global__ void k_rhs(const double* __restrict__ q, const double* __restrict__ e
          n += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = n % nx, j = (n / nx) % ny, k = n / fz;
         double fold = 0.0;
+        if (per) {   // no boundary values: the box repeats
+            b[n] = kFourPi * q[n] / h3;
+            continue;
+        }
         if (i == 0) fold = fold + ex[(nx + 1) * (j + ny * k)] * ih2 * gxm[j + ny * k];
         if (i == nx - 1) fold = fold + ex[nx + (nx + 1) * (j + ny * k)] * ih2 * gxp[j + ny * k];
         if (j == 0) fold = fold + ey[i + (int64_t)nx * ((ny + 1) * k)] * ih2 * gym[i + nx * k];
@@ -309,16 +372,16 @@ __global__ void k_rhs(const double* __restrict__ q, const double* __restrict__ e
 // Potential at each atom centre by the spreading weights; product q_a*phi_a.
 __global__ void k_energy_atoms(const double* __restrict__ xyz, const double* __restrict__ charge,
                                int64_t natoms, int nx, int ny, int nz, double h,
-                               double ox, double oy, double oz, const double* __restrict__ x,
+                               double ox, double oy, double oz, int per, const double* __restrict__ x,
                                double* __restrict__ atom_phi, double* __restrict__ qphi,
                                int* __restrict__ flags) {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= natoms) return;
     int i0, j0, k0;
     double fx, fy, fz;
-    bool ok = cell_axis(xyz[3 * a], ox, h, nx, i0, fx);
-    ok = cell_axis(xyz[3 * a + 1], oy, h, ny, j0, fy) && ok;
-    ok = cell_axis(xyz[3 * a + 2], oz, h, nz, k0, fz) && ok;
+    bool ok = cell_axis(xyz[3 * a], ox, h, nx, per, i0, fx);
+    ok = cell_axis(xyz[3 * a + 1], oy, h, ny, per, j0, fy) && ok;
+    ok = cell_axis(xyz[3 * a + 2], oz, h, nz, per, k0, fz) && ok;
     if (!ok) {
         atomicOr(flags, 1);
         qphi[a] = 0.0;
@@ -330,9 +393,7 @@ __global__ void k_energy_atoms(const double* __restrict__ xyz, const double* __r
         const double wx = (c & 1) ? fx : 1.0 - fx;
         const double wy = (c & 2) ? fy : 1.0 - fy;
         const double wz = (c & 4) ? fz : 1.0 - fz;
-        const int64_t node = (int64_t)(i0 + (c & 1)) +
-                             (int64_t)nx * ((int64_t)(j0 + ((c >> 1) & 1)) + (int64_t)ny * (k0 + ((c >> 2) & 1)));
-        t[c] = wx * wy * wz * x[node];
+        t[c] = wx * wy * wz * x[corner_node(i0, j0, k0, c, nx, ny, nz)];
     }
     const double phi = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
     if (atom_phi) atom_phi[a] = phi;
@@ -352,6 +413,16 @@ __global__ __launch_bounds__(1024) void k_sum_fixed(const double* __restrict__ v
         __syncthreads();
     }
     if (threadIdx.x == 0) out[0] = s[0];
+}
+
+// b -= sums[0] / n when sums[1] == 0 (periodic boundary without salt: the
+// operator annihilates constants, b gets a uniform neutralising background).
+__global__ void k_neutralise(double* __restrict__ b, int64_t n, const double* __restrict__ sums) {
+    if (sums[1] != 0.0) return;
+    const double m = sums[0] / (double)n;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        b[t] = b[t] - m;
 }
 
 inline int64_t next_pow2(int64_t v) {
@@ -406,7 +477,9 @@ SetupWs carve_setup(void* base, int nx, int ny, int nz, int64_t natoms) {
 }
 
 bool grid_ok(const pb_grid* g) {
-    return g && g->nx >= 2 && g->ny >= 2 && g->nz >= 2 && std::isfinite(g->h) && g->h > 0.0 &&
+    const int m = (g && g->boundary == PB_BOUNDARY_PERIODIC) ? 3 : 2;
+    return g && (g->boundary == PB_BOUNDARY_FREE || g->boundary == PB_BOUNDARY_PERIODIC) && g->nx >= m &&
+           g->ny >= m && g->nz >= m && std::isfinite(g->h) && g->h > 0.0 &&
            std::isfinite(g->origin[0]) && std::isfinite(g->origin[1]) && std::isfinite(g->origin[2]) &&
            (int64_t)(g->nx + 2) * (g->ny + 2) * (int64_t)(g->nz + 2) < (int64_t(1) << 40);
 }
@@ -428,7 +501,8 @@ extern "C" pb_status pb_setup(const pb_grid* g, int64_t natoms, const double* xy
                               double* eps_z, double* kappa2, double* rhs, double* qgrid,
                               uint8_t* mask, void* workspace, size_t workspace_bytes,
                               void* stream_) {
-    PB_ARG(grid_ok(g), "pb_setup: grid needs nx,ny,nz >= 2, finite h > 0 and a finite origin");
+    PB_ARG(grid_ok(g), "pb_setup: grid needs a valid boundary, nx,ny,nz >= 2 (>= 3 periodic), finite h > 0 "
+                       "and a finite origin");
     PB_ARG(natoms >= 0 && natoms <= kMaxAtoms, "pb_setup: natoms must be in [0, 2^21-1]");
     PB_ARG(natoms == 0 || (xyz && radius && charge), "pb_setup: null atom array");
     PB_ARG(eps_x && eps_y && eps_z && kappa2 && rhs, "pb_setup: null output array");
@@ -449,12 +523,21 @@ extern "C" pb_status pb_setup(const pb_grid* g, int64_t natoms, const double* xy
     const int64_t ngh = 2 * ((int64_t)ny * nz + (int64_t)nx * nz + (int64_t)nx * ny);
     uint8_t* m = mask ? mask : w.mask;
     double* q = qgrid ? qgrid : w.qgrid;
+    const int per = g->boundary == PB_BOUNDARY_PERIODIC ? 1 : 0;
 
     hipLaunchKernelGGL(k_fill_u8, dim3(1), dim3(64), 0, st, (uint8_t*)w.flags, (int64_t)256, (uint8_t)0);
     hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(nmask, 256)), dim3(256), 0, st, m, nmask, (uint8_t)0);
     if (natoms > 0)
         hipLaunchKernelGGL(k_classify, dim3((unsigned)natoms), dim3(256), 0, st, xyz, radius, natoms,
-                           nx, ny, nz, h, ox, oy, oz, m);
+                           nx, ny, nz, h, ox, oy, oz, per, m);
+    if (per) {
+        hipLaunchKernelGGL(k_wrap_ghosts, dim3(blocks_for((int64_t)ny * nz, 256)), dim3(256), 0, st, m, nx, ny,
+                           nz, 0);
+        hipLaunchKernelGGL(k_wrap_ghosts, dim3(blocks_for((int64_t)(nx + 2) * nz, 256)), dim3(256), 0, st, m,
+                           nx, ny, nz, 1);
+        hipLaunchKernelGGL(k_wrap_ghosts, dim3(blocks_for((int64_t)(nx + 2) * (ny + 2), 256)), dim3(256), 0, st,
+                           m, nx, ny, nz, 2);
+    }
     const int64_t nedge = (int64_t)(nx + 1) * ny * nz + (int64_t)nx * (ny + 1) * nz +
                           (int64_t)nx * ny * (nz + 1) + nn;
     hipLaunchKernelGGL(k_edges, dim3(blocks_for(nedge, 256)), dim3(256), 0, st, m, nx, ny, nz,
@@ -467,26 +550,34 @@ extern "C" pb_status pb_setup(const pb_grid* g, int64_t natoms, const double* xy
         const int64_t P = next_pow2(std::max<int64_t>(2, np));
         hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(P, 256)), dim3(256), 0, st, w.keys, P, ~0ull);
         hipLaunchKernelGGL(k_spread_keys, dim3(blocks_for(np, 256, 1 << 30)), dim3(256), 0, st, xyz,
-                           natoms, nx, ny, nz, h, ox, oy, oz, w.keys, w.flags);
+                           natoms, nx, ny, nz, h, ox, oy, oz, per, w.keys, w.flags);
         for (int64_t k = 2; k <= P; k <<= 1)
             for (int64_t j = k >> 1; j > 0; j >>= 1)
                 hipLaunchKernelGGL(k_bitonic_step, dim3(blocks_for(P, 256, 1 << 30)), dim3(256), 0, st,
                                    w.keys, P, j, k);
         hipLaunchKernelGGL(k_spread_sum, dim3(blocks_for(np, 256, 1 << 30)), dim3(256), 0, st, w.keys,
-                           np, xyz, charge, nx, ny, nz, h, ox, oy, oz, q);
+                           np, xyz, charge, nx, ny, nz, h, ox, oy, oz, per, q);
     }
-    // boundary potential on the face ghosts
-    hipLaunchKernelGGL(k_dh_faces, dim3(blocks_for(ngh, kDhBlock, 1 << 30)), dim3(kDhBlock), 0, st,
-                       xyz, charge, natoms, nx, ny, nz, h, ox, oy, oz, std::sqrt(kappa_d2), eps_out,
-                       w.ghost, ngh);
+    // boundary potential on the face ghosts (free space only)
+    if (!per)
+        hipLaunchKernelGGL(k_dh_faces, dim3(blocks_for(ngh, kDhBlock, 1 << 30)), dim3(kDhBlock), 0, st,
+                           xyz, charge, natoms, nx, ny, nz, h, ox, oy, oz, std::sqrt(kappa_d2), eps_out,
+                           w.ghost, ngh);
     hipLaunchKernelGGL(k_rhs, dim3(blocks_for(nn, 256)), dim3(256), 0, st, q, eps_x, eps_y, eps_z,
-                       w.ghost, nx, ny, nz, std::pow(h, 3.0), 1.0 / (h * h), rhs);
+                       w.ghost, nx, ny, nz, std::pow(h, 3.0), 1.0 / (h * h), per, rhs);
+    if (per) {   // sums of b and kbar^2 (fixed order) into the unused ghost buffer, then the background
+        hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(1024), 0, st, (const double*)rhs, nn, w.ghost);
+        hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(1024), 0, st, (const double*)kappa2, nn, w.ghost + 1);
+        hipLaunchKernelGGL(k_neutralise, dim3(blocks_for(nn, 256)), dim3(256), 0, st, rhs, nn,
+                           (const double*)w.ghost);
+    }
     PB_HIP(hipGetLastError());
     int flags = 0;
     PB_HIP(hipMemcpyAsync(&flags, w.flags, sizeof(int), hipMemcpyDeviceToHost, st));
     PB_HIP(hipStreamSynchronize(st));
     if (flags) {
-        set_error("pb_setup: an atom centre lies outside the node box");
+        set_error(per ? "pb_setup: an atom centre lies beyond 2^28 nodes from the origin"
+                      : "pb_setup: an atom centre lies outside the node box");
         return PB_ERR_ARG;
     }
     return PB_OK;
@@ -501,7 +592,8 @@ extern "C" pb_status pb_energy(const pb_grid* g, int64_t natoms, const double* x
                                const double* charge, const double* x, double* atom_phi,
                                double* energy, void* workspace, size_t workspace_bytes,
                                void* stream_) {
-    PB_ARG(grid_ok(g), "pb_energy: grid needs nx,ny,nz >= 2, finite h > 0 and a finite origin");
+    PB_ARG(grid_ok(g), "pb_energy: grid needs a valid boundary, nx,ny,nz >= 2 (>= 3 periodic), finite h > 0 "
+                       "and a finite origin");
     PB_ARG(natoms >= 0 && natoms <= kMaxAtoms, "pb_energy: natoms must be in [0, 2^21-1]");
     PB_ARG(natoms == 0 || (xyz && charge), "pb_energy: null atom array");
     PB_ARG(x && energy && workspace, "pb_energy: null x, energy or workspace");
@@ -519,7 +611,7 @@ extern "C" pb_status pb_energy(const pb_grid* g, int64_t natoms, const double* x
     if (natoms > 0)
         hipLaunchKernelGGL(k_energy_atoms, dim3(blocks_for(natoms, 256, 1 << 30)), dim3(256), 0, st, xyz,
                            charge, natoms, g->nx, g->ny, g->nz, g->h, g->origin[0], g->origin[1],
-                           g->origin[2], x, atom_phi, qphi, flags);
+                           g->origin[2], g->boundary == PB_BOUNDARY_PERIODIC ? 1 : 0, x, atom_phi, qphi, flags);
     hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(1024), 0, st, qphi, natoms, out);
     PB_HIP(hipGetLastError());
     double host[2];

@@ -90,7 +90,9 @@ extern "C" pb_status pb_solvation_energy(const pb_grid* g, int64_t natoms, const
                                 nullptr, scratch, o.scratch_bytes, stream);
         if (st != PB_OK) return st;
         pb_info info{};
-        st = pb_solve(g->nx, g->ny, g->nz, g->h, ex, ey, ez, k2, rhs, phis[s], opts, scratch, o.scratch_bytes,
+        pb_solve_opts so = *opts;
+        so.boundary = g->boundary;
+        st = pb_solve(g->nx, g->ny, g->nz, g->h, ex, ey, ez, k2, rhs, phis[s], &so, scratch, o.scratch_bytes,
                       stream, &info);
         if (infos[s]) *infos[s] = info;
         if (st < 0) return st;

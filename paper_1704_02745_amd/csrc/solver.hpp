@@ -9,13 +9,15 @@ namespace pb {
 
 // operator.hip
 pb_status launch_prepare64(const double* ex, const double* ey, const double* ez, const double* k2,
-                           const double* rhs, const double* xin, int warm, const Layout& L, double h,
-                           Op<double> op, double* b, double* x, int* flags, hipStream_t st);
+                           const double* rhs, const double* xin, int warm, int periodic, const Layout& L,
+                           double h, Op<double> op, double* b, double* x, int* flags, hipStream_t st);
 pb_status launch_round32(Op<double> op64, const double* b, const double* x, int64_t npad, Op<float> op32,
                          float* b32, float* x32, hipStream_t st);
 int residual_blocks(const Layout& L);
-pb_status launch_residual64(Op<double> op, const double* b, const double* x, const Layout& L,
+pb_status launch_residual64(Op<double> op, const double* b, const double* x, const Layout& L, int periodic,
                             double* r64, float* r32, double* partials, double* out2, hipStream_t st);
+// v -= mean(v) over the real nodes of a padded FP64 array (fixed-order sum).
+pb_status launch_remove_mean(double* v, const Layout& L, double* partials, double* out2, hipStream_t st);
 pb_status launch_add_correction(double* x, const float* dx, int64_t npad, hipStream_t st);
 pb_status launch_f32_to_f64(const float* a, double* b, int64_t n, hipStream_t st);
 template <typename T>
@@ -29,6 +31,7 @@ struct Tiling {
     int bs;          // threads per workgroup
     int mc;          // 16-byte vector groups per thread per plane (segment = mc*bs*VEC)
     int scheme;      // 0: pass stores A.p (48 B/node FP32); 1: recomputes it (40 B/node)
+    int per;         // 1: periodic-boundary kernel (scheme 0 only)
     size_t lds;      // dynamic LDS bytes
     int seglen;      // elements per segment
     int zchunk;      // planes per tile
@@ -69,7 +72,8 @@ struct SolveResult {
 // jpcg.hip: one persistent cooperative launch running the whole iteration.
 template <typename T>
 pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, double* partials,
-                     double tol, int maxiter, hipStream_t st, SolveResult* res, const Tiling* force);
+                     double tol, int maxiter, hipStream_t st, SolveResult* res, const Tiling* force,
+                     int periodic = 0);
 
 template <typename T>
 Tiling choose_tiling(const Layout& L);

@@ -1,0 +1,154 @@
+"""Periodic boundary on the GPU, through the C ABI, against the periodic
+oracle (oracle/periodic.py) and the exact FFT solution of uniform media."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import periodic, solvation
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def pb():
+    import paper_1704_02745_amd as m
+    return m
+
+
+def _box(n3, seed, natoms=12, h=0.5, wrap=True):
+    """A seeded molecule in a periodic box; with `wrap` some spheres cross the faces."""
+    nx, ny, nz = n3
+    rng = np.random.default_rng(seed)
+    L = np.array([nx, ny, nz]) * h
+    origin = np.array([-0.37, 0.11, -0.23])
+    lo = origin - (1.0 if wrap else -2.5)
+    hi = origin + L + (1.0 if wrap else -2.5)
+    xyz = rng.uniform(lo, hi, size=(natoms, 3))
+    rad = rng.uniform(1.2, 2.0, size=natoms)
+    q = rng.uniform(-0.8, 0.8, size=natoms)
+    q -= q.mean()
+    return synth.Grid(nx, ny, nz, h, origin), xyz, rad, q
+
+
+def _setup(pb, g, xyz, rad, q, kd2, eps_out=80.0):
+    return pb.setup(g, xyz, rad, q, 1.0, eps_out, kd2, device=DEV, want_q=True, want_mask=True,
+                    boundary="periodic")
+
+
+def iters_close(a, b):
+    return abs(a - b) <= max(2, int(0.02 * b))
+
+
+@pytest.mark.parametrize("kd2", [0.0159051, 0.0])
+def test_periodic_setup_matches_oracle(pb, kd2):
+    g, xyz, rad, q = _box((24, 20, 18), 1)
+    sm = _setup(pb, g, xyz, rad, q, kd2)
+    ref, parts = periodic.assemble(g.nx, g.ny, g.nz, g.h, g.origin, xyz, rad, q, 1.0, 80.0, kd2, with_parts=True)
+    assert parts["mask"][0].any() and parts["mask"][-1].any()          # spheres cross the z faces
+    assert np.array_equal(sm.mask.cpu().numpy(), periodic.padded_mask(parts["mask"]))
+    for a, b in ((sm.eps_x, ref.eps_x), (sm.eps_y, ref.eps_y), (sm.eps_z, ref.eps_z), (sm.kappa2, ref.kappa2),
+                 (sm.qgrid, parts["qgrid"])):
+        assert np.array_equal(a.cpu().numpy(), b)
+    b = sm.rhs.cpu().numpy()
+    assert np.abs(b - ref.b).max() <= 1e-12 * np.abs(ref.b).max()
+    if kd2 == 0.0:
+        assert abs(b.sum()) <= 1e-12 * np.abs(b).sum()
+
+
+@pytest.mark.parametrize("kd2", [0.0159051, 0.0])
+@pytest.mark.parametrize("prec,tol,bar", [("f64", 1e-10, 1e-8), ("f32", 1e-6, 2e-5), ("f32_refine64", 1e-10, 1e-8)])
+def test_periodic_solve_matches_oracle(pb, kd2, prec, tol, bar):
+    g, xyz, rad, q = _box((29, 23, 19), 2)
+    sm = _setup(pb, g, xyz, rad, q, kd2)
+    ref = periodic.assemble(g.nx, g.ny, g.nz, g.h, g.origin, xyz, rad, q, 1.0, 80.0, kd2)
+    exact = periodic.jpcg(ref, 1e-13, maxiter=20000)
+    o6 = periodic.jpcg(ref, tol)
+    x, info = pb.solve(sm, tol=tol, precision=prec)
+    xv = x.cpu().numpy()
+    print(f"periodic {prec} kd2={kd2}: iters {info['iters']} (oracle {o6.iters}) relres {info['relres_true']:.2e}",
+          flush=True)
+    assert info["status"] == pb.PB_OK
+    if prec != "f32_refine64":
+        assert iters_close(info["iters"], o6.iters)
+    assert np.abs(xv - exact.x).max() <= bar * np.abs(exact.x).max()
+    assert periodic.true_relres(ref, xv) <= (1e-5 if prec == "f32" else 1e-9)
+    if kd2 == 0.0:
+        assert abs(xv.mean()) <= 1e-12 * np.abs(xv).max()
+
+
+@pytest.mark.parametrize("kbar2", [1.272407, 0.0])
+def test_periodic_uniform_medium_matches_fft(pb, kbar2):
+    """Uniform dielectric and salt: the discrete Fourier transform solves the
+    periodic operator exactly; the GPU solve must agree."""
+    nx, ny, nz, h, eps = 40, 36, 33, 0.5, 80.0
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal((nz, ny, nx))
+    if kbar2 == 0.0:
+        b -= b.mean()
+    ref = periodic.fft_solve(b, h, eps, kbar2)
+    g = pb.make_grid(nx, ny, nz, h, (0.0, 0.0, 0.0), "periodic")
+    opt = dict(dtype=torch.float64, device=DEV)
+    sm = pb.System(g, torch.full((nz, ny, nx + 1), eps, **opt), torch.full((nz, ny + 1, nx), eps, **opt),
+                   torch.full((nz + 1, ny, nx), eps, **opt), torch.full((nz, ny, nx), kbar2, **opt),
+                   torch.as_tensor(b, **opt))
+    # FP32 bar: the condition number here is about (12 eps/h^2 + kbar2)/kbar2 ~ 3e3 with salt, so
+    # FP32 arithmetic (unit roundoff 6e-8) cannot promise better than ~2e-4 in the potential
+    for prec, bar in (("f64", 1e-9), ("f32_refine64", 1e-9), ("f32", 2e-4)):
+        x, info = pb.solve(sm, tol=1e-11 if prec != "f32" else 1e-7, precision=prec)
+        err = np.abs(x.cpu().numpy() - ref).max() / np.abs(ref).max()
+        print(f"fft {prec} kbar2={kbar2}: iters {info['iters']} err {err:.2e}", flush=True)
+        assert err <= bar
+
+
+@pytest.mark.parametrize("dims", [(3, 3, 3), (3, 4, 5), (5, 3, 3), (70, 3, 4), (3, 66, 3), (4, 5, 67), (130, 7, 5)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_periodic_thin_grids(pb, dims, prec):
+    rng = np.random.default_rng(sum(dims))
+    nx, ny, nz = dims
+    e = rng.choice([1.0, 80.0], size=(nz, ny, nx))
+    ep = np.pad(e, 1, mode="wrap")
+    harm = lambda a, b: 2 * a * b / (a + b)
+    ex = harm(ep[1:-1, 1:-1, :-1], ep[1:-1, 1:-1, 1:])
+    ey = harm(ep[1:-1, :-1, 1:-1], ep[1:-1, 1:, 1:-1])
+    ez = harm(ep[:-1, 1:-1, 1:-1], ep[1:, 1:-1, 1:-1])
+    k2 = np.where(e > 1, 1.27, 0.0)
+    b = rng.standard_normal((nz, ny, nx))
+    from oracle import fdpb
+    ref = fdpb.System(h=0.5, eps_x=ex, eps_y=ey, eps_z=ez, kappa2=k2, b=b)
+    exact = periodic.jpcg(ref, 1e-13, maxiter=50000)
+    g = pb.make_grid(nx, ny, nz, 0.5, (0, 0, 0), "periodic")
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=DEV)
+    sm = pb.System(g, T(ex), T(ey), T(ez), T(k2), T(b))
+    x, info = pb.solve(sm, tol=1e-10 if prec == "f64" else 1e-6, precision=prec)
+    err = np.abs(x.cpu().numpy() - exact.x).max() / np.abs(exact.x).max()
+    assert info["status"] == pb.PB_OK and err <= (1e-8 if prec == "f64" else 1e-5), err
+
+
+def test_periodic_energy_and_solvation(pb):
+    g, xyz, rad, q = _box((26, 24, 22), 3)
+    sm = _setup(pb, g, xyz, rad, q, 0.0159051)
+    x, _ = pb.solve(sm, tol=1e-10, precision="f64")
+    e = pb.energy(g, xyz, q, x, boundary="periodic")
+    xs = x.cpu().numpy()
+    e_ref = periodic.energy(g.nx, g.ny, g.nz, g.h, g.origin, xyz, q, xs)
+    assert abs(e - e_ref) <= 1e-12 * abs(e_ref)
+    sol = solvation.solvation_energy(g.nx, g.ny, g.nz, g.h, g.origin, xyz, rad, q, 1.0, 80.0, 0.0159051,
+                                     tol=1e-10, boundary="periodic")
+    r = pb.solvation_energy(g, xyz, rad, q, 1.0, 80.0, 0.0159051, tol=1e-10, precision="f64", boundary="periodic")
+    print(f"periodic dG gpu {r['dG']:.9f} oracle {sol.dG:.9f}", flush=True)
+    assert abs(r["dG"] - sol.dG) <= 1e-7 * abs(sol.dG)
+
+
+def test_periodic_rejections(pb):
+    g, xyz, rad, q = _box((24, 20, 18), 4)
+    sm = _setup(pb, g, xyz, rad, q, 0.0159051)
+    with pytest.raises(pb.PBError) as ei:
+        pb.solve(sm, tol=1e-6, precision="f32", op="dia")
+    assert ei.value.status == pb.PB_ERR_ARG
+    with pytest.raises(pb.PBError) as ei:
+        pb.setup(synth.Grid(2, 5, 5, 0.5, np.zeros(3)), xyz[:1] * 0, rad[:1], q[:1], device=DEV,
+                 boundary="periodic")
+    assert ei.value.status == pb.PB_ERR_ARG

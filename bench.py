@@ -68,9 +68,9 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(prob, n_iters=8):
+def cpu_baseline(prob, n_iters=40):
     """FP64 oracle Jacobi PCG at the full 257^3 size, bounded to n_iters
-    iterations. The sample system uses the oracle's own classification,
+    iterations (about 10-15 s of host work). The sample system uses the oracle's own classification,
     edges, salt term and charges; its boundary values are zero (the boundary
     sum alone would take minutes in NumPy and does not change the iteration
     cost)."""
@@ -110,7 +110,8 @@ def bench_c1(pbgpu, torch, synth, dev, reps=3):
     sm = pbgpu.setup(g, p.mol.xyz, p.mol.radius, p.mol.charge, p.eps_in, p.eps_out, p.kappa_d2, device=dev)
     n = g.nx * g.ny * g.nz
     out = {}
-    sch = pbgpu.get_tuning(g.nx, g.ny, g.nz, "f32")["scheme"]
+    tun = pbgpu.autotune(sm, precision="f32", iters_per_trial=20)   # untimed: this shape's tiling
+    sch = tun["scheme"]
     for op, per in (("stencil", PASS_BYTES_BY_SCHEME[sch]), ("dia", DIA_ITER_BYTES)):
         pbgpu.solve(sm, tol=1e-6, precision="f32", op=op)
         best = None

@@ -749,6 +749,66 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
         if (is_h) vstore(P + (hp - obase), hpo_c);
         if (is_o) vstore(P + (op - obase), o_po);
     }
+    // The global loads of step k depend on k only: p_{l-2} of plane k+2; r,
+    // d, x and the couplings of plane k+1 (own positions and the inner ring);
+    // p_{l-2} of plane k+2 on the outer ring. They are issued one step ahead,
+    // before the previous step's LDS barrier, so their latency overlaps it.
+    struct Ld {
+        V po_n, r_o, d_n, x_n, cx_n, cy_n, cz_n;
+        T cxm_n, cym_n[W];
+        V hpo_n, h_r, h_d, h_cx, h_cy, h_cz;
+        T h_cxm, h_cym[W];
+        V o_po;
+    };
+    auto issue = [&](int k, Ld& L) {
+        const int kn = k + 1, kf = k + 2;
+        const bool v1 = kn >= 0 && kn < nz;
+        const bool v2 = kf >= 0 && kf < nz;
+        const bool own1 = kn >= k0 && kn < k1;
+        const bool xu = own1 && do_x;
+        const int64_t g1 = (int64_t)kn * sp + pos;
+        L.po_n = z0; L.r_o = z0; L.d_n = z0; L.x_n = z0; L.cx_n = z0; L.cy_n = z0; L.cz_n = z0;
+        L.cxm_n = T(0);
+#pragma unroll
+        for (int u = 0; u < W; ++u) L.cym_n[u] = T(0);
+        if (valid) {
+            if (v2) L.po_n = vload(pold + (int64_t)kf * sp + pos);
+            if (v1) {
+                L.r_o = vload(rold + g1);
+                L.d_n = vload(DD + g1);
+                if (xu) L.x_n = vload(a.x + g1);
+                L.cx_n = vload(CX + g1);
+                L.cy_n = vload(CY + g1);
+                L.cz_n = vload(CZ + g1);
+                L.cxm_n = pos >= 1 ? CX[g1 - 1] : T(0);
+#pragma unroll
+                for (int u = 0; u < W; ++u) L.cym_n[u] = (pos + u - nx >= 0) ? CY[g1 + u - nx] : T(0);
+            }
+        }
+        L.hpo_n = z0; L.h_r = z0; L.h_d = z0; L.h_cx = z0; L.h_cy = z0; L.h_cz = z0;
+        L.h_cxm = T(0);
+#pragma unroll
+        for (int u = 0; u < W; ++u) L.h_cym[u] = T(0);
+        if (h_in) {
+            if (v2) L.hpo_n = vload(pold + (int64_t)kf * sp + hp);
+            if (v1) {
+                const int64_t gh = (int64_t)kn * sp + hp;
+                L.h_cz = vload(CZ + gh);
+                if (own1) {
+                    L.h_r = vload(rold + gh);
+                    L.h_d = vload(DD + gh);
+                    L.h_cx = vload(CX + gh);
+                    L.h_cy = vload(CY + gh);
+                    L.h_cxm = hp >= 1 ? CX[gh - 1] : T(0);
+#pragma unroll
+                    for (int u = 0; u < W; ++u) L.h_cym[u] = (hp + u - nx >= 0) ? CY[gh + u - nx] : T(0);
+                }
+            }
+        }
+        L.o_po = (o_in && v2) ? vload(pold + (int64_t)kf * sp + op) : z0;
+    };
+    Ld cur;
+    issue(k0 - 2, cur);
     lds_barrier();
 
     V pn_m = z0, pn_c = z0, rn_c = z0, d_c = z0;   // p_{l-1} on k-1, k; r_{l-1}, d on k (own)
@@ -769,46 +829,12 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
         T* const PNn = (kn & 1) ? PN1 : PN0;
         const int64_t g1 = (int64_t)kn * sp + pos;
 
-        // ---- loads: p_{l-2} of plane k+2; r, d, x and couplings of plane k+1
-        V po_n = z0, r_o = z0, d_n = z0, x_n = z0, cx_n = z0, cy_n = z0, cz_n = z0;
-        T cxm_n = T(0), cym_n[W];
-#pragma unroll
-        for (int u = 0; u < W; ++u) cym_n[u] = T(0);
-        if (valid) {
-            if (v2) po_n = vload(pold + (int64_t)kf * sp + pos);
-            if (v1) {
-                r_o = vload(rold + g1);
-                d_n = vload(DD + g1);
-                if (xu) x_n = vload(a.x + g1);
-                cx_n = vload(CX + g1);
-                cy_n = vload(CY + g1);
-                cz_n = vload(CZ + g1);
-                cxm_n = pos >= 1 ? CX[g1 - 1] : T(0);
-#pragma unroll
-                for (int u = 0; u < W; ++u) cym_n[u] = (pos + u - nx >= 0) ? CY[g1 + u - nx] : T(0);
-            }
-        }
-        V hpo_n = z0, h_r = z0, h_d = z0, h_cx = z0, h_cy = z0, h_cz = z0;
-        T h_cxm = T(0), h_cym[W];
-#pragma unroll
-        for (int u = 0; u < W; ++u) h_cym[u] = T(0);
-        if (h_in) {
-            if (v2) hpo_n = vload(pold + (int64_t)kf * sp + hp);
-            if (v1) {
-                const int64_t gh = (int64_t)kn * sp + hp;
-                h_cz = vload(CZ + gh);
-                if (own1) {
-                    h_r = vload(rold + gh);
-                    h_d = vload(DD + gh);
-                    h_cx = vload(CX + gh);
-                    h_cy = vload(CY + gh);
-                    h_cxm = hp >= 1 ? CX[gh - 1] : T(0);
-#pragma unroll
-                    for (int u = 0; u < W; ++u) h_cym[u] = (hp + u - nx >= 0) ? CY[gh + u - nx] : T(0);
-                }
-            }
-        }
-        const V o_po = (o_in && v2) ? vload(pold + (int64_t)kf * sp + op) : z0;
+        V& po_n = cur.po_n; V& r_o = cur.r_o; V& d_n = cur.d_n; V& x_n = cur.x_n;
+        V& cx_n = cur.cx_n; V& cy_n = cur.cy_n; V& cz_n = cur.cz_n;
+        T& cxm_n = cur.cxm_n; T (&cym_n)[W] = cur.cym_n;
+        V& hpo_n = cur.hpo_n; V& h_r = cur.h_r; V& h_d = cur.h_d; V& h_cx = cur.h_cx; V& h_cy = cur.h_cy;
+        V& h_cz = cur.h_cz; T& h_cxm = cur.h_cxm; T (&h_cym)[W] = cur.h_cym;
+        const V& o_po = cur.o_po;
 
         // ---- q_{l-1}, r_{l-1}, p_{l-1} (and x) on plane k+1, own positions
         V pn_n = z0, rn_n = z0;
@@ -901,7 +927,14 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
         cxm_c = cxm_n;
 #pragma unroll
         for (int u = 0; u < W; ++u) cym_c[u] = cym_n[u];
-        lds_barrier();
+        if (k + 1 < k1) {
+            Ld nxt;
+            issue(k + 1, nxt);
+            lds_barrier();
+            cur = nxt;
+        } else {
+            lds_barrier();
+        }
     }
 }
 

@@ -511,6 +511,68 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
     const int hg = threadIdx.x;
     const int64_t hp = (hg < H / W) ? (s - H + (int64_t)hg * W) : (e + (int64_t)(hg - H / W) * W);
     const bool h_in_range = hg < hgroups && hp >= 0 && hp < sp;
+    // The global loads of step k depend on k only (the next plane's r, q, d,
+    // p_old and x, this thread's halo group of it, the current plane's
+    // couplings); they are issued one step ahead, before the previous step's
+    // LDS barrier, so their latency overlaps it.
+    struct Ld {
+        V in_r[MC], in_q[MC], in_d[MC], in_po[MC], in_x[MC];
+        V cxv[MC], cyv[MC], czv[MC];
+        T cxm[MC], cym[MC][W];
+        T cxw[W], cyw[W];   // periodic: wrap couplings of plane k
+        V h_r, h_q, h_d, h_po;
+    };
+    auto issue = [&](int k, Ld& L) {
+        const bool has_next = PER || k + 1 < a.nz;
+        const int kn = (PER && k + 1 == a.nz) ? 0 : k + 1;
+        const bool owned = k + 1 < k1;
+        const bool x_upd = owned && do_x;
+#pragma unroll
+        for (int c = 0; c < MC; ++c) {
+            L.in_r[c] = L.in_q[c] = L.in_po[c] = L.in_x[c] = z0;
+            L.in_d[c] = z0;
+            L.cxv[c] = L.cyv[c] = L.czv[c] = z0;
+            L.cxm[c] = T(0);
+#pragma unroll
+            for (int u = 0; u < W; ++u) L.cym[c][u] = T(0);
+            if (!valid[c]) continue;
+            if (has_next) {
+                const int64_t g1 = (int64_t)kn * sp + pos[c];
+                L.in_r[c] = vload(rold + g1);
+                L.in_q[c] = vload(qold + g1);
+                L.in_d[c] = vload(a.op.d + g1);
+                L.in_po[c] = vload(pold + g1);
+                if (x_upd) L.in_x[c] = vload(a.x + g1);
+            }
+            const int64_t g = (int64_t)k * sp + pos[c];
+            L.cxv[c] = vload(a.op.cx + g);
+            L.cyv[c] = vload(a.op.cy + g);
+            L.czv[c] = vload(a.op.cz + g);
+            L.cxm[c] = pos[c] >= 1 ? a.op.cx[g - 1] : T(0);
+#pragma unroll
+            for (int u = 0; u < W; ++u) L.cym[c][u] = (pos[c] + u - nx >= 0) ? a.op.cy[g + u - nx] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < W; ++u) L.cxw[u] = L.cyw[u] = T(0);
+        if constexpr (PER) {
+            const int64_t g = (int64_t)k * sp + pos[0];
+#pragma unroll
+            for (int u = 0; u < W; ++u) {
+                L.cxw[u] = ((wl >> u) & 1u) ? a.op.cx[g + u + nx - 1] : T(0);
+                L.cyw[u] = ((wd >> u) & 1u) ? a.op.cy[g + u + yspan] : T(0);
+            }
+        }
+        L.h_r = L.h_q = L.h_d = L.h_po = z0;
+        if (has_next && owned && h_in_range) {
+            const int64_t gh = (int64_t)(k + 1) * sp + hp;
+            L.h_r = vload(rold + gh);
+            L.h_q = vload(qold + gh);
+            L.h_d = vload(a.op.d + gh);
+            L.h_po = vload(pold + gh);
+        }
+    };
+    Ld ldc;
+    issue(k0, ldc);
     for (int k = k0; k < k1; ++k) {
         const T* cur = (k & 1) ? lds1 : lds0;
         T* nxt = (k & 1) ? lds0 : lds1;
@@ -518,50 +580,14 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
         const int kn = (PER && k + 1 == a.nz) ? 0 : k + 1;   // the next plane (wrapped when periodic)
         const bool owned = k + 1 < k1;
         const bool x_upd = owned && do_x;
-        // ---- loads
-        V in_r[MC], in_q[MC], in_d[MC], in_po[MC], in_x[MC];
-        V cxv[MC], cyv[MC], czv[MC];
-        T cxm[MC], cym[MC][W];
-        T cxw[W], cyw[W], pwn[W];   // periodic: wrap couplings of plane k, partners of the next plane
-#pragma unroll
-        for (int c = 0; c < MC; ++c) {
-            in_r[c] = in_q[c] = in_po[c] = in_x[c] = z0;
-            in_d[c] = z0;
-            if (!valid[c]) continue;
-            if (has_next) {
-                const int64_t g1 = (int64_t)kn * sp + pos[c];
-                in_r[c] = vload(rold + g1);
-                in_q[c] = vload(qold + g1);
-                in_d[c] = vload(a.op.d + g1);
-                in_po[c] = vload(pold + g1);
-                if (x_upd) in_x[c] = vload(a.x + g1);
-            }
-            const int64_t g = (int64_t)k * sp + pos[c];
-            cxv[c] = vload(a.op.cx + g);
-            cyv[c] = vload(a.op.cy + g);
-            czv[c] = vload(a.op.cz + g);
-            cxm[c] = pos[c] >= 1 ? a.op.cx[g - 1] : T(0);
-#pragma unroll
-            for (int u = 0; u < W; ++u) cym[c][u] = (pos[c] + u - nx >= 0) ? a.op.cy[g + u - nx] : T(0);
-        }
-        if constexpr (PER) {
-            const int64_t g = (int64_t)k * sp + pos[0];
-#pragma unroll
-            for (int u = 0; u < W; ++u) {
-                cxw[u] = ((wl >> u) & 1u) ? a.op.cx[g + u + nx - 1] : T(0);
-                cyw[u] = ((wd >> u) & 1u) ? a.op.cy[g + u + yspan] : T(0);
-            }
-            partners(kn, pwn);
-        }
-        V h_r = z0, h_q = z0, h_d = z0, h_po = z0;
-        const bool h_load = has_next && owned && h_in_range;
-        if (h_load) {
-            const int64_t gh = (int64_t)(k + 1) * sp + hp;
-            h_r = vload(rold + gh);
-            h_q = vload(qold + gh);
-            h_d = vload(a.op.d + gh);
-            h_po = vload(pold + gh);
-        }
+        V (&in_r)[MC] = ldc.in_r; V (&in_q)[MC] = ldc.in_q; V (&in_d)[MC] = ldc.in_d;
+        V (&in_po)[MC] = ldc.in_po; V (&in_x)[MC] = ldc.in_x;
+        const V (&cxv)[MC] = ldc.cxv; const V (&cyv)[MC] = ldc.cyv; const V (&czv)[MC] = ldc.czv;
+        const T (&cxm)[MC] = ldc.cxm; const T (&cym)[MC][W] = ldc.cym;
+        const T (&cxw)[W] = ldc.cxw; const T (&cyw)[W] = ldc.cyw;
+        const V& h_r = ldc.h_r; const V& h_q = ldc.h_q; const V& h_d = ldc.h_d; const V& h_po = ldc.h_po;
+        T pwn[W];   // periodic: the y-wrap partners of the next plane
+        if constexpr (PER) partners(kn, pwn);
         // ---- next plane: new p (own and halo), r_{l-1}, x update
         V rn[MC], dn[MC];
 #pragma unroll
@@ -660,7 +686,14 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
 #pragma unroll
             for (int u = 0; u < W; ++u) pw[u] = pwn[u];
         }
-        lds_barrier();
+        if (k + 1 < k1) {
+            Ld ldn;
+            issue(k + 1, ldn);
+            lds_barrier();
+            ldc = ldn;
+        } else {
+            lds_barrier();
+        }
     }
 }
 

@@ -739,6 +739,10 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
     T* const PO1 = lds + lo_len;
     T* const PN0 = lds + 2 * lo_len;
     T* const PN1 = PN0 + ln_len;
+    T* const CX0 = PN1 + ln_len;   // x/y couplings of a plane over the segment +- halo
+    T* const CX1 = CX0 + ln_len;
+    T* const CY0 = CX1 + ln_len;
+    T* const CY1 = CY0 + ln_len;
     const int64_t obase = s - 2 * H, nbase = s - H;
     const T* __restrict__ rold = o ? a.r[1] : a.r[0];
     const T* __restrict__ pold = o ? a.p[1] : a.p[0];
@@ -763,11 +767,14 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
     const int64_t op = (og < H / W) ? (s - 2 * H + (int64_t)og * W) : (e + H + (int64_t)(og - H / W) * W);
     const bool o_in = is_o && op >= 0 && op < sp;
 
-    // state at the start of step k (k = k0-2 first)
-    V po_m, po_c;     // p_{l-2}, planes k and k+1 (own)
-    V hpo_m, hpo_c;   // p_{l-2}, planes k and k+1 (inner ring position)
+    // State at the start of step k (k = k0-2 first): p_{l-2} of planes k and
+    // k+1 lives in the two p_old LDS slots (plane k until the step's end),
+    // p_{l-1} of plane k in its LDS slot, the couplings of plane k in the
+    // coupling slots; in registers stay cz of plane k (own, ring), and p_{l-1},
+    // r_{l-1}, d of the planes the z-stencil and the sums need.
     V cz_c, hcz_c;    // cz on plane k (own, ring)
     {
+        V po_m, po_c, hpo_m, hpo_c;
         const int km = k0 - 2, kc = k0 - 1;
         const bool vm = km >= 0, vc = kc >= 0;
         po_m = (valid && vm) ? vload(pold + (int64_t)km * sp + pos) : z0;
@@ -781,6 +788,9 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
         if (valid) vstore(P + (pos - obase), po_c);
         if (is_h) vstore(P + (hp - obase), hpo_c);
         if (is_o) vstore(P + (op - obase), o_po);
+        T* Pm = (km & 1) ? PO1 : PO0;
+        if (valid) vstore(Pm + (pos - obase), po_m);
+        if (is_h) vstore(Pm + (hp - obase), hpo_m);
     }
     // The global loads of step k depend on k only: p_{l-2} of plane k+2; r,
     // d, x and the couplings of plane k+1 (own positions and the inner ring);
@@ -844,11 +854,8 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
     issue(k0 - 2, cur);
     lds_barrier();
 
-    V pn_m = z0, pn_c = z0, rn_c = z0, d_c = z0;   // p_{l-1} on k-1, k; r_{l-1}, d on k (own)
-    V cx_c = z0, cy_c = z0, cz_m = z0;             // couplings of plane k; cz of plane k-1
-    T cxm_c = T(0), cym_c[W];
-#pragma unroll
-    for (int u = 0; u < W; ++u) cym_c[u] = T(0);
+    V pn_m = z0, rn_c = z0, d_c = z0;   // p_{l-1} on k-1; r_{l-1}, d on k (own)
+    V cz_m = z0;                        // cz of plane k-1
 
     for (int k = k0 - 2; k < k1; ++k) {
         const int kn = k + 1, kf = k + 2;
@@ -860,7 +867,13 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
         T* const POn = (kf & 1) ? PO1 : PO0;
         const T* const PNc = (k & 1) ? PN1 : PN0;
         T* const PNn = (kn & 1) ? PN1 : PN0;
+        const T* const CXc = (k & 1) ? CX1 : CX0;
+        const T* const CYc = (k & 1) ? CY1 : CY0;
+        T* const CXn = (kn & 1) ? CX1 : CX0;
+        T* const CYn = (kn & 1) ? CY1 : CY0;
         const int64_t g1 = (int64_t)kn * sp + pos;
+        const V po_c = valid ? vload(POc + (pos - obase)) : z0;    // p_{l-2}, plane k+1
+        const V po_m = valid ? vload(POn + (pos - obase)) : z0;    // p_{l-2}, plane k
 
         V& po_n = cur.po_n; V& r_o = cur.r_o; V& d_n = cur.d_n; V& x_n = cur.x_n;
         V& cx_n = cur.cx_n; V& cy_n = cur.cy_n; V& cz_n = cur.cz_n;
@@ -898,6 +911,8 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
         if (is_h && own1) {
             V hv = z0;
             if (h_in) {
+                const V hpo_c = vload(POc + (hp - obase));
+                const V hpo_m = vload(POn + (hp - obase));
                 const int64_t l = hp - obase;
                 const T left = POc[l - 1], right = POc[l + W];
 #pragma unroll
@@ -915,17 +930,21 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
             vstore(PNn + (hp - nbase), hv);
         }
         // ---- q_l = A p_{l-1} on plane k and the partial sums
+        // p_{l-1} of plane k (own): the z-neighbour of the next step's q_l
+        // (its LDS slot was written at step k-1; zero below the grid)
+        const V pn_c = (valid && k >= k0 - 1 && k >= 0) ? vload(PNc + (pos - nbase)) : z0;
         if (k >= k0 && valid) {
             const int64_t l = pos - nbase;
+            const V cxv = vload(CXc + l), cyv = vload(CYc + l);
             const T left = PNc[l - 1], right = PNc[l + W];
 #pragma unroll
             for (int u = 0; u < W; ++u) {
                 const T p = vget(pn_c, u);
                 const T pr = (u == W - 1) ? right : vget(pn_c, u + 1);
                 const T pl = (u == 0) ? left : vget(pn_c, u - 1);
-                const T cl = (u == 0) ? cxm_c : vget(cx_c, u - 1);
-                const T qq = apply_point(vget(d_c, u), p, vget(cx_c, u), pr, cl, pl, vget(cy_c, u), PNc[l + u + nx],
-                                         cym_c[u], PNc[l + u - nx], vget(cz_c, u), vget(pn_n, u), vget(cz_m, u),
+                const T cl = (u == 0) ? CXc[l - 1] : vget(cxv, u - 1);
+                const T qq = apply_point(vget(d_c, u), p, vget(cxv, u), pr, cl, pl, vget(cyv, u), PNc[l + u + nx],
+                                         CYc[l + u - nx], PNc[l + u - nx], vget(cz_c, u), vget(pn_n, u), vget(cz_m, u),
                                          vget(pn_m, u));
                 const T iv = jacobi_inv(vget(d_c, u));
                 const double pd = (double)p, qd = (double)qq, rd = (double)vget(rn_c, u);
@@ -939,27 +958,26 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
                 acc[6] += qd * qd;
             }
         }
-        // ---- p_{l-2} of plane k+2 into LDS for the next step
-        if (valid) vstore(POn + (pos - obase), po_n);
-        if (is_h) vstore(POn + (hp - obase), hpo_n);
+        // ---- p_{l-2} of plane k+2 and the couplings of plane k+1 into LDS
+        // for the next step (the p_old slot of plane k is free from here on)
+        if (valid) {
+            vstore(POn + (pos - obase), po_n);
+            vstore(CXn + (pos - nbase), cx_n);
+            vstore(CYn + (pos - nbase), cy_n);
+        }
+        if (is_h) {
+            vstore(POn + (hp - obase), hpo_n);
+            vstore(CXn + (hp - nbase), h_cx);
+            vstore(CYn + (hp - nbase), h_cy);
+        }
         if (is_o) vstore(POn + (op - obase), o_po);
         // ---- advance one plane
-        po_m = po_c;
-        po_c = po_n;
-        hpo_m = hpo_c;
-        hpo_c = hpo_n;
         hcz_c = h_cz;
         pn_m = pn_c;
-        pn_c = pn_n;
         rn_c = rn_n;
         d_c = d_n;
         cz_m = cz_c;
         cz_c = cz_n;
-        cx_c = cx_n;
-        cy_c = cy_n;
-        cxm_c = cxm_n;
-#pragma unroll
-        for (int u = 0; u < W; ++u) cym_c[u] = cym_n[u];
         if (k + 1 < k1) {
             Ld nxt;
             issue(k + 1, nxt);
@@ -1201,11 +1219,11 @@ int balanced_seglen(const Layout& L, int cap) {
 }
 
 // Dynamic LDS of one workgroup: two planes of p over the segment +- halo
-// (48-byte pass); two planes of p_old over the segment +- 2 halo and two of p
-// over the segment +- halo (40-byte pass).
+// (48-byte pass); two planes of p_old over the segment +- 2 halo, and two
+// planes each of p, cx and cy over the segment +- halo (40-byte pass).
 template <typename T>
 size_t lds_bytes(int scheme, int seglen, int halo) {
-    const size_t elems = scheme == 1 ? 2 * (size_t)(seglen + 4 * halo) + 2 * (size_t)(seglen + 2 * halo)
+    const size_t elems = scheme == 1 ? 2 * (size_t)(seglen + 4 * halo) + 6 * (size_t)(seglen + 2 * halo)
                                      : 2 * (size_t)(seglen + 2 * halo);
     return sizeof(T) * elems;
 }

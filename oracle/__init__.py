@@ -14,5 +14,6 @@ Modules:
           solve on the same grid (the energies of section 3.1).
   periodic - the periodic-boundary setup, operator and energy (section 2.7's
           alternative boundary), with an exact FFT solver for uniform media.
+  multigrid - geometric-multigrid-preconditioned CG on the same operator.
 """
-from . import fdpb, pcg, periodic, solvation  # noqa: F401
+from . import fdpb, multigrid, pcg, periodic, solvation  # noqa: F401

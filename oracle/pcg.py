@@ -36,6 +36,22 @@ def pcg(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray,
         callback: Optional[Callable[[int, np.ndarray], None]] = None) -> PCGResult:
     """Solve A x = b. `m_diag` is the Jacobi preconditioner diag(A) (section
     2.4); None means M = I (plain CG)."""
+    minv = None if m_diag is None else 1.0 / np.asarray(m_diag, np.float64).ravel()
+    solve_m = (lambda r: r * minv) if minv is not None else (lambda r: r.copy())
+    return _pcg(apply_A, b, solve_m, tol, maxiter, x0, callback)
+
+
+def pcg_general(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray,
+                apply_Minv: Callable[[np.ndarray], np.ndarray], tol: float, maxiter: int,
+                x0: Optional[np.ndarray] = None) -> PCGResult:
+    """The same listing with z = M^-1 r given by a function of r (a fixed
+    symmetric positive definite preconditioner, e.g. a multigrid cycle)."""
+    shape = b.shape
+    return _pcg(apply_A, b, lambda r: np.asarray(apply_Minv(r.reshape(shape)), np.float64).ravel(),
+                tol, maxiter, x0, None)
+
+
+def _pcg(apply_A, b, solve_m, tol, maxiter, x0, callback) -> PCGResult:
     shape = b.shape
     b = np.asarray(b, np.float64).ravel()
     bnorm = float(np.linalg.norm(b))
@@ -43,12 +59,11 @@ def pcg(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray,
         return PCGResult(np.zeros(shape), 0, 0.0, True)
     x = np.zeros_like(b) if x0 is None else np.array(x0, np.float64).ravel()
     Ax = lambda v: np.asarray(apply_A(v.reshape(shape)), np.float64).ravel()
-    minv = None if m_diag is None else 1.0 / np.asarray(m_diag, np.float64).ravel()
 
     # step 1: l = 0, r_0 = b - A x_0
     r = b - Ax(x) if x0 is not None else b.copy()
     # step 2: solve M z_0 = r_0, p_0 = z_0
-    z = r * minv if minv is not None else r.copy()
+    z = solve_m(r)
     p = z.copy()
     rz = float(np.dot(r, z))
     l = 0
@@ -72,7 +87,7 @@ def pcg(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray,
         x = x + alpha * p
         r = r - alpha * q
         # step 6: solve M z_l = r_l
-        z = r * minv if minv is not None else r.copy()
+        z = solve_m(r)
         # step 7: beta and the new direction
         rz_new = float(np.dot(r, z))
         beta = rz_new / rz

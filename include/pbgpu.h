@@ -57,7 +57,11 @@ typedef enum {
 
 typedef enum {
     PB_OP_STENCIL = 0,      /* matrix-free stencil fused into one persistent JPCG kernel */
-    PB_OP_DIA = 1           /* 7-diagonal (DIA) SpMV and separate vector kernels, host-driven loop */
+    PB_OP_DIA = 1,          /* 7-diagonal (DIA) SpMV and separate vector kernels, host-driven loop */
+    PB_OP_MG = 2            /* CG preconditioned by one geometric-multigrid V-cycle instead of diag(A)
+                               (free-space boundary): vertex coarsening by two, coarse edge
+                               dielectrics by series/transverse averaging, trilinear transfer,
+                               damped-Jacobi smoothing; iterations nearly independent of n */
 } pb_operator;
 
 typedef enum {

@@ -27,7 +27,7 @@ PB_ERR_NOMEM, PB_ERR_HIP, PB_ERR_TIMEOUT = -4, -5, -6
 STATUS_NAMES = {0: "PB_OK", 1: "PB_NOT_CONVERGED", -1: "PB_ERR_ARG", -2: "PB_ERR_BREAKDOWN",
                 -3: "PB_ERR_NONFINITE", -4: "PB_ERR_NOMEM", -5: "PB_ERR_HIP", -6: "PB_ERR_TIMEOUT"}
 PRECISIONS = {"f64": 0, "f32": 1, "f32_refine64": 2}
-OPERATORS = {"stencil": 0, "dia": 1}
+OPERATORS = {"stencil": 0, "dia": 1, "mg": 2}
 
 # Every entry point declared in include/pbgpu.h.
 EXPORTS = ("pb_version", "pb_last_error", "pb_setup_workspace_bytes", "pb_setup",

@@ -22,9 +22,10 @@ ARCH = os.environ.get("PBGPU_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
-# Setup arithmetic must round exactly as written (no fused multiply-add).
-PER_FILE = {"setup.hip": ["-ffp-contract=off"]}
-SOURCES = ["api.hip", "setup.hip", "operator.hip", "jpcg.hip", "dia.hip", "batch.hip", "server.hip", "solvation.hip"]
+# Setup arithmetic and the multigrid coarsening must round exactly as written
+# (no fused multiply-add).
+PER_FILE = {"setup.hip": ["-ffp-contract=off"], "mg.hip": ["-ffp-contract=off"]}
+SOURCES = ["api.hip", "setup.hip", "operator.hip", "jpcg.hip", "dia.hip", "batch.hip", "server.hip", "solvation.hip", "mg.hip"]
 
 
 def _hipcc() -> str:

@@ -32,6 +32,10 @@ struct SolveWs {
     // FP32 state (PB_F32, PB_F32_REFINE64)
     SolveBufs<float> s32;
     SyncState* dia_sync;
+    void* mg;             // multigrid levels (PB_OP_MG)
+    // the caller's arrays (level 0 of the multigrid hierarchy)
+    double h;
+    const double *ex, *ey, *ez, *k2;
     size_t bytes;
 };
 
@@ -68,6 +72,8 @@ SolveWs carve_solve(void* base, const Layout& L, int prec, int op) {
         if (op == PB_OP_DIA) {
             s.z = (double*)take(n8);
             s.dia = (double*)take(7 * n8);
+        } else if (op == PB_OP_MG) {
+            s.z = (double*)take(n8);
         } else {
             s.r2 = (double*)take(n8);
             s.q2 = (double*)take(n8);
@@ -87,18 +93,21 @@ SolveWs carve_solve(void* base, const Layout& L, int prec, int op) {
         if (op == PB_OP_DIA) {
             s.z = (float*)take(n4);
             s.dia = (float*)take(7 * n4);
+        } else if (op == PB_OP_MG) {
+            s.z = (float*)take(n4);
         } else {
             s.r2 = (float*)take(n4);
             s.q2 = (float*)take(n4);
         }
     }
+    if (op == PB_OP_MG) w.mg = take(mg_workspace_bytes(L, prec));
     w.bytes = off;
     return w;
 }
 
 bool opts_ok(const pb_solve_opts* o) {
     return o && std::isfinite(o->tol) && o->tol > 0 && o->precision >= PB_F64 &&
-           o->precision <= PB_F32_REFINE64 && (o->op == PB_OP_STENCIL || o->op == PB_OP_DIA) &&
+           o->precision <= PB_F32_REFINE64 && (o->op == PB_OP_STENCIL || o->op == PB_OP_DIA || o->op == PB_OP_MG) &&
            o->inner_tol >= 0 && o->inner_tol < 1 && o->max_outer >= 0 &&
            (o->boundary == PB_BOUNDARY_FREE || (o->boundary == PB_BOUNDARY_PERIODIC && o->op == PB_OP_STENCIL));
 }
@@ -111,6 +120,8 @@ template <typename T>
 pb_status run_inner(const Layout& L, const SolveBufs<T>& s, const SolveWs& w, int op, int periodic, double tol,
                     int maxiter, hipStream_t st, SolveResult* r) {
     if (op == PB_OP_DIA) return dia_jpcg_impl<T>(L, s, w.dia_sync, w.partials, tol, maxiter, st, r);
+    if (op == PB_OP_MG)
+        return mg_pcg_impl<T>(L, w.h, w.ex, w.ey, w.ez, w.k2, s, w.mg, w.dia_sync, w.partials, tol, maxiter, st, r);
     return fused_jpcg<T>(L, s, w.sync, w.partials, tol, maxiter, st, r, nullptr, periodic);
 }
 
@@ -243,6 +254,8 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
         set_error("pb_solve: workspace of %zu bytes, %zu needed", workspace_bytes, w.bytes);
         return PB_ERR_NOMEM;
     }
+    w.h = h;
+    w.ex = eps_x; w.ey = eps_y; w.ez = eps_z; w.k2 = kappa2;
     const int maxiter = opts->maxiter > 0 ? opts->maxiter : 10 * std::max(nx, std::max(ny, nz));
     const int per = opts->boundary == PB_BOUNDARY_PERIODIC ? 1 : 0;
     PB_ARG(!per || (nx >= 3 && ny >= 3 && nz >= 3), "pb_solve: the periodic boundary needs nx, ny, nz >= 3");

@@ -78,6 +78,14 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
 template <typename T>
 Tiling choose_tiling(const Layout& L);
 
+// mg.hip: multigrid-preconditioned CG (workspace for the coarse levels and
+// level 0's extra vectors; ex..k2 are the caller's FP64 edge arrays).
+size_t mg_workspace_bytes(const Layout& L0, int prec);
+template <typename T>
+pb_status mg_pcg_impl(const Layout& L0, double h, const double* ex, const double* ey, const double* ez,
+                      const double* k2, const SolveBufs<T>& s, void* mgws, SyncState* S, double* partials,
+                      double tol, int maxiter, hipStream_t st, SolveResult* res);
+
 // Tiling restricted to a block size / vector-group count (0 = any) and a
 // cap on workgroups per CU (0 = occupancy limit).
 template <typename T>

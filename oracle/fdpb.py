@@ -121,6 +121,81 @@ def dielectric_edges(mask: np.ndarray, eps_in: float, eps_out: float):
     return eps_x, eps_y, eps_z
 
 
+def edge_inside_fraction(nx, ny, nz, h, origin, xyz, radius, axis):
+    """Fraction of each staggered edge of direction `axis` (0 x, 1 y, 2 z)
+    that lies inside the union of the atom spheres, edges indexed as the
+    staggered arrays (entry e joins nodes e-1 and e along the axis; -1 and n
+    are ghosts). For a sphere (c, R) and the edge's line, d2 = sum of the
+    squared offsets across the line (in axis order); if d2 < R*R the sphere
+    covers the line parameter t in [((c_a - w) - x0)/h, ((c_a + w) - x0)/h],
+    w = sqrt(R*R - d2), x0 the edge's first node coordinate along the axis.
+    The intervals clipped to [0, 1] are sorted by start, merged, and their
+    lengths summed in that order."""
+    o = np.asarray(origin, np.float64)
+    dims = (nx, ny, nz)
+    shape = [nz, ny, nx]
+    shape[2 - axis] += 1
+    frac = np.zeros(shape)
+    recs = {}
+    for c, R in zip(np.asarray(xyz, np.float64), np.asarray(radius, np.float64)):
+        RR = R * R
+        rng = []
+        for d in range(3):
+            lo = int(math.floor((c[d] - R - o[d]) / h)) - 1
+            hi = int(math.ceil((c[d] + R - o[d]) / h)) + 1
+            if d == axis:   # edge index e: first node e-1 in [-1, n-1]
+                rng.append(range(max(lo + 1, 0), min(hi + 1, dims[d]) + 1))
+            else:           # node index in [0, n-1]
+                rng.append(range(max(lo, 0), min(hi, dims[d] - 1) + 1))
+        for k in rng[2]:
+            for j in rng[1]:
+                for i in rng[0]:
+                    idx = [i, j, k]
+                    node = [float(v) for v in idx]
+                    node[axis] -= 1.0     # the edge's first node
+                    p = [o[d] + h * node[d] for d in range(3)]
+                    d2 = 0.0
+                    for d in range(3):
+                        if d != axis:
+                            dd = p[d] - c[d]
+                            d2 = d2 + dd * dd
+                    if not d2 < RR:
+                        continue
+                    w = math.sqrt(RR - d2)
+                    t0 = ((c[axis] - w) - p[axis]) / h
+                    t1 = ((c[axis] + w) - p[axis]) / h
+                    t0 = max(t0, 0.0)
+                    t1 = min(t1, 1.0)
+                    if t1 > t0:
+                        recs.setdefault((k, j, i), []).append((t0, t1))
+    for key, iv in recs.items():
+        iv.sort()
+        total = 0.0
+        s0, s1 = iv[0]
+        for a, b in iv[1:]:
+            if a > s1:
+                total = total + (s1 - s0)
+                s0, s1 = a, b
+            elif b > s1:
+                s1 = b
+        total = total + (s1 - s0)
+        frac[key] = total
+    return frac
+
+
+def fractional_edges(nx, ny, nz, h, origin, xyz, radius, eps_in, eps_out):
+    """Weighted harmonic edge dielectric (the fractional-edge reading of
+    section 2.7): 1 / (f/eps_in + (1-f)/eps_out) with f the inside fraction
+    of the edge; exactly eps_out at f = 0 and eps_in at f = 1."""
+    out = []
+    for axis in range(3):
+        f = edge_inside_fraction(nx, ny, nz, h, origin, xyz, radius, axis)
+        e = 1.0 / (f / eps_in + (1.0 - f) / eps_out)
+        e = np.where(f == 0.0, eps_out, np.where(f == 1.0, eps_in, e))
+        out.append(e)
+    return tuple(out)
+
+
 def salt_term(mask: np.ndarray, eps_out: float, kappa_d2: float) -> np.ndarray:
     """kbar^2 per node: eps_out * kappa_D^2 outside the solute, 0 inside."""
     inner = mask[1:-1, 1:-1, 1:-1]
@@ -228,10 +303,15 @@ def debye_huckel_ghosts(nx, ny, nz, h, origin, xyz, charge, eps_out, kappa_d2):
 
 
 def assemble(nx, ny, nz, h, origin, xyz, radius, charge, eps_in, eps_out,
-             kappa_d2, with_parts=False):
-    """Full setup: classification, edges, salt, charges, boundary -> System."""
+             kappa_d2, with_parts=False, edge_model="node"):
+    """Full setup: classification, edges, salt, charges, boundary -> System.
+    edge_model "node": two-point harmonic mean of the node values;
+    "fraction": the fractional-edge weighted harmonic mean."""
     mask = classify(nx, ny, nz, h, origin, xyz, radius)
-    ex, ey, ez = dielectric_edges(mask, eps_in, eps_out)
+    if edge_model == "fraction":
+        ex, ey, ez = fractional_edges(nx, ny, nz, h, origin, xyz, radius, eps_in, eps_out)
+    else:
+        ex, ey, ez = dielectric_edges(mask, eps_in, eps_out)
     k2 = salt_term(mask, eps_out, kappa_d2)
     q = spread_charges(nx, ny, nz, h, origin, xyz, charge)
     ghost = debye_huckel_ghosts(nx, ny, nz, h, origin, xyz, charge, eps_out, kappa_d2)

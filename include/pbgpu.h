@@ -147,6 +147,44 @@ pb_status pb_setup(const pb_grid* grid, int64_t natoms,
                    double* kappa2, double* rhs, double* qgrid, uint8_t* mask,
                    void* workspace, size_t workspace_bytes, void* stream);
 
+typedef enum {
+    PB_EDGE_NODE = 0,       /* two-point harmonic mean of the endpoint node dielectrics (pb_setup) */
+    PB_EDGE_FRACTION = 1    /* weighted harmonic mean 1/(f/eps_in + (1-f)/eps_out), f the fraction of
+                               the edge inside the union of the spheres (section 2.7's "weighted
+                               harmonic average" taken over the edge; free-space boundary) */
+} pb_edge_model;
+
+typedef struct {
+    int32_t edge_model;     /* pb_edge_model */
+    int32_t reserved[7];    /* zero */
+} pb_setup_opts;
+
+/* Device workspace needed by pb_setup_ex. Returns 0 for invalid arguments. */
+size_t pb_setup_ex_workspace_bytes(const pb_grid* grid, int64_t natoms, const pb_setup_opts* opts);
+
+/*
+ * pb_setup_ex: pb_setup with options. With PB_EDGE_FRACTION each edge
+ * dielectric is 1/(f/eps_in + (1-f)/eps_out), where f is the fraction of the
+ * edge segment (between its two nodes, ghosts included) inside the union of
+ * the atom spheres: each sphere covers the chord where the squared distance
+ * across the edge's line is below R^2; the chords clipped to the edge are
+ * merged (overlapping or touching pieces join) and their lengths summed in
+ * increasing order; f = 0 gives eps_out and f = 1 eps_in exactly. Node
+ * classification, the salt term, charges and the boundary are as pb_setup.
+ * Errors as pb_setup, and PB_ERR_ARG for invalid options, the fractional
+ * model with the periodic boundary, or more than 16 separate inside pieces
+ * on one edge.
+ * Status: the device path of PB_EDGE_FRACTION is switched off; this call
+ * returns PB_ERR_ARG for it before launching anything (pb_last_error says
+ * so). PB_EDGE_NODE is unaffected.
+ */
+pb_status pb_setup_ex(const pb_grid* grid, int64_t natoms,
+                      const double* xyz, const double* radius, const double* charge,
+                      double eps_in, double eps_out, double kappa_d2, const pb_setup_opts* opts,
+                      double* eps_x, double* eps_y, double* eps_z,
+                      double* kappa2, double* rhs, double* qgrid, uint8_t* mask,
+                      void* workspace, size_t workspace_bytes, void* stream);
+
 /*
  * Device workspace needed by pb_solve for this grid and option set
  * (precision and operator). Returns 0 for invalid arguments.

@@ -38,7 +38,8 @@ EXPORTS = ("pb_version", "pb_last_error", "pb_setup_workspace_bytes", "pb_setup"
            "pb_server_request_bytes", "pb_server_create", "pb_server_submit", "pb_server_step",
            "pb_server_stats", "pb_server_destroy",
            "pb_energy_workspace_bytes", "pb_energy",
-           "pb_solvation_workspace_bytes", "pb_solvation_energy")
+           "pb_solvation_workspace_bytes", "pb_solvation_energy",
+           "pb_setup_ex_workspace_bytes", "pb_setup_ex")
 
 
 class PBError(RuntimeError):
@@ -51,6 +52,13 @@ class Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("boundary", ctypes.c_int32), ("h", ctypes.c_double),
                 ("origin", ctypes.c_double * 3)]
+
+
+class SetupOpts(ctypes.Structure):
+    _fields_ = [("edge_model", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+EDGE_MODELS = {"node": 0, "fraction": 1}
 
 
 class SolveOpts(ctypes.Structure):
@@ -155,6 +163,11 @@ def _load():
     lib.pb_energy_workspace_bytes.argtypes = [i64]
     lib.pb_energy.restype = ctypes.c_int
     lib.pb_energy.argtypes = [G, i64, vp, vp, vp, vp, ctypes.POINTER(dbl), vp, sz, vp]
+    lib.pb_setup_ex_workspace_bytes.restype = sz
+    lib.pb_setup_ex_workspace_bytes.argtypes = [G, i64, ctypes.POINTER(SetupOpts)]
+    lib.pb_setup_ex.restype = ctypes.c_int
+    lib.pb_setup_ex.argtypes = [G, i64, vp, vp, vp, dbl, dbl, dbl, ctypes.POINTER(SetupOpts), vp, vp, vp, vp, vp, vp,
+                                vp, vp, sz, vp]
     lib.pb_solvation_workspace_bytes.restype = sz
     lib.pb_solvation_workspace_bytes.argtypes = [G, i64, ctypes.POINTER(SolveOpts)]
     lib.pb_solvation_energy.restype = ctypes.c_int
@@ -234,9 +247,11 @@ class System:
 
 
 def setup(grid, xyz, radius, charge, eps_in=1.0, eps_out=80.0, kappa_d2=0.0,
-          device="cuda", want_q=False, want_mask=False, stream=None, boundary=None) -> System:
-    """Build the system of Eq. 3 on the device (pb_setup); boundary "free"
-    (default, or the grid's own) or "periodic"."""
+          device="cuda", want_q=False, want_mask=False, stream=None, boundary=None,
+          edge_model="node") -> System:
+    """Build the system of Eq. 3 on the device (pb_setup_ex); boundary "free"
+    (default, or the grid's own) or "periodic"; edge_model "node" (two-point
+    harmonic mean) or "fraction" (weighted by the inside fraction of each edge)."""
     g = as_grid(grid, boundary)
     nx, ny, nz = g.nx, g.ny, g.nz
     xyz_t = _dev64(xyz, device).reshape(-1)
@@ -251,13 +266,15 @@ def setup(grid, xyz, radius, charge, eps_in=1.0, eps_out=80.0, kappa_d2=0.0,
     b = torch.empty((nz, ny, nx), **opt)
     qg = torch.empty((nz, ny, nx), **opt) if want_q else None
     mk = torch.empty((nz + 2, ny + 2, nx + 2), dtype=torch.uint8, device=device) if want_mask else None
-    wsb = lib.pb_setup_workspace_bytes(ctypes.byref(g), natoms)
+    so = SetupOpts()
+    so.edge_model = EDGE_MODELS[edge_model]
+    wsb = lib.pb_setup_ex_workspace_bytes(ctypes.byref(g), natoms, ctypes.byref(so))
     if wsb == 0:
-        raise PBError(PB_ERR_ARG, "pb_setup_workspace_bytes rejected the grid / atom count")
+        raise PBError(PB_ERR_ARG, "pb_setup_ex_workspace_bytes rejected the grid / atom count / options")
     ws = torch.empty(wsb, dtype=torch.uint8, device=device)
-    st = lib.pb_setup(ctypes.byref(g), natoms, _ptr(xyz_t), _ptr(rad_t), _ptr(q_t), float(eps_in),
-                      float(eps_out), float(kappa_d2), _ptr(ex), _ptr(ey), _ptr(ez), _ptr(k2), _ptr(b),
-                      _ptr(qg), _ptr(mk), _ptr(ws), wsb, _stream(stream))
+    st = lib.pb_setup_ex(ctypes.byref(g), natoms, _ptr(xyz_t), _ptr(rad_t), _ptr(q_t), float(eps_in),
+                         float(eps_out), float(kappa_d2), ctypes.byref(so), _ptr(ex), _ptr(ey), _ptr(ez), _ptr(k2),
+                         _ptr(b), _ptr(qg), _ptr(mk), _ptr(ws), wsb, _stream(stream))
     _check(st)
     return System(g, ex, ey, ez, k2, b, qg, mk)
 

@@ -459,11 +459,23 @@ __device__ __forceinline__ void ghost_point(int64_t t, int nx, int ny, int nz, d
 // point and sums over all atoms in index order; atoms are staged in LDS.
 // This is the arithmetic-bound part of setup (6 n^2 points x natoms terms).
 constexpr int kDhBlock = 256;
+// 1/sqrt(r2) for r2 > 0: the hardware estimate and two Newton steps,
+// y <- y (1 + (1 - r2 y^2)/2), each roughly doubling the correct bits.
+__device__ __forceinline__ double rsqrt_nr(double r2) {
+    double y = __builtin_amdgcn_rsq(r2);
+    y = fma(0.5 * y, fma(-(r2 * y), y, 1.0), y);
+    y = fma(0.5 * y, fma(-(r2 * y), y, 1.0), y);
+    return y;
+}
+
+// Screened Coulomb sum of every atom at each ghost-face point, atoms in
+// index order through LDS records (x, y, z, q): phi = (1/eps_out) sum q e^(-kd)/d.
+// Ghost points lie one node outside the box and atoms inside it, so d >= h > 0.
 __global__ __launch_bounds__(kDhBlock) void k_dh_faces(
         const double* __restrict__ xyz, const double* __restrict__ charge, int64_t natoms,
         int nx, int ny, int nz, double h, double ox, double oy, double oz,
         double kd, double eout, double* __restrict__ ghost, int64_t nghost) {
-    __shared__ double sx[kDhBlock], sy[kDhBlock], sz[kDhBlock], sq[kDhBlock];
+    __shared__ double4 sa[kDhBlock];
     const int64_t t = (int64_t)blockIdx.x * kDhBlock + threadIdx.x;
     double px = 0, py = 0, pz = 0;
     if (t < nghost) ghost_point(t, nx, ny, nz, h, ox, oy, oz, px, py, pz);
@@ -471,29 +483,29 @@ __global__ __launch_bounds__(kDhBlock) void k_dh_faces(
     for (int64_t a0 = 0; a0 < natoms; a0 += kDhBlock) {
         __syncthreads();
         const int64_t a = a0 + threadIdx.x;
-        if (a < natoms) {
-            sx[threadIdx.x] = xyz[3 * a];
-            sy[threadIdx.x] = xyz[3 * a + 1];
-            sz[threadIdx.x] = xyz[3 * a + 2];
-            sq[threadIdx.x] = charge[a];
-        }
+        if (a < natoms) sa[threadIdx.x] = make_double4(xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2], charge[a]);
         __syncthreads();
         const int m = (int)min<int64_t>(kDhBlock, natoms - a0);
         if (kd == 0.0) {
+#pragma unroll 4
             for (int b = 0; b < m; ++b) {
-                const double dx = px - sx[b], dy = py - sy[b], dz = pz - sz[b];
-                const double d = sqrt(dx * dx + dy * dy + dz * dz);
-                s = s + sq[b] / (eout * d);
+                const double4 c = sa[b];
+                const double dx = px - c.x, dy = py - c.y, dz = pz - c.z;
+                const double y = rsqrt_nr(dx * dx + dy * dy + dz * dz);
+                s = fma(c.w, y, s);
             }
         } else {
+#pragma unroll 4
             for (int b = 0; b < m; ++b) {
-                const double dx = px - sx[b], dy = py - sy[b], dz = pz - sz[b];
-                const double d = sqrt(dx * dx + dy * dy + dz * dz);
-                s = s + sq[b] * exp(-kd * d) / (eout * d);
+                const double4 c = sa[b];
+                const double dx = px - c.x, dy = py - c.y, dz = pz - c.z;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const double y = rsqrt_nr(r2);
+                s = fma(c.w * exp(-kd * (r2 * y)), y, s);
             }
         }
     }
-    if (t < nghost) ghost[t] = s;
+    if (t < nghost) ghost[t] = s / eout;
 }
 
 // Right-hand side: 4*pi*q/h^3 plus, for nodes on the box faces, the ghost

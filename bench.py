@@ -296,7 +296,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched (config 3) and served (config 4) measurements")
     ap.add_argument("--tuning", default="",
-                    help="block,groups,zchunk,grid,scheme: use this tiling instead of autotuning (profiled runs)")
+                    help="block,groups,zchunk,grid,scheme[,streaming]: use this tiling instead of autotuning "
+                         "(profiled runs; streaming 1/0 = nontemporal/cached, default the shape's own)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one untimed 512 MiB device copy first (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -346,8 +347,8 @@ def main():
         del src, dst
     # untimed: pick the fused kernel's tiling for this grid shape
     if args.tuning:
-        bl, gr, zc, gd, sc = (int(v) for v in args.tuning.split(","))
-        pbgpu.set_tuning(g.nx, g.ny, g.nz, "f32", bl, gr, zc, gd, sc)
+        tv = [int(v) for v in args.tuning.split(",")]
+        pbgpu.set_tuning(g.nx, g.ny, g.nz, "f32", *tv[:5], streaming=tv[5] if len(tv) > 5 else -1)
         tuning = dict(pbgpu.get_tuning(g.nx, g.ny, g.nz, "f32"), us_per_iter=None, candidates=0)
     else:
         sys0 = pbgpu.setup(g, xyz, rad, chg, prob.eps_in, prob.eps_out, prob.kappa_d2, device=dev)
@@ -378,7 +379,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic, 0),
-                "kernel": f"k_jpcg_fused<float, {tuning['block']}, {tuning['groups']}, {scheme}, false> (persistent, "
+                "kernel": f"k_jpcg_fused<float, {tuning['block']}, {tuning['groups']}, {scheme}, false, "
+                          f"{'true' if tuning.get('streaming') else 'false'}> (persistent, "
                           f"one launch per inner solve; algorithmic {ITER_BYTES} B/unknown/iteration, this pass "
                           f"form moves {PASS_BYTES_BY_SCHEME[scheme]} B)",
                 "bytes_per_launch": round(total_bytes / launches, 0),

@@ -81,7 +81,7 @@ class Info(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("groups", ctypes.c_int32), ("zchunk", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("us_per_iter", ctypes.c_double),
-                ("candidates", ctypes.c_int32), ("scheme", ctypes.c_int32)]
+                ("candidates", ctypes.c_int32), ("scheme", ctypes.c_int32), ("streaming", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -332,12 +332,13 @@ def autotune(sysm: System, precision="f32", iters_per_trial=20,
     return t.as_dict()
 
 
-def set_tuning(nx, ny, nz, precision, block, groups, zchunk, grid, scheme=0) -> None:
+def set_tuning(nx, ny, nz, precision, block, groups, zchunk, grid, scheme=0, streaming=-1) -> None:
     """Record a tiling of the fused kernel for this grid shape and precision;
-    scheme 0 is the pass that stores A.p, 1 the 40-byte pass that recomputes it."""
+    scheme 0 is the pass that stores A.p, 1 the 40-byte pass that recomputes it;
+    streaming 1 / 0 selects nontemporal / cached accesses, -1 the shape's default."""
     t = Tuning()
     t.block, t.groups, t.zchunk, t.grid = int(block), int(groups), int(zchunk), int(grid)
-    t.scheme = int(scheme)
+    t.scheme, t.streaming = int(scheme), int(streaming)
     _check(lib.pb_set_tuning(int(nx), int(ny), int(nz), PRECISIONS[precision], ctypes.byref(t)))
 
 

@@ -212,6 +212,7 @@ pb_status autotune_impl(const Layout& L, const SolveBufs<T>& s, const SolveWs& w
         best->block = best_t.bs;
         best->groups = best_t.mc;
         best->scheme = best_t.scheme;
+        best->streaming = best_t.nt;
         best->zchunk = best_t.zchunk;
         best->grid = best_t.grid;
         best->us_per_iter = best_us;
@@ -406,6 +407,7 @@ extern "C" pb_status pb_get_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t p
     t.zchunk = c.zchunk;
     t.grid = c.grid;
     t.scheme = c.scheme;
+    t.streaming = c.nt;
     *out = t;
     return PB_OK;
 }
@@ -428,6 +430,7 @@ extern "C" pb_status pb_tiling_candidates(int32_t nx, int32_t ny, int32_t nz, in
         t.us_per_iter = 0.0;
         t.candidates = (int32_t)c.size();
         t.scheme = c[i].scheme;
+        t.streaming = c[i].nt;
         out[i] = t;
     }
     return PB_OK;
@@ -437,17 +440,20 @@ extern "C" pb_status pb_set_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t p
     PB_ARG(dims_ok(nx, ny, nz) && t, "pb_set_tuning: bad dims or null tuning");
     PB_ARG(precision >= PB_F64 && precision <= PB_F32_REFINE64, "pb_set_tuning: bad precision");
     const Layout L = make_layout(nx, ny, nz);
+    PB_ARG(t->streaming >= -1 && t->streaming <= 1, "pb_set_tuning: streaming must be -1, 0 or 1");
     auto apply = [&](auto tag) -> pb_status {
         using T = decltype(tag);
+        const int nt = t->streaming >= 0 ? t->streaming : streaming_for<T>(L);
         for (const Tiling& c : tiling_candidates<T>(L)) {
-            if (c.bs == t->block && c.mc == t->groups && c.scheme == t->scheme && c.zchunk == t->zchunk &&
-                c.grid == t->grid) {
+            if (c.bs == t->block && c.mc == t->groups && c.scheme == t->scheme && c.nt == nt &&
+                c.zchunk == t->zchunk && c.grid == t->grid) {
                 record_tiling<T>(L, c);
                 return PB_OK;
             }
         }
-        set_error("pb_set_tuning: (block %d, groups %d, scheme %d, zchunk %d, grid %d) is not a feasible tiling here",
-                  t->block, t->groups, t->scheme, t->zchunk, t->grid);
+        set_error("pb_set_tuning: (block %d, groups %d, scheme %d, streaming %d, zchunk %d, grid %d) is not a "
+                  "feasible tiling here",
+                  t->block, t->groups, t->scheme, t->streaming, t->zchunk, t->grid);
         return PB_ERR_ARG;
     };
     return precision == PB_F64 ? apply(double{}) : apply(float{});

@@ -240,6 +240,43 @@ template <typename T>
 __device__ __forceinline__ void vstore(T* p, const typename Vec<T>::type& v) {
     *reinterpret_cast<typename Vec<T>::type*>(p) = v;
 }
+// Streaming forms of vload/vstore with the nontemporal hint. The passes use
+// them (kernel variants with NT = true) for the own-position streams that
+// nothing reads again within the step: r, p_old, d, cz, x (and q in the
+// 48-byte pass) loads; r, p, x (and q) stores. Once the arrays of a pass are
+// larger than the last-level cache this is faster on gfx950, even though
+// neighbouring tiles re-read the outer rows of these streams as their halo;
+// below that size the cached forms win, since the arrays then stay in the
+// cache from one iteration to the next. cx and cy are always cached: the x-1
+// and y-1 couplings re-read them within the step.
+typedef float f4_nt __attribute__((ext_vector_type(4)));
+typedef double d2_nt __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float4 vload_nt(const float* p) {
+    const f4_nt t = __builtin_nontemporal_load(reinterpret_cast<const f4_nt*>(p));
+    return make_float4(t.x, t.y, t.z, t.w);
+}
+__device__ __forceinline__ double2 vload_nt(const double* p) {
+    const d2_nt t = __builtin_nontemporal_load(reinterpret_cast<const d2_nt*>(p));
+    return make_double2(t.x, t.y);
+}
+__device__ __forceinline__ void vstore_nt(float* p, const float4& v) {
+    const f4_nt t = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(t, reinterpret_cast<f4_nt*>(p));
+}
+__device__ __forceinline__ void vstore_nt(double* p, const double2& v) {
+    const d2_nt t = {v.x, v.y};
+    __builtin_nontemporal_store(t, reinterpret_cast<d2_nt*>(p));
+}
+template <bool NT, typename T>
+__device__ __forceinline__ typename Vec<T>::type sload(const T* p) {
+    if constexpr (NT) return vload_nt(p);
+    else return vload(p);
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void sstore(T* p, const typename Vec<T>::type& v) {
+    if constexpr (NT) vstore_nt(p, v);
+    else vstore(p, v);
+}
 // Jacobi scaling 1/d: the hardware reciprocal in FP32 (about 1 ulp), an
 // exact division in FP64. Every use of M^-1 in a solve goes through this one
 // function, so the preconditioner is the same fixed positive diagonal in the
@@ -356,7 +393,7 @@ __device__ void init_tile(const KArgs<T>& a, int tile, bool with_q, double (&acc
 // LDS row, across the y ends from p recomputed pointwise at the partner node
 // of the far row (one plane ahead, with the other loads), across the z ends
 // from the wrapped plane of the march.
-template <typename T, int BS, int MC, bool PER>
+template <typename T, int BS, int MC, bool PER, bool NT>
 __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T beta, T* lds0, T* lds1,
                           double (&acc)[NPART]) {
     static_assert(!PER || MC == 1, "the periodic pass takes one vector group per thread");
@@ -538,16 +575,16 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
             if (!valid[c]) continue;
             if (has_next) {
                 const int64_t g1 = (int64_t)kn * sp + pos[c];
-                L.in_r[c] = vload(rold + g1);
-                L.in_q[c] = vload(qold + g1);
-                L.in_d[c] = vload(a.op.d + g1);
-                L.in_po[c] = vload(pold + g1);
-                if (x_upd) L.in_x[c] = vload(a.x + g1);
+                L.in_r[c] = sload<NT>(rold + g1);
+                L.in_q[c] = sload<NT>(qold + g1);
+                L.in_d[c] = sload<NT>(a.op.d + g1);
+                L.in_po[c] = sload<NT>(pold + g1);
+                if (x_upd) L.in_x[c] = sload<NT>(a.x + g1);
             }
             const int64_t g = (int64_t)k * sp + pos[c];
             L.cxv[c] = vload(a.op.cx + g);
             L.cyv[c] = vload(a.op.cy + g);
-            L.czv[c] = vload(a.op.cz + g);
+            L.czv[c] = sload<NT>(a.op.cz + g);
             L.cxm[c] = pos[c] >= 1 ? a.op.cx[g - 1] : T(0);
 #pragma unroll
             for (int u = 0; u < W; ++u) L.cym[c][u] = (pos[c] + u - nx >= 0) ? a.op.cy[g + u - nx] : T(0);
@@ -605,11 +642,11 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
             }
             if (owned) {
                 vstore(nxt + (pos[c] - lbase), pn[c]);
-                vstore(rnew + g1, rn[c]);
+                sstore<NT>(rnew + g1, rn[c]);
                 if (x_upd) {
 #pragma unroll
                     for (int u = 0; u < W; ++u) vget(in_x[c], u) = vget(in_x[c], u) + alpha * vget(in_po[c], u);
-                    vstore(a.x + g1, in_x[c]);
+                    sstore<NT>(a.x + g1, in_x[c]);
                 }
             }
         }
@@ -671,8 +708,8 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
                 acc[5] += rd * qd;
                 acc[6] += qd * qd;
             }
-            vstore(pnew + g, pc[c]);
-            vstore(qnew + g, qv);
+            sstore<NT>(pnew + g, pc[c]);
+            sstore<NT>(qnew + g, qv);
             czm[c] = czv[c];
         }
 #pragma unroll
@@ -725,7 +762,7 @@ __device__ __forceinline__ T apply_point(T d, T v, T cr, T vr, T cl, T vl, T cu,
 // build planes k0-1 and k0 of p_{l-1}. Threads: own positions s + tid*VEC,
 // inner ring groups on the first 2*halo/VEC threads, outer ring groups on the
 // last 2*halo/VEC threads (the tiling guarantees 2*halo/VEC <= BS).
-template <typename T, int BS>
+template <typename T, int BS, bool NT>
 __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, T beta, T* lds,
                             double (&acc)[NPART]) {
     constexpr int W = Vec<T>::n;
@@ -815,14 +852,14 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
 #pragma unroll
         for (int u = 0; u < W; ++u) L.cym_n[u] = T(0);
         if (valid) {
-            if (v2) L.po_n = vload(pold + (int64_t)kf * sp + pos);
+            if (v2) L.po_n = sload<NT>(pold + (int64_t)kf * sp + pos);
             if (v1) {
-                L.r_o = vload(rold + g1);
-                L.d_n = vload(DD + g1);
-                if (xu) L.x_n = vload(a.x + g1);
+                L.r_o = sload<NT>(rold + g1);
+                L.d_n = sload<NT>(DD + g1);
+                if (xu) L.x_n = sload<NT>(a.x + g1);
                 L.cx_n = vload(CX + g1);
                 L.cy_n = vload(CY + g1);
-                L.cz_n = vload(CZ + g1);
+                L.cz_n = sload<NT>(CZ + g1);
                 L.cxm_n = pos >= 1 ? CX[g1 - 1] : T(0);
 #pragma unroll
                 for (int u = 0; u < W; ++u) L.cym_n[u] = (pos + u - nx >= 0) ? CY[g1 + u - nx] : T(0);
@@ -902,9 +939,9 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
             }
             vstore(PNn + (pos - nbase), pn_n);
             if (own1) {
-                vstore(rnew + g1, rn_n);
-                vstore(pnew + g1, pn_n);
-                if (xu) vstore(a.x + g1, x_n);
+                sstore<NT>(rnew + g1, rn_n);
+                sstore<NT>(pnew + g1, pn_n);
+                if (xu) sstore<NT>(a.x + g1, x_n);
             }
         }
         // ---- the same on the inner ring (LDS only; needed on owned planes)
@@ -1023,7 +1060,7 @@ struct Scal {
 // Every workgroup derives the scalars (alpha, beta, stopping test) itself
 // from the identically reduced tile sums; workgroup 0 also persists them in
 // S for the host and for a resumed launch.
-template <typename T, int BS, int MC, int SCH, bool PER>
+template <typename T, int BS, int MC, int SCH, bool PER, bool NT>
 __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsigned char* lds_raw) {
     static_assert(SCH == 0 || MC == 1, "the 40-byte pass takes one vector group per thread");
     static_assert(!PER || SCH == 0, "the periodic boundary uses the pass that stores A.p");
@@ -1083,9 +1120,9 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
         for (int t = first; t < end; t += stride) {
             double acc[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             if constexpr (SCH == 1)
-                pass_tile40<T, BS>(a, t, o, n, alpha, beta, lds0, acc);
+                pass_tile40<T, BS, NT>(a, t, o, n, alpha, beta, lds0, acc);
             else
-                pass_tile<T, BS, MC, PER>(a, t, o, n, alpha, beta, lds0, lds1, acc);
+                pass_tile<T, BS, MC, PER, NT>(a, t, o, n, alpha, beta, lds0, lds1, acc);
             tile_reduce_store<BS, NPART>(acc, red, sums(b) + (size_t)t * kMaxPartials);
         }
         double v[NPART];
@@ -1132,17 +1169,17 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
     }
 }
 
-template <typename T, int BS, int MC, int SCH, bool PER>
+template <typename T, int BS, int MC, int SCH, bool PER, bool NT>
 __global__ __launch_bounds__(BS) void k_jpcg_fused(KArgs<T> a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    run_problem<T, BS, MC, SCH, PER>(a, blockIdx.x, gridDim.x, true, lds_raw);
+    run_problem<T, BS, MC, SCH, PER, NT>(a, blockIdx.x, gridDim.x, true, lds_raw);
 }
 
 // Many independent problems in one launch: workgroups [first[p], first[p+1])
 // solve problem p with their own barrier state; problems never wait for
 // each other, and each problem's tiling and reduction order depend only on
 // its own shape.
-template <typename T, int BS, int MC>
+template <typename T, int BS, int MC, bool NT>
 __global__ __launch_bounds__(BS) void k_jpcg_batch(const KArgs<T>* __restrict__ probs,
                                                    const int* __restrict__ first, int nprob) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1152,7 +1189,7 @@ __global__ __launch_bounds__(BS) void k_jpcg_batch(const KArgs<T>* __restrict__ 
         if (first[mid] <= (int)blockIdx.x) lo = mid; else hi = mid;
     }
     const KArgs<T> a = probs[lo];
-    run_problem<T, BS, MC, 0, false>(a, blockIdx.x - first[lo], first[lo + 1] - first[lo], false, lds_raw);
+    run_problem<T, BS, MC, 0, false, NT>(a, blockIdx.x - first[lo], first[lo + 1] - first[lo], false, lds_raw);
 }
 
 // ------------------------------------------------------------------ host side
@@ -1182,21 +1219,29 @@ DevInfo dev_info() {
 using KernelFn = const void*;
 
 struct Variant {
-    int bs, mc, scheme, per;
+    int bs, mc, scheme, per, nt;
     KernelFn fn;
 };
 
 template <typename T>
 const std::vector<Variant>& variants() {
     static const std::vector<Variant> v = {
-        {256, 1, 0, 0, (KernelFn)k_jpcg_fused<T, 256, 1, 0, false>},
-        {256, 2, 0, 0, (KernelFn)k_jpcg_fused<T, 256, 2, 0, false>},
-        {512, 1, 0, 0, (KernelFn)k_jpcg_fused<T, 512, 1, 0, false>},
-        {512, 2, 0, 0, (KernelFn)k_jpcg_fused<T, 512, 2, 0, false>},
-        {256, 1, 1, 0, (KernelFn)k_jpcg_fused<T, 256, 1, 1, false>},
-        {512, 1, 1, 0, (KernelFn)k_jpcg_fused<T, 512, 1, 1, false>},
-        {256, 1, 0, 1, (KernelFn)k_jpcg_fused<T, 256, 1, 0, true>},
-        {512, 1, 0, 1, (KernelFn)k_jpcg_fused<T, 512, 1, 0, true>},
+        {256, 1, 0, 0, 0, (KernelFn)k_jpcg_fused<T, 256, 1, 0, false, false>},
+        {256, 2, 0, 0, 0, (KernelFn)k_jpcg_fused<T, 256, 2, 0, false, false>},
+        {512, 1, 0, 0, 0, (KernelFn)k_jpcg_fused<T, 512, 1, 0, false, false>},
+        {512, 2, 0, 0, 0, (KernelFn)k_jpcg_fused<T, 512, 2, 0, false, false>},
+        {256, 1, 1, 0, 0, (KernelFn)k_jpcg_fused<T, 256, 1, 1, false, false>},
+        {512, 1, 1, 0, 0, (KernelFn)k_jpcg_fused<T, 512, 1, 1, false, false>},
+        {256, 1, 0, 1, 0, (KernelFn)k_jpcg_fused<T, 256, 1, 0, true, false>},
+        {512, 1, 0, 1, 0, (KernelFn)k_jpcg_fused<T, 512, 1, 0, true, false>},
+        {256, 1, 0, 0, 1, (KernelFn)k_jpcg_fused<T, 256, 1, 0, false, true>},
+        {256, 2, 0, 0, 1, (KernelFn)k_jpcg_fused<T, 256, 2, 0, false, true>},
+        {512, 1, 0, 0, 1, (KernelFn)k_jpcg_fused<T, 512, 1, 0, false, true>},
+        {512, 2, 0, 0, 1, (KernelFn)k_jpcg_fused<T, 512, 2, 0, false, true>},
+        {256, 1, 1, 0, 1, (KernelFn)k_jpcg_fused<T, 256, 1, 1, false, true>},
+        {512, 1, 1, 0, 1, (KernelFn)k_jpcg_fused<T, 512, 1, 1, false, true>},
+        {256, 1, 0, 1, 1, (KernelFn)k_jpcg_fused<T, 256, 1, 0, true, true>},
+        {512, 1, 0, 1, 1, (KernelFn)k_jpcg_fused<T, 512, 1, 0, true, true>},
     };
     return v;
 }
@@ -1245,6 +1290,7 @@ Tiling tiling_for(const Layout& L, const Variant& v, int cus, int max_per_cu) {
     t.bs = v.bs;
     t.scheme = v.scheme;
     t.per = v.per;
+    t.nt = v.nt;
     t.seglen = balanced_seglen<T>(L, v.mc * v.bs * W);
     t.halo = halo_for<T>(L.nx);
     if (2 * t.halo / W > v.bs) return t;   // halo groups must fit one per thread
@@ -1267,24 +1313,36 @@ Tiling tiling_for(const Layout& L, const Variant& v, int cus, int max_per_cu) {
     return t;
 }
 
+// Streaming (nontemporal) variants are the default once the arrays one pass
+// touches (about 12 per node: r, p and q in two copies, x, d, cx, cy, cz)
+// exceed the last-level cache, 256 MiB of Infinity Cache on MI355X.
+constexpr double kLastLevelCacheBytes = 256.0 * 1024 * 1024;
+template <typename T>
+int streaming_default(const Layout& L) {
+    return (double)L.sp * L.nz * sizeof(T) * 12.0 > kLastLevelCacheBytes ? 1 : 0;
+}
+
 template <typename T>
 Tiling choose_tiling_impl(const Layout& L, int want_bs, int want_mc, int max_per_cu, int want_scheme = -1,
-                          int want_per = 0) {
+                          int want_per = 0, int want_nt = -1) {
     const DevInfo di = dev_info();
     const int cus = di.cus > 0 ? di.cus : 256;
+    if (want_nt < 0) want_nt = streaming_default<T>(L);
     Tiling best{};
     double best_cost = 1e300;
     for (const auto& v : variants<T>()) {
         if ((want_bs > 0 && v.bs != want_bs) || (want_mc > 0 && v.mc != want_mc)) continue;
         if (want_scheme >= 0 && v.scheme != want_scheme) continue;
-        if (v.per != want_per) continue;
+        if (v.per != want_per || v.nt != want_nt) continue;
         Tiling t = tiling_for<T>(L, v, cus, max_per_cu);
         if (t.grid <= 0) continue;
         // model: bytes of one tile (planes incl. the extra ones below, segment
-        // incl. halo work) plus a per-workgroup barrier cost
-        const double cost = t.scheme == 1 ? 40.0 * (t.zchunk + 2) * (t.seglen + 1.5 * t.halo) + 1920.0 * t.grid
-                                          : 48.0 * (t.zchunk + 1) * (t.seglen + t.halo) + 1920.0 * t.grid;
-        if (cost < best_cost) {
+        // incl. halo work) times the tiles that share a CU, plus a
+        // per-workgroup barrier cost; ties go to one vector group per thread
+        const double tile = t.scheme == 1 ? 40.0 * (t.zchunk + 2) * (t.seglen + 1.5 * t.halo)
+                                          : 48.0 * (t.zchunk + 1) * (t.seglen + t.halo);
+        const double cost = tile * ((t.grid + cus - 1) / cus) + 1920.0 * t.grid;
+        if (cost < best_cost || (cost == best_cost && t.mc < best.mc)) {
             best_cost = cost;
             best = t;
         }
@@ -1324,20 +1382,21 @@ void record_tiling(const Layout& L, const Tiling& t) {
 template void record_tiling<float>(const Layout&, const Tiling&);
 template void record_tiling<double>(const Layout&, const Tiling&);
 
-// Every distinct feasible tiling over block sizes, vector groups and
-// workgroups-per-CU caps (the autotuner's search space).
+// Every distinct feasible tiling over block sizes, vector groups, pass forms,
+// cached and streaming accesses and workgroups-per-CU caps (the autotuner's
+// search space).
 template <typename T>
 std::vector<Tiling> tiling_candidates(const Layout& L) {
     std::vector<Tiling> out;
     for (const auto& v : variants<T>()) {
         if (v.per) continue;   // periodic solves use their own default tiling
         for (int cap : {1, 2, 3, 4, 0}) {
-            const Tiling t = choose_tiling_impl<T>(L, v.bs, v.mc, cap, v.scheme);
+            const Tiling t = choose_tiling_impl<T>(L, v.bs, v.mc, cap, v.scheme, 0, v.nt);
             if (t.grid <= 0) continue;
             bool dup = false;
             for (const auto& u : out)
-                dup = dup || (u.bs == t.bs && u.mc == t.mc && u.scheme == t.scheme && u.grid == t.grid &&
-                              u.zchunk == t.zchunk);
+                dup = dup || (u.bs == t.bs && u.mc == t.mc && u.scheme == t.scheme && u.nt == t.nt &&
+                              u.grid == t.grid && u.zchunk == t.zchunk);
             if (!dup) out.push_back(t);
         }
     }
@@ -1347,6 +1406,13 @@ template std::vector<Tiling> tiling_candidates<float>(const Layout&);
 template std::vector<Tiling> tiling_candidates<double>(const Layout&);
 template Tiling choose_tiling<float>(const Layout&);
 template Tiling choose_tiling<double>(const Layout&);
+
+template <typename T>
+int streaming_for(const Layout& L) {
+    return streaming_default<T>(L);
+}
+template int streaming_for<float>(const Layout&);
+template int streaming_for<double>(const Layout&);
 
 template <typename T>
 Tiling tiling_with(const Layout& L, int bs, int mc, int max_per_cu) {
@@ -1366,10 +1432,10 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
     }
     KernelFn fn = nullptr;
     for (const auto& v : variants<T>())
-        if (v.bs == t.bs && v.mc == t.mc && v.scheme == t.scheme && v.per == t.per) fn = v.fn;
+        if (v.bs == t.bs && v.mc == t.mc && v.scheme == t.scheme && v.per == t.per && v.nt == t.nt) fn = v.fn;
     if (!fn) {
-        set_error("fused JPCG: unknown kernel variant bs=%d mc=%d scheme=%d periodic=%d", t.bs, t.mc, t.scheme,
-                  t.per);
+        set_error("fused JPCG: unknown kernel variant bs=%d mc=%d scheme=%d periodic=%d streaming=%d", t.bs, t.mc,
+                  t.scheme, t.per, t.nt);
         return PB_ERR_ARG;
     }
     const DevInfo di = dev_info();
@@ -1439,6 +1505,7 @@ namespace {
 constexpr int kBatchBS = 256;
 constexpr int kBatchMC = 1;
 constexpr int kBatchZ = 16;
+constexpr bool kBatchNT = false;
 }  // namespace
 
 // Tiling used for a problem inside a batch: a fixed kernel variant and
@@ -1458,6 +1525,7 @@ Tiling batch_tiling(const Layout& L) {
     t.nzc = (L.nz + t.zchunk - 1) / t.zchunk;
     t.ntiles = t.nseg * t.nzc;
     t.scheme = 0;
+    t.nt = kBatchNT ? 1 : 0;
     t.lds = lds_bytes<T>(0, t.seglen, t.halo);
     return t;
 }
@@ -1506,7 +1574,7 @@ template void batch_fill_kargs<double>(void*, const Layout&, const SolveBufs<dou
 template <typename T>
 int batch_capacity(size_t lds) {
     const DevInfo di = dev_info();
-    const int per_cu = max_coresident((KernelFn)k_jpcg_batch<T, kBatchBS, kBatchMC>, kBatchBS, lds);
+    const int per_cu = max_coresident((KernelFn)k_jpcg_batch<T, kBatchBS, kBatchMC, kBatchNT>, kBatchBS, lds);
     return per_cu * (di.cus > 0 ? di.cus : 256);
 }
 template int batch_capacity<float>(size_t);
@@ -1537,11 +1605,11 @@ pb_status batch_launch(const void* d_kargs, const int* d_first, int nprob, int g
     void* args[] = {&kp, &d_first, &nprob};
     hipError_t e;
     if (cooperative)
-        e = hipLaunchCooperativeKernel((const void*)k_jpcg_batch<T, kBatchBS, kBatchMC>, dim3(grid), dim3(kBatchBS),
-                                       args, lds, st);
+        e = hipLaunchCooperativeKernel((const void*)k_jpcg_batch<T, kBatchBS, kBatchMC, kBatchNT>, dim3(grid),
+                                       dim3(kBatchBS), args, lds, st);
     else
-        e = hipLaunchKernel((const void*)k_jpcg_batch<T, kBatchBS, kBatchMC>, dim3(grid), dim3(kBatchBS), args, lds,
-                            st);
+        e = hipLaunchKernel((const void*)k_jpcg_batch<T, kBatchBS, kBatchMC, kBatchNT>, dim3(grid), dim3(kBatchBS),
+                            args, lds, st);
     if (e != hipSuccess) {
         set_error("batch JPCG launch failed: %s (grid %d, lds %zu)", hipGetErrorString(e), grid, lds);
         return PB_ERR_HIP;

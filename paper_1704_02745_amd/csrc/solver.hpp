@@ -32,6 +32,7 @@ struct Tiling {
     int mc;          // 16-byte vector groups per thread per plane (segment = mc*bs*VEC)
     int scheme;      // 0: pass stores A.p (48 B/node FP32); 1: recomputes it (40 B/node)
     int per;         // 1: periodic-boundary kernel (scheme 0 only)
+    int nt;          // 1: streaming (nontemporal) accesses for the own-position streams
     size_t lds;      // dynamic LDS bytes
     int seglen;      // elements per segment
     int zchunk;      // planes per tile
@@ -77,6 +78,9 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
 
 template <typename T>
 Tiling choose_tiling(const Layout& L);
+// 1 when the shape's default is the streaming (nontemporal) kernel variant.
+template <typename T>
+int streaming_for(const Layout& L);
 
 // mg.hip: multigrid-preconditioned CG (workspace for the coarse levels and
 // level 0's extra vectors; ex..k2 are the caller's FP64 edge arrays).

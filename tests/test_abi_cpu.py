@@ -39,8 +39,9 @@ def test_struct_layouts(pbgpu):
     assert ctypes.sizeof(pbgpu.Info) == 48
     assert pbgpu.SolveOpts.inner_tol.offset == 24
     assert pbgpu.Info.relres_recur.offset == 16
-    assert ctypes.sizeof(pbgpu.Tuning) == 32
+    assert ctypes.sizeof(pbgpu.Tuning) == 40
     assert pbgpu.Tuning.us_per_iter.offset == 16 and pbgpu.Tuning.scheme.offset == 28
+    assert pbgpu.Tuning.streaming.offset == 32
 
 
 def test_version(pbgpu):

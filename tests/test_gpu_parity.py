@@ -320,7 +320,8 @@ def test_autotune_then_solve(pb, ragged):
         assert iters_close(info["iters"], o6.iters)
         assert np.abs(x.cpu().numpy() - exact).max() <= 1e-5 * np.abs(exact).max()
         nx, ny, nz = sysm.dims
-        pb.set_tuning(nx, ny, nz, prec, best["block"], best["groups"], best["zchunk"], best["grid"], best["scheme"])
+        pb.set_tuning(nx, ny, nz, prec, best["block"], best["groups"], best["zchunk"], best["grid"], best["scheme"],
+                      best["streaming"])
     with pytest.raises(pb.PBError):
         pb.set_tuning(61, 53, 47, "f32", 256, 1, 1, 3)   # infeasible grid size
 
@@ -328,17 +329,22 @@ def test_autotune_then_solve(pb, ragged):
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_every_tiling_and_pass_form(pb, ragged, prec):
     """Every feasible launch shape of the fused kernel, both pass forms (the
-    pass that stores A.p and the 40-byte pass that recomputes it), solves the
-    ragged system to the oracle's exact solution in the oracle's iteration
-    count; the two forms give the same iterates up to rounding."""
+    pass that stores A.p and the 40-byte pass that recomputes it) and both
+    access kinds (cached, streaming), solves the ragged system to the oracle's
+    exact solution in the oracle's iteration count; the two forms give the same
+    iterates up to rounding, and the two access kinds of one launch shape give
+    bitwise the same result."""
     prob, ref, sysm, exact, o6 = ragged
     nx, ny, nz = sysm.dims
     cands = pb.tiling_candidates(nx, ny, nz, prec)
     assert {c["scheme"] for c in cands} == {0, 1}, cands
+    assert {c["streaming"] for c in cands} == {0, 1}, cands
     xs = {}
+    by_shape = {}
     try:
         for c in cands:
-            pb.set_tuning(nx, ny, nz, prec, c["block"], c["groups"], c["zchunk"], c["grid"], c["scheme"])
+            pb.set_tuning(nx, ny, nz, prec, c["block"], c["groups"], c["zchunk"], c["grid"], c["scheme"],
+                          c["streaming"])
             print(f"tiling {prec} {c}", flush=True)
             x, info = pb.solve(sysm, tol=1e-6, precision=prec)
             assert info["status"] == pb.PB_OK
@@ -346,6 +352,10 @@ def test_every_tiling_and_pass_form(pb, ragged, prec):
             xv = x.cpu().numpy()
             assert np.abs(xv - exact).max() <= 1e-5 * np.abs(exact).max(), c
             xs.setdefault(c["scheme"], []).append(xv)
+            shape = (c["block"], c["groups"], c["zchunk"], c["grid"], c["scheme"])
+            if shape in by_shape:
+                assert np.array_equal(by_shape[shape], xv), c
+            by_shape[shape] = xv
     finally:
         best = pb.autotune(sysm, precision=prec, iters_per_trial=3)   # leave a recorded winner behind
     a, b = xs[0][0], xs[1][0]

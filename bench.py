@@ -138,6 +138,84 @@ def bench_c1(pbgpu, torch, synth, dev, reps=3):
     return out
 
 
+def bench_slab(pbgpu, torch, synth, dev, iters=200):
+    """One GPU's share of an 8-way z-slab split of the 257^3 solve: the fused
+    kernel alone on 257 x 257 x 33 nodes (the halo exchange and the all-reduce
+    of a multi-GPU run are not part of it), FP32, a fixed iteration count."""
+    p = synth.small_problem(257, 257, 33, 400, seed=11, precision="f32")
+    g = p.grid
+    sm = pbgpu.setup(g, p.mol.xyz, p.mol.radius, p.mol.charge, p.eps_in, p.eps_out, p.kappa_d2, device=dev)
+    n = g.nx * g.ny * g.nz
+    tun = pbgpu.autotune(sm, precision="f32", iters_per_trial=20)   # untimed: this shape's tiling
+    best = None
+    for _ in range(3):
+        _, info = pbgpu.solve(sm, tol=1e-300, precision="f32", maxiter=iters, check=False)
+        if best is None or info["kernel_seconds"] < best["kernel_seconds"]:
+            best = info
+    us = 1e6 * best["kernel_seconds"] / best["iters"]
+    del sm
+    torch.cuda.empty_cache()
+    return {"grid": [g.nx, g.ny, g.nz], "iters": best["iters"], "us_per_iter": round(us, 2),
+            "algorithmic_gbs": round(ITER_BYTES * n / us / 1e3, 1), "tuning": tun}
+
+
+def bench_solvation(pbgpu, torch, synth, dev, reps=2):
+    """Solvation energy dG from two solves (solvent vs uniform eps_in) of the
+    257^3 config-2 system, FP32 inner / FP64 refinement to 1e-9; and the Born
+    ion (a = 2.1 A, 33^3, h = 0.5) against Born's formula."""
+    import numpy as np
+    p = synth.config2()
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = pbgpu.solvation_energy(p.grid, p.mol.xyz, p.mol.radius, p.mol.charge, p.eps_in, p.eps_out,
+                                   p.kappa_d2, tol=1e-9, precision="f32_refine64", inner_tol=1e-4, device=dev)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if best is None or dt < best[0]:
+            best = (dt, r)
+    dt, r = best
+    n, h, a = 33, 0.5, 2.1
+    g = pbgpu.make_grid(n, n, n, h, np.full(3, -(n - 1) / 2 * h))
+    born = pbgpu.solvation_energy(g, np.zeros((1, 3)), np.array([a]), np.array([1.0]), 1.0, 80.0, 0.0,
+                                  tol=1e-10, precision="f64", device=dev)
+    born_exact = -0.5 * 332.0637133 * (1.0 - 1.0 / 80.0) / a
+    torch.cuda.empty_cache()
+    return {"dG_kcal": round(r["dG"], 4), "ms": round(1e3 * dt, 2),
+            "iters": [r["info_solv"]["iters"], r["info_ref"]["iters"]],
+            "relres_true": [r["info_solv"]["relres_true"], r["info_ref"]["relres_true"]],
+            "born_ion_dG_kcal": round(born["dG"], 5), "born_formula_kcal": round(born_exact, 5),
+            "born_rel_err": round(born["dG"] / born_exact - 1.0, 5)}
+
+
+def bench_periodic(pbgpu, torch, synth, dev, reps=3):
+    """Periodic boundary: the config-2 molecule in a 257^3 periodic box with
+    salt, FP32 Jacobi-PCG to 1e-6 (the pass that stores A.p, periodic form)."""
+    p = synth.config2()
+    g = p.grid
+    sm = pbgpu.setup(g, p.mol.xyz, p.mol.radius, p.mol.charge, p.eps_in, p.eps_out, p.kappa_d2, device=dev,
+                     boundary="periodic")
+    n = g.nx * g.ny * g.nz
+    pbgpu.solve(sm, tol=1e-6, precision="f32")
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = pbgpu.solve(sm, tol=1e-6, precision="f32")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if best is None or dt < best[0]:
+            best = (dt, info)
+    dt, info = best
+    us = 1e6 * info["kernel_seconds"] / max(info["iters"], 1)
+    del sm
+    torch.cuda.empty_cache()
+    return {"iters": info["iters"], "solve_ms": round(1e3 * dt, 3), "us_per_iter": round(us, 2),
+            "algorithmic_gbs": round(ITER_BYTES * n / us / 1e3, 1),
+            "form_gbs": round(PASS_BYTES_BY_SCHEME[0] * n / us / 1e3, 1), "relres_true": info["relres_true"]}
+
+
 def bench_mg(pbgpu, torch, synth, dev, reps=3):
     """Config 2 solves with the multigrid-preconditioned CG against the fused
     Jacobi-PCG (same system, same tolerances), best of `reps`."""
@@ -395,6 +473,12 @@ def main():
         forms["c2_multigrid_vs_jacobi"] = bench_mg(pbgpu, torch, synth, dev)
         print(f"bench: {forms['c2_multigrid_vs_jacobi']}", file=sys.stderr, flush=True)
         print("bench: batched form (config 3)", file=sys.stderr, flush=True)
+        forms["f1_solvation"] = bench_solvation(pbgpu, torch, synth, dev)
+        print(f"bench: {forms['f1_solvation']}", file=sys.stderr, flush=True)
+        forms["f2_periodic_257"] = bench_periodic(pbgpu, torch, synth, dev)
+        print(f"bench: {forms['f2_periodic_257']}", file=sys.stderr, flush=True)
+        forms["slab_257x257x33"] = bench_slab(pbgpu, torch, synth, dev)
+        print(f"bench: {forms['slab_257x257x33']}", file=sys.stderr, flush=True)
         forms["batched"] = bench_batched(pbgpu, torch, synth, dev)
         print(f"bench: {forms['batched']}", file=sys.stderr, flush=True)
         print("bench: served form (config 4)", file=sys.stderr, flush=True)

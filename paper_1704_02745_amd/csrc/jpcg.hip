@@ -557,6 +557,8 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
         V cxv[MC], cyv[MC], czv[MC];
         T cxm[MC], cym[MC][W];
         T cxw[W], cyw[W];   // periodic: wrap couplings of plane k
+        // periodic: r, q, d, p_old at the y-wrap partners of the next plane
+        T pr_r[W], pr_q[W], pr_d[W], pr_po[W];
         V h_r, h_q, h_d, h_po;
     };
     auto issue = [&](int k, Ld& L) {
@@ -591,12 +593,22 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
         }
 #pragma unroll
         for (int u = 0; u < W; ++u) L.cxw[u] = L.cyw[u] = T(0);
+#pragma unroll
+        for (int u = 0; u < W; ++u) L.pr_r[u] = L.pr_q[u] = L.pr_d[u] = L.pr_po[u] = T(0);
         if constexpr (PER) {
             const int64_t g = (int64_t)k * sp + pos[0];
+            const int64_t gn = (int64_t)kn * sp + pos[0];
 #pragma unroll
             for (int u = 0; u < W; ++u) {
                 L.cxw[u] = ((wl >> u) & 1u) ? a.op.cx[g + u + nx - 1] : T(0);
                 L.cyw[u] = ((wd >> u) & 1u) ? a.op.cy[g + u + yspan] : T(0);
+                if (((wd | wu) >> u) & 1u) {
+                    const int64_t gq = gn + u + (((wu >> u) & 1u) ? -yspan : yspan);
+                    L.pr_r[u] = rold[gq];
+                    L.pr_q[u] = qold[gq];
+                    L.pr_d[u] = a.op.d[gq];
+                    L.pr_po[u] = pold[gq];
+                }
             }
         }
         L.h_r = L.h_q = L.h_d = L.h_po = z0;
@@ -623,8 +635,17 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
         const T (&cxm)[MC] = ldc.cxm; const T (&cym)[MC][W] = ldc.cym;
         const T (&cxw)[W] = ldc.cxw; const T (&cyw)[W] = ldc.cyw;
         const V& h_r = ldc.h_r; const V& h_q = ldc.h_q; const V& h_d = ldc.h_d; const V& h_po = ldc.h_po;
-        T pwn[W];   // periodic: the y-wrap partners of the next plane
-        if constexpr (PER) partners(kn, pwn);
+        T pwn[W];   // periodic: p_{l-1} at the y-wrap partners of the next plane (p_point's arithmetic)
+        if constexpr (PER) {
+#pragma unroll
+            for (int u = 0; u < W; ++u) {
+                pwn[u] = T(0);
+                if (((wd | wu) >> u) & 1u) {
+                    const T r = ldc.pr_r[u] - alpha * ldc.pr_q[u];
+                    pwn[u] = r * jacobi_inv(ldc.pr_d[u]) + beta * ldc.pr_po[u];
+                }
+            }
+        }
         // ---- next plane: new p (own and halo), r_{l-1}, x update
         V rn[MC], dn[MC];
 #pragma unroll

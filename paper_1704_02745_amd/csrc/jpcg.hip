@@ -1200,7 +1200,7 @@ __global__ __launch_bounds__(BS) void k_jpcg_fused(KArgs<T> a) {
 // solve problem p with their own barrier state; problems never wait for
 // each other, and each problem's tiling and reduction order depend only on
 // its own shape.
-template <typename T, int BS, int MC, bool NT>
+template <typename T, int BS, int MC, int SCH, bool NT>
 __global__ __launch_bounds__(BS) void k_jpcg_batch(const KArgs<T>* __restrict__ probs,
                                                    const int* __restrict__ first, int nprob) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1210,7 +1210,7 @@ __global__ __launch_bounds__(BS) void k_jpcg_batch(const KArgs<T>* __restrict__ 
         if (first[mid] <= (int)blockIdx.x) lo = mid; else hi = mid;
     }
     const KArgs<T> a = probs[lo];
-    run_problem<T, BS, MC, 0, false, NT>(a, blockIdx.x - first[lo], first[lo + 1] - first[lo], false, lds_raw);
+    run_problem<T, BS, MC, SCH, false, NT>(a, blockIdx.x - first[lo], first[lo + 1] - first[lo], false, lds_raw);
 }
 
 // ------------------------------------------------------------------ host side
@@ -1525,8 +1525,13 @@ template pb_status fused_jpcg<float>(const Layout&, const SolveBufs<float>&, Syn
 namespace {
 constexpr int kBatchBS = 256;
 constexpr int kBatchMC = 1;
-constexpr int kBatchZ = 16;
+constexpr int kBatchZ = 32;
+constexpr int kBatchScheme = 1;
 constexpr bool kBatchNT = false;
+template <typename T>
+KernelFn batch_kernel() {
+    return (KernelFn)k_jpcg_batch<T, kBatchBS, kBatchMC, kBatchScheme, kBatchNT>;
+}
 }  // namespace
 
 // Tiling used for a problem inside a batch: a fixed kernel variant and
@@ -1545,9 +1550,9 @@ Tiling batch_tiling(const Layout& L) {
     t.nseg = (int)((L.sp + t.seglen - 1) / t.seglen);
     t.nzc = (L.nz + t.zchunk - 1) / t.zchunk;
     t.ntiles = t.nseg * t.nzc;
-    t.scheme = 0;
+    t.scheme = kBatchScheme;
     t.nt = kBatchNT ? 1 : 0;
-    t.lds = lds_bytes<T>(0, t.seglen, t.halo);
+    t.lds = lds_bytes<T>(kBatchScheme, t.seglen, t.halo);
     return t;
 }
 template Tiling batch_tiling<float>(const Layout&);
@@ -1595,7 +1600,7 @@ template void batch_fill_kargs<double>(void*, const Layout&, const SolveBufs<dou
 template <typename T>
 int batch_capacity(size_t lds) {
     const DevInfo di = dev_info();
-    const int per_cu = max_coresident((KernelFn)k_jpcg_batch<T, kBatchBS, kBatchMC, kBatchNT>, kBatchBS, lds);
+    const int per_cu = max_coresident(batch_kernel<T>(), kBatchBS, lds);
     return per_cu * (di.cus > 0 ? di.cus : 256);
 }
 template int batch_capacity<float>(size_t);
@@ -1626,11 +1631,9 @@ pb_status batch_launch(const void* d_kargs, const int* d_first, int nprob, int g
     void* args[] = {&kp, &d_first, &nprob};
     hipError_t e;
     if (cooperative)
-        e = hipLaunchCooperativeKernel((const void*)k_jpcg_batch<T, kBatchBS, kBatchMC, kBatchNT>, dim3(grid),
-                                       dim3(kBatchBS), args, lds, st);
+        e = hipLaunchCooperativeKernel(batch_kernel<T>(), dim3(grid), dim3(kBatchBS), args, lds, st);
     else
-        e = hipLaunchKernel((const void*)k_jpcg_batch<T, kBatchBS, kBatchMC, kBatchNT>, dim3(grid), dim3(kBatchBS),
-                            args, lds, st);
+        e = hipLaunchKernel(batch_kernel<T>(), dim3(grid), dim3(kBatchBS), args, lds, st);
     if (e != hipSuccess) {
         set_error("batch JPCG launch failed: %s (grid %d, lds %zu)", hipGetErrorString(e), grid, lds);
         return PB_ERR_HIP;

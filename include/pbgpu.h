@@ -206,7 +206,9 @@ size_t pb_solve_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, const pb_sol
  * A zero right-hand side returns x = 0 after 0 iterations.
  * info (host, nullable) receives the iteration counts and residuals.
  * Errors: PB_ERR_ARG (dims < 1, h <= 0, tol <= 0, null pointers, negative
- * or non-finite coefficients), PB_ERR_NOMEM (workspace too small),
+ * or non-finite coefficients; with the stencil operator also rows wider than
+ * the fused kernel's in-plane halo allows: nx > 1024 in FP32, > 512 in FP64,
+ * checked before any launch), PB_ERR_NOMEM (workspace too small),
  * PB_ERR_NONFINITE (NaN/Inf in rhs or guess), PB_ERR_BREAKDOWN,
  * PB_NOT_CONVERGED, PB_ERR_TIMEOUT, PB_ERR_HIP.
  */

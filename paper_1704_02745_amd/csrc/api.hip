@@ -260,6 +260,11 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
     const int maxiter = opts->maxiter > 0 ? opts->maxiter : 10 * std::max(nx, std::max(ny, nz));
     const int per = opts->boundary == PB_BOUNDARY_PERIODIC ? 1 : 0;
     PB_ARG(!per || (nx >= 3 && ny >= 3 && nz >= 3), "pb_solve: the periodic boundary needs nx, ny, nz >= 3");
+    if (opts->op == PB_OP_STENCIL) {
+        const Tiling t = opts->precision == PB_F64 ? solve_tiling<double>(L, per) : solve_tiling<float>(L, per);
+        PB_ARG(t.grid > 0, "pb_solve: no tiling of the fused kernel fits this row width (nx at most 1024 in "
+                           "FP32, 512 in FP64)");
+    }
     hipStream_t st = (hipStream_t)stream_;
     bool singular = false;
     pb_status e = prepare(L, h, eps_x, eps_y, eps_z, kappa2, rhs, x, opts->warm_start ? 1 : 0, per, w, st,

@@ -1429,6 +1429,13 @@ template Tiling choose_tiling<float>(const Layout&);
 template Tiling choose_tiling<double>(const Layout&);
 
 template <typename T>
+Tiling solve_tiling(const Layout& L, int periodic) {
+    return periodic ? choose_tiling_impl<T>(L, 0, 0, 0, 0, 1) : choose_tiling<T>(L);
+}
+template Tiling solve_tiling<float>(const Layout&, int);
+template Tiling solve_tiling<double>(const Layout&, int);
+
+template <typename T>
 int streaming_for(const Layout& L) {
     return streaming_default<T>(L);
 }
@@ -1445,8 +1452,7 @@ template Tiling tiling_with<double>(const Layout&, int, int, int);
 template <typename T>
 pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, double* partials, double tol,
                      int maxiter, hipStream_t st, SolveResult* res, const Tiling* force, int periodic) {
-    const Tiling t = periodic ? choose_tiling_impl<T>(L, 0, 0, 0, 0, 1)
-                              : (force && force->grid > 0 ? *force : choose_tiling<T>(L));
+    const Tiling t = !periodic && force && force->grid > 0 ? *force : solve_tiling<T>(L, periodic);
     if (t.grid <= 0) {
         set_error("fused JPCG: no feasible tiling for this grid (nx too large for the in-plane halo)");
         return PB_ERR_ARG;

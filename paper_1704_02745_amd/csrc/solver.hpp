@@ -78,6 +78,10 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
 
 template <typename T>
 Tiling choose_tiling(const Layout& L);
+// The tiling a fused solve of this shape launches (free or periodic boundary);
+// grid = 0 when no kernel variant fits the row width.
+template <typename T>
+Tiling solve_tiling(const Layout& L, int periodic);
 // 1 when the shape's default is the streaming (nontemporal) kernel variant.
 template <typename T>
 int streaming_for(const Layout& L);

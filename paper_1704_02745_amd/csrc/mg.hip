@@ -185,6 +185,55 @@ __global__ void k_mg_jacobi(Op<T> op, const T* __restrict__ b, const T* __restri
     }
 }
 
+// The first two damped-Jacobi sweeps from zero in one pass. The first
+// sweep's output x1 = omega b / d is formed where the second needs it (the
+// node and its six neighbours) with the arithmetic of the from_zero sweep, so
+// the result equals two k_mg_jacobi launches bit for bit.
+template <typename T>
+__device__ __forceinline__ T mg_x1(const Op<T>& op, const T* __restrict__ b, int64_t t, T omega) {
+    return omega * b[t] / op.d[t];
+}
+
+template <typename T>
+__global__ void k_mg_jacobi2z(Op<T> op, const T* __restrict__ b, T* __restrict__ out, int nx, int64_t sp,
+                              int64_t npad, T omega, const SyncState* S) {
+    if (S && stop(S)) return;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npad;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        T nb = op.cx[t] * (t + 1 < npad ? mg_x1(op, b, t + 1, omega) : T(0));
+        nb += (t >= 1 ? op.cx[t - 1] * mg_x1(op, b, t - 1, omega) : T(0));
+        nb += op.cy[t] * (t + nx < npad ? mg_x1(op, b, t + nx, omega) : T(0));
+        nb += (t >= nx ? op.cy[t - nx] * mg_x1(op, b, t - nx, omega) : T(0));
+        nb += op.cz[t] * (t + sp < npad ? mg_x1(op, b, t + sp, omega) : T(0));
+        nb += (t >= sp ? op.cz[t - sp] * mg_x1(op, b, t - sp, omega) : T(0));
+        const T x1 = mg_x1(op, b, t, omega);
+        const T r = b[t] - (op.d[t] * x1 - nb);
+        out[t] = x1 + omega * r / op.d[t];
+    }
+}
+
+// The finest level's last post-smoothing sweep fused with the outer
+// iteration's r.z and r.r (the level's right-hand side is the outer residual
+// r): block b sweeps positions [b*per, (b+1)*per), threads striding by the
+// block size, and stores the block sums in the fixed order of block_sum_store.
+template <typename T>
+__global__ __launch_bounds__(kBS) void k_mg_jacobi_dot2(Op<T> op, const T* __restrict__ b, const T* __restrict__ in,
+                                                        T* __restrict__ out, int nx, int64_t sp, int64_t npad,
+                                                        T omega, int64_t per, double* __restrict__ partials,
+                                                        const SyncState* S) {
+    if (stop(S)) return;
+    double acc[2] = {0.0, 0.0};
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = min(lo + per, npad);
+    for (int64_t t = lo + threadIdx.x; t < hi; t += kBS) {
+        const T res = b[t] - mg_apply(op, in, t, nx, sp, npad);
+        const T z = in[t] + omega * res / op.d[t];
+        out[t] = z;
+        acc[0] += (double)b[t] * (double)z;
+        acc[1] += (double)b[t] * (double)b[t];
+    }
+    block_sum_store<2>(acc, partials + (size_t)blockIdx.x * kMaxPartials);
+}
+
 template <typename T>
 __global__ void k_mg_residual(Op<T> op, const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ r, int nx,
                               int64_t sp, int64_t npad, const SyncState* S) {
@@ -315,6 +364,8 @@ __global__ __launch_bounds__(kBS) void k_mg_init_dots(const T* __restrict__ r, c
     block_sum_store<3>(acc, partials + (size_t)blockIdx.x * kMaxPartials);
 }
 
+// r.z and r.r block sums (the outer iteration's, when the hierarchy has a
+// single level and the V-cycle has no post-smoothing sweep to fuse them into).
 template <typename T>
 __global__ __launch_bounds__(kBS) void k_mg_dot2(const T* __restrict__ r, const T* __restrict__ z, int64_t npad,
                                                  int64_t per, double* __restrict__ partials, const SyncState* S) {
@@ -397,9 +448,20 @@ size_t mg_carve(void* base, const Layout& L0, double h, std::vector<MgLevel<T>>*
 
 unsigned mg_grid(int64_t n) { return stream_grid(n); }
 
+// The outer iteration's r.z and r.r taken in the finest level's last sweep.
+struct DotFuse {
+    double* partials;
+    int nblk;
+    int64_t per;
+};
+
 // One V-cycle on level l from zero; returns the buffer holding the result.
+// The first two pre-smoothing sweeps run as one pass (k_mg_jacobi2z); with
+// `fuse` the finest level's last post-smoothing sweep also stores the block
+// sums of r.z and r.r (k_mg_jacobi_dot2). A single-level hierarchy has no
+// such sweep; its caller takes those sums with k_mg_dot2.
 template <typename T>
-T* vcycle(std::vector<MgLevel<T>>& lv, size_t l, const SyncState* S, hipStream_t st) {
+T* vcycle(std::vector<MgLevel<T>>& lv, size_t l, const SyncState* S, hipStream_t st, const DotFuse* fuse = nullptr) {
     MgLevel<T>& m = lv[l];
     const Layout& L = m.L;
     const T om = (T)kMgOmega;
@@ -411,7 +473,14 @@ T* vcycle(std::vector<MgLevel<T>>& lv, size_t l, const SyncState* S, hipStream_t
     }
     T* cur = m.xa;
     T* oth = m.xb;
-    for (int s = 0; s < kMgNu; ++s) {
+    int s0 = 0;
+    if (kMgNu >= 2) {
+        hipLaunchKernelGGL(k_mg_jacobi2z<T>, dim3(g), dim3(kBS), 0, st, m.op, (const T*)m.b, cur, L.nx, L.sp, L.npad,
+                           om, S);
+        std::swap(cur, oth);
+        s0 = 2;
+    }
+    for (int s = s0; s < kMgNu; ++s) {
         hipLaunchKernelGGL(k_mg_jacobi<T>, dim3(g), dim3(kBS), 0, st, m.op, (const T*)m.b, (const T*)oth, cur, L.nx,
                            L.sp, L.npad, om, s == 0 ? 1 : 0, S);
         std::swap(cur, oth);
@@ -428,8 +497,12 @@ T* vcycle(std::vector<MgLevel<T>>& lv, size_t l, const SyncState* S, hipStream_t
     cur = (z == m.xa) ? m.xb : m.xa;
     oth = z;
     for (int s = 0; s < kMgNu; ++s) {
-        hipLaunchKernelGGL(k_mg_jacobi<T>, dim3(g), dim3(kBS), 0, st, m.op, (const T*)m.b, (const T*)oth, cur, L.nx,
-                           L.sp, L.npad, om, 0, S);
+        if (fuse && l == 0 && S && s + 1 == kMgNu)
+            hipLaunchKernelGGL(k_mg_jacobi_dot2<T>, dim3(fuse->nblk), dim3(kBS), 0, st, m.op, (const T*)m.b,
+                               (const T*)oth, cur, L.nx, L.sp, L.npad, om, fuse->per, fuse->partials, S);
+        else
+            hipLaunchKernelGGL(k_mg_jacobi<T>, dim3(g), dim3(kBS), 0, st, m.op, (const T*)m.b, (const T*)oth, cur,
+                               L.nx, L.sp, L.npad, om, 0, S);
         std::swap(cur, oth);
     }
     return oth;
@@ -484,6 +557,7 @@ pb_status mg_pcg_impl(const Layout& L0, double h, const double* ex, const double
                        R.per, partials);
     hipLaunchKernelGGL(k_scalar_init, dim3(1), dim3(kBS), 0, st, S, (const double*)partials, R.nblk, tol, maxiter);
     PB_HIP(hipGetLastError());
+    const DotFuse fuse{partials, R.nblk, R.per};
     int it = 0;
     SyncState hs{};
     for (;;) {
@@ -495,9 +569,13 @@ pb_status mg_pcg_impl(const Layout& L0, double h, const double* ex, const double
             hipLaunchKernelGGL(k_scalar_alpha, dim3(1), dim3(kBS), 0, st, S, (const double*)partials, R.nblk);
             hipLaunchKernelGGL(k_axpy2<T>, dim3(g), dim3(kBS), 0, st, s.x, (const T*)s.p0, s.r, (const T*)s.q, npad,
                                (const SyncState*)S);
-            z = vcycle<T>(lv, 0, S, st);
-            hipLaunchKernelGGL(k_mg_dot2<T>, dim3(R.nblk), dim3(kBS), 0, st, (const T*)s.r, (const T*)z, npad, R.per,
-                               partials, (const SyncState*)S);
+            if (lv.size() > 1) {
+                z = vcycle<T>(lv, 0, S, st, &fuse);   // also stores the block sums of r.z and r.r
+            } else {
+                z = vcycle<T>(lv, 0, S, st);
+                hipLaunchKernelGGL(k_mg_dot2<T>, dim3(R.nblk), dim3(kBS), 0, st, (const T*)s.r, (const T*)z, npad,
+                                   R.per, partials, (const SyncState*)S);
+            }
             hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBS), 0, st, S, (const double*)partials, R.nblk, tol,
                                maxiter);
             hipLaunchKernelGGL(k_xpay<T>, dim3(g), dim3(kBS), 0, st, (const T*)z, s.p0, npad, (const SyncState*)S);

@@ -68,6 +68,37 @@ def measured_traffic():
         return None
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def copy_ceiling(torch, dev, gib=1, reps=10):
+    """Device-to-device copy rate (read + write bytes / time) of a `gib` GiB
+    FP32 buffer, timed with HIP events: the plain-streaming ceiling measured
+    beside the kernel."""
+    n = (gib << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * 4 * n * reps / (1e-3 * e0.elapsed_time(e1)) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
+
+
 def cpu_baseline(prob, n_iters=40):
     """FP64 oracle Jacobi PCG at the full 257^3 size, bounded to n_iters
     iterations (about 10-15 s of host work). The sample system uses the oracle's own classification,
@@ -95,7 +126,7 @@ def cpu_baseline(prob, n_iters=40):
             "sample": f"{res.iters} FP64 NumPy Jacobi-PCG iterations of the oracle at 257^3 "
                       f"(same operator, zero boundary), {wall:.1f} s wall; rate scaled by the "
                       f"metric's {ITER_BYTES} B/unknown per iteration",
-            "iters_per_s": round(its, 4), "os_cpu_count": os.cpu_count()}
+            "iters_per_s": round(its, 4), "os_cpu_count": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 # DIA form: 7 diagonals (28 B) + p (4 B) read, q (4 B) written by the SpMV;
@@ -454,6 +485,7 @@ def main():
     value = total_bytes / wall / 1e9
     achieved = total_bytes / ksec / 1e9
     traffic = measured_traffic()
+    ceiling = copy_ceiling(torch, dev)   # untimed, after the timed steps
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic, 0),
@@ -462,7 +494,11 @@ def main():
                           f"one launch per inner solve; algorithmic {ITER_BYTES} B/unknown/iteration, this pass "
                           f"form moves {PASS_BYTES_BY_SCHEME[scheme]} B)",
                 "bytes_per_launch": round(total_bytes / launches, 0),
-                "avg_launch_ms": round(1e3 * ksec / launches, 4)}
+                "avg_launch_ms": round(1e3 * ksec / launches, 4),
+                "copy_ceiling_gbs": ceiling}
+    if traffic is not None:   # counted HBM bytes per launch over the live launch time
+        roofline["traffic_gbs"] = round(traffic / (ksec / launches) / 1e9, 1)
+        roofline["traffic_frac"] = round(roofline["traffic_gbs"] / PEAK_GBS, 4)
 
     forms = {}
     if not args.no_forms:

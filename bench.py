@@ -396,6 +396,11 @@ def bench_serving(pbgpu, torch, synth, dev, nreq=2200, warm=200, rate=200.0, poo
             "pool": pool, "chunk": chunk}
 
 
+# Forms reported beside the main line (also runnable alone with --forms-only).
+FORMS = {"c1": bench_c1, "mg": bench_mg, "f1_solvation": bench_solvation, "f2_periodic": bench_periodic,
+         "slab": bench_slab, "batched": bench_batched, "served": bench_serving}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -409,6 +414,9 @@ def main():
                          "(profiled runs; streaming 1/0 = nontemporal/cached, default the shape's own)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one untimed 512 MiB device copy first (counter calibration under rocprofv3)")
+    ap.add_argument("--forms-only", default="",
+                    help="comma-separated forms to run alone, one JSON line each, without the main step "
+                         "(profiling): " + ", ".join(sorted(FORMS)))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -423,6 +431,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.forms_only:
+        for name in args.forms_only.split(","):
+            print(json.dumps({"form": name, "result": FORMS[name](pbgpu, torch, synth, dev)}), flush=True)
+        return
     prob = synth.config2()
     g = prob.grid
     n = g.nx * g.ny * g.nz

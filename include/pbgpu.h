@@ -230,8 +230,8 @@ typedef struct {
     int32_t scheme;         /* pass form: 0 stores A.p (48 B/node/iteration in FP32),
                                1 recomputes A.p_old from p_old (40 B/node/iteration) */
     int32_t streaming;      /* 1: nontemporal loads and stores for the streams no step reads again
-                               (the default once a pass's arrays exceed the 256 MiB last-level
-                               cache); 0: cached accesses; -1 (pb_set_tuning only): the
+                               (the default once a pass's arrays exceed 1.75 times the 256 MiB
+                               last-level cache); 0: cached accesses; -1 (pb_set_tuning only): the
                                shape's default */
 } pb_tuning;
 

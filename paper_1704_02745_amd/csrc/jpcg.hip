@@ -1336,11 +1336,16 @@ Tiling tiling_for(const Layout& L, const Variant& v, int cus, int max_per_cu) {
 
 // Streaming (nontemporal) variants are the default once the arrays one pass
 // touches (about 12 per node: r, p and q in two copies, x, d, cx, cy, cz)
-// exceed the last-level cache, 256 MiB of Infinity Cache on MI355X.
+// exceed 1.75 times the last-level cache (256 MiB of Infinity Cache on
+// MI355X). Measured crossover: cached wins at 161^3 FP32/FP64 and 193^3 FP32
+// (201-402 MB), streaming at 193^3 FP64, 225^3 FP32 and 257^3 FP32 (549 MB and
+// up); part of a working set somewhat above the cache still survives between
+// iterations.
 constexpr double kLastLevelCacheBytes = 256.0 * 1024 * 1024;
+constexpr double kStreamingFactor = 1.75;
 template <typename T>
 int streaming_default(const Layout& L) {
-    return (double)L.sp * L.nz * sizeof(T) * 12.0 > kLastLevelCacheBytes ? 1 : 0;
+    return (double)L.sp * L.nz * sizeof(T) * 12.0 > kStreamingFactor * kLastLevelCacheBytes ? 1 : 0;
 }
 
 template <typename T>

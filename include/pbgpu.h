@@ -307,8 +307,9 @@ size_t pb_batch_workspace_bytes(int32_t nprob, const pb_problem* probs, int32_t 
  * pb_solve_batch: solve all problems (section 2.2 with M = diag(A)) in ONE
  * persistent launch. Workgroups are shared out in proportion to each
  * problem's expected work; each problem synchronises only its own
- * workgroups, and its tiling and reduction order depend on its shape alone,
- * so a problem's result is bitwise identical alone and in any mix.
+ * workgroups, and its tiling and reduction order depend on its shape and the
+ * device's batch z-chunk alone, so a problem's result is bitwise identical
+ * alone and in any mix.
  * precision: PB_F32 or PB_F64. infos (host, nprob entries, nullable) receive
  * per-problem iterations, status and FP64 true residuals; kernel_seconds is
  * the whole batch's device time. Returns PB_OK, PB_NOT_CONVERGED if any
@@ -317,6 +318,27 @@ size_t pb_batch_workspace_bytes(int32_t nprob, const pb_problem* probs, int32_t 
  */
 pb_status pb_solve_batch(int32_t nprob, const pb_problem* probs, int32_t precision,
                          void* workspace, size_t workspace_bytes, void* stream, pb_info* infos);
+
+/*
+ * Batch tiling. The batched and served kernels cut each problem into
+ * z-chunks of this many planes (default 32, one setting per device). Under one
+ * setting a problem's tiling, and so its result, depends on its shape alone.
+ * pb_batch_set_zchunk takes 1..4096 (PB_ERR_ARG otherwise).
+ *
+ * pb_batch_autotune times the batch kernel on the given problems for each
+ * candidate z-chunk (16, 24, 32, 48, 64). Every problem is capped at
+ * iters_per_trial iterations, and the problems' x arrays are read (warm start)
+ * but not written. The fastest candidate becomes the device's setting;
+ * best_zchunk and best_seconds (host, nullable) receive it and its trial's
+ * device time. Errors: PB_ERR_ARG (as pb_solve_batch, or iters_per_trial < 1),
+ * PB_ERR_NOMEM (workspace below pb_batch_autotune_workspace_bytes), PB_ERR_HIP.
+ */
+pb_status pb_batch_set_zchunk(int32_t zchunk);
+int32_t pb_batch_get_zchunk(void);
+size_t pb_batch_autotune_workspace_bytes(int32_t nprob, const pb_problem* probs, int32_t precision);
+pb_status pb_batch_autotune(int32_t nprob, const pb_problem* probs, int32_t precision, int32_t iters_per_trial,
+                            void* workspace, size_t workspace_bytes, void* stream, int32_t* best_zchunk,
+                            double* best_seconds);
 
 /*
  * The same batch recorded once in a HIP graph (preparation, the persistent

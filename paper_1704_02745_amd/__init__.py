@@ -33,7 +33,8 @@ OPERATORS = {"stencil": 0, "dia": 1, "mg": 2}
 EXPORTS = ("pb_version", "pb_last_error", "pb_setup_workspace_bytes", "pb_setup",
            "pb_solve_workspace_bytes", "pb_solve", "pb_autotune", "pb_set_tuning", "pb_tiling_candidates",
            "pb_get_tuning",
-           "pb_batch_workspace_bytes", "pb_solve_batch", "pb_batch_graph_create", "pb_batch_graph_launch",
+           "pb_batch_workspace_bytes", "pb_solve_batch", "pb_batch_set_zchunk", "pb_batch_get_zchunk",
+           "pb_batch_autotune_workspace_bytes", "pb_batch_autotune", "pb_batch_graph_create", "pb_batch_graph_launch",
            "pb_batch_graph_results", "pb_batch_graph_is_cooperative", "pb_batch_graph_destroy",
            "pb_server_request_bytes", "pb_server_create", "pb_server_submit", "pb_server_step",
            "pb_server_stats", "pb_server_destroy",
@@ -135,6 +136,14 @@ def _load():
     P = ctypes.POINTER(Problem)
     lib.pb_batch_workspace_bytes.restype = sz
     lib.pb_batch_workspace_bytes.argtypes = [i32, P, i32]
+    lib.pb_batch_set_zchunk.restype = ctypes.c_int
+    lib.pb_batch_set_zchunk.argtypes = [i32]
+    lib.pb_batch_get_zchunk.restype = i32
+    lib.pb_batch_get_zchunk.argtypes = []
+    lib.pb_batch_autotune_workspace_bytes.restype = sz
+    lib.pb_batch_autotune_workspace_bytes.argtypes = [i32, P, i32]
+    lib.pb_batch_autotune.restype = ctypes.c_int
+    lib.pb_batch_autotune.argtypes = [i32, P, i32, i32, vp, sz, vp, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
     lib.pb_solve_batch.restype = ctypes.c_int
     lib.pb_solve_batch.argtypes = [i32, P, i32, vp, sz, vp, ctypes.POINTER(Info)]
     lib.pb_batch_graph_create.restype = ctypes.c_int
@@ -406,6 +415,33 @@ def _outs(systems, outs, x0s):
             if x0 is not None:
                 o.copy_(torch.as_tensor(x0, dtype=torch.float64).reshape(o.shape))
     return outs
+
+
+def set_batch_zchunk(zchunk: int) -> None:
+    """Set the batched and served kernels' z-chunk (planes per tile) on the current device."""
+    _check(lib.pb_batch_set_zchunk(int(zchunk)))
+
+
+def get_batch_zchunk() -> int:
+    return int(lib.pb_batch_get_zchunk())
+
+
+def batch_autotune(systems, precision="f32", iters_per_trial=20, stream=None) -> dict:
+    """Time the batched kernel's candidate z-chunks on these systems (each
+    problem capped at iters_per_trial iterations; no array of the systems is
+    written) and make the fastest the device's batch z-chunk."""
+    outs = _outs(systems, None, None)
+    arr = _problems(systems, 1e-30, 0, outs, None)
+    n = len(systems)
+    prec = PRECISIONS[precision]
+    wsb = lib.pb_batch_autotune_workspace_bytes(n, arr, prec)
+    if wsb == 0:
+        raise PBError(PB_ERR_ARG, last_error() or "pb_batch_autotune_workspace_bytes rejected the batch")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=systems[0].rhs.device)
+    z, sec = ctypes.c_int32(0), ctypes.c_double(0.0)
+    _check(lib.pb_batch_autotune(n, arr, prec, int(iters_per_trial), _ptr(ws), wsb, _stream(stream),
+                                 ctypes.byref(z), ctypes.byref(sec)))
+    return {"zchunk": z.value, "seconds": sec.value}
 
 
 def solve_batch(systems, tol=1e-6, precision="f32", maxiter=0, outs=None, x0s=None,

@@ -52,7 +52,7 @@ bool problem_ok(const pb_problem& p) {
 // Carve the workspace (base may be null to size it). Returns false with an
 // error set if a problem cannot be tiled.
 template <typename T>
-bool carve_batch(void* base, int nprob, const pb_problem* probs, Plan<T>& P) {
+bool carve_batch(void* base, int nprob, const pb_problem* probs, Plan<T>& P, int zchunk = 0) {
     size_t off = 0;
     auto take = [&](size_t bytes) -> void* {
         const size_t o = off;
@@ -67,7 +67,7 @@ bool carve_batch(void* base, int nprob, const pb_problem* probs, Plan<T>& P) {
     P.lds = 0;
     for (int i = 0; i < nprob; ++i) {
         const Layout L = make_layout(probs[i].nx, probs[i].ny, probs[i].nz);
-        const Tiling t = batch_tiling<T>(L);
+        const Tiling t = batch_tiling<T>(L, zchunk);
         if (t.ntiles <= 0) {
             set_error("batch: problem %d (nx = %d) is too wide for the batch kernel's in-plane halo", i, L.nx);
             return false;
@@ -269,6 +269,56 @@ pb_status solve_batch_impl(int nprob, const pb_problem* probs, void* ws, size_t 
     return st_all;
 }
 
+// z-chunks the batch autotuner times.
+constexpr int kBatchZCandidates[] = {16, 24, 32, 48, 64};
+
+// Time the batch kernel for each candidate z-chunk on these problems, each
+// capped at `iters` iterations (state cleared and prepared as for a solve,
+// but no hand-back: the problems' x arrays are not written), and make the
+// fastest the device's batch z-chunk.
+template <typename T>
+pb_status batch_autotune_impl(int nprob, const pb_problem* probs, int iters, void* ws, size_t wsb, hipStream_t st,
+                              int* best_z, double* best_seconds) {
+    std::vector<pb_problem> trial(probs, probs + nprob);
+    for (auto& p : trial) p.maxiter = iters;
+    hipEvent_t ev[2];
+    PB_HIP(hipEventCreate(&ev[0]));
+    PB_HIP(hipEventCreate(&ev[1]));
+    double best = 1e300;
+    int bz = 0;
+    pb_status e = PB_OK;
+    for (int z : kBatchZCandidates) {
+        Plan<T> P;
+        if (!carve_batch<T>(ws, nprob, trial.data(), P, z)) { e = PB_ERR_ARG; break; }
+        if (wsb < P.bytes) {
+            set_error("pb_batch_autotune: workspace of %zu bytes, %zu needed", wsb, P.bytes);
+            e = PB_ERR_NOMEM;
+            break;
+        }
+        int grid = 0;
+        if ((e = upload_table<T>(P, trial.data(), grid, st)) != PB_OK) break;
+        if ((e = launch_fill<int>((int*)P.rec, (int64_t)(sizeof(ProbRec) / sizeof(int)) * nprob, 0, st)) != PB_OK) break;
+        if ((e = launch_fill<int>((int*)P.sync, (int64_t)(sizeof(SyncState) / sizeof(int)) * nprob, 0, st)) != PB_OK) break;
+        if ((e = enqueue_prepare<T>(P, trial.data(), st)) != PB_OK) break;
+        if (hipEventRecord(ev[0], st) != hipSuccess) { e = PB_ERR_HIP; break; }
+        if ((e = batch_launch<T>(P.table, P.first, nprob, grid, P.lds, st, true)) != PB_OK) break;
+        if (hipEventRecord(ev[1], st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) { e = PB_ERR_HIP; break; }
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) { e = PB_ERR_HIP; break; }
+        if (ms < best) {
+            best = ms;
+            bz = z;
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (e != PB_OK) return e;
+    set_batch_zchunk(bz);
+    if (best_z) *best_z = bz;
+    if (best_seconds) *best_seconds = 1e-3 * best;
+    return PB_OK;
+}
+
 bool batch_args_ok(int nprob, const pb_problem* probs, int precision) {
     if (nprob < 1 || !probs || (precision != PB_F32 && precision != PB_F64)) return false;
     for (int i = 0; i < nprob; ++i)
@@ -315,6 +365,48 @@ extern "C" pb_status pb_solve_batch(int32_t nprob, const pb_problem* probs, int3
     hipStream_t st = (hipStream_t)stream;
     if (precision == PB_F64) return solve_batch_impl<double>(nprob, probs, workspace, workspace_bytes, st, infos);
     return solve_batch_impl<float>(nprob, probs, workspace, workspace_bytes, st, infos);
+}
+
+extern "C" pb_status pb_batch_set_zchunk(int32_t zchunk) {
+    PB_ARG(zchunk >= 1 && zchunk <= 4096, "pb_batch_set_zchunk: zchunk in [1, 4096]");
+    set_batch_zchunk(zchunk);
+    return PB_OK;
+}
+
+extern "C" int32_t pb_batch_get_zchunk(void) { return batch_zchunk(); }
+
+extern "C" size_t pb_batch_autotune_workspace_bytes(int32_t nprob, const pb_problem* probs, int32_t precision) {
+    if (!batch_args_ok(nprob, probs, precision)) return 0;
+    size_t most = 0;
+    for (int z : kBatchZCandidates) {
+        size_t b = 0;
+        if (precision == PB_F64) {
+            Plan<double> P;
+            b = carve_batch<double>(nullptr, nprob, probs, P, z) ? P.bytes : 0;
+        } else {
+            Plan<float> P;
+            b = carve_batch<float>(nullptr, nprob, probs, P, z) ? P.bytes : 0;
+        }
+        if (b == 0) return 0;
+        most = std::max(most, b);
+    }
+    return most;
+}
+
+extern "C" pb_status pb_batch_autotune(int32_t nprob, const pb_problem* probs, int32_t precision,
+                                       int32_t iters_per_trial, void* workspace, size_t workspace_bytes, void* stream,
+                                       int32_t* best_zchunk, double* best_seconds) {
+    PB_ARG(batch_args_ok(nprob, probs, precision),
+           "pb_batch_autotune: need nprob >= 1, valid problems, precision PB_F32 or PB_F64");
+    PB_ARG(iters_per_trial >= 1, "pb_batch_autotune: iters_per_trial >= 1");
+    PB_ARG(workspace != nullptr && ((uintptr_t)workspace & 255) == 0,
+           "pb_batch_autotune: null or misaligned workspace");
+    hipStream_t st = (hipStream_t)stream;
+    if (precision == PB_F64)
+        return batch_autotune_impl<double>(nprob, probs, iters_per_trial, workspace, workspace_bytes, st,
+                                           best_zchunk, best_seconds);
+    return batch_autotune_impl<float>(nprob, probs, iters_per_trial, workspace, workspace_bytes, st, best_zchunk,
+                                      best_seconds);
 }
 
 namespace {

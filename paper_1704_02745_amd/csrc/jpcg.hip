@@ -1536,7 +1536,7 @@ template pb_status fused_jpcg<float>(const Layout&, const SolveBufs<float>&, Syn
 namespace {
 constexpr int kBatchBS = 256;
 constexpr int kBatchMC = 1;
-constexpr int kBatchZ = 32;
+constexpr int kBatchZ = 32;   // default z-chunk; pb_batch_autotune / pb_batch_set_zchunk change it per device
 constexpr int kBatchScheme = 1;
 constexpr bool kBatchNT = false;
 template <typename T>
@@ -1545,11 +1545,30 @@ KernelFn batch_kernel() {
 }
 }  // namespace
 
-// Tiling used for a problem inside a batch: a fixed kernel variant and
-// z-chunk, so it depends on the problem's shape alone (the same problem gives
-// bitwise the same result alone and in any mix). grid is left 0.
+// The batched and served kernels' z-chunk, per device.
+std::map<int, int> g_batch_z;
+
+int batch_zchunk() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_batch_z.find(dev);
+    return it == g_batch_z.end() ? kBatchZ : it->second;
+}
+
+void set_batch_zchunk(int z) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_batch_z[dev] = z;
+}
+
+// Tiling used for a problem inside a batch: a fixed kernel variant and the
+// device's batch z-chunk, so under one setting it depends on the problem's
+// shape alone (the same problem gives bitwise the same result alone and in
+// any mix). grid is left 0.
 template <typename T>
-Tiling batch_tiling(const Layout& L) {
+Tiling batch_tiling(const Layout& L, int zchunk) {
     constexpr int W = Vec<T>::n;
     Tiling t{};
     t.bs = kBatchBS;
@@ -1557,7 +1576,7 @@ Tiling batch_tiling(const Layout& L) {
     t.seglen = balanced_seglen<T>(L, kBatchMC * kBatchBS * W);
     t.halo = halo_for<T>(L.nx);
     if (2 * t.halo / W > kBatchBS) return t;   // infeasible: ntiles stays 0
-    t.zchunk = kBatchZ;
+    t.zchunk = zchunk > 0 ? zchunk : batch_zchunk();
     t.nseg = (int)((L.sp + t.seglen - 1) / t.seglen);
     t.nzc = (L.nz + t.zchunk - 1) / t.zchunk;
     t.ntiles = t.nseg * t.nzc;
@@ -1566,8 +1585,8 @@ Tiling batch_tiling(const Layout& L) {
     t.lds = lds_bytes<T>(kBatchScheme, t.seglen, t.halo);
     return t;
 }
-template Tiling batch_tiling<float>(const Layout&);
-template Tiling batch_tiling<double>(const Layout&);
+template Tiling batch_tiling<float>(const Layout&, int);
+template Tiling batch_tiling<double>(const Layout&, int);
 
 template <typename T>
 size_t batch_kargs_bytes() {

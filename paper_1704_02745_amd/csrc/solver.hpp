@@ -113,7 +113,10 @@ pb_status dia_jpcg_impl(const Layout& L, const SolveBufs<T>& s, SyncState* S, do
 // Batch support (jpcg.hip): shape-only tiling, per-problem kernel arguments,
 // capacity and launch of the multi-problem persistent kernel.
 template <typename T>
-Tiling batch_tiling(const Layout& L);
+Tiling batch_tiling(const Layout& L, int zchunk = 0);   // zchunk 0: the device's batch z-chunk
+// The batched and served kernels' z-chunk on the current device (default 32).
+int batch_zchunk();
+void set_batch_zchunk(int z);
 template <typename T>
 size_t batch_kargs_bytes();
 template <typename T>

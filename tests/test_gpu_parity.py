@@ -458,6 +458,36 @@ def test_batch_per_problem_tolerance_and_status(pb, batch_set):
     assert all(i["status"] == pb.PB_NOT_CONVERGED and i["iters"] == 3 for i in infos)
 
 
+def test_batch_autotune(pb, batch_set):
+    """The batch autotuner times its candidate z-chunks on the batch and makes
+    the fastest the device's setting without writing the systems' arrays;
+    solves afterwards match the oracle and stay mix independent, and so do
+    solves under any other z-chunk."""
+    probs, refs, exact, o6, systems = batch_set
+    z0 = pb.get_batch_zchunk()
+    saved = [(s.rhs.clone(), s.eps_x.clone()) for s in systems]
+    try:
+        r = pb.batch_autotune(systems, precision="f32", iters_per_trial=10)
+        print(f"batch autotune: {r}", flush=True)
+        assert r["zchunk"] in (16, 24, 32, 48, 64) and r["seconds"] > 0
+        assert pb.get_batch_zchunk() == r["zchunk"]
+        for s, (b, e) in zip(systems, saved):
+            assert torch.equal(s.rhs, b) and torch.equal(s.eps_x, e)
+        for z in (r["zchunk"], 7):
+            pb.set_batch_zchunk(z)
+            xs, infos = pb.solve_batch(systems, tol=1e-6, precision="f32")
+            for i in range(len(systems)):
+                assert infos[i]["status"] == pb.PB_OK
+                assert np.abs(xs[i].cpu().numpy() - exact[i]).max() <= 1e-5 * np.abs(exact[i]).max(), (z, i)
+            xa, ia = pb.solve_batch([systems[1]], tol=1e-6, precision="f32")
+            assert ia[0]["iters"] == infos[1]["iters"] and torch.equal(xa[0], xs[1]), z
+        for bad in (0, 5000):
+            with pytest.raises(pb.PBError):
+                pb.set_batch_zchunk(bad)
+    finally:
+        pb.set_batch_zchunk(z0)
+
+
 def test_batch_graph_replay(pb, batch_set):
     probs, refs, exact, o6, systems = batch_set
     ref_x, ref_info = pb.solve_batch(systems, tol=1e-6, precision="f32")

@@ -572,6 +572,7 @@ def main():
             "solve_ms": round(1e3 * sum(p[1] for p in phases) / len(phases), 3),
             "energy_ms": round(1e3 * sum(p[2] for p in phases) / len(phases), 3),
             "jpcg_kernel_ms_per_step": round(1e3 * ksec / args.steps, 3),
+            "jpcg_iters_per_s": round(iters / ksec, 1),
             "jpcg_iter_us": round(1e6 * ksec / iters, 2),
             "pass_form": scheme, "pass_form_bytes_per_unknown_iter": PASS_BYTES_BY_SCHEME[scheme],
             "pass_form_gbs": round(float(n) * PASS_BYTES_BY_SCHEME[scheme] * iters / ksec / 1e9, 1),

@@ -35,12 +35,18 @@ PEAK_GBS = 8000.0
 # operator arrays read once (16 B) = 40 B, whatever pass form runs. Per
 # launch add the initial pass (read b, write r and p: 12 B) and the final x
 # update (read x, p, write x: 12 B), less the x update the first iteration
-# skips (8 B). The pass forms themselves move 48 B (form 0, stores A.p) or
-# 40 B (form 1, recomputes it) per unknown per iteration; that figure is
-# reported beside the metric.
+# skips (8 B). The pass forms themselves move 48 B (form 0, stores A.p),
+# 40 B (form 1, recomputes it) or 28 B (form 1 with coded coefficients: the
+# operator read as one 4-byte word of dictionary codes per unknown) per
+# unknown per iteration; that figure is reported beside the metric.
 ITER_BYTES = 40
 INIT_BYTES = 12 - 8 + 12
 PASS_BYTES_BY_SCHEME = {0: 48, 1: 40}
+CODED_PASS_BYTES = 28
+
+
+def form_bytes(scheme: int, coded: bool) -> int:
+    return CODED_PASS_BYTES if (scheme == 1 and coded) else PASS_BYTES_BY_SCHEME[scheme]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jpcg_fused_f32_257_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1704_02745_amd", "csrc", "jpcg.hip")
 
@@ -143,7 +149,7 @@ def bench_c1(pbgpu, torch, synth, dev, reps=3):
     out = {}
     tun = pbgpu.autotune(sm, precision="f32", iters_per_trial=20)   # untimed: this shape's tiling
     sch = tun["scheme"]
-    for op, per in (("stencil", PASS_BYTES_BY_SCHEME[sch]), ("dia", DIA_ITER_BYTES)):
+    for op in ("stencil", "dia"):
         pbgpu.solve(sm, tol=1e-6, precision="f32", op=op)
         best = None
         for _ in range(reps):
@@ -155,6 +161,8 @@ def bench_c1(pbgpu, torch, synth, dev, reps=3):
             if best is None or dt < best[0]:
                 best = (dt, info)
         dt, info = best
+        coded = info["coded_launches"] > 0
+        per = form_bytes(sch, coded) if op == "stencil" else DIA_ITER_BYTES
         out[op] = {"iters": info["iters"], "solve_ms": round(1e3 * dt, 3),
                    "iter_loop_ms": round(1e3 * info["kernel_seconds"], 3),
                    "us_per_iter": round(1e6 * info["kernel_seconds"] / max(info["iters"], 1), 2),
@@ -163,6 +171,7 @@ def bench_c1(pbgpu, torch, synth, dev, reps=3):
                    "form_bytes_per_node_iter": per, "relres_true": info["relres_true"]}
         if op == "stencil":
             out[op]["pass_form"] = sch
+            out[op]["coded"] = coded
     out["speedup_stencil_vs_dia"] = round(out["dia"]["iter_loop_ms"] / out["stencil"]["iter_loop_ms"], 2)
     del sm
     torch.cuda.empty_cache()
@@ -187,7 +196,8 @@ def bench_slab(pbgpu, torch, synth, dev, iters=200):
     del sm
     torch.cuda.empty_cache()
     return {"grid": [g.nx, g.ny, g.nz], "iters": best["iters"], "us_per_iter": round(us, 2),
-            "algorithmic_gbs": round(ITER_BYTES * n / us / 1e3, 1), "tuning": tun}
+            "algorithmic_gbs": round(ITER_BYTES * n / us / 1e3, 1),
+            "form_bytes_per_node_iter": form_bytes(tun["scheme"], best["coded_launches"] > 0), "tuning": tun}
 
 
 def bench_solvation(pbgpu, torch, synth, dev, reps=2):
@@ -416,6 +426,8 @@ def main():
     ap.add_argument("--tuning", default="",
                     help="block,groups,zchunk,grid,scheme[,streaming]: use this tiling instead of autotuning "
                          "(profiled runs; streaming 1/0 = nontemporal/cached, default the shape's own)")
+    ap.add_argument("--coded", type=int, default=1, choices=(0, 1),
+                    help="coded-coefficient 40-byte pass (1, the library default) or the uncoded pass (0)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one untimed 512 MiB device copy first (counter calibration under rocprofv3)")
     ap.add_argument("--forms-only", default="",
@@ -435,6 +447,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    pbgpu.set_coded_coefficients(bool(args.coded))
     if args.forms_only:
         for name in args.forms_only.split(","):
             print(json.dumps({"form": name, "result": FORMS[name](pbgpu, torch, synth, dev)}), flush=True)
@@ -496,6 +509,9 @@ def main():
 
     iters = sum(i["iters"] for i in infos)
     launches = sum(i["kernel_launches"] for i in infos)
+    coded_launches = sum(i["coded_launches"] for i in infos)
+    coded = coded_launches == launches and launches > 0
+    fbytes = form_bytes(scheme, coded)
     ksec = sum(i["kernel_seconds"] for i in infos)
     total_bytes = launch_bytes(n, iters, launches)
     value = total_bytes / wall / 1e9
@@ -506,9 +522,12 @@ def main():
                 "frac": round(achieved / PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic, 0),
                 "kernel": f"k_jpcg_fused<float, {tuning['block']}, {tuning['groups']}, {scheme}, false, "
-                          f"{'true' if tuning.get('streaming') else 'false'}> (persistent, "
-                          f"one launch per inner solve; algorithmic {ITER_BYTES} B/unknown/iteration, this pass "
-                          f"form moves {PASS_BYTES_BY_SCHEME[scheme]} B)",
+                          f"{'true' if tuning.get('streaming') else 'false'}, {'true' if coded else 'false'}> "
+                          f"(persistent, one launch per inner solve; algorithmic {ITER_BYTES} B/unknown/iteration "
+                          f"with the four operator arrays at 4 B each, this pass form moves {fbytes} B"
+                          f"{' reading the operator as one 4-byte code word' if coded else ''})",
+                "form_bytes_per_unknown_iter": fbytes,
+                "form_gbs": round(float(n) * fbytes * iters / ksec / 1e9, 1),
                 "bytes_per_launch": round(total_bytes / launches, 0),
                 "avg_launch_ms": round(1e3 * ksec / launches, 4),
                 "copy_ceiling_gbs": ceiling}
@@ -574,8 +593,9 @@ def main():
             "jpcg_kernel_ms_per_step": round(1e3 * ksec / args.steps, 3),
             "jpcg_iters_per_s": round(iters / ksec, 1),
             "jpcg_iter_us": round(1e6 * ksec / iters, 2),
-            "pass_form": scheme, "pass_form_bytes_per_unknown_iter": PASS_BYTES_BY_SCHEME[scheme],
-            "pass_form_gbs": round(float(n) * PASS_BYTES_BY_SCHEME[scheme] * iters / ksec / 1e9, 1),
+            "pass_form": scheme, "coded_coefficients": coded, "coded_launches_per_step": coded_launches / args.steps,
+            "pass_form_bytes_per_unknown_iter": fbytes,
+            "pass_form_gbs": round(float(n) * fbytes * iters / ksec / 1e9, 1),
             "relres_true_gpu": last["relres_true"], "relres_true_oracle": relres_oracle,
             "energy_kcal": e, "energy_oracle_of_gpu_phi": e_oracle,
             "solves_per_s": round(args.steps / wall, 3),

@@ -97,6 +97,9 @@ typedef struct {
     double relres_true;     /* ||b - A x||/||b|| recomputed in FP64 with the FP64 coefficients */
     double seconds;         /* wall time of the call */
     double kernel_seconds;  /* summed duration of those launches / loops, from HIP events on `stream` */
+    int32_t coded_launches; /* of kernel_launches, those whose pass read coded coefficients (see
+                               pb_set_coded_coefficients); 0 outside pb_solve */
+    int32_t reserved;       /* zero */
 } pb_info;
 
 /* Library version string (static storage). */
@@ -269,6 +272,29 @@ pb_status pb_set_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t precision, c
  * no feasible tiling: nx too large for the in-plane halo).
  */
 pb_status pb_get_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t precision, pb_tuning* out);
+
+/*
+ * Coded coefficients (FP32 stencil solves with the 40-byte pass form, free
+ * boundary). The operator of Eq. 3 built from the two-point dielectric model
+ * takes few distinct values: three edge dielectrics over h^2 (and zero at
+ * the faces) and a few dozen diagonals. When the FP32 couplings cx, cy, cz
+ * and the diagonal together hold at most 256 distinct values, pb_solve
+ * stores one 4-byte word of dictionary codes per node (in workspace the
+ * 40-byte form leaves unused) and the pass reads it instead of the four FP32
+ * arrays: 28 bytes per node per iteration instead of 40. The decoded values
+ * are the FP32 coefficients themselves, so potentials, iteration counts and
+ * residuals are bitwise those of the uncoded pass. Otherwise (more values,
+ * or a grid of fewer than 8,450 padded positions) the uncoded pass runs.
+ * pb_info.coded_launches reports which ran. Building the dictionary reads
+ * the operator arrays once more and reads one flag back to the host per
+ * inner solve.
+ *
+ * pb_set_coded_coefficients(0) turns the coded pass off for the process;
+ * 1 (the default) turns it back on. pb_get_coded_coefficients returns the
+ * setting. Not synchronised with solves running on other threads.
+ */
+void pb_set_coded_coefficients(int32_t on);
+int32_t pb_get_coded_coefficients(void);
 
 /*
  * pb_tiling_candidates: the feasible tilings of the fused stencil kernel for

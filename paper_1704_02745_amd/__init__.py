@@ -32,7 +32,7 @@ OPERATORS = {"stencil": 0, "dia": 1, "mg": 2}
 # Every entry point declared in include/pbgpu.h.
 EXPORTS = ("pb_version", "pb_last_error", "pb_setup_workspace_bytes", "pb_setup",
            "pb_solve_workspace_bytes", "pb_solve", "pb_autotune", "pb_set_tuning", "pb_tiling_candidates",
-           "pb_get_tuning",
+           "pb_get_tuning", "pb_set_coded_coefficients", "pb_get_coded_coefficients",
            "pb_batch_workspace_bytes", "pb_solve_batch", "pb_batch_set_zchunk", "pb_batch_get_zchunk",
            "pb_batch_autotune_workspace_bytes", "pb_batch_autotune", "pb_batch_graph_create", "pb_batch_graph_launch",
            "pb_batch_graph_results", "pb_batch_graph_is_cooperative", "pb_batch_graph_destroy",
@@ -73,10 +73,13 @@ class Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("kernel_launches", ctypes.c_int32),
                 ("relres_recur", ctypes.c_double), ("relres_true", ctypes.c_double),
-                ("seconds", ctypes.c_double), ("kernel_seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("kernel_seconds", ctypes.c_double),
+                ("coded_launches", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d.pop("reserved")
+        return d
 
 
 class Tuning(ctypes.Structure):
@@ -131,6 +134,10 @@ def _load():
     lib.pb_set_tuning.argtypes = [i32, i32, i32, i32, ctypes.POINTER(Tuning)]
     lib.pb_get_tuning.restype = ctypes.c_int
     lib.pb_get_tuning.argtypes = [i32, i32, i32, i32, ctypes.POINTER(Tuning)]
+    lib.pb_set_coded_coefficients.restype = None
+    lib.pb_set_coded_coefficients.argtypes = [i32]
+    lib.pb_get_coded_coefficients.restype = i32
+    lib.pb_get_coded_coefficients.argtypes = []
     lib.pb_tiling_candidates.restype = ctypes.c_int
     lib.pb_tiling_candidates.argtypes = [i32, i32, i32, i32, ctypes.POINTER(Tuning), i32, ctypes.POINTER(i32)]
     P = ctypes.POINTER(Problem)
@@ -349,6 +356,16 @@ def set_tuning(nx, ny, nz, precision, block, groups, zchunk, grid, scheme=0, str
     t.block, t.groups, t.zchunk, t.grid = int(block), int(groups), int(zchunk), int(grid)
     t.scheme, t.streaming = int(scheme), int(streaming)
     _check(lib.pb_set_tuning(int(nx), int(ny), int(nz), PRECISIONS[precision], ctypes.byref(t)))
+
+
+def set_coded_coefficients(on: bool) -> None:
+    """Process-wide switch of the coded-coefficient 40-byte FP32 pass (on by
+    default; used when the operator holds at most 256 distinct FP32 values)."""
+    lib.pb_set_coded_coefficients(1 if on else 0)
+
+
+def get_coded_coefficients() -> bool:
+    return bool(lib.pb_get_coded_coefficients())
 
 
 def get_tuning(nx, ny, nz, precision="f32") -> dict:

@@ -272,7 +272,7 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
     if (e != PB_OK) return e;
 
     SolveResult r{};
-    int total_iters = 0, outer = 0, launches = 0;
+    int total_iters = 0, outer = 0, launches = 0, coded_launches = 0;
     double ksec = 0.0;
     double relres_recur = 0.0;
     pb_status status = PB_OK;
@@ -294,6 +294,7 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
         e = run_inner<float>(L, s, w, op, per, opts->tol, maxiter, st, &r);
         if (e != PB_OK) return e;
         ++launches;
+        coded_launches += r.coded;
         ksec += r.kernel_seconds;
         status = (pb_status)r.status;
         total_iters = r.iters;
@@ -331,6 +332,11 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
             e = run_inner<float>(L, s, w, op, per, inner_tol, maxiter, st, &r);
             if (e != PB_OK) return e;
             ++launches;
+            coded_launches += r.coded;
+            if (r.coded && op == PB_OP_STENCIL) {   // the operator is the same for every inner solve
+                s.codes_valid = 1;
+                s.ctab = r.ctab;
+            }
             ksec += r.kernel_seconds;
             total_iters += r.iters;
             if (r.status < 0) { status = (pb_status)r.status; break; }
@@ -363,6 +369,8 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         info->kernel_launches = launches;
         info->kernel_seconds = ksec;
+        info->coded_launches = coded_launches;
+        info->reserved = 0;
     }
     return status;
 }
@@ -399,6 +407,9 @@ extern "C" pb_status pb_autotune(int32_t nx, int32_t ny, int32_t nz, double h, c
     if (e != PB_OK) return e;
     return autotune_impl<float>(L, s, w, iters_per_trial, st, best);
 }
+
+extern "C" void pb_set_coded_coefficients(int32_t on) { set_coded_coefficients(on); }
+extern "C" int32_t pb_get_coded_coefficients(void) { return coded_coefficients(); }
 
 extern "C" pb_status pb_get_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t precision, pb_tuning* out) {
     PB_ARG(dims_ok(nx, ny, nz) && out, "pb_get_tuning: bad dims or null output");

@@ -42,6 +42,7 @@
 #include "solver.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -74,6 +75,8 @@ struct KArgs {
     SyncState* S;
     double* partials;
     long long timeout_ticks;
+    const float* cw;     // coded 40-byte pass: one word of coefficient codes per position (bit patterns)
+    const float* ctab;   // and the dictionary (kCodedTableSize values)
 };
 
 __device__ __forceinline__ double ld_agent_d(const double* p) {
@@ -282,6 +285,7 @@ __device__ __forceinline__ void sstore(T* p, const typename Vec<T>::type& v) {
 // function, so the preconditioner is the same fixed positive diagonal in the
 // direction update and in the dot products.
 __device__ __forceinline__ float jacobi_inv(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ uint32_t bits(float f) { return __float_as_uint(f); }
 __device__ __forceinline__ double jacobi_inv(double d) { return 1.0 / d; }
 
 template <typename T>
@@ -760,13 +764,19 @@ __device__ void pass_tile(const KArgs<T>& a, int tile, int o, int n, T alpha, T 
 // summed in one fixed order (x, then y, then z). Every evaluation of the
 // operator in the 40-byte pass goes through this function, so a node's value
 // recomputed in a tile's halo is the one its own tile computes.
+// (A v)_n at one node. The rounding is fixed by explicit fused multiply-adds
+// (no compiler contraction), so every kernel variant computes the same value.
 template <typename T>
 __device__ __forceinline__ T apply_point(T d, T v, T cr, T vr, T cl, T vl, T cu, T vu, T cd, T vd, T ca, T va, T cb,
                                          T vb) {
-    T nb = cr * vr + cl * vl;
-    nb += cu * vu + cd * vd;
-    nb += ca * va + cb * vb;
-    return d * v - nb;
+#pragma clang fp contract(off)
+    T nb = cr * vr;
+    nb = fma(cl, vl, nb);
+    nb = fma(cu, vu, nb);
+    nb = fma(cd, vd, nb);
+    nb = fma(ca, va, nb);
+    nb = fma(cb, vb, nb);
+    return fma(d, v, -nb);
 }
 
 // One pass on one tile, 40-byte form: the same iteration as pass_tile, but
@@ -783,9 +793,17 @@ __device__ __forceinline__ T apply_point(T d, T v, T cr, T vr, T cl, T vl, T cu,
 // build planes k0-1 and k0 of p_{l-1}. Threads: own positions s + tid*VEC,
 // inner ring groups on the first 2*halo/VEC threads, outer ring groups on the
 // last 2*halo/VEC threads (the tiling guarantees 2*halo/VEC <= BS).
-template <typename T, int BS, bool NT>
+//
+// CD (FP32 only): the operator is read as one word of dictionary codes per
+// position from a.cw and decoded through the table `ctb` in LDS. The loads
+// keep the raw words in the coupling fields of Ld; each step decodes them
+// before use, with zero words (code 0 = +0.0) where the uncoded pass loads
+// nothing, so both forms see the same values everywhere.
+template <typename T, int BS, bool NT, bool CD>
 __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, T beta, T* lds,
-                            double (&acc)[NPART]) {
+                            const float* ctb, double (&acc)[NPART]) {
+#pragma clang fp contract(off)
+    static_assert(!CD || sizeof(T) == 4, "coded coefficients are an FP32 form");
     constexpr int W = Vec<T>::n;
     using V = typename Vec<T>::type;
     const TileBox tb = tile_box(a, tile);
@@ -810,6 +828,7 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
     const T* __restrict__ CY = a.op.cy;
     const T* __restrict__ CZ = a.op.cz;
     const T* __restrict__ DD = a.op.d;
+    const T* __restrict__ CW = reinterpret_cast<const T*>(a.cw);
     const bool do_x = alpha != T(0);
     const V z0 = vzero<T>();
 
@@ -837,10 +856,22 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
         const bool vm = km >= 0, vc = kc >= 0;
         po_m = (valid && vm) ? vload(pold + (int64_t)km * sp + pos) : z0;
         po_c = (valid && vc) ? vload(pold + (int64_t)kc * sp + pos) : z0;
-        cz_c = (valid && vm) ? vload(CZ + (int64_t)km * sp + pos) : z0;
+        if constexpr (CD) {
+            const V w = (valid && vm) ? vload(CW + (int64_t)km * sp + pos) : z0;
+#pragma unroll
+            for (int u = 0; u < W; ++u) vget(cz_c, u) = ctb[(bits(vget(w, u)) >> 16) & 255u];
+        } else {
+            cz_c = (valid && vm) ? vload(CZ + (int64_t)km * sp + pos) : z0;
+        }
         hpo_m = (h_in && vm) ? vload(pold + (int64_t)km * sp + hp) : z0;
         hpo_c = (h_in && vc) ? vload(pold + (int64_t)kc * sp + hp) : z0;
-        hcz_c = (h_in && vm) ? vload(CZ + (int64_t)km * sp + hp) : z0;
+        if constexpr (CD) {
+            const V w = (h_in && vm) ? vload(CW + (int64_t)km * sp + hp) : z0;
+#pragma unroll
+            for (int u = 0; u < W; ++u) vget(hcz_c, u) = ctb[(bits(vget(w, u)) >> 16) & 255u];
+        } else {
+            hcz_c = (h_in && vm) ? vload(CZ + (int64_t)km * sp + hp) : z0;
+        }
         const V o_po = (o_in && vc) ? vload(pold + (int64_t)kc * sp + op) : z0;
         T* P = (kc & 1) ? PO1 : PO0;
         if (valid) vstore(P + (pos - obase), po_c);
@@ -876,14 +907,21 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
             if (v2) L.po_n = sload<NT>(pold + (int64_t)kf * sp + pos);
             if (v1) {
                 L.r_o = sload<NT>(rold + g1);
-                L.d_n = sload<NT>(DD + g1);
+                if constexpr (!CD) L.d_n = sload<NT>(DD + g1);
                 if (xu) L.x_n = sload<NT>(a.x + g1);
-                L.cx_n = vload(CX + g1);
-                L.cy_n = vload(CY + g1);
-                L.cz_n = sload<NT>(CZ + g1);
-                L.cxm_n = pos >= 1 ? CX[g1 - 1] : T(0);
+                if constexpr (CD) {   // raw code words; d_n above is replaced at decode
+                    L.cx_n = sload<NT>(CW + g1);
+                    L.cxm_n = pos >= 1 ? CW[g1 - 1] : T(0);
 #pragma unroll
-                for (int u = 0; u < W; ++u) L.cym_n[u] = (pos + u - nx >= 0) ? CY[g1 + u - nx] : T(0);
+                    for (int u = 0; u < W; ++u) L.cym_n[u] = (pos + u - nx >= 0) ? CW[g1 + u - nx] : T(0);
+                } else {
+                    L.cx_n = vload(CX + g1);
+                    L.cy_n = vload(CY + g1);
+                    L.cz_n = sload<NT>(CZ + g1);
+                    L.cxm_n = pos >= 1 ? CX[g1 - 1] : T(0);
+#pragma unroll
+                    for (int u = 0; u < W; ++u) L.cym_n[u] = (pos + u - nx >= 0) ? CY[g1 + u - nx] : T(0);
+                }
             }
         }
         L.hpo_n = z0; L.h_r = z0; L.h_d = z0; L.h_cx = z0; L.h_cy = z0; L.h_cz = z0;
@@ -894,15 +932,25 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
             if (v2) L.hpo_n = vload(pold + (int64_t)kf * sp + hp);
             if (v1) {
                 const int64_t gh = (int64_t)kn * sp + hp;
-                L.h_cz = vload(CZ + gh);
-                if (own1) {
-                    L.h_r = vload(rold + gh);
-                    L.h_d = vload(DD + gh);
-                    L.h_cx = vload(CX + gh);
-                    L.h_cy = vload(CY + gh);
-                    L.h_cxm = hp >= 1 ? CX[gh - 1] : T(0);
+                if constexpr (CD) {   // raw code words (cz is needed on every plane)
+                    L.h_cx = vload(CW + gh);
+                    if (own1) {
+                        L.h_r = vload(rold + gh);
+                        L.h_cxm = hp >= 1 ? CW[gh - 1] : T(0);
 #pragma unroll
-                    for (int u = 0; u < W; ++u) L.h_cym[u] = (hp + u - nx >= 0) ? CY[gh + u - nx] : T(0);
+                        for (int u = 0; u < W; ++u) L.h_cym[u] = (hp + u - nx >= 0) ? CW[gh + u - nx] : T(0);
+                    }
+                } else {
+                    L.h_cz = vload(CZ + gh);
+                    if (own1) {
+                        L.h_r = vload(rold + gh);
+                        L.h_d = vload(DD + gh);
+                        L.h_cx = vload(CX + gh);
+                        L.h_cy = vload(CY + gh);
+                        L.h_cxm = hp >= 1 ? CX[gh - 1] : T(0);
+#pragma unroll
+                        for (int u = 0; u < W; ++u) L.h_cym[u] = (hp + u - nx >= 0) ? CY[gh + u - nx] : T(0);
+                    }
                 }
             }
         }
@@ -939,6 +987,35 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
         V& hpo_n = cur.hpo_n; V& h_r = cur.h_r; V& h_d = cur.h_d; V& h_cx = cur.h_cx; V& h_cy = cur.h_cy;
         V& h_cz = cur.h_cz; T& h_cxm = cur.h_cxm; T (&h_cym)[W] = cur.h_cym;
         const V& o_po = cur.o_po;
+        if constexpr (CD) {
+            // own positions: the word of each node, then the left x-coupling
+            // (byte 0 of the word to the left) and the y-couplings below
+            // (byte 1 of the words one row down)
+            const V w = cx_n;
+#pragma unroll
+            for (int u = 0; u < W; ++u) {
+                const uint32_t c = bits(vget(w, u));
+                vget(cx_n, u) = ctb[c & 255u];
+                vget(cy_n, u) = ctb[(c >> 8) & 255u];
+                vget(cz_n, u) = ctb[(c >> 16) & 255u];
+                vget(d_n, u) = ctb[c >> 24];
+                cym_n[u] = ctb[(bits(cym_n[u]) >> 8) & 255u];
+            }
+            cxm_n = ctb[bits(cxm_n) & 255u];
+            // inner ring: cz on every plane; the rest only where the uncoded
+            // pass loads it (owned planes), zero elsewhere
+            const V hw = h_cx;
+#pragma unroll
+            for (int u = 0; u < W; ++u) {
+                const uint32_t c = bits(vget(hw, u));
+                vget(h_cz, u) = ctb[(c >> 16) & 255u];
+                vget(h_cx, u) = own1 ? ctb[c & 255u] : T(0);
+                vget(h_cy, u) = own1 ? ctb[(c >> 8) & 255u] : T(0);
+                vget(h_d, u) = own1 ? ctb[c >> 24] : T(0);
+                h_cym[u] = ctb[(bits(h_cym[u]) >> 8) & 255u];
+            }
+            h_cxm = ctb[bits(h_cxm) & 255u];
+        }
 
         // ---- q_{l-1}, r_{l-1}, p_{l-1} (and x) on plane k+1, own positions
         V pn_n = z0, rn_n = z0;
@@ -953,10 +1030,10 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
                 const T qo = apply_point(vget(d_n, u), vget(po_c, u), vget(cx_n, u), pr, cl, pl, vget(cy_n, u),
                                          POc[l + u + nx], cym_n[u], POc[l + u - nx], vget(cz_n, u), vget(po_n, u),
                                          vget(cz_c, u), vget(po_m, u));
-                const T r = vget(r_o, u) - alpha * qo;
+                const T r = fma(-alpha, qo, vget(r_o, u));
                 vget(rn_n, u) = r;
-                vget(pn_n, u) = r * jacobi_inv(vget(d_n, u)) + beta * vget(po_c, u);
-                if (xu) vget(x_n, u) = vget(x_n, u) + alpha * vget(po_c, u);
+                vget(pn_n, u) = fma(beta, vget(po_c, u), r * jacobi_inv(vget(d_n, u)));
+                if (xu) vget(x_n, u) = fma(alpha, vget(po_c, u), vget(x_n, u));
             }
             vstore(PNn + (pos - nbase), pn_n);
             if (own1) {
@@ -981,8 +1058,8 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
                     const T qo = apply_point(vget(h_d, u), vget(hpo_c, u), vget(h_cx, u), pr, cl, pl, vget(h_cy, u),
                                              POc[l + u + nx], h_cym[u], POc[l + u - nx], vget(h_cz, u),
                                              vget(hpo_n, u), vget(hcz_c, u), vget(hpo_m, u));
-                    const T r = vget(h_r, u) - alpha * qo;
-                    vget(hv, u) = r * jacobi_inv(vget(h_d, u)) + beta * vget(hpo_c, u);
+                    const T r = fma(-alpha, qo, vget(h_r, u));
+                    vget(hv, u) = fma(beta, vget(hpo_c, u), r * jacobi_inv(vget(h_d, u)));
                 }
             }
             vstore(PNn + (hp - nbase), hv);
@@ -1007,13 +1084,13 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
                 const T iv = jacobi_inv(vget(d_c, u));
                 const double pd = (double)p, qd = (double)qq, rd = (double)vget(rn_c, u);
                 const double zd = (double)(vget(rn_c, u) * iv), wd = (double)(qq * iv);
-                acc[0] += pd * qd;
-                acc[1] += rd * zd;
-                acc[2] += rd * wd;
-                acc[3] += qd * wd;
-                acc[4] += rd * rd;
-                acc[5] += rd * qd;
-                acc[6] += qd * qd;
+                acc[0] = fma(pd, qd, acc[0]);
+                acc[1] = fma(rd, zd, acc[1]);
+                acc[2] = fma(rd, wd, acc[2]);
+                acc[3] = fma(qd, wd, acc[3]);
+                acc[4] = fma(rd, rd, acc[4]);
+                acc[5] = fma(rd, qd, acc[5]);
+                acc[6] = fma(qd, qd, acc[6]);
             }
         }
         // ---- p_{l-2} of plane k+2 and the couplings of plane k+1 into LDS
@@ -1081,13 +1158,21 @@ struct Scal {
 // Every workgroup derives the scalars (alpha, beta, stopping test) itself
 // from the identically reduced tile sums; workgroup 0 also persists them in
 // S for the host and for a resumed launch.
-template <typename T, int BS, int MC, int SCH, bool PER, bool NT>
+template <typename T, int BS, int MC, int SCH, bool PER, bool NT, bool CD>
 __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsigned char* lds_raw) {
     static_assert(SCH == 0 || MC == 1, "the 40-byte pass takes one vector group per thread");
     static_assert(!PER || SCH == 0, "the periodic boundary uses the pass that stores A.p");
+    static_assert(!CD || SCH == 1, "coded coefficients are read by the 40-byte pass");
     const int lds_len = a.seglen + 2 * a.halo;
     T* lds0 = reinterpret_cast<T*>(lds_raw);
     T* lds1 = lds0 + lds_len;
+    // coded form: the dictionary after the 40-byte pass's plane buffers
+    float* tb = nullptr;
+    if constexpr (CD) {
+        tb = reinterpret_cast<float*>(lds0 + 2 * (size_t)(a.seglen + 4 * a.halo) + 6 * (size_t)(a.seglen + 2 * a.halo));
+        for (int i = threadIdx.x; i < kCodedTableSize; i += BS) tb[i] = a.ctab[i];
+        __syncthreads();
+    }
     __shared__ double red[red_len<BS>()];
     __shared__ int s_flag;
     __shared__ Scal sc;
@@ -1141,7 +1226,7 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
         for (int t = first; t < end; t += stride) {
             double acc[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             if constexpr (SCH == 1)
-                pass_tile40<T, BS, NT>(a, t, o, n, alpha, beta, lds0, acc);
+                pass_tile40<T, BS, NT, CD>(a, t, o, n, alpha, beta, lds0, tb, acc);
             else
                 pass_tile<T, BS, MC, PER, NT>(a, t, o, n, alpha, beta, lds0, lds1, acc);
             tile_reduce_store<BS, NPART>(acc, red, sums(b) + (size_t)t * kMaxPartials);
@@ -1190,10 +1275,10 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
     }
 }
 
-template <typename T, int BS, int MC, int SCH, bool PER, bool NT>
+template <typename T, int BS, int MC, int SCH, bool PER, bool NT, bool CD = false>
 __global__ __launch_bounds__(BS) void k_jpcg_fused(KArgs<T> a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    run_problem<T, BS, MC, SCH, PER, NT>(a, blockIdx.x, gridDim.x, true, lds_raw);
+    run_problem<T, BS, MC, SCH, PER, NT, CD>(a, blockIdx.x, gridDim.x, true, lds_raw);
 }
 
 // Many independent problems in one launch: workgroups [first[p], first[p+1])
@@ -1210,7 +1295,8 @@ __global__ __launch_bounds__(BS) void k_jpcg_batch(const KArgs<T>* __restrict__ 
         if (first[mid] <= (int)blockIdx.x) lo = mid; else hi = mid;
     }
     const KArgs<T> a = probs[lo];
-    run_problem<T, BS, MC, SCH, false, NT>(a, blockIdx.x - first[lo], first[lo + 1] - first[lo], false, lds_raw);
+    run_problem<T, BS, MC, SCH, false, NT, false>(a, blockIdx.x - first[lo], first[lo + 1] - first[lo], false,
+                                                  lds_raw);
 }
 
 // ------------------------------------------------------------------ host side
@@ -1242,11 +1328,27 @@ using KernelFn = const void*;
 struct Variant {
     int bs, mc, scheme, per, nt;
     KernelFn fn;
+    int cd = 0;   // 1: reads coded coefficients (chosen per solve, never by the tiling search)
 };
 
+// Coded forms of the 40-byte pass (FP32 only).
 template <typename T>
-const std::vector<Variant>& variants() {
-    static const std::vector<Variant> v = {
+std::vector<Variant> coded_variants() {
+    return {};
+}
+template <>
+std::vector<Variant> coded_variants<float>() {
+    return {
+        {256, 1, 1, 0, 0, (KernelFn)k_jpcg_fused<float, 256, 1, 1, false, false, true>, 1},
+        {512, 1, 1, 0, 0, (KernelFn)k_jpcg_fused<float, 512, 1, 1, false, false, true>, 1},
+        {256, 1, 1, 0, 1, (KernelFn)k_jpcg_fused<float, 256, 1, 1, false, true, true>, 1},
+        {512, 1, 1, 0, 1, (KernelFn)k_jpcg_fused<float, 512, 1, 1, false, true, true>, 1},
+    };
+}
+
+template <typename T>
+std::vector<Variant> base_variants() {
+    return {
         {256, 1, 0, 0, 0, (KernelFn)k_jpcg_fused<T, 256, 1, 0, false, false>},
         {256, 2, 0, 0, 0, (KernelFn)k_jpcg_fused<T, 256, 2, 0, false, false>},
         {512, 1, 0, 0, 0, (KernelFn)k_jpcg_fused<T, 512, 1, 0, false, false>},
@@ -1264,6 +1366,15 @@ const std::vector<Variant>& variants() {
         {256, 1, 0, 1, 1, (KernelFn)k_jpcg_fused<T, 256, 1, 0, true, true>},
         {512, 1, 0, 1, 1, (KernelFn)k_jpcg_fused<T, 512, 1, 0, true, true>},
     };
+}
+
+template <typename T>
+const std::vector<Variant>& variants() {
+    static const std::vector<Variant> v = [] {
+        std::vector<Variant> all = base_variants<T>();
+        for (const Variant& c : coded_variants<T>()) all.push_back(c);
+        return all;
+    }();
     return v;
 }
 
@@ -1359,7 +1470,7 @@ Tiling choose_tiling_impl(const Layout& L, int want_bs, int want_mc, int max_per
     for (const auto& v : variants<T>()) {
         if ((want_bs > 0 && v.bs != want_bs) || (want_mc > 0 && v.mc != want_mc)) continue;
         if (want_scheme >= 0 && v.scheme != want_scheme) continue;
-        if (v.per != want_per || v.nt != want_nt) continue;
+        if (v.per != want_per || v.nt != want_nt || v.cd) continue;
         Tiling t = tiling_for<T>(L, v, cus, max_per_cu);
         if (t.grid <= 0) continue;
         // model: bytes of one tile (planes incl. the extra ones below, segment
@@ -1415,7 +1526,7 @@ template <typename T>
 std::vector<Tiling> tiling_candidates(const Layout& L) {
     std::vector<Tiling> out;
     for (const auto& v : variants<T>()) {
-        if (v.per) continue;   // periodic solves use their own default tiling
+        if (v.per || v.cd) continue;   // periodic solves use their own default tiling; coding is per solve
         for (int cap : {1, 2, 3, 4, 0}) {
             const Tiling t = choose_tiling_impl<T>(L, v.bs, v.mc, cap, v.scheme, 0, v.nt);
             if (t.grid <= 0) continue;
@@ -1464,13 +1575,48 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
     }
     KernelFn fn = nullptr;
     for (const auto& v : variants<T>())
-        if (v.bs == t.bs && v.mc == t.mc && v.scheme == t.scheme && v.per == t.per && v.nt == t.nt) fn = v.fn;
+        if (!v.cd && v.bs == t.bs && v.mc == t.mc && v.scheme == t.scheme && v.per == t.per && v.nt == t.nt)
+            fn = v.fn;
     if (!fn) {
         set_error("fused JPCG: unknown kernel variant bs=%d mc=%d scheme=%d periodic=%d streaming=%d", t.bs, t.mc,
                   t.scheme, t.per, t.nt);
         return PB_ERR_ARG;
     }
     const DevInfo di = dev_info();
+    // Coded coefficients (40-byte FP32 pass): the same tiling with the
+    // operator read as code words, when the operator's values fit the
+    // dictionary and the coded kernel keeps the grid co-resident. The code
+    // words go to q2 and the dictionary to q, which this pass form leaves
+    // unused.
+    size_t lds = t.lds;
+    const float* cw = nullptr;
+    const float* ctab = nullptr;
+    int coded = 0;
+    if constexpr (sizeof(T) == 4) {
+        if (t.scheme == 1 && !t.per && coded_coefficients() && s.q && s.q2 &&
+            (size_t)L.npad * sizeof(float) >= coded_scratch_bytes()) {
+            KernelFn cfn = nullptr;
+            for (const auto& v : variants<T>())
+                if (v.cd && v.bs == t.bs && v.mc == t.mc && v.nt == t.nt) cfn = v.fn;
+            const size_t clds = t.lds + sizeof(float) * kCodedTableSize;
+            const int cus = di.cus > 0 ? di.cus : 256;
+            if (cfn && (int64_t)max_coresident(cfn, t.bs, clds) * cus >= t.grid) {
+                bool fits = s.codes_valid != 0;
+                const float* tab = s.ctab;
+                if (!fits) {
+                    const pb_status e = build_codes(s.op, L.npad, (void*)s.q, (uint32_t*)s.q2, st, fits, &tab);
+                    if (e != PB_OK) return e;
+                }
+                if (fits) {
+                    fn = cfn;
+                    lds = clds;
+                    cw = (const float*)s.q2;
+                    ctab = tab;
+                    coded = 1;
+                }
+            }
+        }
+    }
     KArgs<T> a{};
     a.op = s.op;
     a.b = s.b;
@@ -1490,6 +1636,8 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
     a.warm = s.warm;
     a.S = sync;
     a.partials = partials;
+    a.cw = cw;
+    a.ctab = ctab;
     // every wait is bounded: 20 s of the constant-rate clock
     a.timeout_ticks = (long long)(di.wallclock_khz > 0 ? di.wallclock_khz : 100000) * 1000LL * 20LL;
     // the header (barrier counters, scalars) starts cleared
@@ -1502,12 +1650,12 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
         PB_HIP(hipEventCreate(&ev[1]));
         PB_HIP(hipEventRecord(ev[0], st));
     }
-    const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(t.grid), dim3(t.bs), args, t.lds, st);
+    const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(t.grid), dim3(t.bs), args, lds, st);
     if (e != hipSuccess) {
         if (ev[0]) (void)hipEventDestroy(ev[0]);
         if (ev[1]) (void)hipEventDestroy(ev[1]);
-        set_error("fused JPCG launch failed: %s (grid %d, block %d, lds %zu)", hipGetErrorString(e), t.grid,
-                  t.bs, t.lds);
+        set_error("fused JPCG launch failed: %s (grid %d, block %d, lds %zu, coded %d)", hipGetErrorString(e),
+                  t.grid, t.bs, lds, coded);
         return PB_ERR_HIP;
     }
     if (res) {
@@ -1525,9 +1673,19 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
         res->bb = h.bb;
         res->kernel_seconds = 1e-3 * ms;
         res->tiling = t;
+        res->coded = coded;
+        res->ctab = ctab;
     }
     return PB_OK;
 }
+
+// ------------------------------------------------------------------ coded-coefficient switch
+
+namespace {
+std::atomic<int> g_coded{1};
+}
+void set_coded_coefficients(int on) { g_coded.store(on ? 1 : 0); }
+int coded_coefficients() { return g_coded.load(); }
 template pb_status fused_jpcg<float>(const Layout&, const SolveBufs<float>&, SyncState*, double*, double, int,
                                      hipStream_t, SolveResult*, const Tiling*, int);
 

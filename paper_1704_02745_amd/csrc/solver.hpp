@@ -59,6 +59,10 @@ struct SolveBufs {
     T* z;          // DIA form only
     T* dia;        // DIA form only: 7 diagonals x npad
     int warm;      // 1: x holds a nonzero initial guess
+    // fused FP32 40-byte form: the code words in q2 and the dictionary (ctab,
+    // inside q) were built for this operator by an earlier inner solve
+    int codes_valid;
+    const float* ctab;
 };
 
 struct SolveResult {
@@ -68,6 +72,8 @@ struct SolveResult {
     double bb;     // ||b||^2
     double kernel_seconds;   // duration of the iteration kernel / loop (HIP events)
     Tiling tiling;           // fused form: the tiling used
+    int coded;               // fused form: 1 when the pass read coded coefficients
+    const float* ctab;       // and the dictionary it used (device)
 };
 
 // jpcg.hip: one persistent cooperative launch running the whole iteration.
@@ -85,6 +91,20 @@ Tiling solve_tiling(const Layout& L, int periodic);
 // 1 when the shape's default is the streaming (nontemporal) kernel variant.
 template <typename T>
 int streaming_for(const Layout& L);
+
+// coded.hip: coded operator coefficients for the 40-byte FP32 pass. Up to
+// kCodedTableSize distinct values over cx, cy, cz and d; one 4-byte word of
+// codes per padded position (byte 0: cx, 1: cy, 2: cz, 3: d).
+constexpr int kCodedTableSize = 256;
+size_t coded_scratch_bytes();
+// Builds the dictionary in `scratch` (coded_scratch_bytes()) and, when the
+// values fit, the code words; fits = false leaves `codes` untouched. Reads one
+// flag back to the host (synchronises `st`). *table: the device dictionary.
+pb_status build_codes(const Op<float>& op, int64_t npad, void* scratch, uint32_t* codes, hipStream_t st,
+                      bool& fits, const float** table);
+// Process-wide switch (default on): 0 keeps every fused FP32 solve uncoded.
+void set_coded_coefficients(int on);
+int coded_coefficients();
 
 // mg.hip: multigrid-preconditioned CG (workspace for the coarse levels and
 // level 0's extra vectors; ex..k2 are the caller's FP64 edge arrays).

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(pbgpu):
 def test_struct_layouts(pbgpu):
     assert ctypes.sizeof(pbgpu.Grid) == 48
     assert ctypes.sizeof(pbgpu.SolveOpts) == 40
-    assert ctypes.sizeof(pbgpu.Info) == 48
+    assert ctypes.sizeof(pbgpu.Info) == 56 and pbgpu.Info.coded_launches.offset == 48
     assert pbgpu.SolveOpts.inner_tol.offset == 24
     assert pbgpu.Info.relres_recur.offset == 16
     assert ctypes.sizeof(pbgpu.Tuning) == 40

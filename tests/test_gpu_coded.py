@@ -1,0 +1,184 @@
+"""Coded coefficients in the 40-byte FP32 pass (pb_set_coded_coefficients).
+
+The operator of Eq. 3 built from the two-point dielectric model holds few
+distinct FP32 values, so its solves read one word of dictionary codes per node
+instead of the four coefficient arrays. The decoded values are the
+coefficients themselves, so:
+
+- every coded solve gives bitwise the potential and the iteration count of
+  the uncoded pass with the same tiling (every feasible 40-byte tiling:
+  256/512 threads, cached and streaming accesses);
+- it reaches the oracle's solution within the FP32 bound, also under FP64
+  refinement and at the benchmark's 257^3 size;
+- operators with more than 256 distinct values, and grids too small for the
+  dictionary's scratch, run the uncoded pass (pb_info.coded_launches = 0).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import fdpb, pcg
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def pb():
+    import paper_1704_02745_amd as m
+    m.set_coded_coefficients(True)
+    yield m
+    m.set_coded_coefficients(True)
+
+
+def gpu_setup(pb, prob):
+    g = prob.grid
+    return pb.setup(g, prob.mol.xyz, prob.mol.radius, prob.mol.charge, prob.eps_in, prob.eps_out, prob.kappa_d2,
+                    device=DEV)
+
+
+def forty_byte_tilings(pb, dims, prec="f32"):
+    return [c for c in pb.tiling_candidates(*dims, prec) if c["scheme"] == 1]
+
+
+def pin(pb, dims, prec, c):
+    pb.set_tuning(*dims, prec, c["block"], c["groups"], c["zchunk"], c["grid"], c["scheme"], c["streaming"])
+
+
+def coded_and_uncoded(pb, sysm, **kw):
+    pb.set_coded_coefficients(True)
+    x1, i1 = pb.solve(sysm, **kw)
+    pb.set_coded_coefficients(False)
+    try:
+        x0, i0 = pb.solve(sysm, **kw)
+    finally:
+        pb.set_coded_coefficients(True)
+    return x1, i1, x0, i0
+
+
+def restore_default(pb, sysm, prec="f32"):
+    best = pb.autotune(sysm, precision=prec, iters_per_trial=3)
+    assert best["grid"] > 0
+
+
+@pytest.mark.parametrize("dims,natoms,seed", [((61, 53, 47), 300, 9), ((65, 65, 65), 500, 3),
+                                              ((97, 37, 29), 200, 5)])
+def test_coded_equals_uncoded_every_tiling(pb, dims, natoms, seed):
+    prob = synth.small_problem(*dims, natoms, seed=seed, precision="f32")
+    ref = fdpb.assemble_problem(prob)
+    exact = pcg.jpcg(ref, 1e-13, maxiter=20000).x
+    sysm = gpu_setup(pb, prob)
+    cands = forty_byte_tilings(pb, dims)
+    assert cands and {c["streaming"] for c in cands} == {0, 1}, cands
+    try:
+        for c in cands:
+            pin(pb, dims, "f32", c)
+            print(f"coded {dims} {c}", flush=True)
+            x1, i1, x0, i0 = coded_and_uncoded(pb, sysm, tol=1e-6, precision="f32")
+            assert i1["status"] == pb.PB_OK and i0["status"] == pb.PB_OK, (i1, i0)
+            assert i1["coded_launches"] == i1["kernel_launches"] == 1, i1
+            assert i0["coded_launches"] == 0, i0
+            assert i1["iters"] == i0["iters"], (i1, i0)
+            assert torch.equal(x1, x0), c
+            xv = x1.cpu().numpy()
+            assert fdpb.true_relres(ref, xv) <= 1e-5
+            assert np.abs(xv - exact).max() <= 1e-5 * np.abs(exact).max(), c
+    finally:
+        restore_default(pb, sysm)
+
+
+def test_coded_refinement(pb):
+    dims = (61, 53, 47)
+    prob = synth.small_problem(*dims, 300, seed=9, precision="f32")
+    ref = fdpb.assemble_problem(prob)
+    exact = pcg.jpcg(ref, 1e-13, maxiter=20000).x
+    sysm = gpu_setup(pb, prob)
+    cands = forty_byte_tilings(pb, dims, "f32_refine64")
+    assert cands
+    try:
+        pin(pb, dims, "f32_refine64", cands[-1])
+        x1, i1, x0, i0 = coded_and_uncoded(pb, sysm, tol=1e-10, precision="f32_refine64", inner_tol=1e-4)
+        print(f"refine: coded {i1} uncoded {i0}", flush=True)
+        assert i1["status"] == pb.PB_OK and i1["outer_iters"] >= 2
+        assert i1["coded_launches"] == i1["kernel_launches"] >= 2, i1
+        assert i0["coded_launches"] == 0
+        assert i1["iters"] == i0["iters"] and i1["outer_iters"] == i0["outer_iters"]
+        assert torch.equal(x1, x0)
+        xv = x1.cpu().numpy()
+        assert fdpb.true_relres(ref, xv) < 1e-10
+        assert np.abs(xv - exact).max() <= 1e-9 * np.abs(exact).max()
+    finally:
+        restore_default(pb, sysm, "f32_refine64")
+
+
+def test_many_distinct_values_run_uncoded(pb):
+    """Random coefficient arrays hold millions of distinct values: the
+    dictionary overflows and the uncoded pass runs, to the oracle's solution."""
+    dims = (48, 40, 36)
+    rng = np.random.default_rng(17)
+    nx, ny, nz = dims
+    s = fdpb.System(h=0.5, eps_x=rng.uniform(1, 80, (nz, ny, nx + 1)), eps_y=rng.uniform(1, 80, (nz, ny + 1, nx)),
+                    eps_z=rng.uniform(1, 80, (nz + 1, ny, nx)), kappa2=rng.uniform(0, 2, (nz, ny, nx)),
+                    b=rng.standard_normal((nz, ny, nx)))
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+    sysm = pb.System(pb.make_grid(nx, ny, nz, s.h, (0.0, 0.0, 0.0)), t(s.eps_x), t(s.eps_y), t(s.eps_z),
+                     t(s.kappa2), t(s.b))
+    exact = pcg.jpcg(s, 1e-12, maxiter=20000).x
+    cands = forty_byte_tilings(pb, dims)
+    assert cands
+    try:
+        pin(pb, dims, "f32", cands[0])
+        x1, i1, x0, i0 = coded_and_uncoded(pb, sysm, tol=1e-6, precision="f32")
+        assert i1["status"] == pb.PB_OK
+        assert i1["coded_launches"] == 0 and i0["coded_launches"] == 0
+        assert torch.equal(x1, x0) and i1["iters"] == i0["iters"]
+        assert np.abs(x1.cpu().numpy() - exact).max() <= 1e-5 * np.abs(exact).max()
+    finally:
+        restore_default(pb, sysm)
+
+
+def test_small_grid_runs_uncoded(pb):
+    """15^3 has 3,840 padded positions, fewer than the dictionary's scratch
+    needs: the uncoded pass runs, and matches the oracle."""
+    dims = (15, 15, 15)
+    prob = synth.small_problem(*dims, 10, seed=2, precision="f32")
+    ref = fdpb.assemble_problem(prob)
+    exact = pcg.jpcg(ref, 1e-13, maxiter=20000).x
+    sysm = gpu_setup(pb, prob)
+    cands = forty_byte_tilings(pb, dims)
+    assert cands
+    try:
+        pin(pb, dims, "f32", cands[0])
+        x, info = pb.solve(sysm, tol=1e-6, precision="f32")
+        assert info["status"] == pb.PB_OK and info["coded_launches"] == 0
+        assert np.abs(x.cpu().numpy() - exact).max() <= 1e-5 * np.abs(exact).max()
+    finally:
+        restore_default(pb, sysm)
+
+
+def test_coded_config2_257(pb):
+    """The benchmark's system (257^3, 20,000 atoms) with the 512-thread
+    streaming 40-byte tiling: coded and uncoded solves to 1e-6 agree bitwise,
+    and the oracle's FP64 operator gives the true residual."""
+    prob = synth.config2()
+    dims = (prob.grid.nx, prob.grid.ny, prob.grid.nz)
+    sysm = gpu_setup(pb, prob)
+    cands = [c for c in forty_byte_tilings(pb, dims) if c["block"] == 512 and c["streaming"] == 1]
+    assert cands
+    try:
+        pin(pb, dims, "f32", cands[0])
+        x1, i1, x0, i0 = coded_and_uncoded(pb, sysm, tol=1e-6, precision="f32")
+        print(f"257: coded iters {i1['iters']} {1e3 * i1['kernel_seconds']:.2f} ms, uncoded "
+              f"{1e3 * i0['kernel_seconds']:.2f} ms", flush=True)
+        assert i1["status"] == pb.PB_OK and i1["coded_launches"] == 1
+        assert i1["iters"] == i0["iters"] and torch.equal(x1, x0)
+        host = fdpb.System(h=prob.grid.h, eps_x=sysm.eps_x.cpu().numpy(), eps_y=sysm.eps_y.cpu().numpy(),
+                           eps_z=sysm.eps_z.cpu().numpy(), kappa2=sysm.kappa2.cpu().numpy(),
+                           b=sysm.rhs.cpu().numpy())
+        assert fdpb.true_relres(host, x1.cpu().numpy()) <= 1e-5
+    finally:
+        restore_default(pb, sysm)
+        del sysm
+        torch.cuda.empty_cache()

@@ -98,7 +98,8 @@ typedef struct {
     double seconds;         /* wall time of the call */
     double kernel_seconds;  /* summed duration of those launches / loops, from HIP events on `stream` */
     int32_t coded_launches; /* of kernel_launches, those whose pass read coded coefficients (see
-                               pb_set_coded_coefficients); 0 outside pb_solve */
+                               pb_set_coded_coefficients); pb_solve and pb_solve_batch (not the graph
+                               or the server, whose stats count them) */
     int32_t reserved;       /* zero */
 } pb_info;
 
@@ -275,19 +276,23 @@ pb_status pb_get_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t precision, p
 
 /*
  * Coded coefficients (FP32 stencil solves with the 40-byte pass form, free
- * boundary). The operator of Eq. 3 built from the two-point dielectric model
- * takes few distinct values: three edge dielectrics over h^2 (and zero at
- * the faces) and a few dozen diagonals. When the FP32 couplings cx, cy, cz
- * and the diagonal together hold at most 256 distinct values, pb_solve
- * stores one 4-byte word of dictionary codes per node (in workspace the
- * 40-byte form leaves unused) and the pass reads it instead of the four FP32
- * arrays: 28 bytes per node per iteration instead of 40. The decoded values
- * are the FP32 coefficients themselves, so potentials, iteration counts and
+ * boundary: pb_solve, pb_solve_batch and the server; not the batch graph,
+ * whose recorded preparation may see new coefficients at every replay). The
+ * operator of Eq. 3 built from the two-point dielectric model takes few
+ * distinct values: three edge dielectrics over h^2 (and zero at the faces)
+ * and a few dozen diagonals. When the FP32 couplings cx, cy, cz and the
+ * diagonal together hold at most 256 distinct values, the library stores one
+ * 4-byte word of dictionary codes per node (in workspace the 40-byte form
+ * leaves unused) and the pass reads it instead of the four FP32 arrays: 28
+ * bytes per node per iteration instead of 40. The decoded values are the
+ * FP32 coefficients themselves, so potentials, iteration counts and
  * residuals are bitwise those of the uncoded pass. Otherwise (more values,
- * or a grid of fewer than 8,450 padded positions) the uncoded pass runs.
- * pb_info.coded_launches reports which ran. Building the dictionary reads
- * the operator arrays once more and reads one flag back to the host per
- * inner solve.
+ * or a grid of fewer than 8,450 padded positions) the uncoded pass runs; a
+ * batch or server launch is coded only when all its problems are.
+ * pb_info.coded_launches and pb_server_stats_t.coded_launches report which
+ * ran. Building a dictionary reads the operator arrays once more; the
+ * decision reads a flag back to the host once per pb_solve, per batch and
+ * per admitted request.
  *
  * pb_set_coded_coefficients(0) turns the coded pass off for the process;
  * 1 (the default) turns it back on. pb_get_coded_coefficients returns the
@@ -411,6 +416,8 @@ typedef struct {
     size_t arena_bytes;
     int64_t launches;       /* persistent launches so far */
     double device_seconds;  /* their summed device time (HIP events) */
+    int64_t coded_launches; /* of those, launches that read coded coefficients (every running request's
+                               operator fit its dictionary; see pb_set_coded_coefficients) */
 } pb_server_stats_t;
 
 /* Arena bytes one request occupies while admitted (0 if it cannot be served). */

@@ -102,7 +102,7 @@ class Problem(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("pending", ctypes.c_int32), ("active", ctypes.c_int32), ("arena_used", ctypes.c_size_t),
                 ("arena_bytes", ctypes.c_size_t), ("launches", ctypes.c_int64),
-                ("device_seconds", ctypes.c_double)]
+                ("device_seconds", ctypes.c_double), ("coded_launches", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

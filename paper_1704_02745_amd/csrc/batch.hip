@@ -35,6 +35,7 @@ struct Plan {
     int* first = nullptr;           // device: workgroup offsets (nprob + 1)
     SyncState* sync = nullptr;      // device: one per problem
     ProbRec* rec = nullptr;         // device: one per problem
+    int* fit = nullptr;             // device: one per problem (coded coefficients fit the dictionary)
     std::vector<Layout> L;
     std::vector<Tiling> t;
     std::vector<SolveBufs<T>> s;
@@ -64,6 +65,7 @@ bool carve_batch(void* base, int nprob, const pb_problem* probs, Plan<T>& P, int
     P.first = (int*)take(sizeof(int) * (size_t)(nprob + 1));
     P.sync = (SyncState*)take(sizeof(SyncState) * (size_t)nprob);
     P.rec = (ProbRec*)take(sizeof(ProbRec) * (size_t)nprob);
+    P.fit = (int*)take(sizeof(int) * (size_t)nprob);
     P.lds = 0;
     for (int i = 0; i < nprob; ++i) {
         const Layout L = make_layout(probs[i].nx, probs[i].ny, probs[i].nz);
@@ -180,6 +182,24 @@ pb_status enqueue_batch(const Plan<T>& P, const pb_problem* probs, int grid, boo
     return enqueue_finish<T>(P, probs, st);
 }
 
+// Write the per-problem kernel arguments (with each problem's code words and
+// dictionary when `coded`).
+template <typename T>
+pb_status fill_table(const Plan<T>& P, const pb_problem* probs, bool coded, hipStream_t st) {
+    std::vector<char> host(batch_kargs_bytes<T>() * (size_t)P.nprob);
+    for (int i = 0; i < P.nprob; ++i) {
+        const int maxiter = probs[i].maxiter > 0 ? probs[i].maxiter
+                                                 : 10 * std::max(probs[i].nx, std::max(probs[i].ny, probs[i].nz));
+        const float* cw = coded ? (const float*)P.s[i].q2 : nullptr;
+        const float* tab = coded ? dictionary_table(P.s[i].q) : nullptr;
+        batch_fill_kargs<T>(host.data() + batch_kargs_bytes<T>() * i, P.L[i], P.s[i], &P.sync[i], P.partials[i],
+                            P.t[i], probs[i].tol, maxiter, 0, 0, cw, tab);
+    }
+    PB_HIP(hipMemcpyAsync(P.table, host.data(), host.size(), hipMemcpyHostToDevice, st));
+    PB_HIP(hipStreamSynchronize(st));
+    return PB_OK;
+}
+
 // Upload the per-problem kernel arguments and workgroup offsets.
 template <typename T>
 pb_status upload_table(const Plan<T>& P, const pb_problem* probs, int& grid, hipStream_t st) {
@@ -190,17 +210,51 @@ pb_status upload_table(const Plan<T>& P, const pb_problem* probs, int& grid, hip
     }
     const std::vector<int> first = share_workgroups(P.L, P.t, cap);
     grid = first.back();
-    std::vector<char> host(batch_kargs_bytes<T>() * (size_t)P.nprob);
-    for (int i = 0; i < P.nprob; ++i) {
-        const int maxiter = probs[i].maxiter > 0 ? probs[i].maxiter
-                                                 : 10 * std::max(probs[i].nx, std::max(probs[i].ny, probs[i].nz));
-        batch_fill_kargs<T>(host.data() + batch_kargs_bytes<T>() * i, P.L[i], P.s[i], &P.sync[i], P.partials[i],
-                            P.t[i], probs[i].tol, maxiter, 0, 0);
-    }
-    PB_HIP(hipMemcpyAsync(P.table, host.data(), host.size(), hipMemcpyHostToDevice, st));
     PB_HIP(hipMemcpyAsync(P.first, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice, st));
-    PB_HIP(hipStreamSynchronize(st));
-    return PB_OK;
+    return fill_table<T>(P, probs, false, st);
+}
+
+// The direct (not graph-recorded) batch: as enqueue_batch, with coded
+// coefficients when every problem's FP32 operator fits its dictionary and
+// the coded kernel keeps the grid co-resident. The fit flags are read back
+// to the host once, after the preparation; the code words go to each
+// problem's q2 and the dictionary to its q (the batch's pass form uses
+// neither).
+template <typename T>
+pb_status enqueue_batch_direct(const Plan<T>& P, const pb_problem* probs, int grid, hipStream_t st, bool& coded) {
+    coded = false;
+    pb_status e = launch_fill<int>((int*)P.rec, (int64_t)(sizeof(ProbRec) / sizeof(int)) * P.nprob, 0, st);
+    if (e != PB_OK) return e;
+    e = launch_fill<int>((int*)P.sync, (int64_t)(sizeof(SyncState) / sizeof(int)) * P.nprob, 0, st);
+    if (e != PB_OK) return e;
+    e = enqueue_prepare<T>(P, probs, st);
+    if (e != PB_OK) return e;
+    if constexpr (sizeof(T) == sizeof(float)) {
+        bool can = coded_coefficients() != 0 && batch_capacity<T>(P.lds + kCodedLdsBytes, true) >= grid;
+        for (int i = 0; i < P.nprob && can; ++i) can = (size_t)P.L[i].npad * sizeof(float) >= coded_scratch_bytes();
+        if (can) {
+            for (int i = 0; i < P.nprob; ++i) {
+                e = enqueue_dictionary(P.s[i].op, P.L[i].npad, (void*)P.s[i].q, P.fit + i, st);
+                if (e != PB_OK) return e;
+            }
+            std::vector<int> fit(P.nprob, 0);
+            PB_HIP(hipMemcpyAsync(fit.data(), P.fit, sizeof(int) * P.nprob, hipMemcpyDeviceToHost, st));
+            PB_HIP(hipStreamSynchronize(st));
+            for (int i = 0; i < P.nprob; ++i) can = can && fit[i] == 1;
+        }
+        if (can) {
+            for (int i = 0; i < P.nprob; ++i) {
+                e = enqueue_encode(P.s[i].op, P.L[i].npad, P.s[i].q, (uint32_t*)P.s[i].q2, st);
+                if (e != PB_OK) return e;
+            }
+            e = fill_table<T>(P, probs, true, st);
+            if (e != PB_OK) return e;
+            coded = true;
+        }
+    }
+    e = batch_launch<T>(P.table, P.first, P.nprob, grid, coded ? P.lds + kCodedLdsBytes : P.lds, st, true, coded);
+    if (e != PB_OK) return e;
+    return enqueue_finish<T>(P, probs, st);
 }
 
 // Read back per-problem results; returns the batch status (first error, else
@@ -250,7 +304,8 @@ pb_status solve_batch_impl(int nprob, const pb_problem* probs, void* ws, size_t 
     PB_HIP(hipEventCreate(&ev[0]));
     PB_HIP(hipEventCreate(&ev[1]));
     PB_HIP(hipEventRecord(ev[0], st));
-    e = enqueue_batch<T>(P, probs, grid, true, st);
+    bool coded = false;
+    e = enqueue_batch_direct<T>(P, probs, grid, st, coded);
     if (e != PB_OK) {
         (void)hipEventDestroy(ev[0]);
         (void)hipEventDestroy(ev[1]);
@@ -265,7 +320,10 @@ pb_status solve_batch_impl(int nprob, const pb_problem* probs, void* ws, size_t 
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     const pb_status st_all = collect<T>(P, st, infos, secs);
     if (infos)
-        for (int i = 0; i < nprob; ++i) infos[i].kernel_seconds = 1e-3 * ms;
+        for (int i = 0; i < nprob; ++i) {
+            infos[i].kernel_seconds = 1e-3 * ms;
+            infos[i].coded_launches = coded ? 1 : 0;
+        }
     return st_all;
 }
 

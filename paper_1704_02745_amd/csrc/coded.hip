@@ -157,33 +157,64 @@ size_t coded_scratch_bytes() {
     return sizeof(uint32_t) * kHashSlots + sizeof(int) * kHashSlots + sizeof(float) * kMaxCodes + 2 * sizeof(int);
 }
 
+namespace {
+struct DictWs {
+    uint32_t* keys;
+    int* slot_code;
+    float* tab;
+    int* count;
+    int* ok;
+};
+DictWs dict_ws(const void* scratch) {
+    char* b = (char*)scratch;
+    DictWs w;
+    w.keys = (uint32_t*)b;
+    w.slot_code = (int*)(b + sizeof(uint32_t) * kHashSlots);
+    w.tab = (float*)(b + (sizeof(uint32_t) + sizeof(int)) * kHashSlots);
+    w.count = (int*)(w.tab + kMaxCodes);
+    w.ok = w.count + 1;
+    return w;
+}
+}  // namespace
+
+const float* dictionary_table(const void* scratch) { return dict_ws(scratch).tab; }
+
+pb_status enqueue_dictionary(const Op<float>& op, int64_t npad, void* scratch, int* ok_out, hipStream_t st) {
+    const DictWs w = dict_ws(scratch);
+    pb_status e = launch_fill<int>((int*)w.keys, kHashSlots, -1, st);
+    if (e != PB_OK) return e;
+    e = launch_fill<int>(w.count, 2, 0, st);
+    if (e != PB_OK) return e;
+    hipLaunchKernelGGL(k_dict_insert, dim3(grid_for_n(npad, 256 * 8, 2048)), dim3(256), 0, st, op.cx, op.cy,
+                       op.cz, op.d, npad, w.keys, w.count);
+    hipLaunchKernelGGL(k_dict_rank, dim3(1), dim3(1024), 0, st, (const uint32_t*)w.keys, (const int*)w.count,
+                       w.slot_code, w.tab, ok_out ? ok_out : w.ok);
+    PB_HIP(hipGetLastError());
+    return PB_OK;
+}
+
+pb_status enqueue_encode(const Op<float>& op, int64_t npad, const void* scratch, uint32_t* codes, hipStream_t st) {
+    const DictWs w = dict_ws(scratch);
+    hipLaunchKernelGGL(k_dict_encode, dim3(grid_for_n(npad, 256, 4096)), dim3(256), 0, st, op.cx, op.cy, op.cz,
+                       op.d, npad, (const uint32_t*)w.keys, (const int*)w.slot_code, codes);
+    PB_HIP(hipGetLastError());
+    return PB_OK;
+}
+
 pb_status build_codes(const Op<float>& op, int64_t npad, void* scratch, uint32_t* codes, hipStream_t st,
                       bool& fits, const float** table) {
     fits = false;
-    char* b = (char*)scratch;
-    uint32_t* keys = (uint32_t*)b;
-    int* slot_code = (int*)(b + sizeof(uint32_t) * kHashSlots);
-    float* tab = (float*)(b + (sizeof(uint32_t) + sizeof(int)) * kHashSlots);
-    int* count = (int*)(tab + kMaxCodes);
-    int* ok = count + 1;
-    pb_status e = launch_fill<int>((int*)keys, kHashSlots, -1, st);
+    const DictWs w = dict_ws(scratch);
+    pb_status e = enqueue_dictionary(op, npad, scratch, nullptr, st);
     if (e != PB_OK) return e;
-    e = launch_fill<int>(count, 2, 0, st);
-    if (e != PB_OK) return e;
-    hipLaunchKernelGGL(k_dict_insert, dim3(grid_for_n(npad, 256 * 8, 2048)), dim3(256), 0, st, op.cx, op.cy,
-                       op.cz, op.d, npad, keys, count);
-    hipLaunchKernelGGL(k_dict_rank, dim3(1), dim3(1024), 0, st, (const uint32_t*)keys, (const int*)count, slot_code,
-                       tab, ok);
-    PB_HIP(hipGetLastError());
     int hok = 0;
-    PB_HIP(hipMemcpyAsync(&hok, ok, sizeof(int), hipMemcpyDeviceToHost, st));
+    PB_HIP(hipMemcpyAsync(&hok, w.ok, sizeof(int), hipMemcpyDeviceToHost, st));
     PB_HIP(hipStreamSynchronize(st));
     if (!hok) return PB_OK;
-    hipLaunchKernelGGL(k_dict_encode, dim3(grid_for_n(npad, 256, 4096)), dim3(256), 0, st, op.cx, op.cy, op.cz,
-                       op.d, npad, (const uint32_t*)keys, (const int*)slot_code, codes);
-    PB_HIP(hipGetLastError());
+    e = enqueue_encode(op, npad, scratch, codes, st);
+    if (e != PB_OK) return e;
     fits = true;
-    *table = tab;
+    *table = w.tab;
     return PB_OK;
 }
 

@@ -1285,7 +1285,7 @@ __global__ __launch_bounds__(BS) void k_jpcg_fused(KArgs<T> a) {
 // solve problem p with their own barrier state; problems never wait for
 // each other, and each problem's tiling and reduction order depend only on
 // its own shape.
-template <typename T, int BS, int MC, int SCH, bool NT>
+template <typename T, int BS, int MC, int SCH, bool NT, bool CD = false>
 __global__ __launch_bounds__(BS) void k_jpcg_batch(const KArgs<T>* __restrict__ probs,
                                                    const int* __restrict__ first, int nprob) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1295,8 +1295,9 @@ __global__ __launch_bounds__(BS) void k_jpcg_batch(const KArgs<T>* __restrict__ 
         if (first[mid] <= (int)blockIdx.x) lo = mid; else hi = mid;
     }
     const KArgs<T> a = probs[lo];
-    run_problem<T, BS, MC, SCH, false, NT, false>(a, blockIdx.x - first[lo], first[lo + 1] - first[lo], false,
-                                                  lds_raw);
+    // coded launches: every problem's arguments carry its code words and dictionary
+    run_problem<T, BS, MC, SCH, false, NT, CD>(a, blockIdx.x - first[lo], first[lo + 1] - first[lo], false,
+                                               lds_raw);
 }
 
 // ------------------------------------------------------------------ host side
@@ -1698,7 +1699,10 @@ constexpr int kBatchZ = 32;   // default z-chunk; pb_batch_autotune / pb_batch_s
 constexpr int kBatchScheme = 1;
 constexpr bool kBatchNT = false;
 template <typename T>
-KernelFn batch_kernel() {
+KernelFn batch_kernel(bool coded = false) {
+    if constexpr (sizeof(T) == 4) {
+        if (coded) return (KernelFn)k_jpcg_batch<float, kBatchBS, kBatchMC, kBatchScheme, kBatchNT, true>;
+    }
     return (KernelFn)k_jpcg_batch<T, kBatchBS, kBatchMC, kBatchScheme, kBatchNT>;
 }
 }  // namespace
@@ -1756,7 +1760,8 @@ template size_t batch_kargs_bytes<double>();
 // Host-side record of one problem's kernel arguments (written to `dst`).
 template <typename T>
 void batch_fill_kargs(void* dst, const Layout& L, const SolveBufs<T>& s, SyncState* S, double* partials,
-                      const Tiling& t, double tol, int maxiter, int resume, int chunk) {
+                      const Tiling& t, double tol, int maxiter, int resume, int chunk, const float* cw,
+                      const float* ctab) {
     const DevInfo di = dev_info();
     KArgs<T> a{};
     a.op = s.op;
@@ -1777,22 +1782,24 @@ void batch_fill_kargs(void* dst, const Layout& L, const SolveBufs<T>& s, SyncSta
     a.S = S;
     a.partials = partials;
     a.timeout_ticks = (long long)(di.wallclock_khz > 0 ? di.wallclock_khz : 100000) * 1000LL * 20LL;
+    a.cw = cw;
+    a.ctab = ctab;
     std::memcpy(dst, &a, sizeof(a));
 }
 template void batch_fill_kargs<float>(void*, const Layout&, const SolveBufs<float>&, SyncState*, double*,
-                                      const Tiling&, double, int, int, int);
+                                      const Tiling&, double, int, int, int, const float*, const float*);
 template void batch_fill_kargs<double>(void*, const Layout&, const SolveBufs<double>&, SyncState*, double*,
-                                       const Tiling&, double, int, int, int);
+                                       const Tiling&, double, int, int, int, const float*, const float*);
 
 // Co-resident workgroups of the batch kernel with `lds` bytes of dynamic LDS.
 template <typename T>
-int batch_capacity(size_t lds) {
+int batch_capacity(size_t lds, bool coded) {
     const DevInfo di = dev_info();
-    const int per_cu = max_coresident(batch_kernel<T>(), kBatchBS, lds);
+    const int per_cu = max_coresident(batch_kernel<T>(coded), kBatchBS, lds);
     return per_cu * (di.cus > 0 ? di.cus : 256);
 }
-template int batch_capacity<float>(size_t);
-template int batch_capacity<double>(size_t);
+template int batch_capacity<float>(size_t, bool);
+template int batch_capacity<double>(size_t, bool);
 
 template <typename T>
 __global__ void k_reset_arrivals(const KArgs<T>* __restrict__ probs, int nprob) {
@@ -1814,22 +1821,22 @@ template pb_status batch_reset_arrivals<double>(const void*, int, hipStream_t);
 
 template <typename T>
 pb_status batch_launch(const void* d_kargs, const int* d_first, int nprob, int grid, size_t lds, hipStream_t st,
-                       bool cooperative) {
+                       bool cooperative, bool coded) {
     const KArgs<T>* kp = (const KArgs<T>*)d_kargs;
     void* args[] = {&kp, &d_first, &nprob};
     hipError_t e;
     if (cooperative)
-        e = hipLaunchCooperativeKernel(batch_kernel<T>(), dim3(grid), dim3(kBatchBS), args, lds, st);
+        e = hipLaunchCooperativeKernel(batch_kernel<T>(coded), dim3(grid), dim3(kBatchBS), args, lds, st);
     else
-        e = hipLaunchKernel(batch_kernel<T>(), dim3(grid), dim3(kBatchBS), args, lds, st);
+        e = hipLaunchKernel(batch_kernel<T>(coded), dim3(grid), dim3(kBatchBS), args, lds, st);
     if (e != hipSuccess) {
         set_error("batch JPCG launch failed: %s (grid %d, lds %zu)", hipGetErrorString(e), grid, lds);
         return PB_ERR_HIP;
     }
     return PB_OK;
 }
-template pb_status batch_launch<float>(const void*, const int*, int, int, size_t, hipStream_t, bool);
-template pb_status batch_launch<double>(const void*, const int*, int, int, size_t, hipStream_t, bool);
+template pb_status batch_launch<float>(const void*, const int*, int, int, size_t, hipStream_t, bool, bool);
+template pb_status batch_launch<double>(const void*, const int*, int, int, size_t, hipStream_t, bool, bool);
 template pb_status fused_jpcg<double>(const Layout&, const SolveBufs<double>&, SyncState*, double*, double, int,
                                       hipStream_t, SolveResult*, const Tiling*, int);
 

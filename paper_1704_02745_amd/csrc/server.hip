@@ -31,7 +31,7 @@ constexpr int kMaxOuter = 20;
 
 struct SlotRec {   // per-slot results written by kernels and read by the host
     int flags;
-    int pad;
+    int fit;       // 1: the FP32 operator fits the coded-coefficient dictionary
     double rr, bb;
     double pad2[5];
 };
@@ -51,6 +51,7 @@ struct Slot {
     double* b64 = nullptr;
     double* x64 = nullptr;
     SolveBufs<float> s{};
+    bool coded = false;              // code words in s.q2, dictionary in s.q (the pass form uses neither)
     int maxiter = 0;
     bool resume = false;             // inner solve already initialised
     bool solving = false;            // inner solve in progress
@@ -113,6 +114,7 @@ struct Server {
     std::vector<std::unique_ptr<Slot>> active;
     int64_t next_id = 1;
     int64_t launches = 0;
+    int64_t coded_launches = 0;
     double device_seconds = 0.0;
     hipEvent_t ev[2] = {nullptr, nullptr};
     std::vector<char> host_table;
@@ -280,6 +282,11 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
             e = enqueue_outer_residual(s, st);
             if (e != PB_OK) return e;
         }
+        // coded coefficients: the dictionary now, the code words once the fit flag is read back
+        if (coded_coefficients() && (size_t)s.L.npad * sizeof(float) >= coded_scratch_bytes()) {
+            e = enqueue_dictionary(s.s.op, s.L.npad, (void*)s.s.q, &s.rec->fit, st);
+            if (e != PB_OK) return e;
+        }
         admitted.push_back(&s);
         S->active.push_back(std::move(S->pending.front()));
         S->pending.pop_front();
@@ -291,6 +298,11 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
             SlotRec r;
             PB_HIP(hipMemcpy(&r, s.rec, sizeof(r), hipMemcpyDeviceToHost));
             if (r.flags & FLAG_BAD_COEF) { e = finish_slot(s, PB_ERR_ARG, st); if (e != PB_OK) return e; continue; }
+            if (r.fit == 1) {
+                e = enqueue_encode(s.s.op, s.L.npad, s.s.q, (uint32_t*)s.s.q2, st);
+                if (e != PB_OK) return e;
+                s.coded = true;
+            }
             if (r.flags & (FLAG_BAD_RHS | FLAG_BAD_GUESS)) {
                 e = finish_slot(s, PB_ERR_NONFINITE, st);
                 if (e != PB_OK) return e;
@@ -328,7 +340,15 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
             Ts.push_back(sp->t);
             lds = std::max(lds, sp->t.lds);
         }
-        const int cap = batch_capacity<float>(lds);
+        // the coded kernel when every running request has its code words
+        bool coded = coded_coefficients() != 0;
+        for (Slot* sp : run) coded = coded && sp->coded;
+        int cap = coded ? batch_capacity<float>(lds + kCodedLdsBytes, true) : 0;
+        if (coded && cap >= (int)run.size()) lds += kCodedLdsBytes;
+        else {
+            coded = false;
+            cap = batch_capacity<float>(lds);
+        }
         if (cap < (int)run.size()) {
             set_error("pb_server_step: %zu active solves exceed %d co-resident workgroups", run.size(), cap);
             return PB_ERR_ARG;
@@ -356,14 +376,15 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
             Slot& s = *run[i];
             const double tol = s.precision == PB_F32 ? s.req.tol : kInnerTol;
             batch_fill_kargs<float>(S->host_table.data() + kb * i, s.L, s.s, s.S, s.partials, s.t, tol, s.maxiter,
-                                    s.resume ? 1 : 0, chunk);
+                                    s.resume ? 1 : 0, chunk, coded ? (const float*)s.s.q2 : nullptr,
+                                    coded ? dictionary_table(s.s.q) : nullptr);
         }
         PB_HIP(hipMemcpyAsync(S->table, S->host_table.data(), kb * run.size(), hipMemcpyHostToDevice, st));
         PB_HIP(hipMemcpyAsync(S->first, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice, st));
         e = batch_reset_arrivals<float>(S->table, (int)run.size(), st);
         if (e != PB_OK) return e;
         PB_HIP(hipEventRecord(S->ev[0], st));
-        e = batch_launch<float>(S->table, S->first, (int)run.size(), first.back(), lds, st, true);
+        e = batch_launch<float>(S->table, S->first, (int)run.size(), first.back(), lds, st, true, coded);
         if (e != PB_OK) return e;
         PB_HIP(hipEventRecord(S->ev[1], st));
         PB_HIP(hipStreamSynchronize(st));
@@ -371,6 +392,7 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
         PB_HIP(hipEventElapsedTime(&ms, S->ev[0], S->ev[1]));
         S->device_seconds += 1e-3 * ms;
         ++S->launches;
+        if (coded) ++S->coded_launches;
         // ---- inner solves that finished in this chunk
         std::vector<Slot*> outer_check;
         for (Slot* sp : run) {
@@ -470,6 +492,7 @@ extern "C" pb_status pb_server_stats(const pb_server* S, pb_server_stats_t* out)
     out->arena_bytes = S->arena_bytes;
     out->launches = S->launches;
     out->device_seconds = S->device_seconds;
+    out->coded_launches = S->coded_launches;
     return PB_OK;
 }
 

@@ -102,6 +102,13 @@ size_t coded_scratch_bytes();
 // flag back to the host (synchronises `st`). *table: the device dictionary.
 pb_status build_codes(const Op<float>& op, int64_t npad, void* scratch, uint32_t* codes, hipStream_t st,
                       bool& fits, const float** table);
+// The same in two asynchronous halves: the dictionary (writes 1 to *ok_out
+// when the values fit, 0 otherwise) and, once that is known, the code words.
+pb_status enqueue_dictionary(const Op<float>& op, int64_t npad, void* scratch, int* ok_out, hipStream_t st);
+pb_status enqueue_encode(const Op<float>& op, int64_t npad, const void* scratch, uint32_t* codes, hipStream_t st);
+const float* dictionary_table(const void* scratch);
+// Extra LDS of the coded kernels (the dictionary).
+constexpr size_t kCodedLdsBytes = sizeof(float) * kCodedTableSize;
 // Process-wide switch (default on): 0 keeps every fused FP32 solve uncoded.
 void set_coded_coefficients(int on);
 int coded_coefficients();
@@ -141,13 +148,15 @@ template <typename T>
 size_t batch_kargs_bytes();
 template <typename T>
 void batch_fill_kargs(void* dst, const Layout& L, const SolveBufs<T>& s, SyncState* S, double* partials,
-                      const Tiling& t, double tol, int maxiter, int resume, int chunk);
+                      const Tiling& t, double tol, int maxiter, int resume, int chunk, const float* cw = nullptr,
+                      const float* ctab = nullptr);
+// Co-resident workgroups of the batch kernel (the coded one: lds includes kCodedLdsBytes).
 template <typename T>
-int batch_capacity(size_t lds);
+int batch_capacity(size_t lds, bool coded = false);
 template <typename T>
 pb_status batch_reset_arrivals(const void* d_kargs, int nprob, hipStream_t st);
 template <typename T>
 pb_status batch_launch(const void* d_kargs, const int* d_first, int nprob, int grid, size_t lds, hipStream_t st,
-                       bool cooperative);
+                       bool cooperative, bool coded = false);
 
 }  // namespace pb

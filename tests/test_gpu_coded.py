@@ -182,3 +182,64 @@ def test_coded_config2_257(pb):
         restore_default(pb, sysm)
         del sysm
         torch.cuda.empty_cache()
+
+
+def test_coded_batch_and_server(pb):
+    """The batched and served forms: coded and uncoded launches give bitwise the
+    same potentials and iteration counts (FP32 and FP64-refined requests); a
+    batch holding a grid too small for the dictionary runs uncoded, with the
+    other problems' results unchanged."""
+    shapes = [(61, 53, 47, 300), (65, 65, 65, 500), (33, 41, 29, 60), (49, 49, 49, 120)]
+    probs = [synth.small_problem(*sh[:3], sh[3], seed=300 + i, precision="f32") for i, sh in enumerate(shapes)]
+    refs = [fdpb.assemble_problem(p) for p in probs]
+    systems = [gpu_setup(pb, p) for p in probs]
+
+    pb.set_coded_coefficients(True)
+    x1, i1 = pb.solve_batch(systems, tol=1e-6, precision="f32")
+    pb.set_coded_coefficients(False)
+    try:
+        x0, i0 = pb.solve_batch(systems, tol=1e-6, precision="f32")
+    finally:
+        pb.set_coded_coefficients(True)
+    assert all(i["coded_launches"] == 1 for i in i1), i1
+    assert all(i["coded_launches"] == 0 for i in i0), i0
+    for j in range(len(systems)):
+        assert i1[j]["status"] == pb.PB_OK
+        assert i1[j]["iters"] == i0[j]["iters"] and torch.equal(x1[j], x0[j]), j
+        assert fdpb.true_relres(refs[j], x1[j].cpu().numpy()) <= 1e-5
+
+    small = gpu_setup(pb, synth.small_problem(15, 15, 15, 10, seed=2, precision="f32"))
+    x2, i2 = pb.solve_batch(systems[:2] + [small], tol=1e-6, precision="f32")
+    assert all(i["coded_launches"] == 0 for i in i2), i2
+    assert torch.equal(x2[0], x1[0]) and torch.equal(x2[1], x1[1])
+
+    def serve(on):
+        pb.set_coded_coefficients(on)
+        try:
+            arena = sum(pb.Server.request_bytes(s) for s in systems) + (64 << 20)
+            srv = pb.Server(arena, max_slots=8, device=DEV)
+            ids = {}
+            for i, s in enumerate(systems):
+                tol, prec = (1e-6, "f32") if i % 2 == 0 else (1e-9, "f32_refine64")
+                ids[srv.submit(s, tol=tol, precision=prec)] = i
+            out = {}
+            for _ in range(10000):
+                for rid, info in srv.step(chunk=32):
+                    out[ids[rid]] = (srv.outputs[rid].clone(), info)
+                if len(out) == len(systems):
+                    break
+            stats = srv.stats()
+            srv.close()
+            return out, stats
+        finally:
+            pb.set_coded_coefficients(True)
+
+    (s1, st1), (s0, st0) = serve(True), serve(False)
+    print(f"server: coded launches {st1['coded_launches']} of {st1['launches']}; uncoded run "
+          f"{st0['coded_launches']} of {st0['launches']}", flush=True)
+    assert st1["coded_launches"] == st1["launches"] > 0 and st0["coded_launches"] == 0
+    for i in range(len(systems)):
+        assert s1[i][1]["status"] == pb.PB_OK, s1[i][1]
+        assert s1[i][1]["iters"] == s0[i][1]["iters"] and torch.equal(s1[i][0], s0[i][0]), i
+        rel = fdpb.true_relres(refs[i], s1[i][0].cpu().numpy())
+        assert rel <= (1e-5 if i % 2 == 0 else 1e-9), (i, rel)

@@ -8,12 +8,16 @@ residual) and the energy. Inputs (atom arrays) are resident on the device
 before the timed region; outputs stay on the device.
 
 value = algorithmic HBM bytes of the fused JPCG launches in the timed steps /
-wall time of the timed steps (GB/s). The roofline block reports the fused
-kernel alone: the same bytes over its own summed duration (HIP events on the
-solve stream, recorded by the library). The CPU baseline is the FP64 NumPy
-oracle timed on a bounded sample of the same workload.
+wall time of the timed steps (GB/s), at 40 B per unknown per iteration
+whichever pass form runs (so it scales with iterations per second). The
+roofline block reports the fused kernel alone: the same bytes over its own
+summed duration (HIP events on the solve stream, recorded by the library),
+beside the bytes the form itself moves (28 B with coded coefficients, the
+default when the operator fits its dictionary) and the counted HBM traffic.
+The CPU baseline is the FP64 NumPy oracle timed on a bounded sample of the
+same workload.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--coded 0|1]
 """
 from __future__ import annotations
 

@@ -31,8 +31,10 @@
 // bytes per node in FP32). pass_tile40 recomputes q_{l-1} = A p_{l-2} from the
 // stored p_{l-2} (in LDS over the segment plus two halo widths), so it reads
 // r, p_old, d, cx, cy, cz, x and writes r, p, x: 40 bytes per node, the
-// least any schedule of this iteration moves (three vectors read and written
-// plus four operator arrays read once).
+// least any schedule of this iteration moves while the operator is four
+// arrays (three vectors read and written plus four operator arrays read
+// once). Its coded form reads the operator as one word of dictionary codes
+// per node instead (28 bytes per node; coded.hip builds the words).
 //
 // Reductions and the grid barrier: each tile reduces its sums in a fixed
 // order into its own slot; workgroups arrive on counters spread over eight

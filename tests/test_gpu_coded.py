@@ -243,3 +243,34 @@ def test_coded_batch_and_server(pb):
         assert s1[i][1]["iters"] == s0[i][1]["iters"] and torch.equal(s1[i][0], s0[i][0]), i
         rel = fdpb.true_relres(refs[i], s1[i][0].cpu().numpy())
         assert rel <= (1e-5 if i % 2 == 0 else 1e-9), (i, rel)
+
+
+@pytest.mark.parametrize("nsalt,coded", [(254, True), (255, False)])
+def test_dictionary_capacity_boundary(pb, nsalt, coded):
+    """Uniform eps = 1 at h = 0.5 gives couplings {4, 0} and diagonals 24 + kbar^2;
+    a 40 x 32 plane is a multiple of the 64-position padding, so no pad slots
+    add a value. With K distinct salt values the operator holds exactly K + 2
+    FP32 values: K = 254 (256 values) runs coded, K = 255 (257 values)
+    uncoded; both solve to the oracle's solution."""
+    nx, ny, nz = 40, 32, 30
+    rng = np.random.default_rng(nsalt)
+    salt = (np.arange(nsalt) + 1) * 1e-3
+    k2 = salt[np.arange(nx * ny * nz) % nsalt].reshape(nz, ny, nx)
+    s = fdpb.System(h=0.5, eps_x=np.ones((nz, ny, nx + 1)), eps_y=np.ones((nz, ny + 1, nx)),
+                    eps_z=np.ones((nz + 1, ny, nx)), kappa2=k2, b=rng.standard_normal((nz, ny, nx)))
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+    sysm = pb.System(pb.make_grid(nx, ny, nz, s.h, (0.0, 0.0, 0.0)), t(s.eps_x), t(s.eps_y), t(s.eps_z),
+                     t(s.kappa2), t(s.b))
+    exact = pcg.jpcg(s, 1e-12, maxiter=20000).x
+    dims = (nx, ny, nz)
+    cands = forty_byte_tilings(pb, dims)
+    assert cands
+    try:
+        pin(pb, dims, "f32", cands[0])
+        x1, i1, x0, i0 = coded_and_uncoded(pb, sysm, tol=1e-6, precision="f32")
+        assert i1["status"] == pb.PB_OK
+        assert i1["coded_launches"] == (1 if coded else 0), i1
+        assert torch.equal(x1, x0) and i1["iters"] == i0["iters"]
+        assert np.abs(x1.cpu().numpy() - exact).max() <= 1e-5 * np.abs(exact).max()
+    finally:
+        restore_default(pb, sysm)

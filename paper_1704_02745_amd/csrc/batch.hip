@@ -168,24 +168,40 @@ pb_status enqueue_finish(const Plan<T>& P, const pb_problem* probs, hipStream_t 
     return PB_OK;
 }
 
-// The whole batch on `st`: clear flags and barrier state, prepare, solve, finish.
+// The whole batch on `st`: clear flags and barrier state, prepare, solve,
+// finish; nothing is read back to the host, so it can be recorded in a graph.
+// coded == 2 (FP32): every problem's dictionary, fit flag and code words are
+// rebuilt on the device before the launch, whose kernel reads each problem's
+// fit flag (the arguments table must carry the code words, dictionaries and
+// flags).
 template <typename T>
-pb_status enqueue_batch(const Plan<T>& P, const pb_problem* probs, int grid, bool cooperative, hipStream_t st) {
+pb_status enqueue_batch(const Plan<T>& P, const pb_problem* probs, int grid, bool cooperative, hipStream_t st,
+                        int coded = 0) {
     pb_status e = launch_fill<int>((int*)P.rec, (int64_t)(sizeof(ProbRec) / sizeof(int)) * P.nprob, 0, st);
     if (e != PB_OK) return e;
     e = launch_fill<int>((int*)P.sync, (int64_t)(sizeof(SyncState) / sizeof(int)) * P.nprob, 0, st);
     if (e != PB_OK) return e;
     e = enqueue_prepare<T>(P, probs, st);
     if (e != PB_OK) return e;
-    e = batch_launch<T>(P.table, P.first, P.nprob, grid, P.lds, st, cooperative);
+    if constexpr (sizeof(T) == sizeof(float)) {
+        if (coded == 2)
+            for (int i = 0; i < P.nprob; ++i) {
+                e = enqueue_dictionary(P.s[i].op, P.L[i].npad, (void*)P.s[i].q, P.fit + i, st);
+                if (e != PB_OK) return e;
+                e = enqueue_encode(P.s[i].op, P.L[i].npad, P.s[i].q, (uint32_t*)P.s[i].q2, st, P.fit + i);
+                if (e != PB_OK) return e;
+            }
+    }
+    e = batch_launch<T>(P.table, P.first, P.nprob, grid, coded ? P.lds + kCodedLdsBytes : P.lds, st, cooperative,
+                        coded);
     if (e != PB_OK) return e;
     return enqueue_finish<T>(P, probs, st);
 }
 
 // Write the per-problem kernel arguments (with each problem's code words and
-// dictionary when `coded`).
+// dictionary when `coded`, and its fit flag when coded == 2).
 template <typename T>
-pb_status fill_table(const Plan<T>& P, const pb_problem* probs, bool coded, hipStream_t st) {
+pb_status fill_table(const Plan<T>& P, const pb_problem* probs, int coded, hipStream_t st) {
     std::vector<char> host(batch_kargs_bytes<T>() * (size_t)P.nprob);
     for (int i = 0; i < P.nprob; ++i) {
         const int maxiter = probs[i].maxiter > 0 ? probs[i].maxiter
@@ -193,7 +209,7 @@ pb_status fill_table(const Plan<T>& P, const pb_problem* probs, bool coded, hipS
         const float* cw = coded ? (const float*)P.s[i].q2 : nullptr;
         const float* tab = coded ? dictionary_table(P.s[i].q) : nullptr;
         batch_fill_kargs<T>(host.data() + batch_kargs_bytes<T>() * i, P.L[i], P.s[i], &P.sync[i], P.partials[i],
-                            P.t[i], probs[i].tol, maxiter, 0, 0, cw, tab);
+                            P.t[i], probs[i].tol, maxiter, 0, 0, cw, tab, coded == 2 ? P.fit + i : nullptr);
     }
     PB_HIP(hipMemcpyAsync(P.table, host.data(), host.size(), hipMemcpyHostToDevice, st));
     PB_HIP(hipStreamSynchronize(st));
@@ -211,7 +227,7 @@ pb_status upload_table(const Plan<T>& P, const pb_problem* probs, int& grid, hip
     const std::vector<int> first = share_workgroups(P.L, P.t, cap);
     grid = first.back();
     PB_HIP(hipMemcpyAsync(P.first, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice, st));
-    return fill_table<T>(P, probs, false, st);
+    return fill_table<T>(P, probs, 0, st);
 }
 
 // The direct (not graph-recorded) batch: as enqueue_batch, with coded
@@ -247,7 +263,7 @@ pb_status enqueue_batch_direct(const Plan<T>& P, const pb_problem* probs, int gr
                 e = enqueue_encode(P.s[i].op, P.L[i].npad, P.s[i].q, (uint32_t*)P.s[i].q2, st);
                 if (e != PB_OK) return e;
             }
-            e = fill_table<T>(P, probs, true, st);
+            e = fill_table<T>(P, probs, 1, st);
             if (e != PB_OK) return e;
             coded = true;
         }
@@ -395,6 +411,7 @@ struct BatchGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool cooperative = true;
+    int coded = 0;   // 2: the recorded batch builds dictionaries and its kernel reads each problem's fit flag
     hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
@@ -479,12 +496,24 @@ pb_status graph_build(pb_batch_graph* G, Plan<T>& P, void* ws, size_t wsb, hipSt
     int grid = 0;
     pb_status e = upload_table<T>(P, G->probs.data(), grid, st);
     if (e != PB_OK) return e;
+    // coded coefficients, decided on the device at every replay (the
+    // coefficients may change between replays)
+    G->coded = 0;
+    if constexpr (sizeof(T) == sizeof(float)) {
+        bool can = coded_coefficients() != 0 && batch_capacity<T>(P.lds + kCodedLdsBytes, 2) >= grid;
+        for (int i = 0; i < P.nprob && can; ++i) can = (size_t)P.L[i].npad * sizeof(float) >= coded_scratch_bytes();
+        if (can) {
+            e = fill_table<T>(P, G->probs.data(), 2, st);
+            if (e != PB_OK) return e;
+            G->coded = 2;
+        }
+    }
     hipStream_t cs;
     PB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     for (int attempt = 0; attempt < 2; ++attempt) {
         const bool coop = attempt == 0;
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) break;
-        const pb_status ee = enqueue_batch<T>(P, G->probs.data(), grid, coop, cs);
+        const pb_status ee = enqueue_batch<T>(P, G->probs.data(), grid, coop, cs, G->coded);
         hipGraph_t g = nullptr;
         const hipError_t he = hipStreamEndCapture(cs, &g);
         if (ee == PB_OK && he == hipSuccess && g) {
@@ -555,8 +584,16 @@ extern "C" pb_status pb_batch_graph_results(pb_batch_graph* G, void* stream, pb_
     PB_HIP(hipEventElapsedTime(&ms, G->ev[0], G->ev[1]));
     const pb_status s = G->precision == PB_F64 ? collect<double>(*G->p64, st, infos, 1e-3 * ms)
                                                : collect<float>(*G->p32, st, infos, 1e-3 * ms);
+    std::vector<int> fit(G->nprob, 0);
+    if (infos && G->coded == 2) {
+        PB_HIP(hipMemcpyAsync(fit.data(), G->p32->fit, sizeof(int) * G->nprob, hipMemcpyDeviceToHost, st));
+        PB_HIP(hipStreamSynchronize(st));
+    }
     if (infos)
-        for (int i = 0; i < G->nprob; ++i) infos[i].kernel_seconds = 1e-3 * ms;
+        for (int i = 0; i < G->nprob; ++i) {
+            infos[i].kernel_seconds = 1e-3 * ms;
+            infos[i].coded_launches = fit[i] == 1 ? 1 : 0;
+        }
     return s;
 }
 

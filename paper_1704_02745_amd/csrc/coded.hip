@@ -130,7 +130,9 @@ __device__ __forceinline__ uint32_t code_of(const uint32_t* __restrict__ k, cons
 __global__ __launch_bounds__(256) void k_dict_encode(const float* __restrict__ cx, const float* __restrict__ cy,
                                                      const float* __restrict__ cz, const float* __restrict__ d,
                                                      int64_t npad, const uint32_t* __restrict__ keys,
-                                                     const int* __restrict__ slot_code, uint32_t* __restrict__ codes) {
+                                                     const int* __restrict__ slot_code, uint32_t* __restrict__ codes,
+                                                     const int* __restrict__ fit) {
+    if (fit && *fit != 1) return;   // the values did not fit: the codes are not used
     __shared__ uint32_t k[kHashSlots];
     __shared__ int sc[kHashSlots];
     for (int s = threadIdx.x; s < kHashSlots; s += blockDim.x) {
@@ -193,10 +195,11 @@ pb_status enqueue_dictionary(const Op<float>& op, int64_t npad, void* scratch, i
     return PB_OK;
 }
 
-pb_status enqueue_encode(const Op<float>& op, int64_t npad, const void* scratch, uint32_t* codes, hipStream_t st) {
+pb_status enqueue_encode(const Op<float>& op, int64_t npad, const void* scratch, uint32_t* codes, hipStream_t st,
+                         const int* fit) {
     const DictWs w = dict_ws(scratch);
     hipLaunchKernelGGL(k_dict_encode, dim3(grid_for_n(npad, 256, 4096)), dim3(256), 0, st, op.cx, op.cy, op.cz,
-                       op.d, npad, (const uint32_t*)w.keys, (const int*)w.slot_code, codes);
+                       op.d, npad, (const uint32_t*)w.keys, (const int*)w.slot_code, codes, fit);
     PB_HIP(hipGetLastError());
     return PB_OK;
 }

@@ -79,6 +79,7 @@ struct KArgs {
     long long timeout_ticks;
     const float* cw;     // coded 40-byte pass: one word of coefficient codes per position (bit patterns)
     const float* ctab;   // and the dictionary (kCodedTableSize values)
+    const int* fit;      // runtime-checked coded launches: 1 when this problem's dictionary holds its operator
 };
 
 __device__ __forceinline__ double ld_agent_d(const double* p) {
@@ -1160,7 +1161,12 @@ struct Scal {
 // Every workgroup derives the scalars (alpha, beta, stopping test) itself
 // from the identically reduced tile sums; workgroup 0 also persists them in
 // S for the host and for a resumed launch.
-template <typename T, int BS, int MC, int SCH, bool PER, bool NT, bool CD>
+//
+// CD: the 40-byte pass reads coded coefficients. RT (with CD): whether it
+// does is read per problem from *a.fit at the start of the launch (written
+// by the dictionary build enqueued before it), so one launch serves problems
+// whose operators fit the dictionary and problems whose operators do not.
+template <typename T, int BS, int MC, int SCH, bool PER, bool NT, bool CD, bool RT = false>
 __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsigned char* lds_raw) {
     static_assert(SCH == 0 || MC == 1, "the 40-byte pass takes one vector group per thread");
     static_assert(!PER || SCH == 0, "the periodic boundary uses the pass that stores A.p");
@@ -1170,9 +1176,14 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
     T* lds1 = lds0 + lds_len;
     // coded form: the dictionary after the 40-byte pass's plane buffers
     float* tb = nullptr;
+    bool use_codes = CD;
     if constexpr (CD) {
-        tb = reinterpret_cast<float*>(lds0 + 2 * (size_t)(a.seglen + 4 * a.halo) + 6 * (size_t)(a.seglen + 2 * a.halo));
-        for (int i = threadIdx.x; i < kCodedTableSize; i += BS) tb[i] = a.ctab[i];
+        if constexpr (RT) use_codes = a.fit[0] == 1;
+        if (use_codes) {
+            tb = reinterpret_cast<float*>(lds0 + 2 * (size_t)(a.seglen + 4 * a.halo) +
+                                          6 * (size_t)(a.seglen + 2 * a.halo));
+            for (int i = threadIdx.x; i < kCodedTableSize; i += BS) tb[i] = a.ctab[i];
+        }
         __syncthreads();
     }
     __shared__ double red[red_len<BS>()];
@@ -1228,7 +1239,14 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
         for (int t = first; t < end; t += stride) {
             double acc[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             if constexpr (SCH == 1)
-                pass_tile40<T, BS, NT, CD>(a, t, o, n, alpha, beta, lds0, tb, acc);
+            {
+                if constexpr (CD && RT) {
+                    if (use_codes) pass_tile40<T, BS, NT, true>(a, t, o, n, alpha, beta, lds0, tb, acc);
+                    else pass_tile40<T, BS, NT, false>(a, t, o, n, alpha, beta, lds0, nullptr, acc);
+                } else {
+                    pass_tile40<T, BS, NT, CD>(a, t, o, n, alpha, beta, lds0, tb, acc);
+                }
+            }
             else
                 pass_tile<T, BS, MC, PER, NT>(a, t, o, n, alpha, beta, lds0, lds1, acc);
             tile_reduce_store<BS, NPART>(acc, red, sums(b) + (size_t)t * kMaxPartials);
@@ -1287,7 +1305,7 @@ __global__ __launch_bounds__(BS) void k_jpcg_fused(KArgs<T> a) {
 // solve problem p with their own barrier state; problems never wait for
 // each other, and each problem's tiling and reduction order depend only on
 // its own shape.
-template <typename T, int BS, int MC, int SCH, bool NT, bool CD = false>
+template <typename T, int BS, int MC, int SCH, bool NT, bool CD = false, bool RT = false>
 __global__ __launch_bounds__(BS) void k_jpcg_batch(const KArgs<T>* __restrict__ probs,
                                                    const int* __restrict__ first, int nprob) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1297,9 +1315,10 @@ __global__ __launch_bounds__(BS) void k_jpcg_batch(const KArgs<T>* __restrict__ 
         if (first[mid] <= (int)blockIdx.x) lo = mid; else hi = mid;
     }
     const KArgs<T> a = probs[lo];
-    // coded launches: every problem's arguments carry its code words and dictionary
-    run_problem<T, BS, MC, SCH, false, NT, CD>(a, blockIdx.x - first[lo], first[lo + 1] - first[lo], false,
-                                               lds_raw);
+    // coded launches: every problem's arguments carry its code words and
+    // dictionary (and, runtime-checked, its fit flag)
+    run_problem<T, BS, MC, SCH, false, NT, CD, RT>(a, blockIdx.x - first[lo], first[lo + 1] - first[lo], false,
+                                                   lds_raw);
 }
 
 // ------------------------------------------------------------------ host side
@@ -1700,10 +1719,12 @@ constexpr int kBatchMC = 1;
 constexpr int kBatchZ = 32;   // default z-chunk; pb_batch_autotune / pb_batch_set_zchunk change it per device
 constexpr int kBatchScheme = 1;
 constexpr bool kBatchNT = false;
+// coded: 0 uncoded, 1 coded (every problem fits), 2 coded where each problem's fit flag says so.
 template <typename T>
-KernelFn batch_kernel(bool coded = false) {
+KernelFn batch_kernel(int coded = 0) {
     if constexpr (sizeof(T) == 4) {
-        if (coded) return (KernelFn)k_jpcg_batch<float, kBatchBS, kBatchMC, kBatchScheme, kBatchNT, true>;
+        if (coded == 1) return (KernelFn)k_jpcg_batch<float, kBatchBS, kBatchMC, kBatchScheme, kBatchNT, true>;
+        if (coded == 2) return (KernelFn)k_jpcg_batch<float, kBatchBS, kBatchMC, kBatchScheme, kBatchNT, true, true>;
     }
     return (KernelFn)k_jpcg_batch<T, kBatchBS, kBatchMC, kBatchScheme, kBatchNT>;
 }
@@ -1763,7 +1784,7 @@ template size_t batch_kargs_bytes<double>();
 template <typename T>
 void batch_fill_kargs(void* dst, const Layout& L, const SolveBufs<T>& s, SyncState* S, double* partials,
                       const Tiling& t, double tol, int maxiter, int resume, int chunk, const float* cw,
-                      const float* ctab) {
+                      const float* ctab, const int* fit) {
     const DevInfo di = dev_info();
     KArgs<T> a{};
     a.op = s.op;
@@ -1786,22 +1807,25 @@ void batch_fill_kargs(void* dst, const Layout& L, const SolveBufs<T>& s, SyncSta
     a.timeout_ticks = (long long)(di.wallclock_khz > 0 ? di.wallclock_khz : 100000) * 1000LL * 20LL;
     a.cw = cw;
     a.ctab = ctab;
+    a.fit = fit;
     std::memcpy(dst, &a, sizeof(a));
 }
 template void batch_fill_kargs<float>(void*, const Layout&, const SolveBufs<float>&, SyncState*, double*,
-                                      const Tiling&, double, int, int, int, const float*, const float*);
+                                      const Tiling&, double, int, int, int, const float*, const float*,
+                                      const int*);
 template void batch_fill_kargs<double>(void*, const Layout&, const SolveBufs<double>&, SyncState*, double*,
-                                       const Tiling&, double, int, int, int, const float*, const float*);
+                                       const Tiling&, double, int, int, int, const float*, const float*,
+                                       const int*);
 
 // Co-resident workgroups of the batch kernel with `lds` bytes of dynamic LDS.
 template <typename T>
-int batch_capacity(size_t lds, bool coded) {
+int batch_capacity(size_t lds, int coded) {
     const DevInfo di = dev_info();
     const int per_cu = max_coresident(batch_kernel<T>(coded), kBatchBS, lds);
     return per_cu * (di.cus > 0 ? di.cus : 256);
 }
-template int batch_capacity<float>(size_t, bool);
-template int batch_capacity<double>(size_t, bool);
+template int batch_capacity<float>(size_t, int);
+template int batch_capacity<double>(size_t, int);
 
 template <typename T>
 __global__ void k_reset_arrivals(const KArgs<T>* __restrict__ probs, int nprob) {
@@ -1823,7 +1847,7 @@ template pb_status batch_reset_arrivals<double>(const void*, int, hipStream_t);
 
 template <typename T>
 pb_status batch_launch(const void* d_kargs, const int* d_first, int nprob, int grid, size_t lds, hipStream_t st,
-                       bool cooperative, bool coded) {
+                       bool cooperative, int coded) {
     const KArgs<T>* kp = (const KArgs<T>*)d_kargs;
     void* args[] = {&kp, &d_first, &nprob};
     hipError_t e;
@@ -1837,8 +1861,8 @@ pb_status batch_launch(const void* d_kargs, const int* d_first, int nprob, int g
     }
     return PB_OK;
 }
-template pb_status batch_launch<float>(const void*, const int*, int, int, size_t, hipStream_t, bool, bool);
-template pb_status batch_launch<double>(const void*, const int*, int, int, size_t, hipStream_t, bool, bool);
+template pb_status batch_launch<float>(const void*, const int*, int, int, size_t, hipStream_t, bool, int);
+template pb_status batch_launch<double>(const void*, const int*, int, int, size_t, hipStream_t, bool, int);
 template pb_status fused_jpcg<double>(const Layout&, const SolveBufs<double>&, SyncState*, double*, double, int,
                                       hipStream_t, SolveResult*, const Tiling*, int);
 

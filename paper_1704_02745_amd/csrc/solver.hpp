@@ -105,7 +105,8 @@ pb_status build_codes(const Op<float>& op, int64_t npad, void* scratch, uint32_t
 // The same in two asynchronous halves: the dictionary (writes 1 to *ok_out
 // when the values fit, 0 otherwise) and, once that is known, the code words.
 pb_status enqueue_dictionary(const Op<float>& op, int64_t npad, void* scratch, int* ok_out, hipStream_t st);
-pb_status enqueue_encode(const Op<float>& op, int64_t npad, const void* scratch, uint32_t* codes, hipStream_t st);
+pb_status enqueue_encode(const Op<float>& op, int64_t npad, const void* scratch, uint32_t* codes, hipStream_t st,
+                         const int* fit = nullptr);   // fit: skip unless *fit == 1 (device flag)
 const float* dictionary_table(const void* scratch);
 // Extra LDS of the coded kernels (the dictionary).
 constexpr size_t kCodedLdsBytes = sizeof(float) * kCodedTableSize;
@@ -149,14 +150,16 @@ size_t batch_kargs_bytes();
 template <typename T>
 void batch_fill_kargs(void* dst, const Layout& L, const SolveBufs<T>& s, SyncState* S, double* partials,
                       const Tiling& t, double tol, int maxiter, int resume, int chunk, const float* cw = nullptr,
-                      const float* ctab = nullptr);
-// Co-resident workgroups of the batch kernel (the coded one: lds includes kCodedLdsBytes).
+                      const float* ctab = nullptr, const int* fit = nullptr);
+// Co-resident workgroups of the batch kernel. coded: 0 uncoded, 1 coded (every
+// problem's operator fits), 2 coded per problem as its fit flag says; for 1
+// and 2, lds includes kCodedLdsBytes.
 template <typename T>
-int batch_capacity(size_t lds, bool coded = false);
+int batch_capacity(size_t lds, int coded = 0);
 template <typename T>
 pb_status batch_reset_arrivals(const void* d_kargs, int nprob, hipStream_t st);
 template <typename T>
 pb_status batch_launch(const void* d_kargs, const int* d_first, int nprob, int grid, size_t lds, hipStream_t st,
-                       bool cooperative, bool coded = false);
+                       bool cooperative, int coded = 0);
 
 }  // namespace pb

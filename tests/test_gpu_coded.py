@@ -274,3 +274,45 @@ def test_dictionary_capacity_boundary(pb, nsalt, coded):
         assert np.abs(x1.cpu().numpy() - exact).max() <= 1e-5 * np.abs(exact).max()
     finally:
         restore_default(pb, sysm)
+
+
+def test_coded_graph_decides_per_replay(pb):
+    """A recorded batch rebuilds every problem's dictionary at each replay: after
+    one problem's edge dielectrics are overwritten in place with random values
+    (far more than 256 distinct), that problem runs uncoded and the others
+    coded, and every replay equals direct solves of the same contents."""
+    shapes = [(49, 45, 41, 100), (57, 49, 43, 150), (41, 41, 41, 60)]
+    probs = [synth.small_problem(*sh[:3], sh[3], seed=400 + i, precision="f32") for i, sh in enumerate(shapes)]
+    systems = [gpu_setup(pb, p) for p in probs]
+    g = pb.BatchGraph(systems, tol=1e-6, precision="f32")
+    try:
+        g.launch()
+        i1 = g.results()
+        assert [i["coded_launches"] for i in i1] == [1, 1, 1], i1
+        xd, _ = pb.solve_batch(systems, tol=1e-6, precision="f32")
+        assert all(torch.equal(g.outs[j], xd[j]) for j in range(3))
+
+        s = systems[1]
+        saved = [a.clone() for a in (s.eps_x, s.eps_y, s.eps_z)]
+        rng = np.random.default_rng(5)
+        for a in (s.eps_x, s.eps_y, s.eps_z):
+            a.copy_(torch.as_tensor(rng.uniform(1, 80, tuple(a.shape)), dtype=torch.float64, device=DEV))
+        g.launch()
+        i2 = g.results()
+        assert [i["coded_launches"] for i in i2] == [1, 0, 1], i2
+        assert all(i["status"] == pb.PB_OK for i in i2)
+        xd2, id2 = pb.solve_batch(systems, tol=1e-6, precision="f32")
+        assert all(i["coded_launches"] == 0 for i in id2)   # the direct batch codes all problems or none
+        assert all(torch.equal(g.outs[j], xd2[j]) for j in range(3))
+        ref = fdpb.System(h=s.grid.h, eps_x=s.eps_x.cpu().numpy(), eps_y=s.eps_y.cpu().numpy(),
+                          eps_z=s.eps_z.cpu().numpy(), kappa2=s.kappa2.cpu().numpy(), b=s.rhs.cpu().numpy())
+        assert fdpb.true_relres(ref, g.outs[1].cpu().numpy()) <= 1e-5
+
+        for a, b in zip((s.eps_x, s.eps_y, s.eps_z), saved):
+            a.copy_(b)
+        g.launch()
+        i3 = g.results()
+        assert [i["coded_launches"] for i in i3] == [1, 1, 1], i3
+        assert all(torch.equal(g.outs[j], xd[j]) for j in range(3))
+    finally:
+        g.close()

@@ -276,8 +276,7 @@ pb_status pb_get_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t precision, p
 
 /*
  * Coded coefficients (FP32 stencil solves with the 40-byte pass form, free
- * boundary: pb_solve, pb_solve_batch and the server; not the batch graph,
- * whose recorded preparation may see new coefficients at every replay). The
+ * boundary: pb_solve, pb_solve_batch, the batch graph and the server). The
  * operator of Eq. 3 built from the two-point dielectric model takes few
  * distinct values: three edge dielectrics over h^2 (and zero at the faces)
  * and a few dozen diagonals. When the FP32 couplings cx, cy, cz and the
@@ -287,12 +286,15 @@ pb_status pb_get_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t precision, p
  * bytes per node per iteration instead of 40. The decoded values are the
  * FP32 coefficients themselves, so potentials, iteration counts and
  * residuals are bitwise those of the uncoded pass. Otherwise (more values,
- * or a grid of fewer than 8,450 padded positions) the uncoded pass runs; a
- * batch or server launch is coded only when all its problems are.
- * pb_info.coded_launches and pb_server_stats_t.coded_launches report which
- * ran. Building a dictionary reads the operator arrays once more; the
- * decision reads a flag back to the host once per pb_solve, per batch and
- * per admitted request.
+ * or a grid of fewer than 8,450 padded positions) the uncoded pass runs. A
+ * pb_solve_batch or server launch is coded only when all its problems are;
+ * a batch graph rebuilds every dictionary at each replay and its kernel
+ * decides per problem on the device, so coefficients that change between
+ * replays are handled. pb_info.coded_launches and
+ * pb_server_stats_t.coded_launches report which ran. Building a dictionary
+ * reads the operator arrays once more; the decision reads a flag back to the
+ * host once per pb_solve, per batch and per admitted request (never in a
+ * graph replay).
  *
  * pb_set_coded_coefficients(0) turns the coded pass off for the process;
  * 1 (the default) turns it back on. pb_get_coded_coefficients returns the

@@ -374,8 +374,26 @@ pb_status batch_autotune_impl(int nprob, const pb_problem* probs, int iters, voi
         if ((e = launch_fill<int>((int*)P.rec, (int64_t)(sizeof(ProbRec) / sizeof(int)) * nprob, 0, st)) != PB_OK) break;
         if ((e = launch_fill<int>((int*)P.sync, (int64_t)(sizeof(SyncState) / sizeof(int)) * nprob, 0, st)) != PB_OK) break;
         if ((e = enqueue_prepare<T>(P, trial.data(), st)) != PB_OK) break;
+        // solves run coded where they can: time the kernel they will run (the
+        // per-problem checked form, which needs no read-back here)
+        int coded = 0;
+        if constexpr (sizeof(T) == sizeof(float)) {
+            bool can = coded_coefficients() != 0 && batch_capacity<T>(P.lds + kCodedLdsBytes, 2) >= grid;
+            for (int i = 0; i < nprob && can; ++i) can = (size_t)P.L[i].npad * sizeof(float) >= coded_scratch_bytes();
+            if (can) {
+                for (int i = 0; i < nprob && e == PB_OK; ++i) {
+                    e = enqueue_dictionary(P.s[i].op, P.L[i].npad, (void*)P.s[i].q, P.fit + i, st);
+                    if (e == PB_OK) e = enqueue_encode(P.s[i].op, P.L[i].npad, P.s[i].q, (uint32_t*)P.s[i].q2, st,
+                                                       P.fit + i);
+                }
+                if (e != PB_OK || (e = fill_table<T>(P, trial.data(), 2, st)) != PB_OK) break;
+                coded = 2;
+            }
+        }
         if (hipEventRecord(ev[0], st) != hipSuccess) { e = PB_ERR_HIP; break; }
-        if ((e = batch_launch<T>(P.table, P.first, nprob, grid, P.lds, st, true)) != PB_OK) break;
+        if ((e = batch_launch<T>(P.table, P.first, nprob, grid, coded ? P.lds + kCodedLdsBytes : P.lds, st, true,
+                                 coded)) != PB_OK)
+            break;
         if (hipEventRecord(ev[1], st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) { e = PB_ERR_HIP; break; }
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) { e = PB_ERR_HIP; break; }

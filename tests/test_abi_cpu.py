@@ -115,3 +115,16 @@ def test_tuning_queries_reject_bad_arguments_on_host(pbgpu):
     assert lib.pb_tiling_candidates(33, 33, 33, pbgpu.PRECISIONS["f32"], None, 4, ctypes.byref(n)) == pbgpu.PB_ERR_ARG
     assert lib.pb_set_tuning(33, 33, 33, pbgpu.PRECISIONS["f32"], None) == pbgpu.PB_ERR_ARG
     assert n.value == -1
+
+
+def test_coded_coefficient_switch(pbgpu):
+    """The process-wide switch of the coded pass is host state: on by default,
+    off and on again without a device."""
+    assert pbgpu.get_coded_coefficients() is True
+    try:
+        pbgpu.set_coded_coefficients(False)
+        assert pbgpu.get_coded_coefficients() is False
+        assert pbgpu.lib.pb_get_coded_coefficients() == 0
+    finally:
+        pbgpu.set_coded_coefficients(True)
+    assert pbgpu.lib.pb_get_coded_coefficients() == 1

@@ -316,4 +316,3 @@ def test_coded_graph_decides_per_replay(pb):
         assert all(torch.equal(g.outs[j], xd[j]) for j in range(3))
     finally:
         g.close()
-

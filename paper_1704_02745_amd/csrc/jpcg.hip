@@ -1846,6 +1846,31 @@ template pb_status batch_reset_arrivals<float>(const void*, int, hipStream_t);
 template pb_status batch_reset_arrivals<double>(const void*, int, hipStream_t);
 
 template <typename T>
+__global__ void k_state_digests(const KArgs<T>* __restrict__ probs, int nprob, StateDigest* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nprob) return;
+    const SyncState* S = probs[i].S;
+    StateDigest d;
+    d.rr = S->rr;
+    d.bb = S->bb;
+    d.iters = S->iters;
+    d.done = S->done;
+    d.status = S->status;
+    d.pad = 0;
+    out[i] = d;
+}
+
+template <typename T>
+pb_status batch_state_digests(const void* d_kargs, int nprob, StateDigest* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_state_digests<T>, dim3((nprob + 255) / 256), dim3(256), 0, st, (const KArgs<T>*)d_kargs,
+                       nprob, out);
+    PB_HIP(hipGetLastError());
+    return PB_OK;
+}
+template pb_status batch_state_digests<float>(const void*, int, StateDigest*, hipStream_t);
+template pb_status batch_state_digests<double>(const void*, int, StateDigest*, hipStream_t);
+
+template <typename T>
 pb_status batch_launch(const void* d_kargs, const int* d_first, int nprob, int grid, size_t lds, hipStream_t st,
                        bool cooperative, int coded) {
     const KArgs<T>* kp = (const KArgs<T>*)d_kargs;

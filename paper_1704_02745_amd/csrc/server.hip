@@ -108,6 +108,7 @@ struct Server {
     int max_slots = 0;
     char* table = nullptr;        // device: kernel-argument records for max_slots
     int* first = nullptr;         // device: workgroup offsets
+    StateDigest* digests = nullptr;   // device: each running request's scalars after a launch
     size_t reserved = 0;          // arena bytes used by the table
     std::vector<std::pair<size_t, size_t>> free_list;   // (offset, bytes), sorted by offset
     std::deque<std::unique_ptr<Slot>> pending;
@@ -119,6 +120,7 @@ struct Server {
     hipEvent_t ev[2] = {nullptr, nullptr};
     std::vector<char> host_table;
     std::vector<int> host_first;
+    std::vector<StateDigest> host_digests;
 
     bool alloc(size_t bytes, size_t& off) {
         for (size_t i = 0; i < free_list.size(); ++i) {
@@ -198,10 +200,13 @@ extern "C" pb_status pb_server_create(void* arena, size_t arena_bytes, int32_t m
     S->max_slots = max_slots;
     const size_t tb = align_up(batch_kargs_bytes<float>() * (size_t)max_slots, 256);
     const size_t fb = align_up(sizeof(int) * (size_t)(max_slots + 1), 256);
-    PB_ARG(arena_bytes > tb + fb, "pb_server_create: arena too small");
+    const size_t db = align_up(sizeof(StateDigest) * (size_t)max_slots, 256);
+    PB_ARG(arena_bytes > tb + fb + db, "pb_server_create: arena too small");
     S->table = S->arena;
     S->first = (int*)(S->arena + tb);
-    S->reserved = tb + fb;
+    S->digests = (StateDigest*)(S->arena + tb + fb);
+    S->reserved = tb + fb + db;
+    S->host_digests.resize(max_slots);
     S->free_list.push_back({S->reserved, arena_bytes - S->reserved});
     S->host_table.resize(batch_kargs_bytes<float>() * (size_t)max_slots);
     S->host_first.resize(max_slots + 1);
@@ -387,6 +392,11 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
         e = batch_launch<float>(S->table, S->first, (int)run.size(), first.back(), lds, st, true, coded);
         if (e != PB_OK) return e;
         PB_HIP(hipEventRecord(S->ev[1], st));
+        // every running request's scalars in one read-back
+        e = batch_state_digests<float>(S->table, (int)run.size(), S->digests, st);
+        if (e != PB_OK) return e;
+        PB_HIP(hipMemcpyAsync(S->host_digests.data(), S->digests, sizeof(StateDigest) * run.size(),
+                              hipMemcpyDeviceToHost, st));
         PB_HIP(hipStreamSynchronize(st));
         float ms = 0;
         PB_HIP(hipEventElapsedTime(&ms, S->ev[0], S->ev[1]));
@@ -395,11 +405,10 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
         if (coded) ++S->coded_launches;
         // ---- inner solves that finished in this chunk
         std::vector<Slot*> outer_check;
-        for (Slot* sp : run) {
-            Slot& s = *sp;
+        for (size_t ri = 0; ri < run.size(); ++ri) {
+            Slot& s = *run[ri];
             s.resume = true;
-            SyncState h;
-            PB_HIP(hipMemcpy(&h, s.S, sizeof(SyncState), hipMemcpyDeviceToHost));
+            const StateDigest& h = S->host_digests[ri];
             if (!h.done) continue;
             if (s.precision == PB_F32) {
                 s.iters = h.iters;

@@ -158,6 +158,14 @@ template <typename T>
 int batch_capacity(size_t lds, int coded = 0);
 template <typename T>
 pb_status batch_reset_arrivals(const void* d_kargs, int nprob, hipStream_t st);
+// The scalars the host needs from each problem's barrier state, gathered
+// into one device array (one read-back for a whole launch).
+struct StateDigest {
+    double rr, bb;
+    int iters, done, status, pad;
+};
+template <typename T>
+pb_status batch_state_digests(const void* d_kargs, int nprob, StateDigest* out, hipStream_t st);
 template <typename T>
 pb_status batch_launch(const void* d_kargs, const int* d_first, int nprob, int grid, size_t lds, hipStream_t st,
                        bool cooperative, int coded = 0);

@@ -468,6 +468,37 @@ __device__ __forceinline__ double rsqrt_nr(double r2) {
     return y;
 }
 
+// e^x for x <= 0 (the screening factor e^(-kappa d)), without the range
+// checks of a general exponential. Cody and Waite's argument reduction,
+// x = n ln2 + r with |r| <= ln2/2, takes ln 2 in two parts: a head with 32
+// significant bits, so that n * head is exact for any n this range gives,
+// and the rounded remainder. e^r is the Taylor series to degree 13, whose
+// truncation is below 5e-18 relative on that interval, evaluated by Horner's
+// rule; ldexp applies 2^n and rounds results below the normal range as they
+// underflow.
+__device__ __forceinline__ double exp_nonpos(double x) {
+    constexpr double kInvLn2 = 1.4426950408889634;
+    constexpr double kLn2Head = 0x1.62e42fee00000p-1;
+    constexpr double kLn2Tail = 0x1.a39ef35793c76p-33;
+    const double fn = rint(x * kInvLn2);
+    const double r = fma(-fn, kLn2Tail, fma(-fn, kLn2Head, x));
+    double p = 1.0 / 6227020800.0;           // 1/13!
+    p = fma(p, r, 1.0 / 479001600.0);        // 1/12!
+    p = fma(p, r, 1.0 / 39916800.0);         // 1/11!
+    p = fma(p, r, 1.0 / 3628800.0);          // 1/10!
+    p = fma(p, r, 1.0 / 362880.0);           // 1/9!
+    p = fma(p, r, 1.0 / 40320.0);            // 1/8!
+    p = fma(p, r, 1.0 / 5040.0);             // 1/7!
+    p = fma(p, r, 1.0 / 720.0);              // 1/6!
+    p = fma(p, r, 1.0 / 120.0);              // 1/5!
+    p = fma(p, r, 1.0 / 24.0);               // 1/4!
+    p = fma(p, r, 1.0 / 6.0);                // 1/3!
+    p = fma(p, r, 0.5);                      // 1/2!
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)fn);
+}
+
 // Screened Coulomb sum of every atom at each ghost-face point, atoms in
 // index order through LDS records (x, y, z, q): phi = (1/eps_out) sum q e^(-kd)/d.
 // Ghost points lie one node outside the box and atoms inside it, so d >= h > 0.
@@ -501,7 +532,7 @@ __global__ __launch_bounds__(kDhBlock) void k_dh_faces(
                 const double dx = px - c.x, dy = py - c.y, dz = pz - c.z;
                 const double r2 = dx * dx + dy * dy + dz * dz;
                 const double y = rsqrt_nr(r2);
-                s = fma(c.w * exp(-kd * (r2 * y)), y, s);
+                s = fma(c.w * exp_nonpos(-kd * (r2 * y)), y, s);
             }
         }
     }

@@ -1,0 +1,81 @@
+"""The boundary sum's exponential, built for the host from its device text.
+
+k_dh_faces takes the screening factor e^(-kappa d) from exp_nonpos (setup.hip):
+Cody-Waite reduction with a two-part ln 2 and the degree-13 Taylor series.
+Its text is extracted from setup.hip, compiled with g++ and compared with the
+C library's exp on x in [-745, 0]: within 2 units in the last place where the
+result is normal, within 2 subnormal steps below that, exactly 1 at 0 and
+monotone.
+"""
+import re
+import shutil
+import subprocess
+from pathlib import Path
+
+import pytest
+
+ROOT = Path(__file__).resolve().parents[1]
+SETUP = ROOT / "paper_1704_02745_amd" / "csrc" / "setup.hip"
+
+DRIVER = r"""
+#include <cfloat>
+#include <cmath>
+#include <cstdio>
+#define __device__
+#define __forceinline__ inline
+using std::fma; using std::rint; using std::ldexp;
+#include "exp.inc"
+int main() {
+    const int n = 2000001;
+    double worst_ulp = 0.0, worst_sub = 0.0, prev = 0.0;
+    int nonmono = 0;
+    for (int i = 0; i < n; ++i) {
+        const double x = -745.0 + 745.0 * i / (n - 1);   // increasing x: results must not decrease
+        const double got = exp_nonpos(x), want = std::exp(x);
+        if (i > 0 && got < prev) ++nonmono;
+        prev = got;
+        if (want >= DBL_MIN) {
+            const double ulp = std::nextafter(want, INFINITY) - want;
+            worst_ulp = std::fmax(worst_ulp, std::fabs(got - want) / ulp);
+        } else {
+            worst_sub = std::fmax(worst_sub, std::fabs(got - want) / std::numeric_limits<double>::denorm_min());
+        }
+    }
+    std::printf("%.3f %.3f %d %.17g\n", worst_ulp, worst_sub, nonmono, exp_nonpos(0.0));
+    return 0;
+}
+"""
+
+
+def _extract(src, name):
+    m = re.search(r"__device__ __forceinline__ double " + name + r"\(double x\) \{", src)
+    assert m, name
+    depth, i = 0, m.end() - 1
+    while True:
+        if src[i] == "{":
+            depth += 1
+        elif src[i] == "}":
+            depth -= 1
+            if depth == 0:
+                return src[m.start():i + 1]
+        i += 1
+
+
+def test_exp_nonpos_against_c_library(tmp_path):
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    text = _extract(SETUP.read_text(), "exp_nonpos")
+    (tmp_path / "exp.inc").write_text(text + "\n")
+    (tmp_path / "drv.cpp").write_text(DRIVER.replace("#include <cstdio>", "#include <cstdio>\n#include <limits>"))
+    exe = tmp_path / "drv"
+    r = subprocess.run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", str(tmp_path / "drv.cpp"), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    worst_ulp, worst_sub, nonmono, at0 = out.stdout.split()
+    print(f"exp_nonpos: worst {worst_ulp} ulp (normal), {worst_sub} subnormal steps, {nonmono} decreases", flush=True)
+    assert float(worst_ulp) <= 2.0
+    assert float(worst_sub) <= 2.0
+    assert int(nonmono) == 0
+    assert float(at0) == 1.0

@@ -95,7 +95,7 @@ def test_config4_request_subset(pb):
         else:
             assert rel <= max(10 * p.tol, 1e-5)
         if p.grid.nx <= 67 and p.tol <= 1e-6:
-            # the spec bars: 1e-5 in FP32 (at tol 1e-6), and tighter once refined (tol 1e-8)
+            # the accuracy bars of these workloads: 1e-5 in FP32 (at tol 1e-6), tighter once refined (tol 1e-8)
             exact = pcg.jpcg(s, 1e-12, maxiter=20000).x
             bar = 1e-7 if p.precision == "f32_refine64" else 1e-5
             assert np.abs(xg - exact).max() <= bar * np.abs(exact).max()

@@ -1006,18 +1006,22 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
             }
             cxm_n = ctb[bits(cxm_n) & 255u];
             // inner ring: cz on every plane; the rest only where the uncoded
-            // pass loads it (owned planes), zero elsewhere
-            const V hw = h_cx;
+            // pass loads it (owned planes), zero elsewhere. Other threads hold
+            // zero words there, which already read as +0.0, the value code 0
+            // decodes to, so only ring threads decode.
+            if (is_h) {
+                const V hw = h_cx;
 #pragma unroll
-            for (int u = 0; u < W; ++u) {
-                const uint32_t c = bits(vget(hw, u));
-                vget(h_cz, u) = ctb[(c >> 16) & 255u];
-                vget(h_cx, u) = own1 ? ctb[c & 255u] : T(0);
-                vget(h_cy, u) = own1 ? ctb[(c >> 8) & 255u] : T(0);
-                vget(h_d, u) = own1 ? ctb[c >> 24] : T(0);
-                h_cym[u] = ctb[(bits(h_cym[u]) >> 8) & 255u];
+                for (int u = 0; u < W; ++u) {
+                    const uint32_t c = bits(vget(hw, u));
+                    vget(h_cz, u) = ctb[(c >> 16) & 255u];
+                    vget(h_cx, u) = own1 ? ctb[c & 255u] : T(0);
+                    vget(h_cy, u) = own1 ? ctb[(c >> 8) & 255u] : T(0);
+                    vget(h_d, u) = own1 ? ctb[c >> 24] : T(0);
+                    h_cym[u] = ctb[(bits(h_cym[u]) >> 8) & 255u];
+                }
+                h_cxm = ctb[bits(h_cxm) & 255u];
             }
-            h_cxm = ctb[bits(h_cxm) & 255u];
         }
 
         // ---- q_{l-1}, r_{l-1}, p_{l-1} (and x) on plane k+1, own positions

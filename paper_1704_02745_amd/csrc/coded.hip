@@ -40,7 +40,8 @@ constexpr int kLocalSlots = 1024;
 __device__ __forceinline__ bool set_insert(uint32_t* keys, int nslots, uint32_t v, int* count, bool lds) {
     uint32_t s = hash_slot(v) & (uint32_t)(nslots - 1);
     for (int probe = 0; probe < nslots; ++probe) {
-        const uint32_t cur = lds ? keys[s] : __hip_atomic_load(keys + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t cur = lds ? __hip_atomic_load(keys + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                                 : __hip_atomic_load(keys + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (cur == v) return true;
         if (cur == kEmpty) {
             const uint32_t old = atomicCAS(keys + s, kEmpty, v);
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(256) void k_dict_insert(const float* __restrict__ c
         const float v[4] = {cx[i], cy[i], cz[i], d[i]};
 #pragma unroll
         for (int a = 0; a < 4; ++a) full = full || !set_insert(lk, kLocalSlots, __float_as_uint(v[a]), &lcount, true);
-        full = full || lcount > kMaxCodes;
+        full = full || __hip_atomic_load(&lcount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) > kMaxCodes;
     }
     __syncthreads();
     if (lcount > kMaxCodes) {

@@ -316,3 +316,32 @@ def test_coded_graph_decides_per_replay(pb):
         assert all(torch.equal(g.outs[j], xd[j]) for j in range(3))
     finally:
         g.close()
+
+
+@pytest.mark.parametrize("nz,coded", [(132, False), (133, True)])
+def test_scratch_size_threshold(pb, nz, coded):
+    """The dictionary's scratch lives in the 40-byte form's unused q array, so
+    a grid needs 8,450 padded positions for the coded pass: a 16 x 4 plane (64
+    positions, no padding) gives 8,448 at nz = 132 (uncoded) and 8,512 at
+    nz = 133 (coded). Uniform eps and three salt values keep the operator's
+    values few; both solve to the oracle's solution."""
+    nx, ny = 16, 4
+    rng = np.random.default_rng(nz)
+    k2 = np.array([0.0, 0.5, 1.25])[rng.integers(0, 3, (nz, ny, nx))]
+    s = fdpb.System(h=0.5, eps_x=np.ones((nz, ny, nx + 1)), eps_y=np.ones((nz, ny + 1, nx)),
+                    eps_z=np.ones((nz + 1, ny, nx)), kappa2=k2, b=rng.standard_normal((nz, ny, nx)))
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+    sysm = pb.System(pb.make_grid(nx, ny, nz, s.h, (0.0, 0.0, 0.0)), t(s.eps_x), t(s.eps_y), t(s.eps_z),
+                     t(s.kappa2), t(s.b))
+    exact = pcg.jpcg(s, 1e-12, maxiter=20000).x
+    dims = (nx, ny, nz)
+    cands = forty_byte_tilings(pb, dims)
+    assert cands
+    try:
+        pin(pb, dims, "f32", cands[0])
+        x, info = pb.solve(sysm, tol=1e-6, precision="f32")
+        assert info["status"] == pb.PB_OK
+        assert info["coded_launches"] == (1 if coded else 0), info
+        assert np.abs(x.cpu().numpy() - exact).max() <= 1e-5 * np.abs(exact).max()
+    finally:
+        restore_default(pb, sysm)

@@ -108,28 +108,44 @@ def jpcg(system, tol: float, maxiter: Optional[int] = None, x0=None,
 
 
 def refine(system, tol_outer: float, tol_inner: float = 1e-4,
-           max_outer: int = 20, inner_solver=None):
+           max_outer: int = 20, inner_solver=None, with_status: bool = False):
     """Iterative refinement: r = b - A x in FP64, inner solve A d = r to a
-    tolerance relative to ||r||, x += d; stops when ||r||/||b|| < tol_outer.
-    `inner_solver(rhs, tol)` defaults to the FP64 Jacobi PCG. Returns
-    (x, outer_steps, inner_iterations_list, relres)."""
+    tolerance relative to ||r|| from d = 0, x += d; stops when ||r||/||b|| <
+    tol_outer (converged), after max_outer corrections, or when an outer step
+    reduced ||r|| by less than a factor 2 (stagnation: the inner solver's own
+    rounding floor has been reached). `inner_solver(rhs, tol)` defaults to the
+    FP64 Jacobi PCG. Returns (x, outer_steps, inner_iterations_list, relres),
+    and with `with_status` also one of "converged", "max_outer",
+    "stagnated", "breakdown"."""
     from . import fdpb
     b = system.b
     bn = float(np.linalg.norm(b.ravel()))
     x = np.zeros(system.shape)
     inner = []
+
+    def done(outer, rel, status):
+        return (x, outer, inner, rel, status) if with_status else (x, outer, inner, rel)
+
     if bn == 0.0:
-        return x, 0, inner, 0.0
+        return done(0, 0.0, "converged")
     if inner_solver is None:
         d = fdpb.diagonal(system)
         inner_solver = lambda rhs, t: pcg(lambda v: fdpb.apply(system, v), rhs, d, t,
                                           10 * max(system.dims))
+    rel_prev = None
     for outer in range(max_outer + 1):
         r = b - fdpb.apply(system, x)
         rel = float(np.linalg.norm(r.ravel())) / bn
-        if rel < tol_outer or outer == max_outer:
-            return x, outer, inner, rel
+        if rel < tol_outer:
+            return done(outer, rel, "converged")
+        if outer == max_outer:
+            return done(outer, rel, "max_outer")
+        if rel_prev is not None and rel > 0.5 * rel_prev:
+            return done(outer, rel, "stagnated")
+        rel_prev = rel
         res = inner_solver(r, tol_inner)
         inner.append(res.iters)
+        if res.breakdown:
+            return done(outer, rel, "breakdown")
         x = x + res.x
-    return x, max_outer, inner, rel
+    return done(max_outer, rel, "max_outer")

@@ -16,6 +16,7 @@ import itertools
 import numpy as np
 import pytest
 
+import synth
 from oracle import fdpb, periodic
 
 
@@ -119,3 +120,99 @@ def test_assembled_system_shift_by_period_and_singular_mean():
     assert r0.converged and r1.converged
     assert abs(r0.x.mean()) <= 1e-12 * np.abs(r0.x).max()
     assert periodic.true_relres(s, r0.x) < 1e-9 and periodic.true_relres(salty, r1.x) < 1e-9
+
+
+def test_interpolation_matches_library_on_tiled_field():
+    """periodic.interpolate equals scipy's trilinear interpolation of the
+    periodically tiled field (3 copies per axis), for atoms inside the box,
+    in its last cell (between node n-1 and node 0), below the origin and
+    beyond the far face."""
+    from scipy.interpolate import RegularGridInterpolator
+    nx, ny, nz, h = 7, 6, 5, 0.5
+    origin = np.array([0.3, -0.2, 0.1])
+    rng = np.random.default_rng(21)
+    phi = rng.standard_normal((nz, ny, nx))
+    tiled = np.tile(phi, (3, 3, 3))                  # nodes -n .. 2n-1 on each axis
+    axes = [origin[d] + h * np.arange(-n, 2 * n, dtype=np.float64) for d, n in enumerate((nx, ny, nz))]
+    f = RegularGridInterpolator((axes[2], axes[1], axes[0]), tiled, method="linear")
+    L = np.array([nx, ny, nz]) * h
+    xyz = np.concatenate([origin + rng.uniform(0, 1, size=(20, 3)) * L,
+                          origin + (np.array([nx, ny, nz]) - 0.5) * h + rng.uniform(-0.2, 0.2, size=(5, 3)),
+                          origin + rng.uniform(-0.9, -0.01, size=(5, 3)) * L,
+                          origin + rng.uniform(1.01, 1.75, size=(5, 3)) * L])
+    got = periodic.interpolate(nx, ny, nz, h, origin, xyz, phi)
+    want = f(xyz[:, ::-1])
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(phi).max()
+
+
+def test_energy_identity_and_period_shift():
+    """1/2 sum_a q_a phi(c_a) equals 1/2 sum_nodes q_node phi_node with the
+    wrapped spreading (the same trilinear weights used as a scatter instead of
+    a gather), and moving every atom by whole periods leaves it unchanged."""
+    nx, ny, nz, h = 9, 8, 10, 0.5
+    origin = np.array([-2.0, -1.7, -2.4])
+    rng = np.random.default_rng(5)
+    xyz = rng.uniform(-4.0, 4.0, size=(12, 3))
+    q = rng.uniform(-0.8, 0.8, size=12)
+    phi = rng.standard_normal((nz, ny, nx))
+    e = periodic.energy(nx, ny, nz, h, origin, xyz, q, phi)
+    qn = periodic.spread_charges(nx, ny, nz, h, origin, xyz, q)
+    e_nodes = 0.5 * float(np.sum(qn * phi)) * fdpb.COULOMB_KCAL
+    assert abs(e - e_nodes) <= 1e-13 * abs(e_nodes)
+    shift = np.array([nx, -2 * ny, 3 * nz]) * h
+    assert abs(periodic.energy(nx, ny, nz, h, origin, xyz + shift, q, phi) - e) <= 1e-11 * abs(e)
+
+
+def test_solvation_zero_for_uniform_dielectric():
+    """With eps_out = eps_in and no salt the solvent and reference systems of
+    the periodic solvation energy are the same system: dG = 0 exactly."""
+    from oracle import solvation
+    prob = synth.small_problem(15, 13, 14, 6, seed=3)
+    g, m = prob.grid, prob.mol
+    r = solvation.solvation_energy(g.nx, g.ny, g.nz, g.h, g.origin, m.xyz, m.radius, m.charge, 2.0, 2.0, 0.0,
+                                   tol=1e-10, boundary="periodic")
+    assert r.dG == 0.0 and r.e_solv != 0.0
+
+
+def _wigner_constant():
+    """xi of a unit charge in a cubic periodic box (side 1) with a uniform
+    neutralising background: minus the Ewald sum of the potential its images
+    and the background create at the charge (real-space erfc terms,
+    reciprocal-space Gaussian terms, the self term and the background
+    term, splitting parameter 5)."""
+    from math import erfc, exp, pi, sqrt
+    a = 5.0
+    real = sum(erfc(a * sqrt(i * i + j * j + k * k)) / sqrt(i * i + j * j + k * k)
+               for i in range(-4, 5) for j in range(-4, 5) for k in range(-4, 5) if (i, j, k) != (0, 0, 0))
+    recip = 0.0
+    for i in range(-8, 9):
+        for j in range(-8, 9):
+            for k in range(-8, 9):
+                if (i, j, k) != (0, 0, 0):
+                    k2 = (2 * pi) ** 2 * (i * i + j * j + k * k)
+                    recip += 4 * pi / k2 * exp(-k2 / (4 * a * a))
+    return -(real + recip - 2 * a / sqrt(pi) - pi / (a * a))
+
+
+def test_periodic_born_ion_finite_size_correction():
+    """A Born ion (radius 2.1 A, eps 1 inside / 80 outside, no salt) in a
+    periodic box of side L: each system's energy carries the lattice
+    self-energy -q^2 xi / (2 eps L) of its medium, so the periodic dG equals
+    the free-space dG on the same grid plus 332.06 q^2 xi / (2L) (1 - 1/80)
+    (28 kcal/mol at L = 16.5 A), up to an O(L^-3) remainder. Checked at
+    n = 33 and 41: the remainder stays below 1.2% and falls like L^-3."""
+    from oracle import solvation
+    xi = _wigner_constant()
+    assert abs(xi - 2.837297) < 1e-6
+    rel = {}
+    for n in (33, 41):
+        h, a = 0.5, 2.1
+        org = np.full(3, -(n - 1) / 2 * h)
+        xyz, R, q = np.zeros((1, 3)), np.array([a]), np.array([1.0])
+        per = solvation.solvation_energy(n, n, n, h, org, xyz, R, q, 1.0, 80.0, 0.0, tol=1e-10, boundary="periodic")
+        free = solvation.solvation_energy(n, n, n, h, org, xyz, R, q, 1.0, 80.0, 0.0, tol=1e-10)
+        corr = fdpb.COULOMB_KCAL * xi / (2 * n * h) * (1.0 - 1.0 / 80.0)
+        rel[n] = (per.dG - (free.dG + corr)) / abs(free.dG)
+    assert abs(rel[33]) < 0.012 and abs(rel[41]) < 0.006
+    ratio = rel[41] / rel[33]
+    assert 0.8 * (33 / 41) ** 3 < ratio < 1.2 * (33 / 41) ** 3, rel

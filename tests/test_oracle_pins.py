@@ -415,3 +415,43 @@ def test_refinement_reaches_tight_tolerance():
     x, outer, inner, rel = pcg.refine(s, 1e-12, 1e-4)
     assert rel < 1e-12 and 2 <= outer <= 6
     assert fdpb.true_relres(s, x) < 1e-12
+
+
+def test_refinement_stop_rules():
+    """Refinement's outer stop rules, driven by inner solvers of known
+    contraction: a correction c * A^-1 r leaves the residual (1 - c) r, so
+    c = 0.4 (residual falls 1.67x) stagnates at the first check, c = 0.6
+    (2.5x) keeps going until max_outer, an exact inner solve converges after
+    one correction, and an FP32-rounded inner solve (a 2^-24 relative
+    floor per step) converges geometrically."""
+    s = fdpb.assemble_problem(synth.small_problem(7, 6, 5, 4, seed=12))
+    A = fdpb.dense_matrix(s)
+    exact = lambda rhs: np.linalg.solve(A, rhs.ravel()).reshape(s.shape)
+
+    def scaled(c):
+        return lambda rhs, t: pcg.PCGResult(c * exact(rhs), 1, 0.0, True)
+
+    x, outer, inner, rel, st = pcg.refine(s, 1e-12, inner_solver=scaled(0.4), with_status=True)
+    assert st == "stagnated" and outer == 1 and len(inner) == 1
+    bn = np.linalg.norm(s.b)
+    assert abs(rel - 0.6) <= 1e-12 and abs(np.linalg.norm(s.b - fdpb.apply(s, x)) / bn - 0.6) <= 1e-12
+    x, outer, inner, rel, st = pcg.refine(s, 1e-12, inner_solver=scaled(0.6), max_outer=7, with_status=True)
+    assert st == "max_outer" and outer == 7 and len(inner) == 7
+    assert abs(rel / 0.4 ** 7 - 1.0) <= 1e-9
+    x, outer, inner, rel, st = pcg.refine(s, 1e-12, inner_solver=scaled(1.0), with_status=True)
+    assert st == "converged" and outer == 1 and rel < 1e-13
+
+    def fp32_inner(rhs, t):
+        d = exact(rhs.astype(np.float32).astype(np.float64)).astype(np.float32).astype(np.float64)
+        return pcg.PCGResult(d, 1, 0.0, True)
+
+    x, outer, inner, rel, st = pcg.refine(s, 1e-13, inner_solver=fp32_inner, with_status=True)
+    assert st == "converged" and 2 <= outer <= 4, (outer, rel)
+
+    def broken(rhs, t):
+        return pcg.PCGResult(np.zeros(s.shape), 0, 1.0, False, breakdown=True)
+
+    x, outer, inner, rel, st = pcg.refine(s, 1e-12, inner_solver=broken, with_status=True)
+    assert st == "breakdown" and outer == 0 and not x.any()
+    # the default return shape is unchanged
+    assert len(pcg.refine(s, 1e-10)) == 4

@@ -45,7 +45,7 @@ def test_one_vcycle_matches_oracle(pb, c0):
     assert info["iters"] == 1 and err <= 1e-12
 
 
-@pytest.mark.parametrize("prec,tol,bar", [("f64", 1e-10, 1e-8), ("f32_refine64", 1e-10, 1e-8), ("f32", 1e-6, 2e-5)])
+@pytest.mark.parametrize("prec,tol,bar", [("f64", 1e-10, 1e-8), ("f32_refine64", 1e-10, 1e-8), ("f32", 1e-6, 1e-5)])
 def test_mg_solve_matches_oracle(pb, c0, prec, tol, bar):
     s, exact = c0
     o = mg.mgpcg(s, tol if prec != "f32_refine64" else 1e-4)[0]
@@ -56,7 +56,9 @@ def test_mg_solve_matches_oracle(pb, c0, prec, tol, bar):
     assert info["status"] == pb.PB_OK
     if prec != "f32_refine64":
         assert abs(info["iters"] - o.iters) <= 2
-    assert np.abs(xv - exact).max() <= bar * np.abs(exact).max()
+    err = np.abs(xv - exact).max() / np.abs(exact).max()
+    print(f"mg {prec}: phi err {err:.2e} (bar {bar:g})", flush=True)
+    assert err <= bar
 
 
 def test_mg_ragged_molecule_fp32(pb):
@@ -69,7 +71,9 @@ def test_mg_ragged_molecule_fp32(pb):
     print(f"ragged mg iters {info['iters']} (oracle {o.iters}) vs jacobi {jinfo['iters']}", flush=True)
     assert info["status"] == pb.PB_OK and abs(info["iters"] - o.iters) <= 2
     assert info["iters"] * 5 < jinfo["iters"]
-    assert np.abs(x.cpu().numpy() - exact).max() <= 2e-5 * np.abs(exact).max()
+    err = np.abs(x.cpu().numpy() - exact).max() / np.abs(exact).max()
+    print(f"ragged mg fp32: phi err {err:.2e}", flush=True)
+    assert err <= 1e-5
 
 
 def test_mg_iterations_flat_for_uniform_laplacian(pb):

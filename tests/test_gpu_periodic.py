@@ -59,7 +59,7 @@ def test_periodic_setup_matches_oracle(pb, kd2):
 
 
 @pytest.mark.parametrize("kd2", [0.0159051, 0.0])
-@pytest.mark.parametrize("prec,tol,bar", [("f64", 1e-10, 1e-8), ("f32", 1e-6, 2e-5), ("f32_refine64", 1e-10, 1e-8)])
+@pytest.mark.parametrize("prec,tol,bar", [("f64", 1e-10, 1e-8), ("f32", 1e-6, 1e-5), ("f32_refine64", 1e-10, 1e-8)])
 def test_periodic_solve_matches_oracle(pb, kd2, prec, tol, bar):
     g, xyz, rad, q = _box((29, 23, 19), 2)
     sm = _setup(pb, g, xyz, rad, q, kd2)
@@ -73,7 +73,9 @@ def test_periodic_solve_matches_oracle(pb, kd2, prec, tol, bar):
     assert info["status"] == pb.PB_OK
     if prec != "f32_refine64":
         assert iters_close(info["iters"], o6.iters)
-    assert np.abs(xv - exact.x).max() <= bar * np.abs(exact.x).max()
+    err = np.abs(xv - exact.x).max() / np.abs(exact.x).max()
+    print(f"periodic {prec} kd2={kd2}: phi err {err:.2e} (bar {bar:g})", flush=True)
+    assert err <= bar
     assert periodic.true_relres(ref, xv) <= (1e-5 if prec == "f32" else 1e-9)
     if kd2 == 0.0:
         assert abs(xv.mean()) <= 1e-12 * np.abs(xv).max()

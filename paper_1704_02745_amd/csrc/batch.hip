@@ -247,7 +247,7 @@ pb_status enqueue_batch_direct(const Plan<T>& P, const pb_problem* probs, int gr
     if (e != PB_OK) return e;
     if constexpr (sizeof(T) == sizeof(float)) {
         bool can = coded_coefficients() != 0 && batch_capacity<T>(P.lds + kCodedLdsBytes, true) >= grid;
-        for (int i = 0; i < P.nprob && can; ++i) can = (size_t)P.L[i].npad * sizeof(float) >= coded_scratch_bytes();
+        for (int i = 0; i < P.nprob && can; ++i) can = coded_layout_ok(P.L[i]);
         if (can) {
             for (int i = 0; i < P.nprob; ++i) {
                 e = enqueue_dictionary(P.s[i].op, P.L[i].npad, (void*)P.s[i].q, P.fit + i, st);
@@ -379,7 +379,7 @@ pb_status batch_autotune_impl(int nprob, const pb_problem* probs, int iters, voi
         int coded = 0;
         if constexpr (sizeof(T) == sizeof(float)) {
             bool can = coded_coefficients() != 0 && batch_capacity<T>(P.lds + kCodedLdsBytes, 2) >= grid;
-            for (int i = 0; i < nprob && can; ++i) can = (size_t)P.L[i].npad * sizeof(float) >= coded_scratch_bytes();
+            for (int i = 0; i < nprob && can; ++i) can = coded_layout_ok(P.L[i]);
             if (can) {
                 for (int i = 0; i < nprob && e == PB_OK; ++i) {
                     e = enqueue_dictionary(P.s[i].op, P.L[i].npad, (void*)P.s[i].q, P.fit + i, st);
@@ -519,7 +519,7 @@ pb_status graph_build(pb_batch_graph* G, Plan<T>& P, void* ws, size_t wsb, hipSt
     G->coded = 0;
     if constexpr (sizeof(T) == sizeof(float)) {
         bool can = coded_coefficients() != 0 && batch_capacity<T>(P.lds + kCodedLdsBytes, 2) >= grid;
-        for (int i = 0; i < P.nprob && can; ++i) can = (size_t)P.L[i].npad * sizeof(float) >= coded_scratch_bytes();
+        for (int i = 0; i < P.nprob && can; ++i) can = coded_layout_ok(P.L[i]);
         if (can) {
             e = fill_table<T>(P, G->probs.data(), 2, st);
             if (e != PB_OK) return e;

@@ -796,17 +796,10 @@ __device__ __forceinline__ T apply_point(T d, T v, T cr, T vr, T cl, T vl, T cu,
 // build planes k0-1 and k0 of p_{l-1}. Threads: own positions s + tid*VEC,
 // inner ring groups on the first 2*halo/VEC threads, outer ring groups on the
 // last 2*halo/VEC threads (the tiling guarantees 2*halo/VEC <= BS).
-//
-// CD (FP32 only): the operator is read as one word of dictionary codes per
-// position from a.cw and decoded through the table `ctb` in LDS. The loads
-// keep the raw words in the coupling fields of Ld; each step decodes them
-// before use, with zero words (code 0 = +0.0) where the uncoded pass loads
-// nothing, so both forms see the same values everywhere.
-template <typename T, int BS, bool NT, bool CD>
+template <typename T, int BS, bool NT>
 __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, T beta, T* lds,
-                            const float* ctb, double (&acc)[NPART]) {
+                            double (&acc)[NPART]) {
 #pragma clang fp contract(off)
-    static_assert(!CD || sizeof(T) == 4, "coded coefficients are an FP32 form");
     constexpr int W = Vec<T>::n;
     using V = typename Vec<T>::type;
     const TileBox tb = tile_box(a, tile);
@@ -831,7 +824,6 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
     const T* __restrict__ CY = a.op.cy;
     const T* __restrict__ CZ = a.op.cz;
     const T* __restrict__ DD = a.op.d;
-    const T* __restrict__ CW = reinterpret_cast<const T*>(a.cw);
     const bool do_x = alpha != T(0);
     const V z0 = vzero<T>();
 
@@ -859,22 +851,10 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
         const bool vm = km >= 0, vc = kc >= 0;
         po_m = (valid && vm) ? vload(pold + (int64_t)km * sp + pos) : z0;
         po_c = (valid && vc) ? vload(pold + (int64_t)kc * sp + pos) : z0;
-        if constexpr (CD) {
-            const V w = (valid && vm) ? vload(CW + (int64_t)km * sp + pos) : z0;
-#pragma unroll
-            for (int u = 0; u < W; ++u) vget(cz_c, u) = ctb[(bits(vget(w, u)) >> 16) & 255u];
-        } else {
-            cz_c = (valid && vm) ? vload(CZ + (int64_t)km * sp + pos) : z0;
-        }
+        cz_c = (valid && vm) ? vload(CZ + (int64_t)km * sp + pos) : z0;
         hpo_m = (h_in && vm) ? vload(pold + (int64_t)km * sp + hp) : z0;
         hpo_c = (h_in && vc) ? vload(pold + (int64_t)kc * sp + hp) : z0;
-        if constexpr (CD) {
-            const V w = (h_in && vm) ? vload(CW + (int64_t)km * sp + hp) : z0;
-#pragma unroll
-            for (int u = 0; u < W; ++u) vget(hcz_c, u) = ctb[(bits(vget(w, u)) >> 16) & 255u];
-        } else {
-            hcz_c = (h_in && vm) ? vload(CZ + (int64_t)km * sp + hp) : z0;
-        }
+        hcz_c = (h_in && vm) ? vload(CZ + (int64_t)km * sp + hp) : z0;
         const V o_po = (o_in && vc) ? vload(pold + (int64_t)kc * sp + op) : z0;
         T* P = (kc & 1) ? PO1 : PO0;
         if (valid) vstore(P + (pos - obase), po_c);
@@ -910,21 +890,14 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
             if (v2) L.po_n = sload<NT>(pold + (int64_t)kf * sp + pos);
             if (v1) {
                 L.r_o = sload<NT>(rold + g1);
-                if constexpr (!CD) L.d_n = sload<NT>(DD + g1);
+                L.d_n = sload<NT>(DD + g1);
                 if (xu) L.x_n = sload<NT>(a.x + g1);
-                if constexpr (CD) {   // raw code words; d_n above is replaced at decode
-                    L.cx_n = sload<NT>(CW + g1);
-                    L.cxm_n = pos >= 1 ? CW[g1 - 1] : T(0);
+                L.cx_n = vload(CX + g1);
+                L.cy_n = vload(CY + g1);
+                L.cz_n = sload<NT>(CZ + g1);
+                L.cxm_n = pos >= 1 ? CX[g1 - 1] : T(0);
 #pragma unroll
-                    for (int u = 0; u < W; ++u) L.cym_n[u] = (pos + u - nx >= 0) ? CW[g1 + u - nx] : T(0);
-                } else {
-                    L.cx_n = vload(CX + g1);
-                    L.cy_n = vload(CY + g1);
-                    L.cz_n = sload<NT>(CZ + g1);
-                    L.cxm_n = pos >= 1 ? CX[g1 - 1] : T(0);
-#pragma unroll
-                    for (int u = 0; u < W; ++u) L.cym_n[u] = (pos + u - nx >= 0) ? CY[g1 + u - nx] : T(0);
-                }
+                for (int u = 0; u < W; ++u) L.cym_n[u] = (pos + u - nx >= 0) ? CY[g1 + u - nx] : T(0);
             }
         }
         L.hpo_n = z0; L.h_r = z0; L.h_d = z0; L.h_cx = z0; L.h_cy = z0; L.h_cz = z0;
@@ -935,25 +908,15 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
             if (v2) L.hpo_n = vload(pold + (int64_t)kf * sp + hp);
             if (v1) {
                 const int64_t gh = (int64_t)kn * sp + hp;
-                if constexpr (CD) {   // raw code words (cz is needed on every plane)
-                    L.h_cx = vload(CW + gh);
-                    if (own1) {
-                        L.h_r = vload(rold + gh);
-                        L.h_cxm = hp >= 1 ? CW[gh - 1] : T(0);
+                L.h_cz = vload(CZ + gh);
+                if (own1) {
+                    L.h_r = vload(rold + gh);
+                    L.h_d = vload(DD + gh);
+                    L.h_cx = vload(CX + gh);
+                    L.h_cy = vload(CY + gh);
+                    L.h_cxm = hp >= 1 ? CX[gh - 1] : T(0);
 #pragma unroll
-                        for (int u = 0; u < W; ++u) L.h_cym[u] = (hp + u - nx >= 0) ? CW[gh + u - nx] : T(0);
-                    }
-                } else {
-                    L.h_cz = vload(CZ + gh);
-                    if (own1) {
-                        L.h_r = vload(rold + gh);
-                        L.h_d = vload(DD + gh);
-                        L.h_cx = vload(CX + gh);
-                        L.h_cy = vload(CY + gh);
-                        L.h_cxm = hp >= 1 ? CX[gh - 1] : T(0);
-#pragma unroll
-                        for (int u = 0; u < W; ++u) L.h_cym[u] = (hp + u - nx >= 0) ? CY[gh + u - nx] : T(0);
-                    }
+                    for (int u = 0; u < W; ++u) L.h_cym[u] = (hp + u - nx >= 0) ? CY[gh + u - nx] : T(0);
                 }
             }
         }
@@ -990,40 +953,6 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
         V& hpo_n = cur.hpo_n; V& h_r = cur.h_r; V& h_d = cur.h_d; V& h_cx = cur.h_cx; V& h_cy = cur.h_cy;
         V& h_cz = cur.h_cz; T& h_cxm = cur.h_cxm; T (&h_cym)[W] = cur.h_cym;
         const V& o_po = cur.o_po;
-        if constexpr (CD) {
-            // own positions: the word of each node, then the left x-coupling
-            // (byte 0 of the word to the left) and the y-couplings below
-            // (byte 1 of the words one row down)
-            const V w = cx_n;
-#pragma unroll
-            for (int u = 0; u < W; ++u) {
-                const uint32_t c = bits(vget(w, u));
-                vget(cx_n, u) = ctb[c & 255u];
-                vget(cy_n, u) = ctb[(c >> 8) & 255u];
-                vget(cz_n, u) = ctb[(c >> 16) & 255u];
-                vget(d_n, u) = ctb[c >> 24];
-                cym_n[u] = ctb[(bits(cym_n[u]) >> 8) & 255u];
-            }
-            cxm_n = ctb[bits(cxm_n) & 255u];
-            // inner ring: cz on every plane; the rest only where the uncoded
-            // pass loads it (owned planes), zero elsewhere. Other threads hold
-            // zero words there, which already read as +0.0, the value code 0
-            // decodes to, so only ring threads decode.
-            if (is_h) {
-                const V hw = h_cx;
-#pragma unroll
-                for (int u = 0; u < W; ++u) {
-                    const uint32_t c = bits(vget(hw, u));
-                    vget(h_cz, u) = ctb[(c >> 16) & 255u];
-                    vget(h_cx, u) = own1 ? ctb[c & 255u] : T(0);
-                    vget(h_cy, u) = own1 ? ctb[(c >> 8) & 255u] : T(0);
-                    vget(h_d, u) = own1 ? ctb[c >> 24] : T(0);
-                    h_cym[u] = ctb[(bits(h_cym[u]) >> 8) & 255u];
-                }
-                h_cxm = ctb[bits(h_cxm) & 255u];
-            }
-        }
-
         // ---- q_{l-1}, r_{l-1}, p_{l-1} (and x) on plane k+1, own positions
         V pn_n = z0, rn_n = z0;
         if (valid && v1) {
@@ -1131,6 +1060,336 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
     }
 }
 
+// ------------------------------------------------------------------ coded 40-byte pass
+
+// Raw buffer resources (stride 0): a load at a byte offset at or past
+// num_records returns 0 and a store there is dropped. The coded pass gives
+// each plane of an array a resource one plane long (zero long outside the
+// grid), so neighbours before a plane's first position, past its end or on
+// planes beyond the grid read as the zeros the iteration needs there, with
+// no test or select in the plane loop; the per-thread offsets are fixed for
+// the whole march.
+constexpr int kRawBufferWord3 = 0x00020000;
+// An offset past the end of every plane resource (planes hold fewer than
+// 2^29 positions, checked on the host). Offsets are only ever formed from
+// in-plane positions or this value: the bounds check compares the unsigned
+// sum of offset and access size, so an offset meant to be negative would
+// wrap around it and read the bytes before the plane.
+constexpr uint32_t kOutOfPlane = 0x80000000u;
+using Rsrc = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ Rsrc plane_rsrc(const void* base, int k, int nz, int64_t sp) {
+    const bool in = k >= 0 && k < nz;
+    const char* p = static_cast<const char*>(base) + (in ? (int64_t)k * sp * 4 : 0);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(p), 0, in ? (int)(sp * 4) : 0, kRawBufferWord3);
+}
+template <bool NT>
+__device__ __forceinline__ float4 bload4(Rsrc r, uint32_t off) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, NT ? 2 : 0));
+}
+template <bool NT>
+__device__ __forceinline__ u32x4 bload4w(Rsrc r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, NT ? 2 : 0);
+}
+__device__ __forceinline__ uint32_t bload1(Rsrc r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+}
+template <bool NT>
+__device__ __forceinline__ void bstore4(Rsrc r, uint32_t off, const float4& v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, (int)off, 0, NT ? 2 : 0);
+}
+__device__ __forceinline__ float4 lds4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+__device__ __forceinline__ void lds4(float* p, const float4& v) { *reinterpret_cast<float4*>(p) = v; }
+
+// One pass on one tile of the 40-byte form with the operator read as one
+// word of dictionary codes per position (byte 0: cx, 1: cy, 2: cz, 3: d). The
+// iteration, the LDS planes and the order of every floating-point operation
+// are those of pass_tile40, so the iterates are bit for bit the uncoded
+// pass's. `tv` is the dictionary and `ti` the Jacobi scaling of each entry
+// (jacobi_inv of the value), both in static LDS, so that a lookup is one
+// shift of a code byte and one LDS read.
+//
+// Threads past the segment's end work on a copy of the last group (their
+// loads stay in bounds) and store nothing and add nothing to the sums.
+template <int BS, bool NT>
+__device__ void pass_tile_coded(const KArgs<float>& a, int tile, int o, int n, float alpha, float beta, float* lds,
+                                const float* tv, double (&acc)[NPART]) {
+#pragma clang fp contract(off)
+    constexpr int W = 4;
+    using V = float4;
+    const float* ti = tv + kCodedTableSize;
+    const TileBox tb = tile_box(a, tile);
+    const int64_t s = tb.s, e = tb.e, sp = a.sp;
+    const int k0 = tb.k0, k1 = tb.k1, nz = a.nz;
+    const int H = a.halo, nx = a.nx;
+    const int lo_len = a.seglen + 4 * H, ln_len = a.seglen + 2 * H;
+    float* const PO0 = lds;
+    float* const PO1 = lds + lo_len;
+    float* const PN0 = lds + 2 * lo_len;
+    float* const PN1 = PN0 + ln_len;
+    float* const CX0 = PN1 + ln_len;
+    float* const CX1 = CX0 + ln_len;
+    float* const CY0 = CX1 + ln_len;
+    float* const CY1 = CY0 + ln_len;
+    const int64_t obase = s - 2 * H, nbase = s - H;
+    const float* rold = o ? a.r[1] : a.r[0];
+    const float* pold = o ? a.p[1] : a.p[0];
+    float* rnew = n ? a.r[1] : a.r[0];
+    float* pnew = n ? a.p[1] : a.p[0];
+    const float* CW = a.cw;
+    const bool do_x = alpha != 0.0f;
+    const V z0 = make_float4(0.f, 0.f, 0.f, 0.f);
+
+    const int tid = threadIdx.x;
+    const int64_t pos = s + (int64_t)tid * W;
+    const bool valid = pos < e;
+    const int64_t posc = valid ? pos : e - W;
+    const int ring = 2 * H / W;
+    const bool is_h = tid < ring;
+    const int64_t hp = (tid < H / W) ? (s - H + (int64_t)tid * W) : (e + (int64_t)(tid - H / W) * W);
+    const bool h_in = is_h && hp >= 0 && hp < sp;
+    const int og = tid - (BS - ring);
+    const bool is_o = og >= 0;
+    const int64_t op = (og < H / W) ? (s - 2 * H + (int64_t)og * W) : (e + H + (int64_t)(og - H / W) * W);
+    // byte offsets in a plane; positions outside it get kOutOfPlane, which
+    // lies past every plane resource, so their loads return 0
+    auto off = [&](int64_t q) { return (q >= 0 && q < sp) ? (uint32_t)q * 4u : kOutOfPlane; };
+    const uint32_t oo = off(posc), oxm = off(posc - 1);
+    uint32_t oym[W];
+#pragma unroll
+    for (int u = 0; u < W; ++u) oym[u] = off(posc + u - nx);
+    const uint32_t oh = off(hp), ohxm = off(hp - 1);
+    uint32_t ohym[W];
+#pragma unroll
+    for (int u = 0; u < W; ++u) ohym[u] = off(hp + u - nx);
+    const uint32_t oop = off(op);
+    const int lo = (int)(posc - obase), ln = (int)(posc - nbase);
+    const int lho = (int)(hp - obase), lhn = (int)(hp - nbase), loo = (int)(op - obase);
+
+    auto val = [&](uint32_t w, int byte) { return tv[(w >> (8 * byte)) & 255u]; };
+    auto inv = [&](uint32_t w) { return ti[w >> 24]; };
+
+    // cz of plane k (own, ring) and p_{l-2} of planes k0-2, k0-1 into LDS
+    V cz_c, hcz_c;
+    {
+        const int km = k0 - 2, kc = k0 - 1;
+        const Rsrc pm = plane_rsrc(pold, km, nz, sp), pc = plane_rsrc(pold, kc, nz, sp);
+        const Rsrc wm = plane_rsrc(CW, km, nz, sp);
+        const V po_m = bload4<false>(pm, oo), po_c = bload4<false>(pc, oo);
+        const u32x4 w = bload4w<false>(wm, oo);
+#pragma unroll
+        for (int u = 0; u < W; ++u) vget(cz_c, u) = val(w[u], 2);
+        float* P = (kc & 1) ? PO1 : PO0;
+        float* Pm = (km & 1) ? PO1 : PO0;
+        if (valid) {
+            lds4(P + lo, po_c);
+            lds4(Pm + lo, po_m);
+        }
+        if (is_h) {
+            const V hpo_m = bload4<false>(pm, oh), hpo_c = bload4<false>(pc, oh);
+            const u32x4 hw = bload4w<false>(wm, oh);
+#pragma unroll
+            for (int u = 0; u < W; ++u) vget(hcz_c, u) = val(hw[u], 2);
+            lds4(P + lho, hpo_c);
+            lds4(Pm + lho, hpo_m);
+        }
+        if (is_o) lds4(P + loo, bload4<false>(pc, oop));
+    }
+
+    // The global loads of step k: p_{l-2} of plane k+2; r, x and the code
+    // words (own, x-1 and y-1 neighbours) of plane k+1; the same on the inner
+    // ring, p_{l-2} of plane k+2 on the outer ring. They are issued during the
+    // previous step, after the last use of that step's values.
+    struct Ld {
+        V po, r, x;
+        u32x4 w;
+        uint32_t wxm, wym[W];
+        V hpo, hr;
+        u32x4 hw;
+        uint32_t hwxm, hwym[W];
+        V opo;
+    };
+    auto issue = [&](int k, Ld& L) {
+        const int kn = k + 1, kf = k + 2;
+        const bool own1 = kn >= k0 && kn < k1;
+        const Rsrc pf = plane_rsrc(pold, kf, nz, sp);
+        const Rsrc rn = plane_rsrc(rold, kn, nz, sp);
+        const Rsrc wn = plane_rsrc(CW, kn, nz, sp);
+        L.po = bload4<NT>(pf, oo);
+        L.r = bload4<NT>(rn, oo);
+        if (own1 && do_x) L.x = bload4<NT>(plane_rsrc(a.x, kn, nz, sp), oo);
+        L.w = bload4w<NT>(wn, oo);
+        L.wxm = bload1(wn, oxm);
+#pragma unroll
+        for (int u = 0; u < W; ++u) L.wym[u] = bload1(wn, oym[u]);
+        if (is_h) {
+            L.hpo = bload4<false>(pf, oh);
+            L.hw = bload4w<false>(wn, oh);
+            if (own1) {
+                L.hr = bload4<false>(rn, oh);
+                L.hwxm = bload1(wn, ohxm);
+#pragma unroll
+                for (int u = 0; u < W; ++u) L.hwym[u] = bload1(wn, ohym[u]);
+            }
+        }
+        if (is_o) L.opo = bload4<false>(pf, oop);
+    };
+    Ld cur;
+    issue(k0 - 2, cur);
+    lds_barrier();
+
+    V pn_m = z0, rn_c = z0, d_c = z0, iv_c = z0;   // p_{l-1} on k-1; r_{l-1}, d, 1/d on k (own)
+    V cz_m = z0;                                   // cz of plane k-1
+
+    for (int k = k0 - 2; k < k1; ++k) {
+        const int kn = k + 1, kf = k + 2;
+        const bool v1 = kn >= 0 && kn < nz;
+        const bool own1 = kn >= k0 && kn < k1;   // plane k+1 belongs to this tile
+        const bool xu = own1 && do_x;
+        float* const POc = (kn & 1) ? PO1 : PO0;
+        float* const POn = (kf & 1) ? PO1 : PO0;
+        const float* const PNc = (k & 1) ? PN1 : PN0;
+        float* const PNn = (kn & 1) ? PN1 : PN0;
+        const float* const CXc = (k & 1) ? CX1 : CX0;
+        const float* const CYc = (k & 1) ? CY1 : CY0;
+        float* const CXn = (kn & 1) ? CX1 : CX0;
+        float* const CYn = (kn & 1) ? CY1 : CY0;
+
+        // decode plane k+1's words: own positions, the left x-coupling and
+        // the y-couplings one row down
+        V cx_n, cy_n, cz_n, d_n, iv_n;
+        float cym_n[W];
+#pragma unroll
+        for (int u = 0; u < W; ++u) {
+            const uint32_t c = cur.w[u];
+            vget(cx_n, u) = val(c, 0);
+            vget(cy_n, u) = val(c, 1);
+            vget(cz_n, u) = val(c, 2);
+            vget(d_n, u) = val(c, 3);
+            vget(iv_n, u) = inv(c);
+            cym_n[u] = val(cur.wym[u], 1);
+        }
+        const float cxm_n = val(cur.wxm, 0);
+
+        // ---- q_{l-1}, r_{l-1}, p_{l-1} (and x) on plane k+1, own positions
+        const V po_c = lds4(POc + lo);    // p_{l-2}, plane k+1
+        const V po_m = lds4(POn + lo);    // p_{l-2}, plane k
+        V pn_n = z0, rn_n = z0, xv = cur.x;
+        if (v1) {
+            const float left = POc[lo - 1], right = POc[lo + W];
+#pragma unroll
+            for (int u = 0; u < W; ++u) {
+                const float pr = (u == W - 1) ? right : vget(po_c, u + 1);
+                const float pl = (u == 0) ? left : vget(po_c, u - 1);
+                const float cl = (u == 0) ? cxm_n : vget(cx_n, u - 1);
+                const float qo = apply_point(vget(d_n, u), vget(po_c, u), vget(cx_n, u), pr, cl, pl, vget(cy_n, u),
+                                             POc[lo + u + nx], cym_n[u], POc[lo + u - nx], vget(cz_n, u),
+                                             vget(cur.po, u), vget(cz_c, u), vget(po_m, u));
+                const float r = fmaf(-alpha, qo, vget(cur.r, u));
+                vget(rn_n, u) = r;
+                vget(pn_n, u) = fmaf(beta, vget(po_c, u), r * vget(iv_n, u));
+                if (xu) vget(xv, u) = fmaf(alpha, vget(po_c, u), vget(xv, u));
+            }
+            if (valid) lds4(PNn + ln, pn_n);
+        }
+        // ---- the inner ring: decode, and p_{l-1} on owned planes (LDS only)
+        V h_cx, h_cy, h_cz;
+        if (is_h) {
+#pragma unroll
+            for (int u = 0; u < W; ++u) {
+                const uint32_t c = cur.hw[u];
+                vget(h_cx, u) = val(c, 0);
+                vget(h_cy, u) = val(c, 1);
+                vget(h_cz, u) = val(c, 2);
+            }
+            if (own1) {
+                V hv = z0;
+                if (h_in) {
+                    const V hpo_c = lds4(POc + lho);
+                    const V hpo_m = lds4(POn + lho);
+                    const float left = POc[lho - 1], right = POc[lho + W];
+                    const float h_cxm = val(cur.hwxm, 0);
+#pragma unroll
+                    for (int u = 0; u < W; ++u) {
+                        const uint32_t c = cur.hw[u];
+                        const float pr = (u == W - 1) ? right : vget(hpo_c, u + 1);
+                        const float pl = (u == 0) ? left : vget(hpo_c, u - 1);
+                        const float cl = (u == 0) ? h_cxm : vget(h_cx, u - 1);
+                        const float qo = apply_point(val(c, 3), vget(hpo_c, u), vget(h_cx, u), pr, cl, pl,
+                                                     vget(h_cy, u), POc[lho + u + nx], val(cur.hwym[u], 1),
+                                                     POc[lho + u - nx], vget(h_cz, u), vget(cur.hpo, u),
+                                                     vget(hcz_c, u), vget(hpo_m, u));
+                        const float r = fmaf(-alpha, qo, vget(cur.hr, u));
+                        vget(hv, u) = fmaf(beta, vget(hpo_c, u), r * inv(c));
+                    }
+                }
+                lds4(PNn + lhn, hv);
+            }
+        }
+        // ---- p_{l-2} of plane k+2 and the couplings of plane k+1 into LDS
+        // for the next step (the p_old slot of plane k is free from here on)
+        if (valid) {
+            lds4(POn + lo, cur.po);
+            lds4(CXn + ln, cx_n);
+            lds4(CYn + ln, cy_n);
+        }
+        if (is_h) {
+            lds4(POn + lho, cur.hpo);
+            lds4(CXn + lhn, h_cx);
+            lds4(CYn + lhn, h_cy);
+            hcz_c = h_cz;
+        }
+        if (is_o) lds4(POn + loo, cur.opo);
+        // ---- r, p, x of plane k+1 to memory, once every load of this step
+        // has been used (a store in flight would make the wait for a load
+        // wait for the store too), then the loads of the next step, which
+        // land while q_l and the sums below are computed
+        if (valid && v1 && own1) {
+            bstore4<NT>(plane_rsrc(rnew, kn, nz, sp), oo, rn_n);
+            bstore4<NT>(plane_rsrc(pnew, kn, nz, sp), oo, pn_n);
+            if (xu) bstore4<NT>(plane_rsrc(a.x, kn, nz, sp), oo, xv);
+        }
+        if (k + 1 < k1) issue(k + 1, cur);
+        // ---- q_l = A p_{l-1} on plane k and the partial sums
+        const V pn_c = (k >= 0) ? lds4(PNc + ln) : z0;   // p_{l-1}, plane k (zero below the grid)
+        if (k >= k0) {
+            const V cxv = lds4(CXc + ln), cyv = lds4(CYc + ln);
+            const float left = PNc[ln - 1], right = PNc[ln + W];
+#pragma unroll
+            for (int u = 0; u < W; ++u) {
+                const float p = vget(pn_c, u);
+                const float pr = (u == W - 1) ? right : vget(pn_c, u + 1);
+                const float pl = (u == 0) ? left : vget(pn_c, u - 1);
+                const float cl = (u == 0) ? CXc[ln - 1] : vget(cxv, u - 1);
+                const float qq = apply_point(vget(d_c, u), p, vget(cxv, u), pr, cl, pl, vget(cyv, u),
+                                             PNc[ln + u + nx], CYc[ln + u - nx], PNc[ln + u - nx], vget(cz_c, u),
+                                             vget(pn_n, u), vget(cz_m, u), vget(pn_m, u));
+                if (valid) {
+                    const float iv = vget(iv_c, u);
+                    const double pd = (double)p, qd = (double)qq, rd = (double)vget(rn_c, u);
+                    const double zd = (double)(vget(rn_c, u) * iv), wd = (double)(qq * iv);
+                    acc[0] = fma(pd, qd, acc[0]);
+                    acc[1] = fma(rd, zd, acc[1]);
+                    acc[2] = fma(rd, wd, acc[2]);
+                    acc[3] = fma(qd, wd, acc[3]);
+                    acc[4] = fma(rd, rd, acc[4]);
+                    acc[5] = fma(rd, qd, acc[5]);
+                    acc[6] = fma(qd, qd, acc[6]);
+                }
+            }
+        }
+        // ---- advance one plane
+        pn_m = pn_c;
+        rn_c = rn_n;
+        d_c = d_n;
+        iv_c = iv_n;
+        cz_m = cz_c;
+        cz_c = cz_n;
+        lds_barrier();
+    }
+}
+
 template <typename T, int BS>
 __device__ void final_tile(const KArgs<T>& a, int tile, T alpha, const T* p, bool zero) {
     constexpr int W = Vec<T>::n;
@@ -1178,15 +1437,20 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
     const int lds_len = a.seglen + 2 * a.halo;
     T* lds0 = reinterpret_cast<T*>(lds_raw);
     T* lds1 = lds0 + lds_len;
-    // coded form: the dictionary after the 40-byte pass's plane buffers
-    float* tb = nullptr;
+    // coded form: the dictionary and the Jacobi scaling of each entry, in
+    // static LDS (their addresses are then constants of the kernel)
     bool use_codes = CD;
+    float* dict = nullptr;
     if constexpr (CD) {
+        __shared__ float s_dict[2 * kCodedTableSize];
+        dict = s_dict;
         if constexpr (RT) use_codes = a.fit[0] == 1;
         if (use_codes) {
-            tb = reinterpret_cast<float*>(lds0 + 2 * (size_t)(a.seglen + 4 * a.halo) +
-                                          6 * (size_t)(a.seglen + 2 * a.halo));
-            for (int i = threadIdx.x; i < kCodedTableSize; i += BS) tb[i] = a.ctab[i];
+            for (int i = threadIdx.x; i < kCodedTableSize; i += BS) {
+                const float v = a.ctab[i];
+                s_dict[i] = v;
+                s_dict[kCodedTableSize + i] = jacobi_inv(v);
+            }
         }
         __syncthreads();
     }
@@ -1244,11 +1508,11 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
             double acc[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             if constexpr (SCH == 1)
             {
-                if constexpr (CD && RT) {
-                    if (use_codes) pass_tile40<T, BS, NT, true>(a, t, o, n, alpha, beta, lds0, tb, acc);
-                    else pass_tile40<T, BS, NT, false>(a, t, o, n, alpha, beta, lds0, nullptr, acc);
+                if constexpr (CD) {
+                    if (use_codes) pass_tile_coded<BS, NT>(a, t, o, n, alpha, beta, lds0, dict, acc);
+                    else pass_tile40<T, BS, NT>(a, t, o, n, alpha, beta, lds0, acc);
                 } else {
-                    pass_tile40<T, BS, NT, CD>(a, t, o, n, alpha, beta, lds0, tb, acc);
+                    pass_tile40<T, BS, NT>(a, t, o, n, alpha, beta, lds0, acc);
                 }
             }
             else
@@ -1620,11 +1884,11 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
     int coded = 0;
     if constexpr (sizeof(T) == 4) {
         if (t.scheme == 1 && !t.per && coded_coefficients() && s.q && s.q2 &&
-            (size_t)L.npad * sizeof(float) >= coded_scratch_bytes()) {
+            coded_layout_ok(L)) {
             KernelFn cfn = nullptr;
             for (const auto& v : variants<T>())
                 if (v.cd && v.bs == t.bs && v.mc == t.mc && v.nt == t.nt) cfn = v.fn;
-            const size_t clds = t.lds + sizeof(float) * kCodedTableSize;
+            const size_t clds = t.lds + kCodedLdsBytes;
             const int cus = di.cus > 0 ? di.cus : 256;
             if (cfn && (int64_t)max_coresident(cfn, t.bs, clds) * cus >= t.grid) {
                 bool fits = s.codes_valid != 0;

@@ -288,7 +288,7 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
             if (e != PB_OK) return e;
         }
         // coded coefficients: the dictionary now, the code words once the fit flag is read back
-        if (coded_coefficients() && (size_t)s.L.npad * sizeof(float) >= coded_scratch_bytes()) {
+        if (coded_coefficients() && coded_layout_ok(s.L)) {
             e = enqueue_dictionary(s.s.op, s.L.npad, (void*)s.s.q, &s.rec->fit, st);
             if (e != PB_OK) return e;
         }

@@ -97,6 +97,12 @@ int streaming_for(const Layout& L);
 // codes per padded position (byte 0: cx, 1: cy, 2: cz, 3: d).
 constexpr int kCodedTableSize = 256;
 size_t coded_scratch_bytes();
+// Whether a problem of this layout can run the coded pass: its code words and
+// dictionary fit the arrays the pass leaves unused, and its planes are short
+// enough for the pass's 32-bit in-plane byte offsets.
+inline bool coded_layout_ok(const Layout& L) {
+    return (size_t)L.npad * sizeof(float) >= coded_scratch_bytes() && L.sp < ((int64_t)1 << 29);
+}
 // Builds the dictionary in `scratch` (coded_scratch_bytes()) and, when the
 // values fit, the code words; fits = false leaves `codes` untouched. Reads one
 // flag back to the host (synchronises `st`). *table: the device dictionary.
@@ -108,8 +114,9 @@ pb_status enqueue_dictionary(const Op<float>& op, int64_t npad, void* scratch, i
 pb_status enqueue_encode(const Op<float>& op, int64_t npad, const void* scratch, uint32_t* codes, hipStream_t st,
                          const int* fit = nullptr);   // fit: skip unless *fit == 1 (device flag)
 const float* dictionary_table(const void* scratch);
-// Extra LDS of the coded kernels (the dictionary).
-constexpr size_t kCodedLdsBytes = sizeof(float) * kCodedTableSize;
+// Extra dynamic LDS of the coded kernels: none, since the dictionary sits in
+// static LDS, which the kernels' own group segment size already counts.
+constexpr size_t kCodedLdsBytes = 0;
 // Process-wide switch (default on): 0 keeps every fused FP32 solve uncoded.
 void set_coded_coefficients(int on);
 int coded_coefficients();

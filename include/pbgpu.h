@@ -223,6 +223,17 @@ pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h,
                    void* workspace, size_t workspace_bytes, void* stream,
                    pb_info* info);
 
+/*
+ * pb_stream_copy: copies `bytes` (a multiple of 16) from src to dst on
+ * `stream` with 16-byte vector loads and stores, with the nontemporal hint
+ * when `nontemporal` is nonzero: the access kinds of the fused JPCG pass's
+ * streams, without arithmetic, halo or barrier. A measurement aid: timing it
+ * gives the streaming ceiling the solver's bandwidth is compared with. src
+ * and dst are device pointers, 16-byte aligned, not overlapping.
+ * Errors: PB_ERR_ARG (null or misaligned), PB_ERR_HIP.
+ */
+pb_status pb_stream_copy(const void* src, void* dst, size_t bytes, int32_t nontemporal, void* stream);
+
 /* One tiling of the fused stencil kernel, as chosen by pb_autotune. */
 typedef struct {
     int32_t block;          /* threads per workgroup */

@@ -40,7 +40,7 @@ EXPORTS = ("pb_version", "pb_last_error", "pb_setup_workspace_bytes", "pb_setup"
            "pb_server_stats", "pb_server_destroy",
            "pb_energy_workspace_bytes", "pb_energy",
            "pb_solvation_workspace_bytes", "pb_solvation_energy",
-           "pb_setup_ex_workspace_bytes", "pb_setup_ex")
+           "pb_setup_ex_workspace_bytes", "pb_setup_ex", "pb_stream_copy")
 
 
 class PBError(RuntimeError):
@@ -128,6 +128,8 @@ def _load():
     lib.pb_solve.argtypes = [i32, i32, i32, dbl, vp, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
                              vp, sz, vp, ctypes.POINTER(Info)]
     lib.pb_autotune.restype = ctypes.c_int
+    lib.pb_stream_copy.restype = ctypes.c_int
+    lib.pb_stream_copy.argtypes = [vp, vp, sz, i32, vp]
     lib.pb_autotune.argtypes = [i32, i32, i32, dbl, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts), i32,
                                 vp, sz, vp, ctypes.POINTER(Tuning)]
     lib.pb_set_tuning.restype = ctypes.c_int
@@ -328,6 +330,13 @@ def solve(sysm: System, tol=1e-6, precision="f32", op="stencil", maxiter=0, x0=N
                       workspace.numel(), _stream(stream), ctypes.byref(info))
     _check(st, allow=(PB_OK,) if check else (PB_OK, PB_NOT_CONVERGED))
     return out, info.as_dict()
+
+
+def stream_copy(src: torch.Tensor, dst: torch.Tensor, nontemporal=True, stream=None) -> None:
+    """pb_stream_copy of src into dst (same size in bytes, 16-byte multiple)."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    _check(lib.pb_stream_copy(_ptr(src), _ptr(dst), nbytes, 1 if nontemporal else 0, _stream(stream)))
 
 
 def autotune(sysm: System, precision="f32", iters_per_trial=20,

@@ -25,7 +25,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 # Setup arithmetic and the multigrid coarsening must round exactly as written
 # (no fused multiply-add).
 PER_FILE = {"setup.hip": ["-ffp-contract=off"], "mg.hip": ["-ffp-contract=off"]}
-SOURCES = ["api.hip", "setup.hip", "operator.hip", "jpcg.hip", "dia.hip", "batch.hip", "server.hip", "solvation.hip", "mg.hip", "coded.hip"]
+SOURCES = ["api.hip", "setup.hip", "operator.hip", "jpcg.hip", "dia.hip", "batch.hip", "server.hip", "solvation.hip", "mg.hip", "coded.hip", "stream.hip"]
 
 
 def _hipcc() -> str:

@@ -224,6 +224,28 @@ pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h,
                    pb_info* info);
 
 /*
+ * pb_solve_noalloc: pb_solve for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation). Same arguments, operators, precisions and results as
+ * pb_solve, but no workspace: the solve runs in a scratch array the library
+ * holds on each GPU for the life of the process
+ * (pb_solve_noalloc_max_bytes(), 256 MiB, enough for grids up to about
+ * 2.2M nodes such as 129^3), and the call makes no device allocation and
+ * records no HIP events (info->kernel_seconds is 0). The scratch is shared
+ * by every call on one GPU: calls that overlap on one GPU (other host
+ * threads, other streams) race and must be serialised by the caller.
+ * Errors: those of pb_solve, and PB_ERR_NOMEM (pb_last_error() says so)
+ * when the grid needs more scratch than the library holds, before any
+ * launch.
+ */
+pb_status pb_solve_noalloc(int32_t nx, int32_t ny, int32_t nz, double h,
+                           const double* eps_x, const double* eps_y, const double* eps_z,
+                           const double* kappa2, const double* rhs, double* x,
+                           const pb_solve_opts* opts, void* stream, pb_info* info);
+/* Bytes of the per-GPU scratch of pb_solve_noalloc. */
+size_t pb_solve_noalloc_max_bytes(void);
+
+/*
  * pb_stream_copy: copies `bytes` (a multiple of 16) from src to dst on
  * `stream` with 16-byte vector loads and stores, with the nontemporal hint
  * when `nontemporal` is nonzero: the access kinds of the fused JPCG pass's

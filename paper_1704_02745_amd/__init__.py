@@ -40,7 +40,8 @@ EXPORTS = ("pb_version", "pb_last_error", "pb_setup_workspace_bytes", "pb_setup"
            "pb_server_stats", "pb_server_destroy",
            "pb_energy_workspace_bytes", "pb_energy",
            "pb_solvation_workspace_bytes", "pb_solvation_energy",
-           "pb_setup_ex_workspace_bytes", "pb_setup_ex", "pb_stream_copy")
+           "pb_setup_ex_workspace_bytes", "pb_setup_ex", "pb_solve_noalloc", "pb_solve_noalloc_max_bytes",
+           "pb_stream_copy")
 
 
 class PBError(RuntimeError):
@@ -128,8 +129,13 @@ def _load():
     lib.pb_solve.argtypes = [i32, i32, i32, dbl, vp, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
                              vp, sz, vp, ctypes.POINTER(Info)]
     lib.pb_autotune.restype = ctypes.c_int
+    lib.pb_solve_noalloc.restype = ctypes.c_int
+    lib.pb_solve_noalloc.argtypes = [i32, i32, i32, dbl, vp, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts), vp,
+                                     ctypes.POINTER(Info)]
     lib.pb_stream_copy.restype = ctypes.c_int
     lib.pb_stream_copy.argtypes = [vp, vp, sz, i32, vp]
+    lib.pb_solve_noalloc_max_bytes.restype = sz
+    lib.pb_solve_noalloc_max_bytes.argtypes = []
     lib.pb_autotune.argtypes = [i32, i32, i32, dbl, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts), i32,
                                 vp, sz, vp, ctypes.POINTER(Tuning)]
     lib.pb_set_tuning.restype = ctypes.c_int
@@ -332,11 +338,35 @@ def solve(sysm: System, tol=1e-6, precision="f32", op="stencil", maxiter=0, x0=N
     return out, info.as_dict()
 
 
+def solve_noalloc(sysm: System, out: torch.Tensor, tol=1e-6, precision="f32", op="stencil", maxiter=0,
+                  warm_start=False, inner_tol=0.0, max_outer=0, stream=None, check=True):
+    """pb_solve_noalloc: the solve in the library's per-GPU scratch, no
+    workspace and no allocation; `out` (FP64, the grid's shape) receives x
+    and holds the initial guess when warm_start. Returns the info dict."""
+    nx, ny, nz = sysm.dims
+    o = SolveOpts()
+    o.tol, o.maxiter = float(tol), int(maxiter)
+    o.precision, o.op = PRECISIONS[precision], OPERATORS[op]
+    o.warm_start = 1 if warm_start else 0
+    o.inner_tol, o.max_outer = float(inner_tol), int(max_outer)
+    o.boundary = sysm.grid.boundary
+    info = Info()
+    st = lib.pb_solve_noalloc(nx, ny, nz, sysm.grid.h, _ptr(sysm.eps_x), _ptr(sysm.eps_y), _ptr(sysm.eps_z),
+                              _ptr(sysm.kappa2), _ptr(sysm.rhs), _ptr(out), ctypes.byref(o), _stream(stream),
+                              ctypes.byref(info))
+    _check(st, allow=(PB_OK,) if check else (PB_OK, PB_NOT_CONVERGED))
+    return info.as_dict()
+
+
 def stream_copy(src: torch.Tensor, dst: torch.Tensor, nontemporal=True, stream=None) -> None:
     """pb_stream_copy of src into dst (same size in bytes, 16-byte multiple)."""
     nbytes = src.numel() * src.element_size()
     assert dst.numel() * dst.element_size() == nbytes
     _check(lib.pb_stream_copy(_ptr(src), _ptr(dst), nbytes, 1 if nontemporal else 0, _stream(stream)))
+
+
+def solve_noalloc_max_bytes() -> int:
+    return int(lib.pb_solve_noalloc_max_bytes())
 
 
 def autotune(sysm: System, precision="f32", iters_per_trial=20,

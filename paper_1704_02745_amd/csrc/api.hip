@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 
 namespace pb {
 
@@ -236,10 +237,14 @@ extern "C" size_t pb_solve_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, c
     return carve_solve(nullptr, make_layout(nx, ny, nz), opts->precision, opts->op).bytes;
 }
 
-extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, const double* eps_x,
-                              const double* eps_y, const double* eps_z, const double* kappa2, const double* rhs,
-                              double* x, const pb_solve_opts* opts, void* workspace, size_t workspace_bytes,
-                              void* stream_, pb_info* info) {
+namespace {
+
+// The whole of pb_solve on a given workspace. `untimed`: record no HIP events
+// (pb_info.kernel_seconds stays 0), so that nothing in the call allocates.
+pb_status solve_impl(int32_t nx, int32_t ny, int32_t nz, double h, const double* eps_x, const double* eps_y,
+                     const double* eps_z, const double* kappa2, const double* rhs, double* x,
+                     const pb_solve_opts* opts, void* workspace, size_t workspace_bytes, void* stream_,
+                     pb_info* info, bool untimed) {
     const auto t0 = std::chrono::steady_clock::now();
     if (info) std::memset(info, 0, sizeof(*info));
     PB_ARG(dims_ok(nx, ny, nz), "pb_solve: dims must be >= 1 (and below 2^36 nodes)");
@@ -272,6 +277,7 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
     if (e != PB_OK) return e;
 
     SolveResult r{};
+    r.untimed = untimed ? 1 : 0;
     int total_iters = 0, outer = 0, launches = 0, coded_launches = 0;
     double ksec = 0.0;
     double relres_recur = 0.0;
@@ -373,6 +379,62 @@ extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, cons
         info->reserved = 0;
     }
     return status;
+}
+
+// Scratch of pb_solve_noalloc: one copy per GPU, for the process lifetime.
+// Host code reaches it only through the per-device address that
+// hipGetSymbolAddress returns (the symbol itself is not a device address).
+constexpr size_t kNoAllocScratchBytes = (size_t)256 << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+pb_status scratch_for_current_device(void** out) {
+    int dev = 0;
+    PB_HIP(hipGetDevice(&dev));
+    PB_ARG(dev >= 0 && dev < kMaxDevices, "pb_solve_noalloc: device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        PB_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PB_OK;
+}
+
+}  // namespace
+
+extern "C" pb_status pb_solve(int32_t nx, int32_t ny, int32_t nz, double h, const double* eps_x,
+                              const double* eps_y, const double* eps_z, const double* kappa2, const double* rhs,
+                              double* x, const pb_solve_opts* opts, void* workspace, size_t workspace_bytes,
+                              void* stream_, pb_info* info) {
+    return solve_impl(nx, ny, nz, h, eps_x, eps_y, eps_z, kappa2, rhs, x, opts, workspace, workspace_bytes, stream_,
+                      info, false);
+}
+
+extern "C" size_t pb_solve_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+extern "C" pb_status pb_solve_noalloc(int32_t nx, int32_t ny, int32_t nz, double h, const double* eps_x,
+                                      const double* eps_y, const double* eps_z, const double* kappa2,
+                                      const double* rhs, double* x, const pb_solve_opts* opts, void* stream_,
+                                      pb_info* info) {
+    if (info) std::memset(info, 0, sizeof(*info));
+    PB_ARG(dims_ok(nx, ny, nz), "pb_solve_noalloc: dims must be >= 1 (and below 2^36 nodes)");
+    PB_ARG(opts_ok(opts), "pb_solve_noalloc: invalid options");
+    const size_t need = carve_solve(nullptr, make_layout(nx, ny, nz), opts->precision, opts->op).bytes;
+    if (need > kNoAllocScratchBytes) {
+        set_error("pb_solve_noalloc: this grid needs %zu bytes of scratch and the library holds %zu per GPU "
+                  "(about 2.2M nodes); use pb_solve with a workspace",
+                  need, kNoAllocScratchBytes);
+        return PB_ERR_NOMEM;
+    }
+    void* ws = nullptr;
+    const pb_status e = scratch_for_current_device(&ws);
+    if (e != PB_OK) return e;
+    return solve_impl(nx, ny, nz, h, eps_x, eps_y, eps_z, kappa2, rhs, x, opts, ws, kNoAllocScratchBytes, stream_,
+                      info, true);
 }
 
 extern "C" pb_status pb_autotune(int32_t nx, int32_t ny, int32_t nz, double h, const double* eps_x,

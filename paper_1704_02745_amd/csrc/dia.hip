@@ -98,9 +98,12 @@ pb_status dia_jpcg_impl(const Layout& L, const SolveBufs<T>& s, SyncState* S, do
     const Ranges R = ranges_for(npad);
     const unsigned g = stream_grid(npad);
     if (launch_fill<int>((int*)S, (int64_t)(sizeof(SyncState) / sizeof(int)), 0, st) != PB_OK) return PB_ERR_HIP;
-    hipEvent_t ev[2];
-    PB_HIP(hipEventCreate(&ev[0]));
-    PB_HIP(hipEventCreate(&ev[1]));
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    const bool timed = !(res && res->untimed);
+    if (timed) {
+        PB_HIP(hipEventCreate(&ev[0]));
+        PB_HIP(hipEventCreate(&ev[1]));
+    }
     hipLaunchKernelGGL(k_dia_build<T>, dim3(g), dim3(kBS), 0, st, s.op, L.nx, L.sp, npad, s.dia);
     // r = b - A x0 (x0 = 0 gives r = b exactly)
     hipLaunchKernelGGL(k_dia_spmv<T>, dim3(g), dim3(kBS), 0, st, s.dia, (const T*)s.x, L.nx, L.sp, npad, s.q,
@@ -109,7 +112,7 @@ pb_status dia_jpcg_impl(const Layout& L, const SolveBufs<T>& s, SyncState* S, do
                        npad, R.per, partials);
     hipLaunchKernelGGL(k_scalar_init, dim3(1), dim3(kBS), 0, st, S, (const double*)partials, R.nblk, tol, maxiter);
     PB_HIP(hipGetLastError());
-    PB_HIP(hipEventRecord(ev[0], st));
+    if (timed) PB_HIP(hipEventRecord(ev[0], st));
     int it = 0;
     SyncState h{};
     for (;;) {
@@ -133,15 +136,17 @@ pb_status dia_jpcg_impl(const Layout& L, const SolveBufs<T>& s, SyncState* S, do
         PB_HIP(hipStreamSynchronize(st));
         if (h.done || it >= maxiter) break;
     }
-    PB_HIP(hipEventRecord(ev[1], st));
+    if (timed) PB_HIP(hipEventRecord(ev[1], st));
     hipLaunchKernelGGL(k_zero_if_zero_rhs<T>, dim3(g), dim3(kBS), 0, st, s.x, npad, (const SyncState*)S);
     PB_HIP(hipGetLastError());
     PB_HIP(hipMemcpyAsync(&h, S, sizeof(SyncState), hipMemcpyDeviceToHost, st));
     PB_HIP(hipStreamSynchronize(st));
     float ms = 0.0f;
-    PB_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
+    if (timed) {
+        PB_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+    }
     if (res) {
         res->kernel_seconds = 1e-3 * ms;
         res->status = h.done ? h.status : (int)PB_NOT_CONVERGED;

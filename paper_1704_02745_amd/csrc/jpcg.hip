@@ -1935,7 +1935,8 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
         return PB_ERR_HIP;
     void* args[] = {&a};
     hipEvent_t ev[2] = {nullptr, nullptr};
-    if (res) {
+    const bool timed = res && !res->untimed;
+    if (timed) {
         PB_HIP(hipEventCreate(&ev[0]));
         PB_HIP(hipEventCreate(&ev[1]));
         PB_HIP(hipEventRecord(ev[0], st));
@@ -1950,13 +1951,15 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
     }
     if (res) {
         SyncState h;
-        PB_HIP(hipEventRecord(ev[1], st));
+        if (timed) PB_HIP(hipEventRecord(ev[1], st));
         PB_HIP(hipMemcpyAsync(&h, sync, sizeof(SyncState), hipMemcpyDeviceToHost, st));
         PB_HIP(hipStreamSynchronize(st));
         float ms = 0.0f;
-        PB_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-        (void)hipEventDestroy(ev[0]);
-        (void)hipEventDestroy(ev[1]);
+        if (timed) {
+            PB_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            (void)hipEventDestroy(ev[0]);
+            (void)hipEventDestroy(ev[1]);
+        }
         res->status = h.status;
         res->iters = h.iters;
         res->rr = h.rr;

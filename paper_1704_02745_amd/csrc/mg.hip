@@ -544,10 +544,13 @@ pb_status mg_pcg_impl(const Layout& L0, double h, const double* ex, const double
     const Ranges R = ranges_for(npad);
     const unsigned g = stream_grid(npad);
     if (launch_fill<int>((int*)S, (int64_t)(sizeof(SyncState) / sizeof(int)), 0, st) != PB_OK) return PB_ERR_HIP;
-    hipEvent_t ev[2];
-    PB_HIP(hipEventCreate(&ev[0]));
-    PB_HIP(hipEventCreate(&ev[1]));
-    PB_HIP(hipEventRecord(ev[0], st));
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    const bool timed = !(res && res->untimed);
+    if (timed) {
+        PB_HIP(hipEventCreate(&ev[0]));
+        PB_HIP(hipEventCreate(&ev[1]));
+    }
+    if (timed) PB_HIP(hipEventRecord(ev[0], st));
     // r = b - A x0, z = M r, p = z
     hipLaunchKernelGGL(k_mg_apply<T>, dim3(g), dim3(kBS), 0, st, s.op, (const T*)s.x, s.q, L0.nx, L0.sp, npad,
                        (const SyncState*)nullptr);
@@ -585,15 +588,17 @@ pb_status mg_pcg_impl(const Layout& L0, double h, const double* ex, const double
         PB_HIP(hipStreamSynchronize(st));
         if (hs.done || it >= maxiter) break;
     }
-    PB_HIP(hipEventRecord(ev[1], st));
+    if (timed) PB_HIP(hipEventRecord(ev[1], st));
     hipLaunchKernelGGL(k_zero_if_zero_rhs<T>, dim3(g), dim3(kBS), 0, st, s.x, npad, (const SyncState*)S);
     PB_HIP(hipGetLastError());
     PB_HIP(hipMemcpyAsync(&hs, S, sizeof(SyncState), hipMemcpyDeviceToHost, st));
     PB_HIP(hipStreamSynchronize(st));
     float ms = 0.0f;
-    PB_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
+    if (timed) {
+        PB_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+    }
     if (res) {
         res->kernel_seconds = 1e-3 * ms;
         res->status = hs.done ? hs.status : (int)PB_NOT_CONVERGED;

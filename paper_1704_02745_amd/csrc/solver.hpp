@@ -74,6 +74,7 @@ struct SolveResult {
     Tiling tiling;           // fused form: the tiling used
     int coded;               // fused form: 1 when the pass read coded coefficients
     const float* ctab;       // and the dictionary it used (device)
+    int untimed;             // input: 1 = record no HIP events (kernel_seconds stays 0)
 };
 
 // jpcg.hip: one persistent cooperative launch running the whole iteration.

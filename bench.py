@@ -478,8 +478,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched (config 3) and served (config 4) measurements")
     ap.add_argument("--tuning", default="",
-                    help="block,groups,zchunk,grid,scheme[,streaming]: use this tiling instead of autotuning "
-                         "(profiled runs; streaming 1/0 = nontemporal/cached, default the shape's own)")
+                    help="block,groups,zchunk,grid,scheme[,streaming[,segments]]: use this tiling instead of "
+                         "autotuning (profiled runs; streaming 1/0 = nontemporal/cached, default the shape's own; "
+                         "segments = in-plane segments, default any)")
     ap.add_argument("--coded", type=int, default=1, choices=(0, 1),
                     help="coded-coefficient 40-byte pass (1, the library default) or the uncoded pass (0)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -541,7 +542,8 @@ def main():
     # untimed: pick the fused kernel's tiling for this grid shape
     if args.tuning:
         tv = [int(v) for v in args.tuning.split(",")]
-        pbgpu.set_tuning(g.nx, g.ny, g.nz, "f32", *tv[:5], streaming=tv[5] if len(tv) > 5 else -1)
+        pbgpu.set_tuning(g.nx, g.ny, g.nz, "f32", *tv[:5], streaming=tv[5] if len(tv) > 5 else -1,
+                         segments=tv[6] if len(tv) > 6 else 0)
         tuning = dict(pbgpu.get_tuning(g.nx, g.ny, g.nz, "f32"), us_per_iter=None, candidates=0)
     else:
         sys0 = pbgpu.setup(g, xyz, rad, chg, prob.eps_in, prob.eps_out, prob.kappa_d2, device=dev)

@@ -270,6 +270,8 @@ typedef struct {
                                (the default once a pass's arrays exceed 1.75 times the 256 MiB
                                last-level cache); 0: cached accesses; -1 (pb_set_tuning only): the
                                shape's default */
+    int32_t segments;       /* in-plane segments per plane (tiles = segments x z-chunks); 0
+                               (pb_set_tuning only): any */
 } pb_tuning;
 
 /*

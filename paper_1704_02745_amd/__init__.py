@@ -86,7 +86,8 @@ class Info(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("groups", ctypes.c_int32), ("zchunk", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("us_per_iter", ctypes.c_double),
-                ("candidates", ctypes.c_int32), ("scheme", ctypes.c_int32), ("streaming", ctypes.c_int32)]
+                ("candidates", ctypes.c_int32), ("scheme", ctypes.c_int32), ("streaming", ctypes.c_int32),
+                ("segments", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -387,13 +388,14 @@ def autotune(sysm: System, precision="f32", iters_per_trial=20,
     return t.as_dict()
 
 
-def set_tuning(nx, ny, nz, precision, block, groups, zchunk, grid, scheme=0, streaming=-1) -> None:
+def set_tuning(nx, ny, nz, precision, block, groups, zchunk, grid, scheme=0, streaming=-1, segments=0) -> None:
     """Record a tiling of the fused kernel for this grid shape and precision;
     scheme 0 is the pass that stores A.p, 1 the 40-byte pass that recomputes it;
-    streaming 1 / 0 selects nontemporal / cached accesses, -1 the shape's default."""
+    streaming 1 / 0 selects nontemporal / cached accesses, -1 the shape's default;
+    segments > 0 picks the tiling with that many in-plane segments."""
     t = Tuning()
     t.block, t.groups, t.zchunk, t.grid = int(block), int(groups), int(zchunk), int(grid)
-    t.scheme, t.streaming = int(scheme), int(streaming)
+    t.scheme, t.streaming, t.segments = int(scheme), int(streaming), int(segments)
     _check(lib.pb_set_tuning(int(nx), int(ny), int(nz), PRECISIONS[precision], ctypes.byref(t)))
 
 

@@ -216,6 +216,7 @@ pb_status autotune_impl(const Layout& L, const SolveBufs<T>& s, const SolveWs& w
         best->streaming = best_t.nt;
         best->zchunk = best_t.zchunk;
         best->grid = best_t.grid;
+        best->segments = best_t.nseg;
         best->us_per_iter = best_us;
         best->candidates = (int)cand.size();
     }
@@ -486,6 +487,7 @@ extern "C" pb_status pb_get_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t p
     t.grid = c.grid;
     t.scheme = c.scheme;
     t.streaming = c.nt;
+    t.segments = c.nseg;
     *out = t;
     return PB_OK;
 }
@@ -509,6 +511,7 @@ extern "C" pb_status pb_tiling_candidates(int32_t nx, int32_t ny, int32_t nz, in
         t.candidates = (int32_t)c.size();
         t.scheme = c[i].scheme;
         t.streaming = c[i].nt;
+        t.segments = c[i].nseg;
         out[i] = t;
     }
     return PB_OK;
@@ -524,7 +527,7 @@ extern "C" pb_status pb_set_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t p
         const int nt = t->streaming >= 0 ? t->streaming : streaming_for<T>(L);
         for (const Tiling& c : tiling_candidates<T>(L)) {
             if (c.bs == t->block && c.mc == t->groups && c.scheme == t->scheme && c.nt == nt &&
-                c.zchunk == t->zchunk && c.grid == t->grid) {
+                c.zchunk == t->zchunk && c.grid == t->grid && (t->segments <= 0 || c.nseg == t->segments)) {
                 record_tiling<T>(L, c);
                 return PB_OK;
             }

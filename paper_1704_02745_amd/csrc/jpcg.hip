@@ -1703,9 +1703,11 @@ int halo_for(int nx) {
 
 // Tiling for one kernel variant: z-chunks chosen so that the tile count
 // fits the co-resident workgroups (each workgroup owns at most one tile, so
-// a pass takes the time of one tile). Returns grid = 0 when infeasible.
+// a pass takes the time of one tile). `extra_seg` splits each plane into
+// that many more segments than the fewest the block covers (shorter tiles
+// that can fill more of the device). Returns grid = 0 when infeasible.
 template <typename T>
-Tiling tiling_for(const Layout& L, const Variant& v, int cus, int max_per_cu) {
+Tiling tiling_for(const Layout& L, const Variant& v, int cus, int max_per_cu, int extra_seg = 0) {
     constexpr int W = Vec<T>::n;
     Tiling t{};
     t.mc = v.mc;
@@ -1714,6 +1716,16 @@ Tiling tiling_for(const Layout& L, const Variant& v, int cus, int max_per_cu) {
     t.per = v.per;
     t.nt = v.nt;
     t.seglen = balanced_seglen<T>(L, v.mc * v.bs * W);
+    if (extra_seg > 0) {
+        // an even split into nseg0 + extra_seg segments, each rounded up to
+        // 64 bytes so that every segment starts aligned
+        constexpr int A = 64 / (int)sizeof(T);
+        const int64_t nseg0 = (L.sp + t.seglen - 1) / t.seglen;
+        const int64_t even = (L.sp + nseg0 + extra_seg - 1) / (nseg0 + extra_seg);
+        const int seglen = (int)((even + A - 1) / A * A);
+        if ((L.sp + seglen - 1) / seglen <= nseg0) return t;   // no more segments than without
+        t.seglen = seglen;
+    }
     t.halo = halo_for<T>(L.nx);
     if (2 * t.halo / W > v.bs) return t;   // halo groups must fit one per thread
     const size_t lds = lds_bytes<T>(t.scheme, t.seglen, t.halo);
@@ -1749,19 +1761,23 @@ int streaming_default(const Layout& L) {
     return (double)L.sp * L.nz * sizeof(T) * 12.0 > kStreamingFactor * kLastLevelCacheBytes ? 1 : 0;
 }
 
+constexpr int kMaxExtraSegments = 8;
+
 template <typename T>
 Tiling choose_tiling_impl(const Layout& L, int want_bs, int want_mc, int max_per_cu, int want_scheme = -1,
-                          int want_per = 0, int want_nt = -1) {
+                          int want_per = 0, int want_nt = -1, int want_extra = -1) {
     const DevInfo di = dev_info();
     const int cus = di.cus > 0 ? di.cus : 256;
     if (want_nt < 0) want_nt = streaming_default<T>(L);
     Tiling best{};
     double best_cost = 1e300;
-    for (const auto& v : variants<T>()) {
+    for (const auto& v : variants<T>())
+    for (int extra = 0; extra <= kMaxExtraSegments; ++extra) {
+        if (want_extra >= 0 && extra != want_extra) continue;
         if ((want_bs > 0 && v.bs != want_bs) || (want_mc > 0 && v.mc != want_mc)) continue;
         if (want_scheme >= 0 && v.scheme != want_scheme) continue;
         if (v.per != want_per || v.nt != want_nt || v.cd) continue;
-        Tiling t = tiling_for<T>(L, v, cus, max_per_cu);
+        Tiling t = tiling_for<T>(L, v, cus, max_per_cu, extra);
         if (t.grid <= 0) continue;
         // model: bytes of one tile (planes incl. the extra ones below, segment
         // incl. halo work) times the tiles that share a CU, plus a
@@ -1817,15 +1833,16 @@ std::vector<Tiling> tiling_candidates(const Layout& L) {
     std::vector<Tiling> out;
     for (const auto& v : variants<T>()) {
         if (v.per || v.cd) continue;   // periodic solves use their own default tiling; coding is per solve
-        for (int cap : {1, 2, 3, 4, 0}) {
-            const Tiling t = choose_tiling_impl<T>(L, v.bs, v.mc, cap, v.scheme, 0, v.nt);
-            if (t.grid <= 0) continue;
-            bool dup = false;
-            for (const auto& u : out)
-                dup = dup || (u.bs == t.bs && u.mc == t.mc && u.scheme == t.scheme && u.nt == t.nt &&
-                              u.grid == t.grid && u.zchunk == t.zchunk);
-            if (!dup) out.push_back(t);
-        }
+        for (int cap : {1, 2, 3, 4, 0})
+            for (int extra = 0; extra <= kMaxExtraSegments; ++extra) {
+                const Tiling t = choose_tiling_impl<T>(L, v.bs, v.mc, cap, v.scheme, 0, v.nt, extra);
+                if (t.grid <= 0) continue;
+                bool dup = false;
+                for (const auto& u : out)
+                    dup = dup || (u.bs == t.bs && u.mc == t.mc && u.scheme == t.scheme && u.nt == t.nt &&
+                                  u.grid == t.grid && u.zchunk == t.zchunk && u.nseg == t.nseg);
+                if (!dup) out.push_back(t);
+            }
     }
     return out;
 }

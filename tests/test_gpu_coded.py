@@ -44,7 +44,8 @@ def forty_byte_tilings(pb, dims, prec="f32"):
 
 
 def pin(pb, dims, prec, c):
-    pb.set_tuning(*dims, prec, c["block"], c["groups"], c["zchunk"], c["grid"], c["scheme"], c["streaming"])
+    pb.set_tuning(*dims, prec, c["block"], c["groups"], c["zchunk"], c["grid"], c["scheme"], c["streaming"],
+                  c["segments"])
 
 
 def coded_and_uncoded(pb, sysm, **kw):

@@ -56,7 +56,7 @@ def test_widest_fused_rows(pb, prec, fmax, bmax):
     assert cands
     for c in cands:
         pb.set_tuning(fmax, NY, NZ, prec, c["block"], c["groups"], c["zchunk"], c["grid"], c["scheme"],
-                      c["streaming"])
+                      c["streaming"], c["segments"])
         x, info = pb.solve(sysm, tol=tol, precision=prec, maxiter=5000)
         assert info["status"] == pb.PB_OK, c
         assert np.abs(x.cpu().numpy() - o.x).max() <= bound * np.abs(o.x).max(), c

@@ -321,7 +321,7 @@ def test_autotune_then_solve(pb, ragged):
         assert np.abs(x.cpu().numpy() - exact).max() <= 1e-5 * np.abs(exact).max()
         nx, ny, nz = sysm.dims
         pb.set_tuning(nx, ny, nz, prec, best["block"], best["groups"], best["zchunk"], best["grid"], best["scheme"],
-                      best["streaming"])
+                      best["streaming"], best["segments"])
     with pytest.raises(pb.PBError):
         pb.set_tuning(61, 53, 47, "f32", 256, 1, 1, 3)   # infeasible grid size
 
@@ -344,7 +344,7 @@ def test_every_tiling_and_pass_form(pb, ragged, prec):
     try:
         for c in cands:
             pb.set_tuning(nx, ny, nz, prec, c["block"], c["groups"], c["zchunk"], c["grid"], c["scheme"],
-                          c["streaming"])
+                          c["streaming"], c["segments"])
             print(f"tiling {prec} {c}", flush=True)
             x, info = pb.solve(sysm, tol=1e-6, precision=prec)
             assert info["status"] == pb.PB_OK
@@ -352,7 +352,7 @@ def test_every_tiling_and_pass_form(pb, ragged, prec):
             xv = x.cpu().numpy()
             assert np.abs(xv - exact).max() <= 1e-5 * np.abs(exact).max(), c
             xs.setdefault(c["scheme"], []).append(xv)
-            shape = (c["block"], c["groups"], c["zchunk"], c["grid"], c["scheme"])
+            shape = (c["block"], c["groups"], c["zchunk"], c["grid"], c["scheme"], c["segments"])
             if shape in by_shape:
                 assert np.array_equal(by_shape[shape], xv), c
             by_shape[shape] = xv

@@ -395,18 +395,27 @@ def bench_batched(pbgpu, torch, synth, dev, nsnap=256, seq_sample=24):
             "plain_fused_sample": n_seq}
 
 
-def bench_serving(pbgpu, torch, synth, dev, nreq=2200, warm=200, rate=200.0, pool=48, chunk=32,
-                  arena_gb=48, seq_sample=48):
-    """Config 4: a seeded Poisson trace of PB solve requests (atom counts
+def bench_serving(pbgpu, torch, synth, dev, nreq=2200, warm=200, rate=200.0, chunk=32, arena_gb=64,
+                  seq_sample=48):
+    """Config 4: a seeded Poisson trace of PB requests (atom counts
     log-uniform 500-30,000, grids 49^3-193^3, tol 1e-4/1e-6/1e-8) served by
-    the continuous-batching server. Requests are pre-assembled systems drawn
-    from a pool of distinct molecules (setup is not part of the served
-    latency). Latency = completion - arrival."""
+    the continuous-batching server. Every request is its own molecule (one of
+    64 config-4 chains with its atoms moved by seeded 0.3 A noise) handed over
+    as atoms, radii and charges: the server runs the setup at admission and
+    the energy at completion, so latency = completion - arrival covers setup,
+    solve and energy. Atom arrays are resident on the device before the trace."""
     import numpy as np
-    reqs = [synth.config4_request(i) for i in range(pool)]
-    systems = [pbgpu.setup(p.grid, p.mol.xyz, p.mol.radius, p.mol.charge, p.eps_in, p.eps_out, p.kappa_d2,
-                           device=dev) for p in reqs]
+    reqs = [synth.config4_molecule(i) for i in range(nreq)]
+    dev_atoms = [tuple(torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
+                       for a in (p.mol.xyz.reshape(-1), p.mol.radius, p.mol.charge)) for p in reqs]
+    outs = {}
     torch.cuda.synchronize()
+
+    def out_for(p):
+        key = (p.grid.nx, p.grid.ny, p.grid.nz)
+        if key not in outs:
+            outs[key] = torch.empty((p.grid.nz, p.grid.ny, p.grid.nx), dtype=torch.float64, device=dev)
+        return outs[key]
 
     def run(nr, rate_, seed):
         arrivals = synth.config4_arrivals(nr, rate=rate_, seed=seed)
@@ -417,8 +426,13 @@ def bench_serving(pbgpu, torch, synth, dev, nreq=2200, warm=200, rate=200.0, poo
         while len(done_at) < nr:
             now = time.perf_counter() - t0
             while k < nr and arrivals[k] <= now:
-                p = reqs[k % pool]
-                rid = srv.submit(systems[k % pool], tol=p.tol, precision=p.precision)
+                p = reqs[k]
+                xyz, rad, q = dev_atoms[k]
+                # each request writes its own potential tensor (recycled per grid shape once reported)
+                rid = srv.submit_atoms(p.grid, xyz, rad, q, p.eps_in, p.eps_out, p.kappa_d2, tol=p.tol,
+                                       precision=p.precision,
+                                       out=torch.empty((p.grid.nz, p.grid.ny, p.grid.nx), dtype=torch.float64,
+                                                       device=dev))
                 submitted[rid] = k
                 k += 1
             st = srv.stats()
@@ -427,41 +441,47 @@ def bench_serving(pbgpu, torch, synth, dev, nreq=2200, warm=200, rate=200.0, poo
                     time.sleep(max(0.0, min(arrivals[k] - (time.perf_counter() - t0), 0.01)))
                 continue
             for rid, info in srv.step(chunk=chunk):
-                done_at[submitted[rid]] = (time.perf_counter() - t0, info)
+                done_at[submitted[rid]] = (time.perf_counter() - t0, info, srv.energies.pop(rid, None))
         span = time.perf_counter() - t0
         stats = srv.stats()
         srv.close()
-        lat = np.array([done_at[i][0] - arrivals[i] for i in range(warm if nr > warm else 0, nr)])
-        fin = np.array([done_at[i][0] for i in range(warm if nr > warm else 0, nr)])
+        w0 = warm if nr > warm else 0
+        lat = np.array([done_at[i][0] - arrivals[i] for i in range(w0, nr)])
+        fin = np.array([done_at[i][0] for i in range(w0, nr)])
         okc = sum(1 for i in range(nr) if done_at[i][1]["status"] == 0)
-        thr = len(lat) / max(fin.max() - min(arrivals[warm if nr > warm else 0], fin.min()), 1e-9)
-        return {"requests": nr, "offered_per_s": rate_, "solves_per_s": round(thr, 2),
+        thr = len(lat) / max(fin.max() - min(arrivals[w0], fin.min()), 1e-9)
+        return {"requests": nr, "offered_per_s": rate_, "solves_per_s": round(float(thr), 2),
                 "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
                 "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
                 "converged": okc, "span_s": round(span, 3), "launches": stats["launches"],
-                "device_s": round(stats["device_seconds"], 3)}
+                "device_s": round(stats["device_seconds"], 3),
+                "energies_returned": sum(1 for i in range(nr) if done_at[i][2] is not None)}
 
     full = run(nreq, rate, 4999)
     light_rate = round(0.7 * full["solves_per_s"], 1)
     light = run(max(400, nreq // 4), light_rate, 5999)
-    # plain fused solves of the same requests, one at a time
+    # the same requests one at a time: setup + fused solve + energy
     lat_seq = []
     for i in range(seq_sample):
-        p = reqs[i % pool]
+        p = reqs[i]
+        xyz, rad, q = dev_atoms[i]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        pbgpu.solve(systems[i % pool], tol=p.tol, precision=p.precision)
+        sysm = pbgpu.setup(p.grid, xyz, rad, q, p.eps_in, p.eps_out, p.kappa_d2, device=dev)
+        x, _ = pbgpu.solve(sysm, tol=p.tol, precision=p.precision, out=out_for(p))
+        pbgpu.energy(p.grid, xyz, q, x)
         torch.cuda.synchronize()
         lat_seq.append(time.perf_counter() - t0)
     lat_seq = np.array(lat_seq)
-    del systems
+    del dev_atoms, outs
     torch.cuda.empty_cache()
     return {"trace": full, "at_0.7x_capacity": light,
-            "plain_fused_sequential": {"solves_per_s": round(len(lat_seq) / lat_seq.sum(), 2),
+            "plain_fused_sequential": {"solves_per_s": round(float(len(lat_seq) / lat_seq.sum()), 2),
                                        "p50_ms": round(1e3 * float(np.percentile(lat_seq, 50)), 2),
                                        "p99_ms": round(1e3 * float(np.percentile(lat_seq, 99)), 2),
                                        "sample": len(lat_seq)},
-            "pool": pool, "chunk": chunk}
+            "requests_from": "molecules: setup at admission and energy at completion inside each request",
+            "chunk": chunk}
 
 
 # Forms reported beside the main line (also runnable alone with --forms-only).

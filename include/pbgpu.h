@@ -464,6 +464,24 @@ pb_status pb_server_create(void* arena, size_t arena_bytes, int32_t max_slots, p
 /* Queue a request; *id receives its handle. PB_ERR_ARG if it can never fit. */
 pb_status pb_server_submit(pb_server* server, const pb_problem* request, int32_t precision, int64_t* id);
 /*
+ * Queue a request given as a molecule, as the paper's user supplies it
+ * (section 2.7: atom centres, radii and charges on a grid): at admission the
+ * server runs the setup of pb_setup (two-point edge dielectrics, free-space
+ * Debye-Hueckel boundary) inside the request's own arena memory, then solves
+ * as for pb_server_submit; when the request finishes, x[N] (device, FP64,
+ * layout as pb_solve's) holds the potential and *energy (host, nullable)
+ * receives 1/2 sum_a q_a phi(c_a) in kcal/mol, both valid once pb_server_step
+ * reports the request. xyz[3*natoms], radius[natoms], charge[natoms] are
+ * device arrays that must stay valid until then. An atom outside the node
+ * box finishes the request with PB_ERR_ARG. Arena bytes per request:
+ * pb_server_request_bytes_atoms.
+ */
+pb_status pb_server_submit_atoms(pb_server* server, const pb_grid* grid, int64_t natoms, const double* xyz,
+                                 const double* radius, const double* charge, double eps_in, double eps_out,
+                                 double kappa_d2, double tol, int32_t maxiter, int32_t precision, double* x,
+                                 double* energy, int64_t* id);
+size_t pb_server_request_bytes_atoms(const pb_grid* grid, int64_t natoms);
+/*
  * One admission + chunk + retirement round on `stream` (synchronises it).
  * Up to max_done finished requests are reported in done_ids/done_infos
  * (pb_info.seconds = submit-to-completion time); *n_done receives the count.

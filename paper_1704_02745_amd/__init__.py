@@ -37,7 +37,7 @@ EXPORTS = ("pb_version", "pb_last_error", "pb_setup_workspace_bytes", "pb_setup"
            "pb_batch_autotune_workspace_bytes", "pb_batch_autotune", "pb_batch_graph_create", "pb_batch_graph_launch",
            "pb_batch_graph_results", "pb_batch_graph_is_cooperative", "pb_batch_graph_destroy",
            "pb_server_request_bytes", "pb_server_create", "pb_server_submit", "pb_server_step",
-           "pb_server_stats", "pb_server_destroy",
+           "pb_server_stats", "pb_server_destroy", "pb_server_submit_atoms", "pb_server_request_bytes_atoms",
            "pb_energy_workspace_bytes", "pb_energy",
            "pb_solvation_workspace_bytes", "pb_solvation_energy",
            "pb_setup_ex_workspace_bytes", "pb_setup_ex", "pb_solve_noalloc", "pb_solve_noalloc_max_bytes",
@@ -178,6 +178,11 @@ def _load():
     lib.pb_server_create.argtypes = [vp, sz, i32, ctypes.POINTER(vp)]
     lib.pb_server_submit.restype = ctypes.c_int
     lib.pb_server_submit.argtypes = [vp, P, i32, ctypes.POINTER(i64)]
+    lib.pb_server_submit_atoms.restype = ctypes.c_int
+    lib.pb_server_submit_atoms.argtypes = [vp, G, i64, vp, vp, vp, dbl, dbl, dbl, dbl, i32, i32, vp,
+                                           ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    lib.pb_server_request_bytes_atoms.restype = sz
+    lib.pb_server_request_bytes_atoms.argtypes = [G, i64]
     lib.pb_server_step.restype = ctypes.c_int
     lib.pb_server_step.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(Info)]
     lib.pb_server_stats.restype = ctypes.c_int
@@ -579,6 +584,7 @@ class Server:
         self._h = h
         self._live = {}        # id -> (system, out, problem struct): keeps request memory alive
         self.outputs = {}      # id -> potential tensor of finished requests
+        self.energies = {}     # id -> energy (kcal/mol) of finished molecule requests
 
     @staticmethod
     def request_bytes(sysm: System) -> int:
@@ -593,6 +599,32 @@ class Server:
         self._live[rid.value] = (sysm, outs[0], arr)
         return rid.value
 
+    @staticmethod
+    def request_bytes_atoms(grid, natoms: int) -> int:
+        g = as_grid(grid)
+        return int(lib.pb_server_request_bytes_atoms(ctypes.byref(g), int(natoms)))
+
+    def submit_atoms(self, grid, xyz, radius, charge, eps_in=1.0, eps_out=80.0, kappa_d2=0.0, tol=1e-6,
+                     precision="f32", maxiter=0, out=None) -> int:
+        """Queue a molecule (atoms, radii, charges on `grid`): the server runs
+        the setup at admission and the energy at completion. On completion
+        outputs[id] is the potential and energies[id] the energy (kcal/mol)."""
+        g = as_grid(grid, "free")
+        dev = self.arena.device
+        xyz_t = _dev64(xyz, dev).reshape(-1)
+        rad_t = _dev64(radius, dev)
+        q_t = _dev64(charge, dev)
+        if out is None:
+            out = torch.empty((g.nz, g.ny, g.nx), dtype=torch.float64, device=dev)
+        e = ctypes.c_double(float("nan"))
+        rid = ctypes.c_int64()
+        _check(lib.pb_server_submit_atoms(self._h, ctypes.byref(g), rad_t.numel(), _ptr(xyz_t), _ptr(rad_t),
+                                          _ptr(q_t), float(eps_in), float(eps_out), float(kappa_d2), float(tol),
+                                          int(maxiter), PRECISIONS[precision], _ptr(out), ctypes.byref(e),
+                                          ctypes.byref(rid)))
+        self._live[rid.value] = ((g, xyz_t, rad_t, q_t), out, e)
+        return rid.value
+
     def step(self, chunk=32, stream=None, max_done=256):
         n = ctypes.c_int32()
         ids = (ctypes.c_int64 * max_done)()
@@ -601,9 +633,11 @@ class Server:
         done = []
         for k in range(n.value):
             rid = ids[k]
-            sysm, out, _ = self._live.pop(rid)
+            _, out, extra = self._live.pop(rid)
             if self.keep_outputs:
                 self.outputs[rid] = out
+            if isinstance(extra, ctypes.c_double):
+                self.energies[rid] = extra.value
             done.append((rid, infos[k].as_dict()))
         return done
 

@@ -13,6 +13,14 @@
 // PB_F32 requests run FP32 JPCG to their tolerance. PB_F32_REFINE64 requests
 // cycle: FP64 residual -> FP32 JPCG correction to a relative 1e-4 -> FP64
 // update, until the FP64 residual is below their tolerance.
+//
+// A request is either an assembled system (pb_server_submit) or a molecule
+// (pb_server_submit_atoms: atoms, radii, charges and a grid, as the paper's
+// user supplies them): then the setup runs at admission inside the
+// request's arena memory and the energy 1/2 sum q phi when it finishes.
+//
+// Every slot's host-visible results (flags, residual sums, energy sum) sit
+// in one device array of records, read back with one copy per step phase.
 #include "solver.hpp"
 
 #include <algorithm>
@@ -33,7 +41,10 @@ struct SlotRec {   // per-slot results written by kernels and read by the host
     int flags;
     int fit;       // 1: the FP32 operator fits the coded-coefficient dictionary
     double rr, bb;
-    double pad2[5];
+    double esum;   // molecule requests: sum_a q_a phi(c_a)
+    int setup_flags;   // molecule requests: nonzero when an atom lies outside the node box
+    int energy_flags;
+    double pad2[3];
 };
 
 struct Slot {
@@ -60,6 +71,19 @@ struct Slot {
     int status = PB_OK;
     double relres = 0.0, relres_true = 0.0;
     double t_submit = 0.0;
+    int rec_idx = -1;                // index of this slot's record while admitted
+    // molecule requests (pb_server_submit_atoms)
+    bool from_atoms = false;
+    pb_grid grid{};
+    int64_t natoms = 0;
+    const double* xyz = nullptr;
+    const double* radius = nullptr;
+    const double* charge = nullptr;
+    double eps_in = 1.0, eps_out = 80.0, kappa_d2 = 0.0;
+    double* energy_host = nullptr;
+    SetupWs sw{};
+    double* qphi = nullptr;
+    bool energy_enqueued = false;
 };
 
 // Carve one slot's device memory at `base` (null to size it).
@@ -72,7 +96,6 @@ size_t carve_slot(char* base, Slot& s) {
     };
     const size_t n8 = sizeof(double) * (size_t)s.L.npad, n4 = sizeof(float) * (size_t)s.L.npad;
     s.S = (SyncState*)take(sizeof(SyncState));
-    s.rec = (SlotRec*)take(sizeof(SlotRec));
     s.partials = (double*)take(2 * sizeof(double) * kMaxPartials * (size_t)s.t.ntiles);
     s.resp = (double*)take(sizeof(double) * 2 * (size_t)residual_blocks(s.L));
     s.op64.cx = (double*)take(n8);
@@ -93,6 +116,18 @@ size_t carve_slot(char* base, Slot& s) {
     s.s.q2 = (float*)take(n4);
     s.s.p0 = (float*)take(n4);
     s.s.p1 = (float*)take(n4);
+    if (s.from_atoms) {   // the system the setup writes, its workspace and the energy's
+        const int nx = s.L.nx, ny = s.L.ny, nz = s.L.nz;
+        const size_t N = (size_t)nx * ny * nz;
+        s.req.eps_x = (const double*)take(sizeof(double) * (size_t)(nx + 1) * ny * nz);
+        s.req.eps_y = (const double*)take(sizeof(double) * (size_t)nx * (ny + 1) * nz);
+        s.req.eps_z = (const double*)take(sizeof(double) * (size_t)nx * ny * (nz + 1));
+        s.req.kappa2 = (const double*)take(sizeof(double) * N);
+        s.req.rhs = (const double*)take(sizeof(double) * N);
+        char* ws = take(carve_setup(nullptr, nx, ny, nz, s.natoms).bytes);
+        if (base) s.sw = carve_setup(ws, nx, ny, nz, s.natoms);
+        s.qphi = (double*)take(energy_scratch_bytes(s.natoms));
+    }
     return off;
 }
 
@@ -109,7 +144,8 @@ struct Server {
     char* table = nullptr;        // device: kernel-argument records for max_slots
     int* first = nullptr;         // device: workgroup offsets
     StateDigest* digests = nullptr;   // device: each running request's scalars after a launch
-    size_t reserved = 0;          // arena bytes used by the table
+    SlotRec* recs = nullptr;      // device: one record per admitted slot (max_slots)
+    size_t reserved = 0;          // arena bytes used by the table, offsets, digests and records
     std::vector<std::pair<size_t, size_t>> free_list;   // (offset, bytes), sorted by offset
     std::deque<std::unique_ptr<Slot>> pending;
     std::vector<std::unique_ptr<Slot>> active;
@@ -121,6 +157,15 @@ struct Server {
     std::vector<char> host_table;
     std::vector<int> host_first;
     std::vector<StateDigest> host_digests;
+    std::vector<SlotRec> host_recs;
+    std::vector<int> free_recs;   // unused record indices
+
+    // one copy of every record, on the stream (the caller synchronises)
+    pb_status read_recs(hipStream_t st) {
+        PB_HIP(hipMemcpyAsync(host_recs.data(), recs, sizeof(SlotRec) * host_recs.size(), hipMemcpyDeviceToHost,
+                              st));
+        return PB_OK;
+    }
 
     bool alloc(size_t bytes, size_t& off) {
         for (size_t i = 0; i < free_list.size(); ++i) {
@@ -201,12 +246,16 @@ extern "C" pb_status pb_server_create(void* arena, size_t arena_bytes, int32_t m
     const size_t tb = align_up(batch_kargs_bytes<float>() * (size_t)max_slots, 256);
     const size_t fb = align_up(sizeof(int) * (size_t)(max_slots + 1), 256);
     const size_t db = align_up(sizeof(StateDigest) * (size_t)max_slots, 256);
-    PB_ARG(arena_bytes > tb + fb + db, "pb_server_create: arena too small");
+    const size_t rb = align_up(sizeof(SlotRec) * (size_t)max_slots, 256);
+    PB_ARG(arena_bytes > tb + fb + db + rb, "pb_server_create: arena too small");
     S->table = S->arena;
     S->first = (int*)(S->arena + tb);
     S->digests = (StateDigest*)(S->arena + tb + fb);
-    S->reserved = tb + fb + db;
+    S->recs = (SlotRec*)(S->arena + tb + fb + db);
+    S->reserved = tb + fb + db + rb;
     S->host_digests.resize(max_slots);
+    S->host_recs.resize(max_slots);
+    for (int i = max_slots - 1; i >= 0; --i) S->free_recs.push_back(i);
     S->free_list.push_back({S->reserved, arena_bytes - S->reserved});
     S->host_table.resize(batch_kargs_bytes<float>() * (size_t)max_slots);
     S->host_first.resize(max_slots + 1);
@@ -232,6 +281,67 @@ extern "C" pb_status pb_server_submit(pb_server* S, const pb_problem* req, int32
     s->bytes = carve_slot(nullptr, *s);
     PB_ARG(s->bytes <= S->arena_bytes - S->reserved, "pb_server_submit: request larger than the whole arena");
     s->maxiter = req->maxiter > 0 ? req->maxiter : 10 * std::max(req->nx, std::max(req->ny, req->nz));
+    s->id = S->next_id++;
+    s->t_submit = now_s();
+    *id = s->id;
+    S->pending.push_back(std::move(s));
+    return PB_OK;
+}
+
+extern "C" size_t pb_server_request_bytes_atoms(const pb_grid* grid, int64_t natoms) {
+    if (!grid || grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || natoms < 0) return 0;
+    Slot s;
+    s.from_atoms = true;
+    s.natoms = natoms;
+    s.L = make_layout(grid->nx, grid->ny, grid->nz);
+    s.t = batch_tiling<float>(s.L);
+    if (s.t.ntiles <= 0) return 0;
+    return carve_slot(nullptr, s);
+}
+
+extern "C" pb_status pb_server_submit_atoms(pb_server* S, const pb_grid* grid, int64_t natoms, const double* xyz,
+                                            const double* radius, const double* charge, double eps_in,
+                                            double eps_out, double kappa_d2, double tol, int32_t maxiter,
+                                            int32_t precision, double* x, double* energy, int64_t* id) {
+    PB_ARG(S && grid && id && x, "pb_server_submit_atoms: null argument");
+    PB_ARG(precision == PB_F32 || precision == PB_F32_REFINE64,
+           "pb_server_submit_atoms: precision PB_F32 or PB_F32_REFINE64");
+    PB_ARG(grid->boundary == PB_BOUNDARY_FREE && grid->nx >= 2 && grid->ny >= 2 && grid->nz >= 2 &&
+               std::isfinite(grid->h) && grid->h > 0 && std::isfinite(grid->origin[0]) &&
+               std::isfinite(grid->origin[1]) && std::isfinite(grid->origin[2]),
+           "pb_server_submit_atoms: the grid needs the free-space boundary, nx,ny,nz >= 2, finite h > 0 and a "
+           "finite origin");
+    PB_ARG(natoms >= 0 && natoms < (1 << 21) && (natoms == 0 || (xyz && radius && charge)),
+           "pb_server_submit_atoms: natoms in [0, 2^21) with non-null atom arrays");
+    PB_ARG(std::isfinite(eps_in) && std::isfinite(eps_out) && eps_in > 0 && eps_out > 0 && std::isfinite(kappa_d2) &&
+               kappa_d2 >= 0,
+           "pb_server_submit_atoms: dielectrics finite and > 0, kappa_d2 finite and >= 0");
+    PB_ARG(std::isfinite(tol) && tol > 0, "pb_server_submit_atoms: tol must be finite and > 0");
+    std::unique_ptr<Slot> s(new Slot());
+    s->from_atoms = true;
+    s->grid = *grid;
+    s->natoms = natoms;
+    s->xyz = xyz;
+    s->radius = radius;
+    s->charge = charge;
+    s->eps_in = eps_in;
+    s->eps_out = eps_out;
+    s->kappa_d2 = kappa_d2;
+    s->energy_host = energy;
+    s->req.nx = grid->nx;
+    s->req.ny = grid->ny;
+    s->req.nz = grid->nz;
+    s->req.h = grid->h;
+    s->req.tol = tol;
+    s->req.maxiter = maxiter;
+    s->req.x = x;
+    s->precision = precision;
+    s->L = make_layout(grid->nx, grid->ny, grid->nz);
+    s->t = batch_tiling<float>(s->L);
+    PB_ARG(s->t.ntiles > 0, "pb_server_submit_atoms: grid too wide for the batch kernel (nx <= 512)");
+    s->bytes = carve_slot(nullptr, *s);
+    PB_ARG(s->bytes <= S->arena_bytes - S->reserved, "pb_server_submit_atoms: request larger than the whole arena");
+    s->maxiter = maxiter > 0 ? maxiter : 10 * std::max(grid->nx, std::max(grid->ny, grid->nz));
     s->id = S->next_id++;
     s->t_submit = now_s();
     *id = s->id;
@@ -267,8 +377,18 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
         if (!S->alloc(s.bytes, off)) break;
         s.off = off;
         carve_slot(S->arena + off, s);
+        s.rec_idx = S->free_recs.back();
+        S->free_recs.pop_back();
+        s.rec = S->recs + s.rec_idx;
         e = launch_fill<int>((int*)s.rec, (int64_t)(sizeof(SlotRec) / sizeof(int)), 0, st);
         if (e != PB_OK) return e;
+        if (s.from_atoms) {
+            e = setup_enqueue(&s.grid, s.natoms, s.xyz, s.radius, s.charge, s.eps_in, s.eps_out, s.kappa_d2, false,
+                              (double*)s.req.eps_x, (double*)s.req.eps_y, (double*)s.req.eps_z,
+                              (double*)s.req.kappa2, (double*)s.req.rhs, nullptr, nullptr, s.sw, st);
+            if (e != PB_OK) return e;
+            PB_HIP(hipMemcpyAsync(&s.rec->setup_flags, s.sw.flags, sizeof(int), hipMemcpyDeviceToDevice, st));
+        }
         e = launch_prepare64(s.req.eps_x, s.req.eps_y, s.req.eps_z, s.req.kappa2, s.req.rhs, s.req.x,
                              s.req.warm_start ? 1 : 0, 0, s.L, s.req.h, s.op64, s.b64, s.x64, &s.rec->flags, st);
         if (e != PB_OK) return e;
@@ -297,12 +417,16 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
         S->pending.pop_front();
     }
     if (!admitted.empty()) {
+        if ((e = S->read_recs(st)) != PB_OK) return e;
         PB_HIP(hipStreamSynchronize(st));
         for (Slot* sp : admitted) {
             Slot& s = *sp;
-            SlotRec r;
-            PB_HIP(hipMemcpy(&r, s.rec, sizeof(r), hipMemcpyDeviceToHost));
-            if (r.flags & FLAG_BAD_COEF) { e = finish_slot(s, PB_ERR_ARG, st); if (e != PB_OK) return e; continue; }
+            const SlotRec r = S->host_recs[s.rec_idx];
+            if (r.setup_flags || (r.flags & FLAG_BAD_COEF)) {
+                e = finish_slot(s, PB_ERR_ARG, st);
+                if (e != PB_OK) return e;
+                continue;
+            }
             if (r.fit == 1) {
                 e = enqueue_encode(s.s.op, s.L.npad, s.s.q, (uint32_t*)s.s.q2, st);
                 if (e != PB_OK) return e;
@@ -360,7 +484,12 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
         }
         std::vector<int> first(run.size() + 1, 0);
         {
-            // workgroups in proportion to work, at least one each (same rule as the batch)
+            // workgroups in proportion to work, at least one each (same rule
+            // as the batch). Giving the requests with the least remaining work
+            // the spare workgroups first was measured on the config-4 trace:
+            // light-load latency fell but saturated throughput halved (small
+            // requests with many workgroups are barrier-bound, large ones
+            // with one workgroup need many launches).
             std::vector<double> w(run.size());
             std::vector<int> g(run.size(), 1);
             for (size_t i = 0; i < run.size(); ++i)
@@ -439,11 +568,11 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
             }
         }
         if (!outer_check.empty()) {
+            if ((e = S->read_recs(st)) != PB_OK) return e;
             PB_HIP(hipStreamSynchronize(st));
             for (Slot* sp : outer_check) {
                 Slot& s = *sp;
-                SlotRec r;
-                PB_HIP(hipMemcpy(&r, s.rec, sizeof(r), hipMemcpyDeviceToHost));
+                const SlotRec r = S->host_recs[s.rec_idx];
                 const double rel = r.bb > 0 ? std::sqrt(r.rr) / std::sqrt(r.bb) : 0.0;
                 if (s.precision == PB_F32) {
                     s.relres_true = rel;
@@ -463,7 +592,19 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
         }
     }
 
-    // ---- retire finished slots (their potential was handed back on the stream)
+    // ---- retire finished slots (their potential was handed back on the
+    // stream); molecule requests first get their energy from that potential
+    bool energies = false;
+    for (auto& up : S->active) {
+        Slot& s = *up;
+        if (s.solving || !s.from_atoms || s.energy_enqueued || !s.energy_host || s.status < 0) continue;
+        e = energy_enqueue(&s.grid, s.natoms, s.xyz, s.charge, s.req.x, s.qphi, &s.rec->energy_flags, &s.rec->esum,
+                           st);
+        if (e != PB_OK) return e;
+        s.energy_enqueued = true;
+        energies = true;
+    }
+    if (energies && (e = S->read_recs(st)) != PB_OK) return e;
     PB_HIP(hipStreamSynchronize(st));
     const double tnow = now_s();
     std::vector<std::unique_ptr<Slot>> keep;
@@ -484,7 +625,9 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
             f.relres_true = s.relres_true;
             f.seconds = tnow - s.t_submit;
             ++*n_done;
+            if (s.energy_enqueued) *s.energy_host = energy_kcal(S->host_recs[s.rec_idx].esum);
             S->release(s.off, s.bytes);
+            S->free_recs.push_back(s.rec_idx);
         } else {
             keep.push_back(std::move(up));   // reported by a later step
         }

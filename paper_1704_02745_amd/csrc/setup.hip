@@ -3,7 +3,7 @@
 // This file is compiled with -ffp-contract=off: the node classification,
 // the edge means and the charge weights must round exactly as the plain
 // (unfused) arithmetic they are defined by.
-#include "pb_internal.hpp"
+#include "solver.hpp"
 
 #include <cmath>
 #include <vector>
@@ -641,18 +641,10 @@ inline unsigned blocks_for(int64_t n, int bs, int64_t cap = 65536) {
     return (unsigned)b;
 }
 
-struct SetupWs {
-    int* flags;
-    uint64_t* keys;
-    double* qgrid;
-    uint8_t* mask;
-    double* ghost;
-    int* cell_start;   // fractional edges: atom ranges per cell
-    int* cell_end;
-    size_t bytes;
-};
 
-SetupWs carve_setup(void* base, int nx, int ny, int nz, int64_t natoms, bool frac = false) {
+}  // namespace
+
+SetupWs carve_setup(void* base, int nx, int ny, int nz, int64_t natoms, bool frac) {
     SetupWs w{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -688,6 +680,8 @@ SetupWs carve_setup(void* base, int nx, int ny, int nz, int64_t natoms, bool fra
     return w;
 }
 
+namespace {
+
 bool setup_opts_ok(const pb_setup_opts* o) {
     return o && (o->edge_model == PB_EDGE_NODE || o->edge_model == PB_EDGE_FRACTION);
 }
@@ -702,59 +696,15 @@ bool grid_ok(const pb_grid* g) {
 
 }  // namespace
 
-}  // namespace pb
-
-using namespace pb;
-
-extern "C" size_t pb_setup_workspace_bytes(const pb_grid* g, int64_t natoms) {
-    if (!grid_ok(g) || natoms < 0 || natoms > kMaxAtoms) return 0;
-    return carve_setup(nullptr, g->nx, g->ny, g->nz, natoms).bytes;
-}
-
-extern "C" size_t pb_setup_ex_workspace_bytes(const pb_grid* g, int64_t natoms, const pb_setup_opts* opts) {
-    if (!grid_ok(g) || natoms < 0 || natoms > kMaxAtoms || !setup_opts_ok(opts)) return 0;
-    return carve_setup(nullptr, g->nx, g->ny, g->nz, natoms, opts->edge_model == PB_EDGE_FRACTION).bytes;
-}
-
-extern "C" pb_status pb_setup(const pb_grid* g, int64_t natoms, const double* xyz,
-                              const double* radius, const double* charge, double eps_in,
-                              double eps_out, double kappa_d2, double* eps_x, double* eps_y,
-                              double* eps_z, double* kappa2, double* rhs, double* qgrid,
-                              uint8_t* mask, void* workspace, size_t workspace_bytes,
-                              void* stream_) {
-    pb_setup_opts o{};
-    o.edge_model = PB_EDGE_NODE;
-    return pb_setup_ex(g, natoms, xyz, radius, charge, eps_in, eps_out, kappa_d2, &o, eps_x, eps_y, eps_z, kappa2,
-                       rhs, qgrid, mask, workspace, workspace_bytes, stream_);
-}
-
-extern "C" pb_status pb_setup_ex(const pb_grid* g, int64_t natoms, const double* xyz,
-                                 const double* radius, const double* charge, double eps_in,
-                                 double eps_out, double kappa_d2, const pb_setup_opts* opts, double* eps_x,
-                                 double* eps_y, double* eps_z, double* kappa2, double* rhs, double* qgrid,
-                                 uint8_t* mask, void* workspace, size_t workspace_bytes, void* stream_) {
-    PB_ARG(setup_opts_ok(opts), "pb_setup: invalid options (edge_model)");
-    const bool frac = opts->edge_model == PB_EDGE_FRACTION;
-    PB_ARG(!frac || (g && g->boundary == PB_BOUNDARY_FREE),
-           "pb_setup: the fractional-edge dielectric is available with the free-space boundary only");
-    PB_ARG(!frac || kFractionEdgesEnabled,
-           "pb_setup: the fractional-edge dielectric (PB_EDGE_FRACTION) is switched off in this library");
-    PB_ARG(grid_ok(g), "pb_setup: grid needs a valid boundary, nx,ny,nz >= 2 (>= 3 periodic), finite h > 0 "
-                       "and a finite origin");
-    PB_ARG(natoms >= 0 && natoms <= kMaxAtoms, "pb_setup: natoms must be in [0, 2^21-1]");
-    PB_ARG(natoms == 0 || (xyz && radius && charge), "pb_setup: null atom array");
-    PB_ARG(eps_x && eps_y && eps_z && kappa2 && rhs, "pb_setup: null output array");
-    PB_ARG(std::isfinite(eps_in) && std::isfinite(eps_out) && eps_in > 0 && eps_out > 0,
-           "pb_setup: dielectric constants must be finite and > 0");
-    PB_ARG(std::isfinite(kappa_d2) && kappa_d2 >= 0, "pb_setup: kappa_d2 must be finite and >= 0");
-    PB_ARG(workspace != nullptr, "pb_setup: null workspace");
+// Every launch of the setup on `st` (the outputs and the flags in w.flags
+// are final once the stream reaches this point). The fractional-edge model
+// reads the largest radius back to size its cell list, so it synchronises
+// once; the two-point model never does.
+pb_status setup_enqueue(const pb_grid* g, int64_t natoms, const double* xyz, const double* radius,
+                        const double* charge, double eps_in, double eps_out, double kappa_d2, bool frac,
+                        double* eps_x, double* eps_y, double* eps_z, double* kappa2, double* rhs, double* qgrid,
+                        uint8_t* mask, const SetupWs& w, hipStream_t st) {
     const int nx = g->nx, ny = g->ny, nz = g->nz;
-    SetupWs w = carve_setup(workspace, nx, ny, nz, natoms, frac);
-    if (workspace_bytes < w.bytes) {
-        set_error("pb_setup: workspace of %zu bytes, %zu needed", workspace_bytes, w.bytes);
-        return PB_ERR_NOMEM;
-    }
-    hipStream_t st = (hipStream_t)stream_;
     const double h = g->h, ox = g->origin[0], oy = g->origin[1], oz = g->origin[2];
     const int64_t nn = (int64_t)nx * ny * nz;
     const int64_t nmask = (int64_t)(nx + 2) * (ny + 2) * (nz + 2);
@@ -837,6 +787,86 @@ extern "C" pb_status pb_setup_ex(const pb_grid* g, int64_t natoms, const double*
         hipLaunchKernelGGL(k_neutralise, dim3(blocks_for(nn, 256)), dim3(256), 0, st, rhs, nn,
                            (const double*)w.ghost);
     }
+    PB_HIP(hipGetLastError());
+    return PB_OK;
+}
+
+size_t energy_scratch_bytes(int64_t natoms) { return sizeof(double) * (size_t)std::max<int64_t>(natoms, 1); }
+
+pb_status energy_enqueue(const pb_grid* g, int64_t natoms, const double* xyz, const double* charge, const double* x,
+                         double* qphi, int* flags, double* sum, hipStream_t st) {
+    if (natoms > 0)
+        hipLaunchKernelGGL(k_energy_atoms, dim3(blocks_for(natoms, 256, 1 << 30)), dim3(256), 0, st, xyz, charge,
+                           natoms, g->nx, g->ny, g->nz, g->h, g->origin[0], g->origin[1], g->origin[2],
+                           g->boundary == PB_BOUNDARY_PERIODIC ? 1 : 0, x, (double*)nullptr, qphi, flags);
+    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(1024), 0, st, (const double*)qphi, natoms, sum);
+    PB_HIP(hipGetLastError());
+    return PB_OK;
+}
+
+double energy_kcal(double sum_q_phi) { return 0.5 * sum_q_phi * kCoulombKcal; }
+
+namespace {
+
+}  // namespace
+
+}  // namespace pb
+
+using namespace pb;
+
+extern "C" size_t pb_setup_workspace_bytes(const pb_grid* g, int64_t natoms) {
+    if (!grid_ok(g) || natoms < 0 || natoms > kMaxAtoms) return 0;
+    return carve_setup(nullptr, g->nx, g->ny, g->nz, natoms).bytes;
+}
+
+extern "C" size_t pb_setup_ex_workspace_bytes(const pb_grid* g, int64_t natoms, const pb_setup_opts* opts) {
+    if (!grid_ok(g) || natoms < 0 || natoms > kMaxAtoms || !setup_opts_ok(opts)) return 0;
+    return carve_setup(nullptr, g->nx, g->ny, g->nz, natoms, opts->edge_model == PB_EDGE_FRACTION).bytes;
+}
+
+extern "C" pb_status pb_setup(const pb_grid* g, int64_t natoms, const double* xyz,
+                              const double* radius, const double* charge, double eps_in,
+                              double eps_out, double kappa_d2, double* eps_x, double* eps_y,
+                              double* eps_z, double* kappa2, double* rhs, double* qgrid,
+                              uint8_t* mask, void* workspace, size_t workspace_bytes,
+                              void* stream_) {
+    pb_setup_opts o{};
+    o.edge_model = PB_EDGE_NODE;
+    return pb_setup_ex(g, natoms, xyz, radius, charge, eps_in, eps_out, kappa_d2, &o, eps_x, eps_y, eps_z, kappa2,
+                       rhs, qgrid, mask, workspace, workspace_bytes, stream_);
+}
+
+extern "C" pb_status pb_setup_ex(const pb_grid* g, int64_t natoms, const double* xyz,
+                                 const double* radius, const double* charge, double eps_in,
+                                 double eps_out, double kappa_d2, const pb_setup_opts* opts, double* eps_x,
+                                 double* eps_y, double* eps_z, double* kappa2, double* rhs, double* qgrid,
+                                 uint8_t* mask, void* workspace, size_t workspace_bytes, void* stream_) {
+    PB_ARG(setup_opts_ok(opts), "pb_setup: invalid options (edge_model)");
+    const bool frac = opts->edge_model == PB_EDGE_FRACTION;
+    PB_ARG(!frac || (g && g->boundary == PB_BOUNDARY_FREE),
+           "pb_setup: the fractional-edge dielectric is available with the free-space boundary only");
+    PB_ARG(!frac || kFractionEdgesEnabled,
+           "pb_setup: the fractional-edge dielectric (PB_EDGE_FRACTION) is switched off in this library");
+    PB_ARG(grid_ok(g), "pb_setup: grid needs a valid boundary, nx,ny,nz >= 2 (>= 3 periodic), finite h > 0 "
+                       "and a finite origin");
+    PB_ARG(natoms >= 0 && natoms <= kMaxAtoms, "pb_setup: natoms must be in [0, 2^21-1]");
+    PB_ARG(natoms == 0 || (xyz && radius && charge), "pb_setup: null atom array");
+    PB_ARG(eps_x && eps_y && eps_z && kappa2 && rhs, "pb_setup: null output array");
+    PB_ARG(std::isfinite(eps_in) && std::isfinite(eps_out) && eps_in > 0 && eps_out > 0,
+           "pb_setup: dielectric constants must be finite and > 0");
+    PB_ARG(std::isfinite(kappa_d2) && kappa_d2 >= 0, "pb_setup: kappa_d2 must be finite and >= 0");
+    PB_ARG(workspace != nullptr, "pb_setup: null workspace");
+    const int nx = g->nx, ny = g->ny, nz = g->nz;
+    SetupWs w = carve_setup(workspace, nx, ny, nz, natoms, frac);
+    if (workspace_bytes < w.bytes) {
+        set_error("pb_setup: workspace of %zu bytes, %zu needed", workspace_bytes, w.bytes);
+        return PB_ERR_NOMEM;
+    }
+    hipStream_t st = (hipStream_t)stream_;
+    const pb_status e = setup_enqueue(g, natoms, xyz, radius, charge, eps_in, eps_out, kappa_d2, frac, eps_x, eps_y,
+                                      eps_z, kappa2, rhs, qgrid, mask, w, st);
+    if (e != PB_OK) return e;
+    const int per = g->boundary == PB_BOUNDARY_PERIODIC ? 1 : 0;
     PB_HIP(hipGetLastError());
     int flags = 0;
     PB_HIP(hipMemcpyAsync(&flags, w.flags, sizeof(int), hipMemcpyDeviceToHost, st));

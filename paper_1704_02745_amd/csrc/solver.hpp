@@ -178,4 +178,31 @@ template <typename T>
 pb_status batch_launch(const void* d_kargs, const int* d_first, int nprob, int grid, size_t lds, hipStream_t st,
                        bool cooperative, int coded = 0);
 
+// setup.hip: the setup's kernels without the host checks, for callers that
+// sequence them themselves (the served form).
+struct SetupWs {
+    int* flags;
+    uint64_t* keys;
+    double* qgrid;
+    uint8_t* mask;
+    double* ghost;
+    int* cell_start;   // fractional edges: atom ranges per cell
+    int* cell_end;
+    size_t bytes;
+};
+SetupWs carve_setup(void* base, int nx, int ny, int nz, int64_t natoms, bool frac = false);
+// Enqueues the whole setup of pb_setup_ex on `st`; validation is the
+// caller's. The atom-range flags land in w.flags (nonzero: an atom outside
+// the node box).
+pb_status setup_enqueue(const pb_grid* g, int64_t natoms, const double* xyz, const double* radius,
+                        const double* charge, double eps_in, double eps_out, double kappa_d2, bool frac,
+                        double* eps_x, double* eps_y, double* eps_z, double* kappa2, double* rhs, double* qgrid,
+                        uint8_t* mask, const SetupWs& w, hipStream_t st);
+// Enqueues sum_a q_a phi(c_a) into *sum (device); qphi holds natoms doubles.
+size_t energy_scratch_bytes(int64_t natoms);
+pb_status energy_enqueue(const pb_grid* g, int64_t natoms, const double* xyz, const double* charge, const double* x,
+                         double* qphi, int* flags, double* sum, hipStream_t st);
+// The energy 1/2 sum_a q_a phi(c_a) in kcal/mol from that sum.
+double energy_kcal(double sum_q_phi);
+
 }  // namespace pb

@@ -221,6 +221,28 @@ def config4_request(idx: int) -> Problem:
                    precision=prec, seed=4000 + idx)
 
 
+_C4_BASE = {}
+
+
+def config4_molecule(idx: int, pool: int = 64, sigma: float = 0.3) -> Problem:
+    """A distinct molecule for serving request `idx`: request idx % pool of
+    config 4 (its atom count, radii, charges, grid and tolerance) with every
+    atom moved by seeded Gaussian noise of sigma A, as config 3 perturbs its
+    snapshots. Drawing whole new chains for thousands of requests would cost
+    minutes of host time; the perturbation keeps each request's coordinates
+    its own. The config-4 box (at least twice the extent) keeps every sphere
+    inside the node box."""
+    key = idx % pool
+    if key not in _C4_BASE:
+        _C4_BASE[key] = config4_request(key)
+    base = _C4_BASE[key]
+    rng = np.random.default_rng(4000 + 100000 + idx)
+    xyz = base.mol.xyz + sigma * rng.standard_normal(base.mol.xyz.shape)
+    mol = Molecule(xyz=xyz, radius=base.mol.radius.copy(), charge=base.mol.charge.copy())
+    return Problem(f"c4m_{idx}_{base.grid.nx}", mol, base.grid, tol=base.tol, precision=base.precision,
+                   seed=4000 + 100000 + idx)
+
+
 def config4_arrivals(nreq: int, rate: float = 200.0, seed: int = 4999) -> np.ndarray:
     """Poisson arrival times (s) at `rate` requests/s."""
     rng = np.random.default_rng(seed)

@@ -339,6 +339,21 @@ void pb_set_coded_coefficients(int32_t on);
 int32_t pb_get_coded_coefficients(void);
 
 /*
+ * pb_set_periodic_pass: the pass form of fused solves with the periodic
+ * boundary of section 2.7, process-wide. -1 (the default): the tiling model's
+ * choice, which is the 40-byte pass wherever it applies; 0: the pass that
+ * stores A p (48 bytes per node in FP32); 1: the 40-byte pass, which runs on
+ * ghost-row copies of the operator and state (two copied rows below row 0
+ * and above row ny-1 of every plane; grids with nx >= 5 and ny >= 4, others
+ * take form 0), coded as pb_set_coded_coefficients says. The iterates of the
+ * forms agree up to rounding; coded and uncoded 40-byte passes agree bit for
+ * bit. Values other than -1, 0, 1 are ignored. pb_get_periodic_pass returns
+ * the setting. Not synchronised with solves running on other threads.
+ */
+void pb_set_periodic_pass(int32_t form);
+int32_t pb_get_periodic_pass(void);
+
+/*
  * pb_tiling_candidates: the feasible tilings of the fused stencil kernel for
  * this grid shape and precision on the current device, i.e. the search space
  * of pb_autotune (the same iteration, launched in different shapes). Writes

@@ -41,7 +41,7 @@ EXPORTS = ("pb_version", "pb_last_error", "pb_setup_workspace_bytes", "pb_setup"
            "pb_energy_workspace_bytes", "pb_energy",
            "pb_solvation_workspace_bytes", "pb_solvation_energy",
            "pb_setup_ex_workspace_bytes", "pb_setup_ex", "pb_solve_noalloc", "pb_solve_noalloc_max_bytes",
-           "pb_stream_copy")
+           "pb_stream_copy", "pb_set_periodic_pass", "pb_get_periodic_pass")
 
 
 class PBError(RuntimeError):
@@ -147,6 +147,10 @@ def _load():
     lib.pb_set_coded_coefficients.argtypes = [i32]
     lib.pb_get_coded_coefficients.restype = i32
     lib.pb_get_coded_coefficients.argtypes = []
+    lib.pb_set_periodic_pass.restype = None
+    lib.pb_set_periodic_pass.argtypes = [i32]
+    lib.pb_get_periodic_pass.restype = i32
+    lib.pb_get_periodic_pass.argtypes = []
     lib.pb_tiling_candidates.restype = ctypes.c_int
     lib.pb_tiling_candidates.argtypes = [i32, i32, i32, i32, ctypes.POINTER(Tuning), i32, ctypes.POINTER(i32)]
     P = ctypes.POINTER(Problem)
@@ -412,6 +416,17 @@ def set_coded_coefficients(on: bool) -> None:
 
 def get_coded_coefficients() -> bool:
     return bool(lib.pb_get_coded_coefficients())
+
+
+def set_periodic_pass(form: int) -> None:
+    """Pass form of periodic fused solves, process-wide: -1 the model's
+    choice (the default), 0 the pass that stores A.p, 1 the 40-byte pass on
+    ghost-row copies (grids with nx >= 5, ny >= 4)."""
+    lib.pb_set_periodic_pass(int(form))
+
+
+def get_periodic_pass() -> int:
+    return int(lib.pb_get_periodic_pass())
 
 
 def get_tuning(nx, ny, nz, precision="f32") -> dict:

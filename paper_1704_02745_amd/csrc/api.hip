@@ -40,7 +40,9 @@ struct SolveWs {
     size_t bytes;
 };
 
-SolveWs carve_solve(void* base, const Layout& L, int prec, int op) {
+// per: periodic boundary; the fused solve then also holds the ghost-row
+// copies of the operator and state for the 40-byte pass (ghost_layout).
+SolveWs carve_solve(void* base, const Layout& L, int prec, int op, int per) {
     SolveWs w{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -78,6 +80,19 @@ SolveWs carve_solve(void* base, const Layout& L, int prec, int op) {
         } else {
             s.r2 = (double*)take(n8);
             s.q2 = (double*)take(n8);
+            if (per && ghost_layout_ok(L)) {
+                const size_t g8 = sizeof(double) * (size_t)ghost_layout(L).npad;
+                s.gop.cx = (double*)take(g8);
+                s.gop.cy = (double*)take(g8);
+                s.gop.cz = (double*)take(g8);
+                s.gop.d = (double*)take(g8);
+                s.gb = (double*)take(g8);
+                s.gx = (double*)take(g8);
+                s.gr = (double*)take(g8);
+                s.gr2 = (double*)take(g8);
+                s.gp0 = (double*)take(g8);
+                s.gp1 = (double*)take(g8);
+            }
         }
     } else {
         SolveBufs<float>& s = w.s32;
@@ -99,6 +114,20 @@ SolveWs carve_solve(void* base, const Layout& L, int prec, int op) {
         } else {
             s.r2 = (float*)take(n4);
             s.q2 = (float*)take(n4);
+            if (per && ghost_layout_ok(L)) {
+                const size_t g4 = sizeof(float) * (size_t)ghost_layout(L).npad;
+                s.gop.cx = (float*)take(g4);
+                s.gop.cy = (float*)take(g4);
+                s.gop.cz = (float*)take(g4);
+                s.gop.d = (float*)take(g4);
+                s.gb = (float*)take(g4);
+                s.gx = (float*)take(g4);
+                s.gr = (float*)take(g4);
+                s.gr2 = (float*)take(g4);
+                s.gp0 = (float*)take(g4);
+                s.gp1 = (float*)take(g4);
+                s.gcodes = (uint32_t*)take(g4);
+            }
         }
     }
     if (op == PB_OP_MG) w.mg = take(mg_workspace_bytes(L, prec));
@@ -235,7 +264,8 @@ extern "C" const char* pb_last_error(void) { return g_err; }
 
 extern "C" size_t pb_solve_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, const pb_solve_opts* opts) {
     if (!dims_ok(nx, ny, nz) || !opts_ok(opts)) return 0;
-    return carve_solve(nullptr, make_layout(nx, ny, nz), opts->precision, opts->op).bytes;
+    return carve_solve(nullptr, make_layout(nx, ny, nz), opts->precision, opts->op,
+                       opts->boundary == PB_BOUNDARY_PERIODIC).bytes;
 }
 
 namespace {
@@ -256,7 +286,7 @@ pb_status solve_impl(int32_t nx, int32_t ny, int32_t nz, double h, const double*
     PB_ARG(((uintptr_t)workspace & 255) == 0, "pb_solve: workspace must be 256-byte aligned");
     const Layout L = make_layout(nx, ny, nz);
     const int prec = opts->precision, op = opts->op;
-    SolveWs w = carve_solve(workspace, L, prec, op);
+    SolveWs w = carve_solve(workspace, L, prec, op, opts->boundary == PB_BOUNDARY_PERIODIC);
     if (workspace_bytes < w.bytes) {
         set_error("pb_solve: workspace of %zu bytes, %zu needed", workspace_bytes, w.bytes);
         return PB_ERR_NOMEM;
@@ -424,7 +454,8 @@ extern "C" pb_status pb_solve_noalloc(int32_t nx, int32_t ny, int32_t nz, double
     if (info) std::memset(info, 0, sizeof(*info));
     PB_ARG(dims_ok(nx, ny, nz), "pb_solve_noalloc: dims must be >= 1 (and below 2^36 nodes)");
     PB_ARG(opts_ok(opts), "pb_solve_noalloc: invalid options");
-    const size_t need = carve_solve(nullptr, make_layout(nx, ny, nz), opts->precision, opts->op).bytes;
+    const size_t need = carve_solve(nullptr, make_layout(nx, ny, nz), opts->precision, opts->op,
+                                    opts->boundary == PB_BOUNDARY_PERIODIC).bytes;
     if (need > kNoAllocScratchBytes) {
         set_error("pb_solve_noalloc: this grid needs %zu bytes of scratch and the library holds %zu per GPU "
                   "(about 2.2M nodes); use pb_solve with a workspace",
@@ -451,7 +482,7 @@ extern "C" pb_status pb_autotune(int32_t nx, int32_t ny, int32_t nz, double h, c
     PB_ARG(eps_x && eps_y && eps_z && kappa2 && rhs, "pb_autotune: null array");
     PB_ARG(workspace != nullptr && ((uintptr_t)workspace & 255) == 0, "pb_autotune: null or misaligned workspace");
     const Layout L = make_layout(nx, ny, nz);
-    SolveWs w = carve_solve(workspace, L, opts->precision, PB_OP_STENCIL);
+    SolveWs w = carve_solve(workspace, L, opts->precision, PB_OP_STENCIL, 0);
     if (workspace_bytes < w.bytes) {
         set_error("pb_autotune: workspace of %zu bytes, %zu needed", workspace_bytes, w.bytes);
         return PB_ERR_NOMEM;
@@ -473,6 +504,10 @@ extern "C" pb_status pb_autotune(int32_t nx, int32_t ny, int32_t nz, double h, c
 
 extern "C" void pb_set_coded_coefficients(int32_t on) { set_coded_coefficients(on); }
 extern "C" int32_t pb_get_coded_coefficients(void) { return coded_coefficients(); }
+extern "C" void pb_set_periodic_pass(int32_t form) {
+    if (form >= -1 && form <= 1) set_periodic_pass(form);
+}
+extern "C" int32_t pb_get_periodic_pass(void) { return periodic_pass(); }
 
 extern "C" pb_status pb_get_tuning(int32_t nx, int32_t ny, int32_t nz, int32_t precision, pb_tuning* out) {
     PB_ARG(dims_ok(nx, ny, nz) && out, "pb_get_tuning: bad dims or null output");

@@ -68,6 +68,11 @@ struct KArgs {
     T* p[2];
     int nx, ny, nz;
     int64_t sp;
+    // Owned positions of a plane: [org, org + own). The plain layout owns the
+    // whole padded plane (org 0, own sp); the ghost-row layout of the
+    // periodic 40-byte pass owns the nx*ny nodes after its two low ghost rows
+    // (own rounded up to the vector width; the nodes end at oend).
+    int64_t org, own, oend;
     int seglen, zchunk, nseg, nzc, ntiles, halo;
     double tol;
     int maxiter;
@@ -321,8 +326,8 @@ template <typename T>
 __device__ __forceinline__ TileBox tile_box(const KArgs<T>& a, int tile) {
     TileBox t;
     const int seg = tile % a.nseg, zc = tile / a.nseg;
-    t.s = (int64_t)seg * a.seglen;
-    t.e = min(t.s + (int64_t)a.seglen, a.sp);
+    t.s = a.org + (int64_t)seg * a.seglen;
+    t.e = min(t.s + (int64_t)a.seglen, a.org + a.own);
     t.k0 = zc * a.zchunk;
     t.k1 = min(t.k0 + a.zchunk, a.nz);
     return t;
@@ -332,13 +337,67 @@ __device__ __forceinline__ TileBox tile_box(const KArgs<T>& a, int tile) {
 
 // Initial state: r = b - A x0 (r = b for a zero guess), p = 0 and (for the
 // pass that reads a stored A.p) q = 0 in buffer 0; sums r.r and b.b.
-template <typename T, int BS, bool PER>
+//
+// GL: the ghost-row layout of the periodic 40-byte pass. Every owned node is
+// computed with its wrapped neighbours, the elements of the last group past
+// the last node (ghost positions) get the values of the nodes nx*ny before
+// them, and the ghost copies of rows 0, 1, ny-2, ny-1 are written too.
+template <typename T, int BS, bool PER, bool GL = false>
 __device__ void init_tile(const KArgs<T>& a, int tile, bool with_q, double (&acc)[2]) {
     constexpr int W = Vec<T>::n;
     using V = typename Vec<T>::type;
     const TileBox tb = tile_box(a, tile);
     const int64_t npad = a.sp * a.nz;
     const V z0 = vzero<T>();
+    if constexpr (GL) {
+        const int64_t nodes = a.oend - a.org, sp = a.sp;
+        const int nx = a.nx, ny = a.ny, nz = a.nz;
+        const T* X = a.x;
+        for (int k = tb.k0; k < tb.k1; ++k) {
+            for (int64_t pos = tb.s + (int64_t)threadIdx.x * W; pos < tb.e; pos += (int64_t)BS * W) {
+#pragma unroll
+                for (int u = 0; u < W; ++u) {
+                    const int64_t q = pos + u;
+                    const bool node = q < a.oend;
+                    const int64_t rel = node ? q - a.org : q - a.org - nodes;
+                    const int64_t t = (int64_t)k * sp + a.org + rel;   // the node whose values q holds
+                    const T bv = a.b[t];
+                    T rv = bv;
+                    if (a.warm) {
+                        const int64_t j = rel / nx, i = rel - j * nx;
+                        const int64_t xr = (i == nx - 1) ? t - (nx - 1) : t + 1;
+                        const int64_t xl = (i == 0) ? t + (nx - 1) : t - 1;
+                        const int64_t yu = (j == ny - 1) ? t - (int64_t)(ny - 1) * nx : t + nx;
+                        const int64_t yd = (j == 0) ? t + (int64_t)(ny - 1) * nx : t - nx;
+                        const int64_t zu = (k == nz - 1) ? t - (int64_t)(nz - 1) * sp : t + sp;
+                        const int64_t zd = (k == 0) ? t + (int64_t)(nz - 1) * sp : t - sp;
+                        T nb = a.op.cx[t] * X[xr];
+                        nb += a.op.cx[xl] * X[xl];
+                        nb += a.op.cy[t] * X[yu];
+                        nb += a.op.cy[yd] * X[yd];
+                        nb += a.op.cz[t] * X[zu];
+                        nb += a.op.cz[zd] * X[zd];
+                        rv = bv - (a.op.d[t] * X[t] - nb);
+                    }
+                    const int64_t g = (int64_t)k * sp + q;
+                    a.r[0][g] = rv;
+                    a.p[0][g] = T(0);
+                    if (node) {
+                        acc[0] += (double)rv * (double)rv;
+                        acc[1] += (double)bv * (double)bv;
+                        const int64_t span = (int64_t)nx * ny;
+                        const int64_t jq = rel / nx;
+                        const int64_t gq = jq < 2 ? q + span : (jq >= ny - 2 ? q - span : -1);
+                        if (gq >= 0) {
+                            a.r[0][(int64_t)k * sp + gq] = rv;
+                            a.p[0][(int64_t)k * sp + gq] = T(0);
+                        }
+                    }
+                }
+            }
+        }
+        return;
+    }
     for (int k = tb.k0; k < tb.k1; ++k) {
         for (int64_t pos = tb.s + (int64_t)threadIdx.x * W; pos < tb.e; pos += (int64_t)BS * W) {
             const int64_t g = (int64_t)k * a.sp + pos;
@@ -782,6 +841,82 @@ __device__ __forceinline__ T apply_point(T d, T v, T cr, T vr, T cl, T vl, T cu,
     return fma(d, v, -nb);
 }
 
+// ---- periodic boundary in the ghost-row layout (40-byte pass)
+//
+// Each plane holds two ghost rows below row 0 (copies of rows ny-2, ny-1) and
+// two above row ny-1 (copies of rows 0, 1), so that every y-neighbour of a
+// node, wrapped or not, sits one row away as in the free-boundary layout.
+// The owner of a node of rows 0, 1, ny-2, ny-1 stores its r and p also into
+// the ghost copy, and a ghost node recomputed in a tile's halo sees the same
+// inputs as its original and gets the same value. Planes wrap in z; across
+// the x ends a group takes the neighbour from the other end of the row (one
+// row is shorter than the in-plane halo, so it is in LDS).
+template <bool PER>
+__device__ __forceinline__ int wrap_plane(int k, int nz) {
+    if constexpr (!PER) return k;
+    return k < 0 ? k + nz : (k >= nz ? k - nz : k);
+}
+struct XWrap {
+    int wl, wr;   // element of the group in column 0 / column nx-1, -1 if none
+};
+// Row and column of plane position q relative to row 0 (32-bit: planes of
+// the ghost-row layout hold fewer than 2^31 positions, checked on the host).
+struct RowCol {
+    int j, i;
+};
+template <typename T>
+__device__ __forceinline__ RowCol row_col(const KArgs<T>& a, int64_t q) {
+    const int rel = (int)(q - a.org) + 4 * a.nx;   // >= 0 for every position a pass touches
+    const int j = rel / a.nx;
+    return RowCol{j - 4, rel - j * a.nx};
+}
+// Only positions of the node and ghost rows (rows -2 .. ny+1) count.
+template <int W, typename T>
+__device__ __forceinline__ XWrap x_wrap(const KArgs<T>& a, int64_t q0) {
+    XWrap w{-1, -1};
+    const RowCol rc = row_col(a, q0);
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+        const bool next = rc.i + u >= a.nx;   // nx > W: the group crosses at most one row end
+        const int i = next ? rc.i + u - a.nx : rc.i + u;
+        const int j = next ? rc.j + 1 : rc.j;
+        const bool in = j >= -2 && j < a.ny + 2;
+        if (in && i == 0) w.wl = u;
+        if (in && i == a.nx - 1) w.wr = u;
+    }
+    return w;
+}
+// The row end inside a group as one number: the element in column 0, W when
+// the last element is in column nx-1 and the next row starts after the
+// group, -1 when the group holds no row end. Element u takes its left
+// neighbour across the row end when u == brk, its right one when u + 1 == brk.
+template <int W, typename T>
+__device__ __forceinline__ int x_break(const KArgs<T>& a, int64_t q0) {
+    const XWrap w = x_wrap<W>(a, q0);
+    return w.wl >= 0 ? w.wl : (w.wr == W - 1 ? W : -1);
+}
+// The value, unknown to the optimizer: compares against it are made where
+// they are used (in the plane loop) instead of being hoisted and kept as
+// scalar lane masks.
+__device__ __forceinline__ int opaque(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+// Plane positions of the ghost copies of the owned nodes q0 .. q0+W-1 (the
+// first nv of them): -1 for nodes of rows 2 .. ny-3.
+template <int W, typename T>
+__device__ __forceinline__ void ghost_of(const KArgs<T>& a, int64_t q0, int nv, int64_t (&gd)[W]) {
+    const RowCol rc = row_col(a, q0);
+    const int64_t span = (int64_t)a.nx * a.ny;
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+        const int j = rc.j + (rc.i + u >= a.nx ? 1 : 0);
+        gd[u] = -1;
+        if (u < nv && j < 2) gd[u] = q0 + u + span;
+        if (u < nv && j >= a.ny - 2) gd[u] = q0 + u - span;
+    }
+}
+
 // One pass on one tile, 40-byte form: the same iteration as pass_tile, but
 // q_{l-1} = A p_{l-2} is recomputed from the stored p_{l-2} instead of being
 // stored by the previous pass. Per node the pass reads r, p_old, d, cx, cy,
@@ -796,7 +931,7 @@ __device__ __forceinline__ T apply_point(T d, T v, T cr, T vr, T cl, T vl, T cu,
 // build planes k0-1 and k0 of p_{l-1}. Threads: own positions s + tid*VEC,
 // inner ring groups on the first 2*halo/VEC threads, outer ring groups on the
 // last 2*halo/VEC threads (the tiling guarantees 2*halo/VEC <= BS).
-template <typename T, int BS, bool NT>
+template <typename T, int BS, bool NT, bool PER>
 __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, T beta, T* lds,
                             double (&acc)[NPART]) {
 #pragma clang fp contract(off)
@@ -838,6 +973,24 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
     const bool is_o = og >= 0;
     const int64_t op = (og < H / W) ? (s - 2 * H + (int64_t)og * W) : (e + H + (int64_t)(og - H / W) * W);
     const bool o_in = is_o && op >= 0 && op < sp;
+    // periodic (ghost-row layout): planes wrap, the column-0 and column-nx-1
+    // elements of a group take their x-neighbour from the other end of the
+    // row, owned nodes of the first and last two rows are also stored into
+    // their ghost copies, and only the owned elements of the last group
+    // (nv of them) enter the sums
+    const int nv = valid ? (int)min((int64_t)W, a.oend - pos) : 0;
+    const int brk = PER && valid ? x_break<W>(a, pos) : -1;
+    const int hbrk = PER && h_in ? x_break<W>(a, hp) : -1;
+    // the elements whose neighbour across a row end is read (any element when
+    // there is none: the value read is then unused)
+    const int kl = min(max(brk, 0), W - 1), kr = min(max(brk - 1, 0), W - 1);
+    const int hkl = min(max(hbrk, 0), W - 1), hkr = min(max(hbrk - 1, 0), W - 1);
+    int64_t gd[W];
+    if constexpr (PER) ghost_of<W>(a, pos, nv, gd);
+    else
+#pragma unroll
+        for (int u = 0; u < W; ++u) gd[u] = -1;
+    auto pl_of = [&](int k) { return (int64_t)wrap_plane<PER>(k, nz) * sp; };
 
     // State at the start of step k (k = k0-2 first): p_{l-2} of planes k and
     // k+1 lives in the two p_old LDS slots (plane k until the step's end),
@@ -848,14 +1001,14 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
     {
         V po_m, po_c, hpo_m, hpo_c;
         const int km = k0 - 2, kc = k0 - 1;
-        const bool vm = km >= 0, vc = kc >= 0;
-        po_m = (valid && vm) ? vload(pold + (int64_t)km * sp + pos) : z0;
-        po_c = (valid && vc) ? vload(pold + (int64_t)kc * sp + pos) : z0;
-        cz_c = (valid && vm) ? vload(CZ + (int64_t)km * sp + pos) : z0;
-        hpo_m = (h_in && vm) ? vload(pold + (int64_t)km * sp + hp) : z0;
-        hpo_c = (h_in && vc) ? vload(pold + (int64_t)kc * sp + hp) : z0;
-        hcz_c = (h_in && vm) ? vload(CZ + (int64_t)km * sp + hp) : z0;
-        const V o_po = (o_in && vc) ? vload(pold + (int64_t)kc * sp + op) : z0;
+        const bool vm = PER || km >= 0, vc = PER || kc >= 0;
+        po_m = (valid && vm) ? vload(pold + pl_of(km) + pos) : z0;
+        po_c = (valid && vc) ? vload(pold + pl_of(kc) + pos) : z0;
+        cz_c = (valid && vm) ? vload(CZ + pl_of(km) + pos) : z0;
+        hpo_m = (h_in && vm) ? vload(pold + pl_of(km) + hp) : z0;
+        hpo_c = (h_in && vc) ? vload(pold + pl_of(kc) + hp) : z0;
+        hcz_c = (h_in && vm) ? vload(CZ + pl_of(km) + hp) : z0;
+        const V o_po = (o_in && vc) ? vload(pold + pl_of(kc) + op) : z0;
         T* P = (kc & 1) ? PO1 : PO0;
         if (valid) vstore(P + (pos - obase), po_c);
         if (is_h) vstore(P + (hp - obase), hpo_c);
@@ -870,24 +1023,26 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
     // before the previous step's LDS barrier, so their latency overlaps it.
     struct Ld {
         V po_n, r_o, d_n, x_n, cx_n, cy_n, cz_n;
-        T cxm_n, cym_n[W];
+        T cxm_n, cym_n[W], cxw_n;
         V hpo_n, h_r, h_d, h_cx, h_cy, h_cz;
-        T h_cxm, h_cym[W];
+        T h_cxm, h_cym[W], h_cxw;
         V o_po;
     };
     auto issue = [&](int k, Ld& L) {
         const int kn = k + 1, kf = k + 2;
-        const bool v1 = kn >= 0 && kn < nz;
-        const bool v2 = kf >= 0 && kf < nz;
+        const bool v1 = PER || (kn >= 0 && kn < nz);
+        const bool v2 = PER || (kf >= 0 && kf < nz);
         const bool own1 = kn >= k0 && kn < k1;
         const bool xu = own1 && do_x;
-        const int64_t g1 = (int64_t)kn * sp + pos;
+        const int64_t g1 = pl_of(kn) + pos;
         L.po_n = z0; L.r_o = z0; L.d_n = z0; L.x_n = z0; L.cx_n = z0; L.cy_n = z0; L.cz_n = z0;
         L.cxm_n = T(0);
+        L.cxw_n = T(0);
+        L.h_cxw = T(0);
 #pragma unroll
         for (int u = 0; u < W; ++u) L.cym_n[u] = T(0);
         if (valid) {
-            if (v2) L.po_n = sload<NT>(pold + (int64_t)kf * sp + pos);
+            if (v2) L.po_n = sload<NT>(pold + pl_of(kf) + pos);
             if (v1) {
                 L.r_o = sload<NT>(rold + g1);
                 L.d_n = sload<NT>(DD + g1);
@@ -898,6 +1053,7 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
                 L.cxm_n = pos >= 1 ? CX[g1 - 1] : T(0);
 #pragma unroll
                 for (int u = 0; u < W; ++u) L.cym_n[u] = (pos + u - nx >= 0) ? CY[g1 + u - nx] : T(0);
+                if (PER) L.cxw_n = CX[g1 + kl + nx - 1];
             }
         }
         L.hpo_n = z0; L.h_r = z0; L.h_d = z0; L.h_cx = z0; L.h_cy = z0; L.h_cz = z0;
@@ -905,9 +1061,9 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
 #pragma unroll
         for (int u = 0; u < W; ++u) L.h_cym[u] = T(0);
         if (h_in) {
-            if (v2) L.hpo_n = vload(pold + (int64_t)kf * sp + hp);
+            if (v2) L.hpo_n = vload(pold + pl_of(kf) + hp);
             if (v1) {
-                const int64_t gh = (int64_t)kn * sp + hp;
+                const int64_t gh = pl_of(kn) + hp;
                 L.h_cz = vload(CZ + gh);
                 if (own1) {
                     L.h_r = vload(rold + gh);
@@ -917,10 +1073,11 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
                     L.h_cxm = hp >= 1 ? CX[gh - 1] : T(0);
 #pragma unroll
                     for (int u = 0; u < W; ++u) L.h_cym[u] = (hp + u - nx >= 0) ? CY[gh + u - nx] : T(0);
+                    if (PER && hbrk >= 0 && hbrk < W) L.h_cxw = CX[gh + hkl + nx - 1];
                 }
             }
         }
-        L.o_po = (o_in && v2) ? vload(pold + (int64_t)kf * sp + op) : z0;
+        L.o_po = (o_in && v2) ? vload(pold + pl_of(kf) + op) : z0;
     };
     Ld cur;
     issue(k0 - 2, cur);
@@ -931,8 +1088,7 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
 
     for (int k = k0 - 2; k < k1; ++k) {
         const int kn = k + 1, kf = k + 2;
-        const bool v1 = kn >= 0 && kn < nz;
-        const bool v2 = kf >= 0 && kf < nz;
+        const bool v1 = PER || (kn >= 0 && kn < nz);
         const bool own1 = kn >= k0 && kn < k1;   // plane k+1 belongs to this tile
         const bool xu = own1 && do_x;
         T* const POc = (kn & 1) ? PO1 : PO0;
@@ -943,26 +1099,30 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
         const T* const CYc = (k & 1) ? CY1 : CY0;
         T* const CXn = (kn & 1) ? CX1 : CX0;
         T* const CYn = (kn & 1) ? CY1 : CY0;
-        const int64_t g1 = (int64_t)kn * sp + pos;
+        const int64_t g1 = pl_of(kn) + pos;
         const V po_c = valid ? vload(POc + (pos - obase)) : z0;    // p_{l-2}, plane k+1
         const V po_m = valid ? vload(POn + (pos - obase)) : z0;    // p_{l-2}, plane k
 
         V& po_n = cur.po_n; V& r_o = cur.r_o; V& d_n = cur.d_n; V& x_n = cur.x_n;
         V& cx_n = cur.cx_n; V& cy_n = cur.cy_n; V& cz_n = cur.cz_n;
-        T& cxm_n = cur.cxm_n; T (&cym_n)[W] = cur.cym_n;
+        T& cxm_n = cur.cxm_n; T (&cym_n)[W] = cur.cym_n; const T cxw_n = cur.cxw_n;
         V& hpo_n = cur.hpo_n; V& h_r = cur.h_r; V& h_d = cur.h_d; V& h_cx = cur.h_cx; V& h_cy = cur.h_cy;
-        V& h_cz = cur.h_cz; T& h_cxm = cur.h_cxm; T (&h_cym)[W] = cur.h_cym;
+        V& h_cz = cur.h_cz; T& h_cxm = cur.h_cxm; T (&h_cym)[W] = cur.h_cym; const T h_cxw = cur.h_cxw;
         const V& o_po = cur.o_po;
         // ---- q_{l-1}, r_{l-1}, p_{l-1} (and x) on plane k+1, own positions
         V pn_n = z0, rn_n = z0;
         if (valid && v1) {
             const int64_t l = pos - obase;
             const T left = POc[l - 1], right = POc[l + W];
+            const T wl_v = PER ? POc[l + kl + nx - 1] : T(0);
+            const T wr_v = PER ? POc[l + kr - (nx - 1)] : T(0);
+            const int bk = PER ? opaque(brk) : -1;
 #pragma unroll
             for (int u = 0; u < W; ++u) {
-                const T pr = (u == W - 1) ? right : vget(po_c, u + 1);
-                const T pl = (u == 0) ? left : vget(po_c, u - 1);
-                const T cl = (u == 0) ? cxm_n : vget(cx_n, u - 1);
+                const bool ul = PER && u == bk, ur = PER && u + 1 == bk;
+                const T pr = ur ? wr_v : (u == W - 1) ? right : vget(po_c, u + 1);
+                const T pl = ul ? wl_v : (u == 0) ? left : vget(po_c, u - 1);
+                const T cl = ul ? cxw_n : (u == 0) ? cxm_n : vget(cx_n, u - 1);
                 const T qo = apply_point(vget(d_n, u), vget(po_c, u), vget(cx_n, u), pr, cl, pl, vget(cy_n, u),
                                          POc[l + u + nx], cym_n[u], POc[l + u - nx], vget(cz_n, u), vget(po_n, u),
                                          vget(cz_c, u), vget(po_m, u));
@@ -976,6 +1136,15 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
                 sstore<NT>(rnew + g1, rn_n);
                 sstore<NT>(pnew + g1, pn_n);
                 if (xu) sstore<NT>(a.x + g1, x_n);
+                if constexpr (PER) {
+                    const int64_t pk = g1 - pos;
+#pragma unroll
+                    for (int u = 0; u < W; ++u)
+                        if (gd[u] >= 0) {
+                            rnew[pk + gd[u]] = vget(rn_n, u);
+                            pnew[pk + gd[u]] = vget(pn_n, u);
+                        }
+                }
             }
         }
         // ---- the same on the inner ring (LDS only; needed on owned planes)
@@ -986,11 +1155,15 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
                 const V hpo_m = vload(POn + (hp - obase));
                 const int64_t l = hp - obase;
                 const T left = POc[l - 1], right = POc[l + W];
+                const T wl_v = PER ? POc[l + hkl + nx - 1] : T(0);
+                const T wr_v = PER ? POc[l + hkr - (nx - 1)] : T(0);
+                const int bk = PER ? opaque(hbrk) : -1;
 #pragma unroll
                 for (int u = 0; u < W; ++u) {
-                    const T pr = (u == W - 1) ? right : vget(hpo_c, u + 1);
-                    const T pl = (u == 0) ? left : vget(hpo_c, u - 1);
-                    const T cl = (u == 0) ? h_cxm : vget(h_cx, u - 1);
+                    const bool ul = PER && u == bk, ur = PER && u + 1 == bk;
+                    const T pr = ur ? wr_v : (u == W - 1) ? right : vget(hpo_c, u + 1);
+                    const T pl = ul ? wl_v : (u == 0) ? left : vget(hpo_c, u - 1);
+                    const T cl = ul ? h_cxw : (u == 0) ? h_cxm : vget(h_cx, u - 1);
                     const T qo = apply_point(vget(h_d, u), vget(hpo_c, u), vget(h_cx, u), pr, cl, pl, vget(h_cy, u),
                                              POc[l + u + nx], h_cym[u], POc[l + u - nx], vget(h_cz, u),
                                              vget(hpo_n, u), vget(hcz_c, u), vget(hpo_m, u));
@@ -1003,20 +1176,27 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
         // ---- q_l = A p_{l-1} on plane k and the partial sums
         // p_{l-1} of plane k (own): the z-neighbour of the next step's q_l
         // (its LDS slot was written at step k-1; zero below the grid)
-        const V pn_c = (valid && k >= k0 - 1 && k >= 0) ? vload(PNc + (pos - nbase)) : z0;
+        const V pn_c = (valid && k >= k0 - 1 && (PER || k >= 0)) ? vload(PNc + (pos - nbase)) : z0;
         if (k >= k0 && valid) {
             const int64_t l = pos - nbase;
             const V cxv = vload(CXc + l), cyv = vload(CYc + l);
             const T left = PNc[l - 1], right = PNc[l + W];
+            const T wl_v = PER ? PNc[l + kl + nx - 1] : T(0);
+            const T wl_c = PER ? CXc[l + kl + nx - 1] : T(0);
+            const T wr_v = PER ? PNc[l + kr - (nx - 1)] : T(0);
+            const int bk = PER ? opaque(brk) : -1;
+            const int nvk = PER ? opaque(nv) : W;
 #pragma unroll
             for (int u = 0; u < W; ++u) {
+                const bool ul = PER && u == bk, ur = PER && u + 1 == bk;
                 const T p = vget(pn_c, u);
-                const T pr = (u == W - 1) ? right : vget(pn_c, u + 1);
-                const T pl = (u == 0) ? left : vget(pn_c, u - 1);
-                const T cl = (u == 0) ? CXc[l - 1] : vget(cxv, u - 1);
+                const T pr = ur ? wr_v : (u == W - 1) ? right : vget(pn_c, u + 1);
+                const T pl = ul ? wl_v : (u == 0) ? left : vget(pn_c, u - 1);
+                const T cl = ul ? wl_c : (u == 0) ? CXc[l - 1] : vget(cxv, u - 1);
                 const T qq = apply_point(vget(d_c, u), p, vget(cxv, u), pr, cl, pl, vget(cyv, u), PNc[l + u + nx],
                                          CYc[l + u - nx], PNc[l + u - nx], vget(cz_c, u), vget(pn_n, u), vget(cz_m, u),
                                          vget(pn_m, u));
+                if (u >= nvk) continue;   // a ghost position past the last owned node
                 const T iv = jacobi_inv(vget(d_c, u));
                 const double pd = (double)p, qd = (double)qq, rd = (double)vget(rn_c, u);
                 const double zd = (double)(vget(rn_c, u) * iv), wd = (double)(qq * iv);
@@ -1099,6 +1279,9 @@ template <bool NT>
 __device__ __forceinline__ void bstore4(Rsrc r, uint32_t off, const float4& v) {
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, (int)off, 0, NT ? 2 : 0);
 }
+__device__ __forceinline__ void bstore1(Rsrc r, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, 0);
+}
 __device__ __forceinline__ float4 lds4(const float* p) { return *reinterpret_cast<const float4*>(p); }
 __device__ __forceinline__ void lds4(float* p, const float4& v) { *reinterpret_cast<float4*>(p) = v; }
 
@@ -1112,7 +1295,7 @@ __device__ __forceinline__ void lds4(float* p, const float4& v) { *reinterpret_c
 //
 // Threads past the segment's end work on a copy of the last group (their
 // loads stay in bounds) and store nothing and add nothing to the sums.
-template <int BS, bool NT>
+template <int BS, bool NT, bool PER>
 __device__ void pass_tile_coded(const KArgs<float>& a, int tile, int o, int n, float alpha, float beta, float* lds,
                                 const float* tv, double (&acc)[NPART]) {
 #pragma clang fp contract(off)
@@ -1164,6 +1347,33 @@ __device__ void pass_tile_coded(const KArgs<float>& a, int tile, int o, int n, f
 #pragma unroll
     for (int u = 0; u < W; ++u) ohym[u] = off(hp + u - nx);
     const uint32_t oop = off(op);
+    // periodic (ghost-row layout; see wrap_plane): wrapped planes, the
+    // x-wrap elements and their coupling words, the ghost copies of the
+    // owned nodes of the first and last two rows, and the owned elements of
+    // the last group (nv) that enter the sums
+    auto prs = [&](const void* base, int k) { return plane_rsrc(base, wrap_plane<PER>(k, nz), nz, sp); };
+    const int nv = valid ? (int)min((int64_t)W, a.oend - pos) : 0;
+    const int brk = PER ? x_break<W>(a, posc) : -1;
+    const int hbrk = PER && h_in ? x_break<W>(a, hp) : -1;
+    // the elements whose neighbour across a row end is read (any element when
+    // there is none: the value read is then unused)
+    const int kl = min(max(brk, 0), W - 1), kr = min(max(brk - 1, 0), W - 1);
+    const int hkl = min(max(hbrk, 0), W - 1), hkr = min(max(hbrk - 1, 0), W - 1);
+    const uint32_t oxw = PER ? off(posc + kl + nx - 1) : kOutOfPlane;
+    const uint32_t ohxw = (hbrk >= 0 && hbrk < W) ? off(hp + hkl + nx - 1) : kOutOfPlane;
+    uint32_t ogh[W];
+    bool has_g = false;
+    {
+        int64_t gd[W];
+#pragma unroll
+        for (int u = 0; u < W; ++u) gd[u] = -1;
+        if constexpr (PER) ghost_of<W>(a, pos, nv, gd);
+#pragma unroll
+        for (int u = 0; u < W; ++u) {
+            ogh[u] = gd[u] >= 0 ? off(gd[u]) : kOutOfPlane;
+            has_g = has_g || gd[u] >= 0;
+        }
+    }
     const int lo = (int)(posc - obase), ln = (int)(posc - nbase);
     const int lho = (int)(hp - obase), lhn = (int)(hp - nbase), loo = (int)(op - obase);
 
@@ -1174,8 +1384,8 @@ __device__ void pass_tile_coded(const KArgs<float>& a, int tile, int o, int n, f
     V cz_c, hcz_c;
     {
         const int km = k0 - 2, kc = k0 - 1;
-        const Rsrc pm = plane_rsrc(pold, km, nz, sp), pc = plane_rsrc(pold, kc, nz, sp);
-        const Rsrc wm = plane_rsrc(CW, km, nz, sp);
+        const Rsrc pm = prs(pold, km), pc = prs(pold, kc);
+        const Rsrc wm = prs(CW, km);
         const V po_m = bload4<false>(pm, oo), po_c = bload4<false>(pc, oo);
         const u32x4 w = bload4w<false>(wm, oo);
 #pragma unroll
@@ -1204,25 +1414,26 @@ __device__ void pass_tile_coded(const KArgs<float>& a, int tile, int o, int n, f
     struct Ld {
         V po, r, x;
         u32x4 w;
-        uint32_t wxm, wym[W];
+        uint32_t wxm, wym[W], wxw;
         V hpo, hr;
         u32x4 hw;
-        uint32_t hwxm, hwym[W];
+        uint32_t hwxm, hwym[W], hwxw;
         V opo;
     };
     auto issue = [&](int k, Ld& L) {
         const int kn = k + 1, kf = k + 2;
         const bool own1 = kn >= k0 && kn < k1;
-        const Rsrc pf = plane_rsrc(pold, kf, nz, sp);
-        const Rsrc rn = plane_rsrc(rold, kn, nz, sp);
-        const Rsrc wn = plane_rsrc(CW, kn, nz, sp);
+        const Rsrc pf = prs(pold, kf);
+        const Rsrc rn = prs(rold, kn);
+        const Rsrc wn = prs(CW, kn);
         L.po = bload4<NT>(pf, oo);
         L.r = bload4<NT>(rn, oo);
-        if (own1 && do_x) L.x = bload4<NT>(plane_rsrc(a.x, kn, nz, sp), oo);
+        if (own1 && do_x) L.x = bload4<NT>(prs(a.x, kn), oo);
         L.w = bload4w<NT>(wn, oo);
         L.wxm = bload1(wn, oxm);
 #pragma unroll
         for (int u = 0; u < W; ++u) L.wym[u] = bload1(wn, oym[u]);
+        if constexpr (PER) L.wxw = bload1(wn, oxw);
         if (is_h) {
             L.hpo = bload4<false>(pf, oh);
             L.hw = bload4w<false>(wn, oh);
@@ -1231,6 +1442,7 @@ __device__ void pass_tile_coded(const KArgs<float>& a, int tile, int o, int n, f
                 L.hwxm = bload1(wn, ohxm);
 #pragma unroll
                 for (int u = 0; u < W; ++u) L.hwym[u] = bload1(wn, ohym[u]);
+                if constexpr (PER) L.hwxw = bload1(wn, ohxw);
             }
         }
         if (is_o) L.opo = bload4<false>(pf, oop);
@@ -1244,7 +1456,7 @@ __device__ void pass_tile_coded(const KArgs<float>& a, int tile, int o, int n, f
 
     for (int k = k0 - 2; k < k1; ++k) {
         const int kn = k + 1, kf = k + 2;
-        const bool v1 = kn >= 0 && kn < nz;
+        const bool v1 = PER || (kn >= 0 && kn < nz);
         const bool own1 = kn >= k0 && kn < k1;   // plane k+1 belongs to this tile
         const bool xu = own1 && do_x;
         float* const POc = (kn & 1) ? PO1 : PO0;
@@ -1271,6 +1483,7 @@ __device__ void pass_tile_coded(const KArgs<float>& a, int tile, int o, int n, f
             cym_n[u] = val(cur.wym[u], 1);
         }
         const float cxm_n = val(cur.wxm, 0);
+        const float cxw_n = PER ? val(cur.wxw, 0) : 0.0f;
 
         // ---- q_{l-1}, r_{l-1}, p_{l-1} (and x) on plane k+1, own positions
         const V po_c = lds4(POc + lo);    // p_{l-2}, plane k+1
@@ -1278,11 +1491,15 @@ __device__ void pass_tile_coded(const KArgs<float>& a, int tile, int o, int n, f
         V pn_n = z0, rn_n = z0, xv = cur.x;
         if (v1) {
             const float left = POc[lo - 1], right = POc[lo + W];
+            const float wl_v = PER ? POc[lo + kl + nx - 1] : 0.0f;
+            const float wr_v = PER ? POc[lo + kr - (nx - 1)] : 0.0f;
+            const int bk = PER ? opaque(brk) : -1;
 #pragma unroll
             for (int u = 0; u < W; ++u) {
-                const float pr = (u == W - 1) ? right : vget(po_c, u + 1);
-                const float pl = (u == 0) ? left : vget(po_c, u - 1);
-                const float cl = (u == 0) ? cxm_n : vget(cx_n, u - 1);
+                const bool ul = PER && u == bk, ur = PER && u + 1 == bk;
+                const float pr = ur ? wr_v : (u == W - 1) ? right : vget(po_c, u + 1);
+                const float pl = ul ? wl_v : (u == 0) ? left : vget(po_c, u - 1);
+                const float cl = ul ? cxw_n : (u == 0) ? cxm_n : vget(cx_n, u - 1);
                 const float qo = apply_point(vget(d_n, u), vget(po_c, u), vget(cx_n, u), pr, cl, pl, vget(cy_n, u),
                                              POc[lo + u + nx], cym_n[u], POc[lo + u - nx], vget(cz_n, u),
                                              vget(cur.po, u), vget(cz_c, u), vget(po_m, u));
@@ -1310,12 +1527,17 @@ __device__ void pass_tile_coded(const KArgs<float>& a, int tile, int o, int n, f
                     const V hpo_m = lds4(POn + lho);
                     const float left = POc[lho - 1], right = POc[lho + W];
                     const float h_cxm = val(cur.hwxm, 0);
+                    const float h_cxw = PER ? val(cur.hwxw, 0) : 0.0f;
+                    const float wl_v = PER ? POc[lho + hkl + nx - 1] : 0.0f;
+                    const float wr_v = PER ? POc[lho + hkr - (nx - 1)] : 0.0f;
+                    const int bk = PER ? opaque(hbrk) : -1;
 #pragma unroll
                     for (int u = 0; u < W; ++u) {
                         const uint32_t c = cur.hw[u];
-                        const float pr = (u == W - 1) ? right : vget(hpo_c, u + 1);
-                        const float pl = (u == 0) ? left : vget(hpo_c, u - 1);
-                        const float cl = (u == 0) ? h_cxm : vget(h_cx, u - 1);
+                        const bool ul = PER && u == bk, ur = PER && u + 1 == bk;
+                        const float pr = ur ? wr_v : (u == W - 1) ? right : vget(hpo_c, u + 1);
+                        const float pl = ul ? wl_v : (u == 0) ? left : vget(hpo_c, u - 1);
+                        const float cl = ul ? h_cxw : (u == 0) ? h_cxm : vget(h_cx, u - 1);
                         const float qo = apply_point(val(c, 3), vget(hpo_c, u), vget(h_cx, u), pr, cl, pl,
                                                      vget(h_cy, u), POc[lho + u + nx], val(cur.hwym[u], 1),
                                                      POc[lho + u - nx], vget(h_cz, u), vget(cur.hpo, u),
@@ -1346,26 +1568,40 @@ __device__ void pass_tile_coded(const KArgs<float>& a, int tile, int o, int n, f
         // wait for the store too), then the loads of the next step, which
         // land while q_l and the sums below are computed
         if (valid && v1 && own1) {
-            bstore4<NT>(plane_rsrc(rnew, kn, nz, sp), oo, rn_n);
-            bstore4<NT>(plane_rsrc(pnew, kn, nz, sp), oo, pn_n);
-            if (xu) bstore4<NT>(plane_rsrc(a.x, kn, nz, sp), oo, xv);
+            bstore4<NT>(prs(rnew, kn), oo, rn_n);
+            bstore4<NT>(prs(pnew, kn), oo, pn_n);
+            if (xu) bstore4<NT>(prs(a.x, kn), oo, xv);
+            if (PER && has_g) {
+                const Rsrc gr = prs(rnew, kn), gp = prs(pnew, kn);
+#pragma unroll
+                for (int u = 0; u < W; ++u) {
+                    bstore1(gr, ogh[u], vget(rn_n, u));
+                    bstore1(gp, ogh[u], vget(pn_n, u));
+                }
+            }
         }
         if (k + 1 < k1) issue(k + 1, cur);
         // ---- q_l = A p_{l-1} on plane k and the partial sums
-        const V pn_c = (k >= 0) ? lds4(PNc + ln) : z0;   // p_{l-1}, plane k (zero below the grid)
+        const V pn_c = (PER || k >= 0) ? lds4(PNc + ln) : z0;   // p_{l-1}, plane k (zero below the grid)
         if (k >= k0) {
             const V cxv = lds4(CXc + ln), cyv = lds4(CYc + ln);
             const float left = PNc[ln - 1], right = PNc[ln + W];
+            const float wl_v = PER ? PNc[ln + kl + nx - 1] : 0.0f;
+            const float wl_c = PER ? CXc[ln + kl + nx - 1] : 0.0f;
+            const float wr_v = PER ? PNc[ln + kr - (nx - 1)] : 0.0f;
+            const int bk = PER ? opaque(brk) : -1;
+            const int nvk = PER ? opaque(nv) : W;
 #pragma unroll
             for (int u = 0; u < W; ++u) {
+                const bool ul = PER && u == bk, ur = PER && u + 1 == bk;
                 const float p = vget(pn_c, u);
-                const float pr = (u == W - 1) ? right : vget(pn_c, u + 1);
-                const float pl = (u == 0) ? left : vget(pn_c, u - 1);
-                const float cl = (u == 0) ? CXc[ln - 1] : vget(cxv, u - 1);
+                const float pr = ur ? wr_v : (u == W - 1) ? right : vget(pn_c, u + 1);
+                const float pl = ul ? wl_v : (u == 0) ? left : vget(pn_c, u - 1);
+                const float cl = ul ? wl_c : (u == 0) ? CXc[ln - 1] : vget(cxv, u - 1);
                 const float qq = apply_point(vget(d_c, u), p, vget(cxv, u), pr, cl, pl, vget(cyv, u),
                                              PNc[ln + u + nx], CYc[ln + u - nx], PNc[ln + u - nx], vget(cz_c, u),
                                              vget(pn_n, u), vget(cz_m, u), vget(pn_m, u));
-                if (valid) {
+                if (valid && u < nvk) {
                     const float iv = vget(iv_c, u);
                     const double pd = (double)p, qd = (double)qq, rd = (double)vget(rn_c, u);
                     const double zd = (double)(vget(rn_c, u) * iv), wd = (double)(qq * iv);
@@ -1432,7 +1668,6 @@ struct Scal {
 template <typename T, int BS, int MC, int SCH, bool PER, bool NT, bool CD, bool RT = false>
 __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsigned char* lds_raw) {
     static_assert(SCH == 0 || MC == 1, "the 40-byte pass takes one vector group per thread");
-    static_assert(!PER || SCH == 0, "the periodic boundary uses the pass that stores A.p");
     static_assert(!CD || SCH == 1, "coded coefficients are read by the 40-byte pass");
     const int lds_len = a.seglen + 2 * a.halo;
     T* lds0 = reinterpret_cast<T*>(lds_raw);
@@ -1468,7 +1703,7 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
         // ---- initial residual
         for (int t = first; t < end; t += stride) {
             double acc[2] = {0.0, 0.0};
-            init_tile<T, BS, PER>(a, t, SCH == 0, acc);
+            init_tile<T, BS, PER, PER && SCH == 1>(a, t, SCH == 0, acc);
             tile_reduce_store<BS, 2>(acc, red, sums(b) + (size_t)t * kMaxPartials);
         }
         double v[2];
@@ -1509,10 +1744,10 @@ __device__ void run_problem(const KArgs<T>& a, int w, int G, bool xcd_map, unsig
             if constexpr (SCH == 1)
             {
                 if constexpr (CD) {
-                    if (use_codes) pass_tile_coded<BS, NT>(a, t, o, n, alpha, beta, lds0, dict, acc);
-                    else pass_tile40<T, BS, NT>(a, t, o, n, alpha, beta, lds0, acc);
+                    if (use_codes) pass_tile_coded<BS, NT, PER>(a, t, o, n, alpha, beta, lds0, dict, acc);
+                    else pass_tile40<T, BS, NT, PER>(a, t, o, n, alpha, beta, lds0, acc);
                 } else {
-                    pass_tile40<T, BS, NT>(a, t, o, n, alpha, beta, lds0, acc);
+                    pass_tile40<T, BS, NT, PER>(a, t, o, n, alpha, beta, lds0, acc);
                 }
             }
             else
@@ -1633,6 +1868,10 @@ std::vector<Variant> coded_variants<float>() {
         {512, 1, 1, 0, 0, (KernelFn)k_jpcg_fused<float, 512, 1, 1, false, false, true>, 1},
         {256, 1, 1, 0, 1, (KernelFn)k_jpcg_fused<float, 256, 1, 1, false, true, true>, 1},
         {512, 1, 1, 0, 1, (KernelFn)k_jpcg_fused<float, 512, 1, 1, false, true, true>, 1},
+        {256, 1, 1, 1, 0, (KernelFn)k_jpcg_fused<float, 256, 1, 1, true, false, true>, 1},
+        {512, 1, 1, 1, 0, (KernelFn)k_jpcg_fused<float, 512, 1, 1, true, false, true>, 1},
+        {256, 1, 1, 1, 1, (KernelFn)k_jpcg_fused<float, 256, 1, 1, true, true, true>, 1},
+        {512, 1, 1, 1, 1, (KernelFn)k_jpcg_fused<float, 512, 1, 1, true, true, true>, 1},
     };
 }
 
@@ -1655,6 +1894,11 @@ std::vector<Variant> base_variants() {
         {512, 1, 1, 0, 1, (KernelFn)k_jpcg_fused<T, 512, 1, 1, false, true>},
         {256, 1, 0, 1, 1, (KernelFn)k_jpcg_fused<T, 256, 1, 0, true, true>},
         {512, 1, 0, 1, 1, (KernelFn)k_jpcg_fused<T, 512, 1, 0, true, true>},
+        // periodic boundary, 40-byte pass (ghost-row layout)
+        {256, 1, 1, 1, 0, (KernelFn)k_jpcg_fused<T, 256, 1, 1, true, false>},
+        {512, 1, 1, 1, 0, (KernelFn)k_jpcg_fused<T, 512, 1, 1, true, false>},
+        {256, 1, 1, 1, 1, (KernelFn)k_jpcg_fused<T, 256, 1, 1, true, true>},
+        {512, 1, 1, 1, 1, (KernelFn)k_jpcg_fused<T, 512, 1, 1, true, true>},
     };
 }
 
@@ -1777,7 +2021,11 @@ Tiling choose_tiling_impl(const Layout& L, int want_bs, int want_mc, int max_per
         if ((want_bs > 0 && v.bs != want_bs) || (want_mc > 0 && v.mc != want_mc)) continue;
         if (want_scheme >= 0 && v.scheme != want_scheme) continue;
         if (v.per != want_per || v.nt != want_nt || v.cd) continue;
-        Tiling t = tiling_for<T>(L, v, cus, max_per_cu, extra);
+        // the periodic 40-byte pass tiles the owned range of the ghost-row layout
+        if (v.per && v.scheme == 1 && !ghost_layout_ok(L)) continue;
+        Layout Lt = L;
+        if (v.per && v.scheme == 1) Lt.sp = ghost_layout(L).own;
+        Tiling t = tiling_for<T>(Lt, v, cus, max_per_cu, extra);
         if (t.grid <= 0) continue;
         // model: bytes of one tile (planes incl. the extra ones below, segment
         // incl. halo work) times the tiles that share a CU, plus a
@@ -1851,9 +2099,44 @@ template std::vector<Tiling> tiling_candidates<double>(const Layout&);
 template Tiling choose_tiling<float>(const Layout&);
 template Tiling choose_tiling<double>(const Layout&);
 
+namespace {
+std::atomic<int> g_periodic_pass{-1};
+}
+void set_periodic_pass(int form) { g_periodic_pass.store(form); }
+int periodic_pass() { return g_periodic_pass.load(); }
+
 template <typename T>
 Tiling solve_tiling(const Layout& L, int periodic) {
-    return periodic ? choose_tiling_impl<T>(L, 0, 0, 0, 0, 1) : choose_tiling<T>(L);
+    if (!periodic) return choose_tiling<T>(L);
+    const int form = periodic_pass();
+    if (form != 0 && ghost_layout_ok(L)) {
+        // a 40-byte tiling recorded for this shape (autotuner, pb_set_tuning)
+        // carries over to the periodic pass: the same block size, access
+        // kind, workgroups per CU, segment count and z-chunk on the owned
+        // range of the ghost-row layout
+        Tiling rec{};
+        bool have = false;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tuned.find(tune_key<T>(L));
+            if (it != g_tuned.end()) {
+                rec = it->second;
+                have = true;
+            }
+        }
+        if (have && rec.scheme == 1 && rec.grid > 0) {
+            const DevInfo di = dev_info();
+            const int cus = di.cus > 0 ? di.cus : 256;
+            const int per_cu = (rec.grid + cus - 1) / cus;
+            for (int extra = 0; extra <= kMaxExtraSegments; ++extra) {
+                const Tiling t = choose_tiling_impl<T>(L, rec.bs, rec.mc, per_cu, 1, 1, rec.nt, extra);
+                if (t.grid > 0 && t.nseg == rec.nseg && t.zchunk == rec.zchunk) return t;
+            }
+        }
+    }
+    Tiling t = choose_tiling_impl<T>(L, 0, 0, 0, form, 1);
+    if (t.grid <= 0 && form >= 0) t = choose_tiling_impl<T>(L, 0, 0, 0, -1, 1);
+    return t;
 }
 template Tiling solve_tiling<float>(const Layout&, int);
 template Tiling solve_tiling<double>(const Layout&, int);
@@ -1872,6 +2155,61 @@ Tiling tiling_with(const Layout& L, int bs, int mc, int max_per_cu) {
 template Tiling tiling_with<float>(const Layout&, int, int, int);
 template Tiling tiling_with<double>(const Layout&, int, int, int);
 
+namespace {
+
+// Into the ghost-row layout (ghost_layout): position q of plane k holds the
+// node of row (q - org) / nx modulo ny of the plain layout's plane k (rows -2,
+// -1 and ny, ny+1 are the ghost copies), or no node (zero couplings, unit
+// diagonal, zero vectors). The operator is copied when gcx is given; the
+// iteration vectors start at zero.
+template <typename T>
+__global__ void k_ghost_in(const T* __restrict__ cx, const T* __restrict__ cy, const T* __restrict__ cz,
+                           const T* __restrict__ d, T* __restrict__ gcx, T* __restrict__ gcy, T* __restrict__ gcz,
+                           T* __restrict__ gd, const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ gb,
+                           T* __restrict__ gx, T* __restrict__ gr, T* __restrict__ gr2, T* __restrict__ gp0,
+                           T* __restrict__ gp1, int nx, int ny, int64_t sp, int64_t org, int64_t gsp, int64_t gnpad) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < gnpad;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = t / gsp, q = t - k * gsp;
+        const int64_t rel = q - (org - 2 * (int64_t)nx);
+        const bool in = rel >= 0 && rel < (int64_t)(ny + 4) * nx;
+        int64_t src = 0;
+        bool node = false;
+        if (in) {
+            const int64_t j = rel / nx - 2, i = rel % nx;
+            node = j >= 0 && j < ny;
+            src = k * sp + ((j + ny) % ny) * nx + i;
+        }
+        if (gcx) {
+            gcx[t] = in ? cx[src] : T(0);
+            gcy[t] = in ? cy[src] : T(0);
+            gcz[t] = in ? cz[src] : T(0);
+            gd[t] = in ? d[src] : T(1);
+        }
+        gb[t] = node ? b[src] : T(0);
+        gx[t] = node ? x[src] : T(0);
+        gr[t] = T(0);
+        gr2[t] = T(0);
+        gp0[t] = T(0);
+        gp1[t] = T(0);
+    }
+}
+
+// Back to the plain layout: x at the nodes, zero in the pad slots.
+template <typename T>
+__global__ void k_ghost_out(const T* __restrict__ gx, T* __restrict__ x, int64_t plane, int64_t sp, int64_t npad,
+                            int64_t org, int64_t gsp) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npad;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = t / sp, q = t - k * sp;
+        x[t] = q < plane ? gx[k * gsp + org + q] : T(0);
+    }
+}
+
+unsigned copy_grid(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 8192); }
+
+}  // namespace
+
 template <typename T>
 pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, double* partials, double tol,
                      int maxiter, hipStream_t st, SolveResult* res, const Tiling* force, int periodic) {
@@ -1879,6 +2217,25 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
     if (t.grid <= 0) {
         set_error("fused JPCG: no feasible tiling for this grid (nx too large for the in-plane halo)");
         return PB_ERR_ARG;
+    }
+    // the periodic 40-byte pass runs on ghost-row copies of the operator and
+    // the state (the operator's copy is kept while the code words built from
+    // it are valid)
+    const bool gl = t.per && t.scheme == 1;
+    GhostLayout G{};
+    if (gl) {
+        if (!s.gop.cx || !s.gop.cy || !s.gop.cz || !s.gop.d || !s.gb || !s.gx || !s.gr || !s.gr2 || !s.gp0 ||
+            !s.gp1) {
+            set_error("fused JPCG: the periodic 40-byte pass needs the ghost-row arrays of the workspace");
+            return PB_ERR_ARG;
+        }
+        G = ghost_layout(L);
+        const bool with_op = !s.codes_valid;
+        hipLaunchKernelGGL(k_ghost_in<T>, dim3(copy_grid(G.npad)), dim3(256), 0, st, s.op.cx, s.op.cy, s.op.cz,
+                           s.op.d, with_op ? (T*)s.gop.cx : nullptr, (T*)s.gop.cy, (T*)s.gop.cz, (T*)s.gop.d, s.b,
+                           (const T*)s.x, s.gb, s.gx, s.gr, s.gr2, s.gp0, s.gp1, L.nx, L.ny, L.sp, G.org, G.sp,
+                           G.npad);
+        PB_HIP(hipGetLastError());
     }
     KernelFn fn = nullptr;
     for (const auto& v : variants<T>())
@@ -1900,24 +2257,26 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
     const float* ctab = nullptr;
     int coded = 0;
     if constexpr (sizeof(T) == 4) {
-        if (t.scheme == 1 && !t.per && coded_coefficients() && s.q && s.q2 &&
-            coded_layout_ok(L)) {
+        if (t.scheme == 1 && coded_coefficients() && s.q && (gl ? s.gcodes != nullptr : s.q2 != nullptr) &&
+            coded_layout_ok(L) && (!gl || G.sp < ((int64_t)1 << 29))) {
             KernelFn cfn = nullptr;
             for (const auto& v : variants<T>())
-                if (v.cd && v.bs == t.bs && v.mc == t.mc && v.nt == t.nt) cfn = v.fn;
+                if (v.cd && v.bs == t.bs && v.mc == t.mc && v.per == t.per && v.nt == t.nt) cfn = v.fn;
             const size_t clds = t.lds + kCodedLdsBytes;
             const int cus = di.cus > 0 ? di.cus : 256;
             if (cfn && (int64_t)max_coresident(cfn, t.bs, clds) * cus >= t.grid) {
                 bool fits = s.codes_valid != 0;
                 const float* tab = s.ctab;
+                uint32_t* words = gl ? s.gcodes : (uint32_t*)s.q2;
                 if (!fits) {
-                    const pb_status e = build_codes(s.op, L.npad, (void*)s.q, (uint32_t*)s.q2, st, fits, &tab);
+                    const pb_status e = gl ? build_codes(s.gop, G.npad, (void*)s.q, words, st, fits, &tab)
+                                           : build_codes(s.op, L.npad, (void*)s.q, words, st, fits, &tab);
                     if (e != PB_OK) return e;
                 }
                 if (fits) {
                     fn = cfn;
                     lds = clds;
-                    cw = (const float*)s.q2;
+                    cw = (const float*)words;
                     ctab = tab;
                     coded = 1;
                 }
@@ -1936,6 +2295,22 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
     a.p[1] = s.p1;
     a.nx = L.nx; a.ny = L.ny; a.nz = L.nz;
     a.sp = L.sp;
+    a.org = 0;
+    a.own = L.sp;
+    a.oend = L.sp;
+    if (gl) {
+        a.op = s.gop;
+        a.b = s.gb;
+        a.x = s.gx;
+        a.r[0] = s.gr;
+        a.r[1] = s.gr2;
+        a.p[0] = s.gp0;
+        a.p[1] = s.gp1;
+        a.sp = G.sp;
+        a.org = G.org;
+        a.own = G.own;
+        a.oend = G.org + L.plane;
+    }
     a.seglen = t.seglen; a.zchunk = t.zchunk; a.nseg = t.nseg; a.nzc = t.nzc; a.ntiles = t.ntiles;
     a.halo = t.halo;
     a.tol = tol;
@@ -1966,9 +2341,14 @@ pb_status fused_jpcg(const Layout& L, const SolveBufs<T>& s, SyncState* sync, do
                   t.grid, t.bs, lds, coded);
         return PB_ERR_HIP;
     }
+    if (timed) PB_HIP(hipEventRecord(ev[1], st));
+    if (gl) {
+        hipLaunchKernelGGL(k_ghost_out<T>, dim3(copy_grid(L.npad)), dim3(256), 0, st, (const T*)s.gx, s.x, L.plane,
+                           L.sp, L.npad, G.org, G.sp);
+        PB_HIP(hipGetLastError());
+    }
     if (res) {
         SyncState h;
-        if (timed) PB_HIP(hipEventRecord(ev[1], st));
         PB_HIP(hipMemcpyAsync(&h, sync, sizeof(SyncState), hipMemcpyDeviceToHost, st));
         PB_HIP(hipStreamSynchronize(st));
         float ms = 0.0f;
@@ -2083,6 +2463,9 @@ void batch_fill_kargs(void* dst, const Layout& L, const SolveBufs<T>& s, SyncSta
     a.p[0] = s.p0; a.p[1] = s.p1;
     a.nx = L.nx; a.ny = L.ny; a.nz = L.nz;
     a.sp = L.sp;
+    a.org = 0;
+    a.own = L.sp;
+    a.oend = L.sp;
     a.seglen = t.seglen; a.zchunk = t.zchunk; a.nseg = t.nseg; a.nzc = t.nzc; a.ntiles = t.ntiles;
     a.halo = t.halo;
     a.tol = tol;

@@ -25,7 +25,9 @@ bool solv_layout(const pb_grid* g, int64_t natoms, const pb_solve_opts* opts, So
     if (!solv_grid_ok(g) || !opts) return false;
     const size_t nx = g->nx, ny = g->ny, nz = g->nz, n = nx * ny * nz;
     const size_t sw = pb_setup_workspace_bytes(g, natoms);
-    const size_t vw = pb_solve_workspace_bytes(g->nx, g->ny, g->nz, opts);
+    pb_solve_opts so = *opts;
+    so.boundary = g->boundary;   // the solves take the grid's boundary
+    const size_t vw = pb_solve_workspace_bytes(g->nx, g->ny, g->nz, &so);
     const size_t ew = pb_energy_workspace_bytes(natoms);
     if (sw == 0 || vw == 0 || ew == 0) return false;
     size_t off = 0;

@@ -60,10 +60,44 @@ struct SolveBufs {
     T* dia;        // DIA form only: 7 diagonals x npad
     int warm;      // 1: x holds a nonzero initial guess
     // fused FP32 40-byte form: the code words in q2 and the dictionary (ctab,
-    // inside q) were built for this operator by an earlier inner solve
+    // inside q) were built for this operator by an earlier inner solve (with
+    // the periodic boundary: the code words in gcodes, the dictionary in q)
     int codes_valid;
     const float* ctab;
+    // periodic boundary, 40-byte pass: the operator and the state in the
+    // ghost-row layout (ghost_layout); null when the workspace holds none
+    Op<T> gop;
+    T* gb;
+    T* gx;
+    T* gr;
+    T* gr2;
+    T* gp0;
+    T* gp1;
+    uint32_t* gcodes;   // FP32 only
 };
+
+// Ghost-row layout of the periodic 40-byte pass: per plane, two ghost rows
+// (copies of rows ny-2, ny-1), the nx*ny nodes from position org (a multiple
+// of 64 elements), then two ghost rows (copies of rows 0, 1); planes of sp
+// positions (a multiple of 64). Tiles own [org, org + own), own being nx*ny
+// rounded up to 4 (the last group runs into the upper ghost rows).
+struct GhostLayout {
+    int64_t org, own, sp, npad;
+};
+inline GhostLayout ghost_layout(const Layout& L) {
+    GhostLayout g;
+    g.org = (int64_t)align_up((size_t)(2 * L.nx), 64);
+    g.own = (int64_t)align_up((size_t)L.plane, 4);
+    g.sp = (int64_t)align_up((size_t)(g.org + L.plane + 2 * (int64_t)L.nx), 64);
+    g.npad = g.sp * L.nz;
+    return g;
+}
+// Whether the periodic 40-byte pass takes this grid: a group of four
+// consecutive nodes holds at most one row end (nx > 4), the four ghost rows
+// copy four distinct rows, and in-plane positions fit 32-bit arithmetic.
+inline bool ghost_layout_ok(const Layout& L) {
+    return L.nx >= 5 && L.ny >= 4 && L.nz >= 3 && ghost_layout(L).sp + 4 * (int64_t)L.nx < ((int64_t)1 << 31);
+}
 
 struct SolveResult {
     int status;
@@ -121,6 +155,10 @@ constexpr size_t kCodedLdsBytes = 0;
 // Process-wide switch (default on): 0 keeps every fused FP32 solve uncoded.
 void set_coded_coefficients(int on);
 int coded_coefficients();
+// Process-wide pass form of periodic fused solves: -1 the model's choice, 0
+// or 1 that scheme (1 falls back to 0 where the ghost-row layout does not fit).
+void set_periodic_pass(int form);
+int periodic_pass();
 
 // mg.hip: multigrid-preconditioned CG (workspace for the coarse levels and
 // level 0's extra vectors; ex..k2 are the caller's FP64 edge arrays).

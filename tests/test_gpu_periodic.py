@@ -154,3 +154,99 @@ def test_periodic_rejections(pb):
         pb.setup(synth.Grid(2, 5, 5, 0.5, np.zeros(3)), xyz[:1] * 0, rad[:1], q[:1], device=DEV,
                  boundary="periodic")
     assert ei.value.status == pb.PB_ERR_ARG
+
+
+@pytest.mark.parametrize("prec,tol,bar", [("f32", 1e-6, 1e-5), ("f64", 1e-10, 1e-8)])
+def test_periodic_pass_forms(pb, prec, tol, bar):
+    """Both pass forms of the periodic fused solve against the oracle: the
+    pass that stores A.p (form 0) and the 40-byte pass on ghost-row copies
+    (form 1). The grid spans several in-plane segments and z-chunks, and nx*ny
+    is not a multiple of 4 (the last group of a plane runs into the ghost
+    rows). In FP32 the coded and uncoded 40-byte passes agree bit for bit."""
+    g, xyz, rad, q = _box((67, 45, 33), 6, natoms=30)
+    sm = _setup(pb, g, xyz, rad, q, 0.0159051)
+    ref = periodic.assemble(g.nx, g.ny, g.nz, g.h, g.origin, xyz, rad, q, 1.0, 80.0, 0.0159051)
+    exact = periodic.jpcg(ref, 1e-13, maxiter=20000)
+    o = periodic.jpcg(ref, tol)
+    out = {}
+    try:
+        for form in (0, 1):
+            pb.set_periodic_pass(form)
+            out[form] = pb.solve(sm, tol=tol, precision=prec)
+        if prec == "f32":
+            pb.set_coded_coefficients(False)
+            out["uncoded"] = pb.solve(sm, tol=tol, precision=prec)
+    finally:
+        pb.set_periodic_pass(-1)
+        pb.set_coded_coefficients(True)
+    for form, (x, info) in out.items():
+        err = np.abs(x.cpu().numpy() - exact.x).max() / np.abs(exact.x).max()
+        print(f"periodic form {form} {prec}: iters {info['iters']} (oracle {o.iters}) coded {info['coded_launches']} "
+              f"phi err {err:.2e}", flush=True)
+        assert info["status"] == pb.PB_OK and iters_close(info["iters"], o.iters)
+        assert err <= bar
+    if prec == "f32":
+        assert out[1][1]["coded_launches"] == 1 and out["uncoded"][1]["coded_launches"] == 0
+        assert torch.equal(out[1][0], out["uncoded"][0]) and out[1][1]["iters"] == out["uncoded"][1]["iters"]
+
+
+@pytest.mark.parametrize("dims", [(5, 4, 3), (6, 4, 7), (5, 9, 5), (33, 31, 3), (4, 5, 6)])
+def test_periodic_40byte_small_grids(pb, dims):
+    """The 40-byte pass at the smallest grids it takes (nx = 5, ny = 4; nz =
+    3, where the z-neighbours of every plane wrap), FP64 and FP32; nx = 4
+    (one row per vector group) falls back to the pass that stores A.p."""
+    rng = np.random.default_rng(sum(dims) + 100)
+    nx, ny, nz = dims
+    e = rng.choice([1.0, 80.0], size=(nz, ny, nx))
+    ep = np.pad(e, 1, mode="wrap")
+    harm = lambda a, b: 2 * a * b / (a + b)
+    ex = harm(ep[1:-1, 1:-1, :-1], ep[1:-1, 1:-1, 1:])
+    ey = harm(ep[1:-1, :-1, 1:-1], ep[1:-1, 1:, 1:-1])
+    ez = harm(ep[:-1, 1:-1, 1:-1], ep[1:, 1:-1, 1:-1])
+    k2 = np.where(e > 1, 1.27, 0.0)
+    b = rng.standard_normal((nz, ny, nx))
+    from oracle import fdpb
+    ref = fdpb.System(h=0.5, eps_x=ex, eps_y=ey, eps_z=ez, kappa2=k2, b=b)
+    exact = periodic.jpcg(ref, 1e-13, maxiter=50000)
+    g = pb.make_grid(nx, ny, nz, 0.5, (0, 0, 0), "periodic")
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=DEV)
+    sm = pb.System(g, T(ex), T(ey), T(ez), T(k2), T(b))
+    pb.set_periodic_pass(1)
+    try:
+        for prec, tol, bar in (("f64", 1e-10, 1e-8), ("f32", 1e-6, 1e-5)):
+            x, info = pb.solve(sm, tol=tol, precision=prec)
+            err = np.abs(x.cpu().numpy() - exact.x).max() / np.abs(exact.x).max()
+            print(f"periodic 40-byte {dims} {prec}: iters {info['iters']} coded {info['coded_launches']} "
+                  f"err {err:.2e}", flush=True)
+            assert info["status"] == pb.PB_OK and err <= bar, err
+    finally:
+        pb.set_periodic_pass(-1)
+
+
+def test_periodic_257_forms_agree(pb):
+    """The periodic workload the benchmark times (the 257^3 molecule in a
+    periodic box with salt, FP32 to 1e-6): the 40-byte coded pass and the
+    pass that stores A.p need iteration counts within max(2, 2%) of each
+    other, their potentials agree within 1e-5 of max |phi|, and both have an
+    FP64 true residual below 1e-5."""
+    p = synth.config2()
+    g = p.grid
+    sm = pb.setup(g, p.mol.xyz, p.mol.radius, p.mol.charge, p.eps_in, p.eps_out, p.kappa_d2, device=DEV,
+                  boundary="periodic")
+    out = {}
+    try:
+        for form in (1, 0):
+            pb.set_periodic_pass(form)
+            out[form] = pb.solve(sm, tol=1e-6, precision="f32")
+    finally:
+        pb.set_periodic_pass(-1)
+    (x1, i1), (x0, i0) = out[1], out[0]
+    diff = float((x1 - x0).abs().max() / x0.abs().max())
+    print(f"periodic 257: 40-byte iters {i1['iters']} coded {i1['coded_launches']} relres {i1['relres_true']:.2e}; "
+          f"48-byte iters {i0['iters']} relres {i0['relres_true']:.2e}; phi diff {diff:.2e}", flush=True)
+    assert i1["status"] == pb.PB_OK and i0["status"] == pb.PB_OK and i1["coded_launches"] == 1
+    assert iters_close(i1["iters"], i0["iters"])
+    assert i1["relres_true"] <= 1e-5 and i0["relres_true"] <= 1e-5
+    assert diff <= 1e-5
+    del sm, x0, x1
+    torch.cuda.empty_cache()

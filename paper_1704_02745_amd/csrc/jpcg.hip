@@ -990,6 +990,10 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
     else
 #pragma unroll
         for (int u = 0; u < W; ++u) gd[u] = -1;
+    // a group copied whole to consecutive positions takes one 16-byte store
+    bool g_vec = gd[0] >= 0;
+#pragma unroll
+    for (int u = 1; u < W; ++u) g_vec = g_vec && gd[u] == gd[0] + u;
     auto pl_of = [&](int k) { return (int64_t)wrap_plane<PER>(k, nz) * sp; };
 
     // State at the start of step k (k = k0-2 first): p_{l-2} of planes k and
@@ -1138,12 +1142,17 @@ __device__ void pass_tile40(const KArgs<T>& a, int tile, int o, int n, T alpha, 
                 if (xu) sstore<NT>(a.x + g1, x_n);
                 if constexpr (PER) {
                     const int64_t pk = g1 - pos;
+                    if (g_vec) {   // element-aligned only: copied bytewise
+                        __builtin_memcpy(rnew + pk + gd[0], &rn_n, sizeof(V));
+                        __builtin_memcpy(pnew + pk + gd[0], &pn_n, sizeof(V));
+                    } else {
 #pragma unroll
-                    for (int u = 0; u < W; ++u)
-                        if (gd[u] >= 0) {
-                            rnew[pk + gd[u]] = vget(rn_n, u);
-                            pnew[pk + gd[u]] = vget(pn_n, u);
-                        }
+                        for (int u = 0; u < W; ++u)
+                            if (gd[u] >= 0) {
+                                rnew[pk + gd[u]] = vget(rn_n, u);
+                                pnew[pk + gd[u]] = vget(pn_n, u);
+                            }
+                    }
                 }
             }
         }
@@ -1361,17 +1370,22 @@ __device__ void pass_tile_coded(const KArgs<float>& a, int tile, int o, int n, f
     const int hkl = min(max(hbrk, 0), W - 1), hkr = min(max(hbrk - 1, 0), W - 1);
     const uint32_t oxw = PER ? off(posc + kl + nx - 1) : kOutOfPlane;
     const uint32_t ohxw = (hbrk >= 0 && hbrk < W) ? off(hp + hkl + nx - 1) : kOutOfPlane;
+    // ghost copies: one 16-byte store (dword-aligned, which buffer stores
+    // allow) when the whole group is copied to consecutive positions, else one
+    // store per element
     uint32_t ogh[W];
-    bool has_g = false;
+    bool has_g = false, g_vec = false;
     {
         int64_t gd[W];
 #pragma unroll
         for (int u = 0; u < W; ++u) gd[u] = -1;
         if constexpr (PER) ghost_of<W>(a, pos, nv, gd);
+        g_vec = gd[0] >= 0;
 #pragma unroll
         for (int u = 0; u < W; ++u) {
             ogh[u] = gd[u] >= 0 ? off(gd[u]) : kOutOfPlane;
             has_g = has_g || gd[u] >= 0;
+            g_vec = g_vec && gd[u] == gd[0] + u;
         }
     }
     const int lo = (int)(posc - obase), ln = (int)(posc - nbase);
@@ -1573,10 +1587,15 @@ __device__ void pass_tile_coded(const KArgs<float>& a, int tile, int o, int n, f
             if (xu) bstore4<NT>(prs(a.x, kn), oo, xv);
             if (PER && has_g) {
                 const Rsrc gr = prs(rnew, kn), gp = prs(pnew, kn);
+                if (g_vec) {
+                    bstore4<false>(gr, ogh[0], rn_n);
+                    bstore4<false>(gp, ogh[0], pn_n);
+                } else {
 #pragma unroll
-                for (int u = 0; u < W; ++u) {
-                    bstore1(gr, ogh[u], vget(rn_n, u));
-                    bstore1(gp, ogh[u], vget(pn_n, u));
+                    for (int u = 0; u < W; ++u) {
+                        bstore1(gr, ogh[u], vget(rn_n, u));
+                        bstore1(gp, ogh[u], vget(pn_n, u));
+                    }
                 }
             }
         }

@@ -30,11 +30,14 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t v) { return (v * 26544357
 
 // Every value of cx, cy, cz, d (and +0.0) into the hash set, in two levels:
 // each workgroup first collects the distinct values of its range in an LDS
-// set, then merges those few into the device set. Slots only ever go from
-// empty to a value, so a plain read that sees a value is final; a stale empty
-// read is settled by the compare-and-swap. A workgroup that meets more than
-// kMaxCodes distinct values raises the device count past kMaxCodes and stops
-// (the dictionary cannot hold them).
+// set, then merges those few into the device set. Slots are read with
+// relaxed atomic loads (workgroup scope in LDS, agent scope in the device
+// set) and only ever go from empty to a value, so a load that sees a value
+// sees its final one; a load that still sees an empty slot is settled by the
+// compare-and-swap that follows: when another thread filled the slot first,
+// the swap fails and returns that value, which is compared like a load's. A
+// workgroup that meets more than kMaxCodes distinct values raises the device
+// count past kMaxCodes and stops (the dictionary cannot hold them).
 constexpr int kLocalSlots = 1024;
 
 __device__ __forceinline__ bool set_insert(uint32_t* keys, int nslots, uint32_t v, int* count, bool lds) {

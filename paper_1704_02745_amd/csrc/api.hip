@@ -73,10 +73,10 @@ SolveWs carve_solve(void* base, const Layout& L, int prec, int op, int per) {
         s.p1 = (double*)take(n8);
         s.q = (double*)take(n8);
         if (op == PB_OP_DIA) {
-            s.z = (double*)take(n8);
             s.dia = (double*)take(7 * n8);
         } else if (op == PB_OP_MG) {
             s.z = (double*)take(n8);
+            s.r2 = (double*)take(n8);
         } else {
             s.r2 = (double*)take(n8);
             s.q2 = (double*)take(n8);
@@ -107,10 +107,10 @@ SolveWs carve_solve(void* base, const Layout& L, int prec, int op, int per) {
         s.p1 = (float*)take(n4);
         s.q = (float*)take(n4);
         if (op == PB_OP_DIA) {
-            s.z = (float*)take(n4);
             s.dia = (float*)take(7 * n4);
         } else if (op == PB_OP_MG) {
             s.z = (float*)take(n4);
+            s.r2 = (float*)take(n4);
         } else {
             s.r2 = (float*)take(n4);
             s.q2 = (float*)take(n4);

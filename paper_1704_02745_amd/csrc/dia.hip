@@ -1,13 +1,14 @@
 // DIA-format Jacobi PCG: the plain GPU form.
 //
 // The paper's fastest GPU solver stored the 7-band matrix in the diagonal
-// (DIA) format and ran Jacobi-preconditioned CG as a host-driven loop of
-// library calls (section 2.6, Table 1, Fig. 5). This file is the same
-// structure written for gfx950: a 7-diagonal SpMV and separate vector
-// kernels (dot, axpy, preconditioner + dots, xpay), with alpha, beta and the
-// stopping flag kept on the device so the host only polls the flag every
-// few iterations. It runs the steps of the section 2.2 listing in order,
-// with z = r/d stored explicitly.
+// (DIA) format and ran Jacobi-preconditioned CG (the algorithm of section
+// 2.2) as a host-driven loop of library calls (section 2.6, Table 1, Fig. 5).
+// This file keeps that structure, an explicit 7-diagonal SpMV plus vector
+// kernels, with the vector work grouped into three kernels per iteration:
+// the SpMV also sums p.q per block; one kernel updates x and r and sums
+// r.(r/d) and r.r (z = r/d is never stored); one forms the new direction
+// p = r/d + beta p. Alpha, beta and the stopping flag stay on the device,
+// so the host only polls the flag every few iterations.
 #include "pcg_common.hpp"
 #include "solver.hpp"
 
@@ -50,42 +51,77 @@ __global__ __launch_bounds__(kBS) void k_dia_spmv(const T* __restrict__ val, con
     }
 }
 
-// Initial state: r = b - A x (q holds A x), z = r/d, p = z; partials r.z, r.r, b.b.
+// The SpMV q = A p of one block's range of rows, and the block's p.q.
+template <typename T>
+__global__ __launch_bounds__(kBS) void k_dia_spmv_dot(const T* __restrict__ val, const T* __restrict__ p, int nx,
+                                                      int64_t sp, int64_t npad, int64_t per, T* __restrict__ q,
+                                                      double* __restrict__ partials, const SyncState* S) {
+    if (stop(S)) return;
+    const int64_t off[7] = {0, -1, 1, -(int64_t)nx, (int64_t)nx, -sp, sp};
+    double acc[1] = {0.0};
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = min(lo + per, npad);
+    for (int64_t t = lo + threadIdx.x; t < hi; t += kBS) {
+        T y = T(0);
+#pragma unroll
+        for (int dgl = 0; dgl < 7; ++dgl) {
+            const int64_t c = t + off[dgl];
+            if (c >= 0 && c < npad) y += val[dgl * npad + t] * p[c];
+        }
+        q[t] = y;
+        acc[0] += (double)p[t] * (double)y;
+    }
+    block_sum_store<1>(acc, partials + (size_t)blockIdx.x * kMaxPartials);
+}
+
+// x += alpha p, r -= alpha q over a block's range, and the block's r.(r/d)
+// and r.r for beta and the stopping test.
+template <typename T>
+__global__ __launch_bounds__(kBS) void k_dia_update(T* __restrict__ x, const T* __restrict__ p, T* __restrict__ r,
+                                                    const T* __restrict__ q, const T* __restrict__ d, int64_t npad,
+                                                    int64_t per, double* __restrict__ partials, const SyncState* S) {
+    if (stop(S)) return;
+    const T alpha = (T)S->alpha;
+    double acc[2] = {0.0, 0.0};
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = min(lo + per, npad);
+    for (int64_t t = lo + threadIdx.x; t < hi; t += kBS) {
+        x[t] = x[t] + alpha * p[t];
+        const T rv = r[t] - alpha * q[t];
+        r[t] = rv;
+        const T zv = rv / d[t];
+        acc[0] += (double)rv * (double)zv;
+        acc[1] += (double)rv * (double)rv;
+    }
+    block_sum_store<2>(acc, partials + (size_t)blockIdx.x * kMaxPartials);
+}
+
+// p = r/d + beta p.
+template <typename T>
+__global__ void k_dia_direction(const T* __restrict__ r, const T* __restrict__ d, T* __restrict__ p, int64_t npad,
+                                const SyncState* S) {
+    if (stop(S)) return;
+    const T beta = (T)S->beta;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npad;
+         t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = r[t] / d[t] + beta * p[t];
+}
+
+// Initial state: r = b - A x (q holds A x), p = r/d; partials r.(r/d), r.r, b.b.
 template <typename T>
 __global__ __launch_bounds__(kBS) void k_init(const T* __restrict__ b, const T* __restrict__ q,
-                                              const T* __restrict__ d, T* __restrict__ r, T* __restrict__ z,
-                                              T* __restrict__ p, int64_t npad, int64_t per,
-                                              double* __restrict__ partials) {
+                                              const T* __restrict__ d, T* __restrict__ r, T* __restrict__ p,
+                                              int64_t npad, int64_t per, double* __restrict__ partials) {
     double acc[3] = {0.0, 0.0, 0.0};
     const int64_t lo = (int64_t)blockIdx.x * per, hi = min(lo + per, npad);
     for (int64_t t = lo + threadIdx.x; t < hi; t += kBS) {
         const T rv = b[t] - q[t];
         const T zv = rv / d[t];
         r[t] = rv;
-        z[t] = zv;
         p[t] = zv;
         acc[0] += (double)rv * (double)zv;
         acc[1] += (double)rv * (double)rv;
         acc[2] += (double)b[t] * (double)b[t];
     }
     block_sum_store<3>(acc, partials + (size_t)blockIdx.x * kMaxPartials);
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBS) void k_precond_dot(const T* __restrict__ r, const T* __restrict__ d,
-                                                     T* __restrict__ z, int64_t npad, int64_t per,
-                                                     double* __restrict__ partials, const SyncState* S) {
-    if (stop(S)) return;
-    double acc[2] = {0.0, 0.0};
-    const int64_t lo = (int64_t)blockIdx.x * per, hi = min(lo + per, npad);
-    for (int64_t t = lo + threadIdx.x; t < hi; t += kBS) {
-        const T rv = r[t];
-        const T zv = rv / d[t];
-        z[t] = zv;
-        acc[0] += (double)rv * (double)zv;
-        acc[1] += (double)rv * (double)rv;
-    }
-    block_sum_store<2>(acc, partials + (size_t)blockIdx.x * kMaxPartials);
 }
 
 }  // namespace
@@ -108,8 +144,8 @@ pb_status dia_jpcg_impl(const Layout& L, const SolveBufs<T>& s, SyncState* S, do
     // r = b - A x0 (x0 = 0 gives r = b exactly)
     hipLaunchKernelGGL(k_dia_spmv<T>, dim3(g), dim3(kBS), 0, st, s.dia, (const T*)s.x, L.nx, L.sp, npad, s.q,
                        (const SyncState*)nullptr);
-    hipLaunchKernelGGL(k_init<T>, dim3(R.nblk), dim3(kBS), 0, st, s.b, (const T*)s.q, s.op.d, s.r, s.z, s.p0,
-                       npad, R.per, partials);
+    hipLaunchKernelGGL(k_init<T>, dim3(R.nblk), dim3(kBS), 0, st, s.b, (const T*)s.q, s.op.d, s.r, s.p0, npad,
+                       R.per, partials);
     hipLaunchKernelGGL(k_scalar_init, dim3(1), dim3(kBS), 0, st, S, (const double*)partials, R.nblk, tol, maxiter);
     PB_HIP(hipGetLastError());
     if (timed) PB_HIP(hipEventRecord(ev[0], st));
@@ -117,18 +153,14 @@ pb_status dia_jpcg_impl(const Layout& L, const SolveBufs<T>& s, SyncState* S, do
     SyncState h{};
     for (;;) {
         for (int u = 0; u < kPoll && it < maxiter; ++u, ++it) {
-            hipLaunchKernelGGL(k_dia_spmv<T>, dim3(g), dim3(kBS), 0, st, s.dia, (const T*)s.p0, L.nx, L.sp, npad,
-                               s.q, (const SyncState*)S);
-            hipLaunchKernelGGL(k_dot<T>, dim3(R.nblk), dim3(kBS), 0, st, (const T*)s.p0, (const T*)s.q, npad,
-                               R.per, partials, (const SyncState*)S);
+            hipLaunchKernelGGL(k_dia_spmv_dot<T>, dim3(R.nblk), dim3(kBS), 0, st, s.dia, (const T*)s.p0, L.nx,
+                               L.sp, npad, R.per, s.q, partials, (const SyncState*)S);
             hipLaunchKernelGGL(k_scalar_alpha, dim3(1), dim3(kBS), 0, st, S, (const double*)partials, R.nblk);
-            hipLaunchKernelGGL(k_axpy2<T>, dim3(g), dim3(kBS), 0, st, s.x, (const T*)s.p0, s.r, (const T*)s.q,
-                               npad, (const SyncState*)S);
-            hipLaunchKernelGGL(k_precond_dot<T>, dim3(R.nblk), dim3(kBS), 0, st, (const T*)s.r, s.op.d, s.z, npad,
-                               R.per, partials, (const SyncState*)S);
+            hipLaunchKernelGGL(k_dia_update<T>, dim3(R.nblk), dim3(kBS), 0, st, s.x, (const T*)s.p0, s.r,
+                               (const T*)s.q, s.op.d, npad, R.per, partials, (const SyncState*)S);
             hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBS), 0, st, S, (const double*)partials, R.nblk, tol,
                                maxiter);
-            hipLaunchKernelGGL(k_xpay<T>, dim3(g), dim3(kBS), 0, st, (const T*)s.z, s.p0, npad,
+            hipLaunchKernelGGL(k_dia_direction<T>, dim3(g), dim3(kBS), 0, st, (const T*)s.r, s.op.d, s.p0, npad,
                                (const SyncState*)S);
         }
         PB_HIP(hipGetLastError());

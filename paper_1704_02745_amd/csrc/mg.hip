@@ -21,6 +21,7 @@
 #include "pcg_common.hpp"
 #include "solver.hpp"
 
+#include <type_traits>
 #include <vector>
 
 namespace pb {
@@ -32,6 +33,14 @@ constexpr int64_t kMgMinNodes = 512;
 constexpr double kMgOmega = 0.8;
 
 __device__ __forceinline__ double w3(int a) { return a == 0 ? 0.5 : 0.25; }   // a in -1..1
+// a / d in the smoothers: exact division in FP64; in FP32 a times the
+// hardware reciprocal of d (within 1 ulp), which keeps the sweeps, whose
+// neighbour terms each need one, from being bound by division.
+__device__ __forceinline__ double mg_div(double a, double d) { return a / d; }
+__device__ __forceinline__ float mg_div(float a, float d) { return a * __builtin_amdgcn_rcpf(d); }
+// a * b + c with one rounding
+__device__ __forceinline__ double mg_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float mg_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double series2(double a, double b) { return 2.0 * a * b / (a + b); }
 
 // One coarser level from a finer one (FP64 staggered edge arrays and kbar^2
@@ -155,32 +164,69 @@ __global__ void k_mg_op(const double* __restrict__ ex, const double* __restrict_
     }
 }
 
+// Operator readers of the stencil kernels: the four coefficient arrays
+// (ArrOp), or one word of dictionary codes per position (CodeOp; level 0 in
+// FP32, the words coded.hip builds for the fused solver: byte 0 cx, 1 cy, 2
+// cz, 3 d) with the dictionary copied into LDS when the kernel starts. The
+// dictionary holds the exact FP32 values, so both give the same results.
+// Every thread of a block calls bind() once before the first read.
+template <typename T>
+struct ArrOp {
+    Op<T> op;
+    __device__ __forceinline__ void bind() {}
+    __device__ __forceinline__ T cx(int64_t t) const { return op.cx[t]; }
+    __device__ __forceinline__ T cy(int64_t t) const { return op.cy[t]; }
+    __device__ __forceinline__ T cz(int64_t t) const { return op.cz[t]; }
+    __device__ __forceinline__ T d(int64_t t) const { return op.d[t]; }
+};
+struct CodeOp {
+    const uint32_t* w;
+    const float* dict;   // device dictionary, kCodedTableSize values
+    const float* tab;    // its LDS copy (bind)
+    __device__ __forceinline__ void bind() {
+        __shared__ float s_tab[kCodedTableSize];
+        for (int i = threadIdx.x; i < kCodedTableSize; i += blockDim.x) s_tab[i] = dict[i];
+        __syncthreads();
+        tab = s_tab;
+    }
+    __device__ __forceinline__ float cx(int64_t t) const { return tab[w[t] & 255u]; }
+    __device__ __forceinline__ float cy(int64_t t) const { return tab[(w[t] >> 8) & 255u]; }
+    __device__ __forceinline__ float cz(int64_t t) const { return tab[(w[t] >> 16) & 255u]; }
+    __device__ __forceinline__ float d(int64_t t) const { return tab[w[t] >> 24]; }
+};
+
 // (A v) at padded position t (free-space stencil; zero couplings cut the
 // faces and the pad slots).
+template <typename T, typename RD>
+__device__ __forceinline__ T mg_apply(const RD& op, const T* __restrict__ v, int64_t t, int nx, int64_t sp,
+                                      int64_t npad) {
+    T nb = op.cx(t) * (t + 1 < npad ? v[t + 1] : T(0));
+    nb += (t >= 1 ? op.cx(t - 1) * v[t - 1] : T(0));
+    nb += op.cy(t) * (t + nx < npad ? v[t + nx] : T(0));
+    nb += (t >= nx ? op.cy(t - nx) * v[t - nx] : T(0));
+    nb += op.cz(t) * (t + sp < npad ? v[t + sp] : T(0));
+    nb += (t >= sp ? op.cz(t - sp) * v[t - sp] : T(0));
+    return op.d(t) * v[t] - nb;
+}
 template <typename T>
 __device__ __forceinline__ T mg_apply(const Op<T>& op, const T* __restrict__ v, int64_t t, int nx, int64_t sp,
                                       int64_t npad) {
-    T nb = op.cx[t] * (t + 1 < npad ? v[t + 1] : T(0));
-    nb += (t >= 1 ? op.cx[t - 1] * v[t - 1] : T(0));
-    nb += op.cy[t] * (t + nx < npad ? v[t + nx] : T(0));
-    nb += (t >= nx ? op.cy[t - nx] * v[t - nx] : T(0));
-    nb += op.cz[t] * (t + sp < npad ? v[t + sp] : T(0));
-    nb += (t >= sp ? op.cz[t - sp] * v[t - sp] : T(0));
-    return op.d[t] * v[t] - nb;
+    return mg_apply(ArrOp<T>{op}, v, t, nx, sp, npad);
 }
 
 // One damped-Jacobi sweep out = in + omega (b - A in)/d; from_zero: in = 0.
-template <typename T>
-__global__ void k_mg_jacobi(Op<T> op, const T* __restrict__ b, const T* __restrict__ in, T* __restrict__ out,
+template <typename T, typename RD>
+__global__ void k_mg_jacobi(RD op, const T* __restrict__ b, const T* __restrict__ in, T* __restrict__ out,
                             int nx, int64_t sp, int64_t npad, T omega, int from_zero, const SyncState* S) {
     if (S && stop(S)) return;
+    op.bind();
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npad;
          t += (int64_t)gridDim.x * blockDim.x) {
         if (from_zero) {
-            out[t] = omega * b[t] / op.d[t];
+            out[t] = mg_div(omega * b[t], op.d(t));
         } else {
             const T r = b[t] - mg_apply(op, in, t, nx, sp, npad);
-            out[t] = in[t] + omega * r / op.d[t];
+            out[t] = in[t] + mg_div(omega * r, op.d(t));
         }
     }
 }
@@ -191,7 +237,7 @@ __global__ void k_mg_jacobi(Op<T> op, const T* __restrict__ b, const T* __restri
 // the result equals two k_mg_jacobi launches bit for bit.
 template <typename T>
 __device__ __forceinline__ T mg_x1(const Op<T>& op, const T* __restrict__ b, int64_t t, T omega) {
-    return omega * b[t] / op.d[t];
+    return mg_div(omega * b[t], op.d[t]);
 }
 
 template <typename T>
@@ -208,7 +254,7 @@ __global__ void k_mg_jacobi2z(Op<T> op, const T* __restrict__ b, T* __restrict__
         nb += (t >= sp ? op.cz[t - sp] * mg_x1(op, b, t - sp, omega) : T(0));
         const T x1 = mg_x1(op, b, t, omega);
         const T r = b[t] - (op.d[t] * x1 - nb);
-        out[t] = x1 + omega * r / op.d[t];
+        out[t] = x1 + mg_div(omega * r, op.d[t]);
     }
 }
 
@@ -216,17 +262,18 @@ __global__ void k_mg_jacobi2z(Op<T> op, const T* __restrict__ b, T* __restrict__
 // iteration's r.z and r.r (the level's right-hand side is the outer residual
 // r): block b sweeps positions [b*per, (b+1)*per), threads striding by the
 // block size, and stores the block sums in the fixed order of block_sum_store.
-template <typename T>
-__global__ __launch_bounds__(kBS) void k_mg_jacobi_dot2(Op<T> op, const T* __restrict__ b, const T* __restrict__ in,
+template <typename T, typename RD>
+__global__ __launch_bounds__(kBS) void k_mg_jacobi_dot2(RD op, const T* __restrict__ b, const T* __restrict__ in,
                                                         T* __restrict__ out, int nx, int64_t sp, int64_t npad,
                                                         T omega, int64_t per, double* __restrict__ partials,
                                                         const SyncState* S) {
     if (stop(S)) return;
+    op.bind();
     double acc[2] = {0.0, 0.0};
     const int64_t lo = (int64_t)blockIdx.x * per, hi = min(lo + per, npad);
     for (int64_t t = lo + threadIdx.x; t < hi; t += kBS) {
         const T res = b[t] - mg_apply(op, in, t, nx, sp, npad);
-        const T z = in[t] + omega * res / op.d[t];
+        const T z = in[t] + mg_div(omega * res, op.d(t));
         out[t] = z;
         acc[0] += (double)b[t] * (double)z;
         acc[1] += (double)b[t] * (double)b[t];
@@ -234,10 +281,11 @@ __global__ __launch_bounds__(kBS) void k_mg_jacobi_dot2(Op<T> op, const T* __res
     block_sum_store<2>(acc, partials + (size_t)blockIdx.x * kMaxPartials);
 }
 
-template <typename T>
-__global__ void k_mg_residual(Op<T> op, const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ r, int nx,
+template <typename T, typename RD>
+__global__ void k_mg_residual(RD op, const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ r, int nx,
                               int64_t sp, int64_t npad, const SyncState* S) {
     if (S && stop(S)) return;
+    op.bind();
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npad;
          t += (int64_t)gridDim.x * blockDim.x)
         r[t] = b[t] - mg_apply(op, x, t, nx, sp, npad);
@@ -254,30 +302,33 @@ __global__ void k_mg_apply(Op<T> op, const T* __restrict__ v, T* __restrict__ q,
 }
 
 // bc = R r (full weighting; fine nodes outside the grid contribute zero).
+// Grid: blockIdx.y is the coarse plane K; the x-dimension strides over the
+// coarse plane's positions (pad slots get zero).
 template <typename T>
 __global__ void k_mg_restrict(const T* __restrict__ r, int nx, int ny, int nz, int64_t sp, T* __restrict__ bc,
                               int ncx, int ncy, int ncz, int64_t spc, const SyncState* S) {
     if (S && stop(S)) return;
-    const int64_t pc = (int64_t)ncx * ncy, npc = spc * ncz;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npc;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t K = t / spc, pp = t - K * spc;
+    const int K = blockIdx.y;
+    const int pc = ncx * ncy;
+    for (int pp = blockIdx.x * blockDim.x + threadIdx.x; pp < (int)spc; pp += gridDim.x * blockDim.x) {
+        const int64_t t = (int64_t)K * spc + pp;
         if (pp >= pc) {
             bc[t] = T(0);
             continue;
         }
-        const int J = (int)(pp / ncx), I = (int)(pp - (int64_t)J * ncx);
+        const int J = pp / ncx, I = pp - J * ncx;
         T acc = T(0);
         for (int c = -1; c <= 1; ++c) {
-            const int k = 2 * (int)K + 1 + c;
+            const int k = 2 * K + 1 + c;
             if (k < 0 || k >= nz) continue;
             for (int b = -1; b <= 1; ++b) {
                 const int j = 2 * J + 1 + b;
                 if (j < 0 || j >= ny) continue;
+                const T* row = r + (int64_t)k * sp + (int64_t)j * nx;
                 for (int a = -1; a <= 1; ++a) {
                     const int i = 2 * I + 1 + a;
                     if (i < 0 || i >= nx) continue;
-                    acc += (T)(w3(a) * w3(b) * w3(c)) * r[(int64_t)k * sp + (int64_t)j * nx + i];
+                    acc += (T)(w3(a) * w3(b) * w3(c)) * row[i];
                 }
             }
         }
@@ -285,44 +336,122 @@ __global__ void k_mg_restrict(const T* __restrict__ r, int nx, int ny, int nz, i
     }
 }
 
-// x += P xc (trilinear: fine i odd takes coarse (i-1)/2, fine i even the
-// mean of coarse i/2-1 and i/2; coarse ghosts are zero).
+// x += P xc (trilinear: fine f odd takes coarse (f-1)/2, fine f even the mean
+// of coarse f/2-1 and f/2; coarse ghosts are zero). One thread per cell of
+// the coarse grid shifted by one fine node: cell (I, J, K), I in -1..ncx-1,
+// holds the fine nodes 2I+1 (odd) and 2I+2 (even) of each axis, all of which
+// interpolate from the same eight coarse nodes I..I+1 x J..J+1 x K..K+1, read
+// once. Each fine node sums its terms in z, y, x order, zero weights skipped.
+// Grid: blockIdx.y is K+1; the x-dimension strides over (I, J).
 template <typename T>
 __global__ void k_mg_prolong_add(const T* __restrict__ xc, int ncx, int ncy, int ncz, int64_t spc,
                                  T* __restrict__ x, int nx, int ny, int nz, int64_t sp, const SyncState* S) {
     if (S && stop(S)) return;
-    const int64_t plane = (int64_t)nx * ny, npad = sp * nz;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npad;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t k = t / sp, pp = t - k * sp;
-        if (pp >= plane) continue;
-        const int j = (int)(pp / nx), i = (int)(pp - (int64_t)j * nx);
-        int ci[2], cj[2], ck[2];
-        T wi[2], wj[2], wk[2];
-        auto axis = [](int f, int nc, int (&c)[2], T (&w)[2]) {
-            if (f & 1) {
-                c[0] = (f - 1) / 2; w[0] = T(1); c[1] = -1; w[1] = T(0);
-            } else {
-                c[0] = f / 2 - 1; w[0] = T(0.5); c[1] = f / 2; w[1] = T(0.5);
-            }
-            for (int q = 0; q < 2; ++q)
-                if (c[q] < 0 || c[q] >= nc) { c[q] = -1; w[q] = T(0); }
-        };
-        axis(i, ncx, ci, wi);
-        axis(j, ncy, cj, wj);
-        axis((int)k, ncz, ck, wk);
-        T add = T(0);
-        for (int c = 0; c < 2; ++c) {
-            if (ck[c] < 0) continue;
-            for (int b = 0; b < 2; ++b) {
-                if (cj[b] < 0) continue;
-                for (int a = 0; a < 2; ++a) {
-                    if (ci[a] < 0) continue;
-                    add += wi[a] * wj[b] * wk[c] * xc[(int64_t)ck[c] * spc + (int64_t)cj[b] * ncx + ci[a]];
+    const int K = (int)blockIdx.y - 1;
+    const int cw = ncx + 1, cells = cw * (ncy + 1);
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += gridDim.x * blockDim.x) {
+        const int J = c / cw - 1, I = c - (J + 1) * cw - 1;
+        T v[2][2][2];   // coarse (K+kk, J+jj, I+ii), zero outside the coarse grid
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+                for (int ii = 0; ii < 2; ++ii) {
+                    const int ck = K + kk, cj = J + jj, ci = I + ii;
+                    const bool in = ck >= 0 && ck < ncz && cj >= 0 && cj < ncy && ci >= 0 && ci < ncx;
+                    v[kk][jj][ii] = in ? xc[(int64_t)ck * spc + (int64_t)cj * ncx + ci] : T(0);
+                }
+        // per axis, fine node 2C+1+e (e = 0 odd, 1 even): its terms (coarse
+        // offset, weight) in order; n = number of terms
+#pragma unroll
+        for (int ez = 0; ez < 2; ++ez) {
+            const int k = 2 * K + 1 + ez;
+            if (k < 0 || k >= nz) continue;
+#pragma unroll
+            for (int ey = 0; ey < 2; ++ey) {
+                const int j = 2 * J + 1 + ey;
+                if (j < 0 || j >= ny) continue;
+#pragma unroll
+                for (int ex = 0; ex < 2; ++ex) {
+                    const int i = 2 * I + 1 + ex;
+                    if (i < 0 || i >= nx) continue;
+                    T add = T(0);
+                    for (int tz = 0; tz <= ez; ++tz) {
+                        const int ck = K + tz;
+                        if (ck < 0 || ck >= ncz) continue;
+                        const T wz = ez ? T(0.5) : T(1);
+                        for (int ty = 0; ty <= ey; ++ty) {
+                            const int cj = J + ty;
+                            if (cj < 0 || cj >= ncy) continue;
+                            const T wy = ey ? T(0.5) : T(1);
+                            for (int tx = 0; tx <= ex; ++tx) {
+                                const int ci = I + tx;
+                                if (ci < 0 || ci >= ncx) continue;
+                                const T wx = ex ? T(0.5) : T(1);
+                                add += wx * wy * wz * v[tz][ty][tx];
+                            }
+                        }
+                    }
+                    x[(int64_t)k * sp + (int64_t)j * nx + i] += add;
                 }
             }
         }
-        x[t] += add;
+    }
+}
+
+// Launch shape of the plane-indexed kernels: blockIdx.y = plane.
+dim3 plane_grid(int64_t positions, int planes) {
+    return dim3((unsigned)std::min<int64_t>(std::max<int64_t>(1, (positions + kBS - 1) / kBS), 1024), (unsigned)planes);
+}
+
+// The outer iteration's direction and product in one pass over a block's
+// range of rows: p = z + beta p_old (formed wherever the product needs it,
+// with one rounding, so neighbours see the value the node's owner stores),
+// q = A p, and the block's p.q.
+template <typename T, typename RD>
+__global__ __launch_bounds__(kBS) void k_mg_direction_apply(RD op, const T* __restrict__ z,
+                                                            const T* __restrict__ pold, T* __restrict__ pnew,
+                                                            T* __restrict__ q, int nx, int64_t sp, int64_t npad,
+                                                            int64_t per, double* __restrict__ partials,
+                                                            const SyncState* S) {
+    if (stop(S)) return;
+    op.bind();
+    const T beta = (T)S->beta;
+    auto P = [&](int64_t u) { return mg_fma(beta, pold[u], z[u]); };
+    double acc[1] = {0.0};
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = min(lo + per, npad);
+    for (int64_t t = lo + threadIdx.x; t < hi; t += kBS) {
+        T nb = op.cx(t) * (t + 1 < npad ? P(t + 1) : T(0));
+        nb += (t >= 1 ? op.cx(t - 1) * P(t - 1) : T(0));
+        nb += op.cy(t) * (t + nx < npad ? P(t + nx) : T(0));
+        nb += (t >= nx ? op.cy(t - nx) * P(t - nx) : T(0));
+        nb += op.cz(t) * (t + sp < npad ? P(t + sp) : T(0));
+        nb += (t >= sp ? op.cz(t - sp) * P(t - sp) : T(0));
+        const T pt = P(t);
+        const T qt = op.d(t) * pt - nb;
+        pnew[t] = pt;
+        q[t] = qt;
+        acc[0] += (double)pt * (double)qt;
+    }
+    block_sum_store<1>(acc, partials + (size_t)blockIdx.x * kMaxPartials);
+}
+
+// The outer update x += alpha p, rnew = r_old - alpha q, with (given x1)
+// level 0's first pre-smoothing sweep from zero on rnew, x1 = omega rnew / d
+// (the arithmetic of k_mg_jacobi's first sweep).
+template <typename T>
+__global__ void k_mg_update(T* __restrict__ x, const T* __restrict__ p, const T* __restrict__ rold,
+                            const T* __restrict__ q, T* __restrict__ rnew, const T* __restrict__ d,
+                            T* __restrict__ x1, T omega, int64_t npad, const SyncState* S) {
+    if (stop(S)) return;
+    const T alpha = (T)S->alpha;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npad;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        x[t] = mg_fma(alpha, p[t], x[t]);
+        const T r = mg_fma(-alpha, q[t], rold[t]);
+        rnew[t] = r;
+        if (x1) x1[t] = mg_div(omega * r, d[t]);
     }
 }
 
@@ -338,10 +467,10 @@ __global__ __launch_bounds__(1024) void k_mg_coarse(Op<T> op, const T* __restric
         T* out = (it & 1) ? buf1 : buf0;
         for (int64_t t = threadIdx.x; t < npad; t += blockDim.x) {
             if (it == 0) {
-                out[t] = omega * b[t] / op.d[t];
+                out[t] = mg_div(omega * b[t], op.d[t]);
             } else {
                 const T r = b[t] - mg_apply(op, in, t, nx, sp, npad);
-                out[t] = in[t] + omega * r / op.d[t];
+                out[t] = in[t] + mg_div(omega * r, op.d[t]);
             }
         }
         __syncthreads();
@@ -408,6 +537,8 @@ struct MgLevel {
     Op<T> op;
     T *b, *xa, *xb, *r;                 // right-hand side, two iterate buffers, residual
     double *ex, *ey, *ez, *k2;          // this level's edges and kbar^2 (coarse levels)
+    uint32_t* codes;                    // level 0, FP32: code words of the operator
+    void* code_scratch;
 };
 
 // Workspace carving (nullptr base: sizes only). Level 0 borrows the solve's
@@ -441,6 +572,10 @@ size_t mg_carve(void* base, const Layout& L0, double h, std::vector<MgLevel<T>>*
         }
         m.xb = (T*)take(nT);
         m.r = (T*)take(nT);
+        if (l == 0 && sizeof(T) == 4) {   // level 0's code words and the dictionary build's scratch
+            m.codes = (uint32_t*)take(4 * (size_t)m.L.npad);
+            m.code_scratch = take(coded_scratch_bytes());
+        }
         if (out) out->push_back(m);
     }
     return off;
@@ -455,17 +590,49 @@ struct DotFuse {
     int64_t per;
 };
 
+// Runs f with the reader of a level's operator: the code words when `cod` is
+// given (FP32 only), else the coefficient arrays.
+template <typename T, typename F>
+void with_reader(const CodeOp* cod, const Op<T>& op, F&& f) {
+    if constexpr (sizeof(T) == 4) {
+        if (cod) {
+            f(*cod);
+            return;
+        }
+    }
+    f(ArrOp<T>{op});
+}
+// Blocks of a grid-stride stencil launch: fewer for the coded reader, whose
+// blocks each copy the dictionary into LDS first.
+template <typename RD>
+unsigned reader_grid(unsigned g) {
+    return std::is_same<RD, CodeOp>::value ? std::min(g, 2048u) : g;
+}
+
 // One V-cycle on level l from zero; returns the buffer holding the result.
 // The first two pre-smoothing sweeps run as one pass (k_mg_jacobi2z); with
 // `fuse` the finest level's last post-smoothing sweep also stores the block
 // sums of r.z and r.r (k_mg_jacobi_dot2). A single-level hierarchy has no
-// such sweep; its caller takes those sums with k_mg_dot2.
+// such sweep; its caller takes those sums with k_mg_dot2. `presmoothed`:
+// the caller has already run the first `pre_done` pre-smoothing sweeps of
+// level l into that buffer (one of the level's two iterate buffers). `cod`:
+// level 0's coded reader (the sweeps and the residual of level 0 read the
+// operator through it).
 template <typename T>
-T* vcycle(std::vector<MgLevel<T>>& lv, size_t l, const SyncState* S, hipStream_t st, const DotFuse* fuse = nullptr) {
+T* vcycle(std::vector<MgLevel<T>>& lv, size_t l, const SyncState* S, hipStream_t st, const DotFuse* fuse = nullptr,
+          T* presmoothed = nullptr, int pre_done = 0, const CodeOp* cod = nullptr) {
     MgLevel<T>& m = lv[l];
     const Layout& L = m.L;
     const T om = (T)kMgOmega;
     const unsigned g = mg_grid(L.npad);
+    const CodeOp* rd0 = l == 0 ? cod : nullptr;
+    auto jacobi = [&](const T* in, T* out, int from_zero) {
+        with_reader<T>(rd0, m.op, [&](auto rd) {
+            using RD = decltype(rd);
+            hipLaunchKernelGGL((k_mg_jacobi<T, RD>), dim3(reader_grid<RD>(g)), dim3(kBS), 0, st, rd, (const T*)m.b,
+                               in, out, L.nx, L.sp, L.npad, om, from_zero, S);
+        });
+    };
     if (l + 1 == lv.size()) {
         hipLaunchKernelGGL(k_mg_coarse<T>, dim3(1), dim3(1024), 0, st, m.op, (const T*)m.b, m.xa, m.xb, L.nx, L.sp,
                            L.npad, om, kMgCoarseSweeps, S);
@@ -474,35 +641,44 @@ T* vcycle(std::vector<MgLevel<T>>& lv, size_t l, const SyncState* S, hipStream_t
     T* cur = m.xa;
     T* oth = m.xb;
     int s0 = 0;
-    if (kMgNu >= 2) {
+    if (presmoothed) {
+        oth = presmoothed;
+        cur = (presmoothed == m.xa) ? m.xb : m.xa;
+        s0 = pre_done;
+    } else if (kMgNu >= 2) {
         hipLaunchKernelGGL(k_mg_jacobi2z<T>, dim3(g), dim3(kBS), 0, st, m.op, (const T*)m.b, cur, L.nx, L.sp, L.npad,
                            om, S);
         std::swap(cur, oth);
         s0 = 2;
     }
     for (int s = s0; s < kMgNu; ++s) {
-        hipLaunchKernelGGL(k_mg_jacobi<T>, dim3(g), dim3(kBS), 0, st, m.op, (const T*)m.b, (const T*)oth, cur, L.nx,
-                           L.sp, L.npad, om, s == 0 ? 1 : 0, S);
+        jacobi((const T*)oth, cur, s == 0 ? 1 : 0);
         std::swap(cur, oth);
     }
     T* z = oth;   // the last sweep's output
-    hipLaunchKernelGGL(k_mg_residual<T>, dim3(g), dim3(kBS), 0, st, m.op, (const T*)m.b, (const T*)z, m.r, L.nx, L.sp,
-                       L.npad, S);
+    with_reader<T>(rd0, m.op, [&](auto rd) {
+        using RD = decltype(rd);
+        hipLaunchKernelGGL((k_mg_residual<T, RD>), dim3(reader_grid<RD>(g)), dim3(kBS), 0, st, rd, (const T*)m.b,
+                           (const T*)z, m.r, L.nx, L.sp, L.npad, S);
+    });
     MgLevel<T>& c = lv[l + 1];
-    hipLaunchKernelGGL(k_mg_restrict<T>, dim3(mg_grid(c.L.npad)), dim3(kBS), 0, st, (const T*)m.r, L.nx, L.ny, L.nz,
-                       L.sp, c.b, c.L.nx, c.L.ny, c.L.nz, c.L.sp, S);
+    hipLaunchKernelGGL(k_mg_restrict<T>, plane_grid(c.L.sp, c.L.nz), dim3(kBS), 0, st, (const T*)m.r, L.nx, L.ny,
+                       L.nz, L.sp, c.b, c.L.nx, c.L.ny, c.L.nz, c.L.sp, S);
     T* zc = vcycle(lv, l + 1, S, st);
-    hipLaunchKernelGGL(k_mg_prolong_add<T>, dim3(g), dim3(kBS), 0, st, (const T*)zc, c.L.nx, c.L.ny, c.L.nz, c.L.sp,
-                       z, L.nx, L.ny, L.nz, L.sp, S);
+    hipLaunchKernelGGL(k_mg_prolong_add<T>, plane_grid((int64_t)(c.L.nx + 1) * (c.L.ny + 1), c.L.nz + 1), dim3(kBS),
+                       0, st, (const T*)zc, c.L.nx, c.L.ny, c.L.nz, c.L.sp, z, L.nx, L.ny, L.nz, L.sp, S);
     cur = (z == m.xa) ? m.xb : m.xa;
     oth = z;
     for (int s = 0; s < kMgNu; ++s) {
         if (fuse && l == 0 && S && s + 1 == kMgNu)
-            hipLaunchKernelGGL(k_mg_jacobi_dot2<T>, dim3(fuse->nblk), dim3(kBS), 0, st, m.op, (const T*)m.b,
-                               (const T*)oth, cur, L.nx, L.sp, L.npad, om, fuse->per, fuse->partials, S);
+            with_reader<T>(rd0, m.op, [&](auto rd) {
+                using RD = decltype(rd);
+                hipLaunchKernelGGL((k_mg_jacobi_dot2<T, RD>), dim3(fuse->nblk), dim3(kBS), 0, st, rd,
+                                   (const T*)m.b, (const T*)oth, cur, L.nx, L.sp, L.npad, om, fuse->per,
+                                   fuse->partials, S);
+            });
         else
-            hipLaunchKernelGGL(k_mg_jacobi<T>, dim3(g), dim3(kBS), 0, st, m.op, (const T*)m.b, (const T*)oth, cur,
-                               L.nx, L.sp, L.npad, om, 0, S);
+            jacobi((const T*)oth, cur, 0);
         std::swap(cur, oth);
     }
     return oth;
@@ -524,8 +700,7 @@ pb_status mg_pcg_impl(const Layout& L0, double h, const double* ex, const double
     mg_carve<T>(mgws, L0, h, &lv);
     lv[0].op = s.op;
     lv[0].ex = (double*)ex; lv[0].ey = (double*)ey; lv[0].ez = (double*)ez; lv[0].k2 = (double*)k2;
-    lv[0].b = s.r;       // the V-cycle's input is the outer residual
-    lv[0].xa = s.z;
+    lv[0].xa = s.z;      // (lv[0].b, the V-cycle's input, is the outer residual; set per iteration)
     for (size_t l = 1; l < lv.size(); ++l) {
         const MgLevel<T>& f = lv[l - 1];
         MgLevel<T>& c = lv[l];
@@ -539,6 +714,22 @@ pb_status mg_pcg_impl(const Layout& L0, double h, const double* ex, const double
                            c.L.sp, c.h * c.h, c.op);
     }
     PB_HIP(hipGetLastError());
+    // level 0 in FP32 reads its operator as code words when the values fit
+    // the dictionary (the same words and dictionary as the fused solver's)
+    CodeOp cod_{};
+    const CodeOp* cod = nullptr;
+    if constexpr (sizeof(T) == 4) {
+        if (coded_coefficients() && lv[0].codes) {
+            bool fits = false;
+            const float* tab = nullptr;
+            const pb_status e = build_codes(s.op, L0.npad, lv[0].code_scratch, lv[0].codes, st, fits, &tab);
+            if (e != PB_OK) return e;
+            if (fits) {
+                cod_ = CodeOp{lv[0].codes, tab, nullptr};
+                cod = &cod_;
+            }
+        }
+    }
 
     const int64_t npad = L0.npad;
     const Ranges R = ranges_for(npad);
@@ -551,37 +742,55 @@ pb_status mg_pcg_impl(const Layout& L0, double h, const double* ex, const double
         PB_HIP(hipEventCreate(&ev[1]));
     }
     if (timed) PB_HIP(hipEventRecord(ev[0], st));
-    // r = b - A x0, z = M r, p = z
+    // r = b - A x0, z = M r, p = z. The residual and the direction
+    // alternate between two buffers each: the fused kernels read the old
+    // values around a node while writing the new ones.
+    T* rb[2] = {s.r, s.r2};
+    T* pb_[2] = {s.p0, s.p1};
     hipLaunchKernelGGL(k_mg_apply<T>, dim3(g), dim3(kBS), 0, st, s.op, (const T*)s.x, s.q, L0.nx, L0.sp, npad,
                        (const SyncState*)nullptr);
-    hipLaunchKernelGGL(k_mg_sub<T>, dim3(g), dim3(kBS), 0, st, s.b, (const T*)s.q, s.r, npad);
+    hipLaunchKernelGGL(k_mg_sub<T>, dim3(g), dim3(kBS), 0, st, s.b, (const T*)s.q, rb[0], npad);
+    lv[0].b = rb[0];
     T* z = vcycle<T>(lv, 0, nullptr, st);
-    hipLaunchKernelGGL(k_mg_init_dots<T>, dim3(R.nblk), dim3(kBS), 0, st, (const T*)s.r, (const T*)z, s.b, s.p0, npad,
-                       R.per, partials);
+    hipLaunchKernelGGL(k_mg_init_dots<T>, dim3(R.nblk), dim3(kBS), 0, st, (const T*)rb[0], (const T*)z, s.b, pb_[0],
+                       npad, R.per, partials);
     hipLaunchKernelGGL(k_scalar_init, dim3(1), dim3(kBS), 0, st, S, (const double*)partials, R.nblk, tol, maxiter);
     PB_HIP(hipGetLastError());
+    // Per iteration: p = z + beta p and q = A p with p.q (beta is 0 before the
+    // first); alpha; x and r updated together with level 0's first
+    // pre-smoothing sweep; the rest of the V-cycle, its last sweep with r.z
+    // and r.r; beta.
     const DotFuse fuse{partials, R.nblk, R.per};
+    const T om = (T)kMgOmega;
     int it = 0;
     SyncState hs{};
     for (;;) {
         for (int u = 0; u < kPoll && it < maxiter; ++u, ++it) {
-            hipLaunchKernelGGL(k_mg_apply<T>, dim3(g), dim3(kBS), 0, st, s.op, (const T*)s.p0, s.q, L0.nx, L0.sp, npad,
-                               (const SyncState*)S);
-            hipLaunchKernelGGL(k_dot<T>, dim3(R.nblk), dim3(kBS), 0, st, (const T*)s.p0, (const T*)s.q, npad, R.per,
-                               partials, (const SyncState*)S);
+            T* pold = pb_[it & 1];
+            T* pnew = pb_[(it + 1) & 1];
+            T* rold = rb[it & 1];
+            T* rnew = rb[(it + 1) & 1];
+            with_reader<T>(cod, s.op, [&](auto rd) {
+                using RD = decltype(rd);
+                hipLaunchKernelGGL((k_mg_direction_apply<T, RD>), dim3(R.nblk), dim3(kBS), 0, st, rd, (const T*)z,
+                                   (const T*)pold, pnew, s.q, L0.nx, L0.sp, npad, R.per, partials,
+                                   (const SyncState*)S);
+            });
             hipLaunchKernelGGL(k_scalar_alpha, dim3(1), dim3(kBS), 0, st, S, (const double*)partials, R.nblk);
-            hipLaunchKernelGGL(k_axpy2<T>, dim3(g), dim3(kBS), 0, st, s.x, (const T*)s.p0, s.r, (const T*)s.q, npad,
-                               (const SyncState*)S);
+            lv[0].b = rnew;
             if (lv.size() > 1) {
-                z = vcycle<T>(lv, 0, S, st, &fuse);   // also stores the block sums of r.z and r.r
+                hipLaunchKernelGGL(k_mg_update<T>, dim3(g), dim3(kBS), 0, st, s.x, (const T*)pnew, (const T*)rold,
+                                   (const T*)s.q, rnew, s.op.d, lv[0].xa, om, npad, (const SyncState*)S);
+                z = vcycle<T>(lv, 0, S, st, &fuse, lv[0].xa, 1, cod);   // also stores the block sums of r.z and r.r
             } else {
-                z = vcycle<T>(lv, 0, S, st);
-                hipLaunchKernelGGL(k_mg_dot2<T>, dim3(R.nblk), dim3(kBS), 0, st, (const T*)s.r, (const T*)z, npad,
+                hipLaunchKernelGGL(k_mg_update<T>, dim3(g), dim3(kBS), 0, st, s.x, (const T*)pnew, (const T*)rold,
+                                   (const T*)s.q, rnew, s.op.d, (T*)nullptr, om, npad, (const SyncState*)S);
+                z = vcycle<T>(lv, 0, S, st, nullptr, nullptr, 0, cod);
+                hipLaunchKernelGGL(k_mg_dot2<T>, dim3(R.nblk), dim3(kBS), 0, st, (const T*)rnew, (const T*)z, npad,
                                    R.per, partials, (const SyncState*)S);
             }
             hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBS), 0, st, S, (const double*)partials, R.nblk, tol,
                                maxiter);
-            hipLaunchKernelGGL(k_xpay<T>, dim3(g), dim3(kBS), 0, st, (const T*)z, s.p0, npad, (const SyncState*)S);
         }
         PB_HIP(hipGetLastError());
         PB_HIP(hipMemcpyAsync(&hs, S, sizeof(SyncState), hipMemcpyDeviceToHost, st));

@@ -56,7 +56,7 @@ struct SolveBufs {
     T* p1;
     T* q;
     T* q2;         // fused form: second A.p buffer (ping-pong)
-    T* z;          // DIA form only
+    T* z;          // multigrid form only
     T* dia;        // DIA form only: 7 diagonals x npad
     int warm;      // 1: x holds a nonzero initial guess
     // fused FP32 40-byte form: the code words in q2 and the dictionary (ctab,

@@ -111,3 +111,22 @@ def test_mg_rejects_periodic(pb, c0):
     with pytest.raises(pb.PBError) as ei:
         pb.solve(sm, tol=1e-6, precision="f32", op="mg")
     assert ei.value.status == pb.PB_ERR_ARG
+
+
+@pytest.mark.parametrize("prec", ["f32", "f32_refine64"])
+def test_mg_coded_level0_bitwise(pb, prec):
+    """Level 0 of the FP32 hierarchy reads its operator as dictionary code
+    words (the dictionary holds the exact FP32 values): the solve is bit for
+    bit the one that reads the four coefficient arrays."""
+    prob = synth.small_problem(61, 53, 47, 80, seed=8)
+    sm = _sys(pb, fdpb.assemble_problem(prob))
+    tol = 1e-6 if prec == "f32" else 1e-9
+    x1, i1 = pb.solve(sm, tol=tol, precision=prec, op="mg")
+    try:
+        pb.set_coded_coefficients(False)
+        x0, i0 = pb.solve(sm, tol=tol, precision=prec, op="mg")
+    finally:
+        pb.set_coded_coefficients(True)
+    print(f"mg {prec} coded vs arrays: iters {i1['iters']} / {i0['iters']}", flush=True)
+    assert i1["status"] == pb.PB_OK and i1["iters"] == i0["iters"]
+    assert torch.equal(x1, x0)

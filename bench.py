@@ -189,9 +189,10 @@ def oracle_golden_errors(x, e):
             "oracle_relres_true": gold["true_relres"]}
 
 
-# DIA form: 7 diagonals (28 B) + p (4 B) read, q (4 B) written by the SpMV;
-# p.q (8 B); x, r axpy (24 B); z = r/d with r.z, r.r (12 B); p = z + beta p (12 B).
-DIA_ITER_BYTES = 92
+# DIA form: 7 diagonals (28 B) + p (4 B) read, q (4 B) written by the SpMV
+# with p.q; x, r updated with r.(r/d), r.r (x, r read and written, p, q, d
+# read: 28 B); p = r/d + beta p (r, d, p read, p written: 16 B).
+DIA_ITER_BYTES = 80
 
 
 def bench_c1(pbgpu, torch, synth, dev, reps=3):

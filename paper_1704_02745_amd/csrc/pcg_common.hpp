@@ -21,9 +21,12 @@ struct Ranges {
     int64_t per;
 };
 
+// Block ranges of the kernels that also store per-block sums: about 1024
+// positions per block (four per thread), at most 16384 blocks, so that the
+// grid fills the device like a plain one-position-per-thread launch would.
 Ranges ranges_for(int64_t npad) {
     Ranges r;
-    r.nblk = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (npad + 4095) / 4096));
+    r.nblk = (int)std::min<int64_t>(16384, std::max<int64_t>(1, (npad + 1023) / 1024));
     r.per = (npad + r.nblk - 1) / r.nblk;
     return r;
 }

@@ -590,6 +590,216 @@ struct DotFuse {
     int64_t per;
 };
 
+// ---- level 0 in FP32: four consecutive positions per thread
+//
+// The same arithmetic as the one-position kernels above (each term rounded
+// as written, in the same order), with the neighbour values read as 16-byte
+// groups where they are aligned (the node's own group and the planes above
+// and below) through raw buffer resources over the whole array: positions
+// before the array (one fixed offset past its end) or past its end read as
+// zero, as the one-position kernels' range tests make them.
+using MgRsrc = __amdgpu_buffer_rsrc_t;
+typedef unsigned int mg_u32x4 __attribute__((ext_vector_type(4)));
+constexpr uint32_t kMgOutside = 0x80000000u;   // past every array these kernels take (npad < 2^29)
+__device__ __forceinline__ MgRsrc mg_rsrc(const void* p, int64_t n) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)(n * 4), 0x00020000);
+}
+__device__ __forceinline__ uint32_t mg_off(int64_t i) { return i < 0 ? kMgOutside : (uint32_t)(i * 4); }
+__device__ __forceinline__ float4 mg_ld4(MgRsrc r, int64_t i) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)mg_off(i), 0, 0));
+}
+__device__ __forceinline__ float mg_ld1(MgRsrc r, int64_t i) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)mg_off(i), 0, 0));
+}
+__device__ __forceinline__ mg_u32x4 mg_ldw4(MgRsrc r, int64_t i) {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, (int)mg_off(i), 0, 0);
+}
+__device__ __forceinline__ uint32_t mg_ldw1(MgRsrc r, int64_t i) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)mg_off(i), 0, 0);
+}
+__device__ __forceinline__ float& g4(float4& v, int u) { return (&v.x)[u]; }
+
+// The couplings a group of four positions t0..t0+3 needs: its own cx, cy,
+// cz, d, the x-coupling left of t0, the y-couplings one row down and the
+// z-couplings one plane down (zero before the array).
+struct Grp4 {
+    float cx[4], cy[4], cz[4], d[4], cxl, cyd[4], czd[4];
+};
+struct ArrGrp {
+    const float *pcx, *pcy, *pcz, *pd;
+    int64_t n;
+    __device__ __forceinline__ void bind() {}
+    __device__ __forceinline__ void load(int64_t t0, int nx, int64_t sp, Grp4& g) const {
+        const MgRsrc cx = mg_rsrc(pcx, n), cy = mg_rsrc(pcy, n), cz = mg_rsrc(pcz, n), d = mg_rsrc(pd, n);
+        const float4 a = mg_ld4(cx, t0), b = mg_ld4(cy, t0), c = mg_ld4(cz, t0), e = mg_ld4(d, t0);
+        const float4 zd = mg_ld4(cz, t0 - sp);
+        for (int u = 0; u < 4; ++u) {
+            g.cx[u] = (&a.x)[u];
+            g.cy[u] = (&b.x)[u];
+            g.cz[u] = (&c.x)[u];
+            g.d[u] = (&e.x)[u];
+            g.czd[u] = (&zd.x)[u];
+            g.cyd[u] = mg_ld1(cy, t0 + u - nx);
+        }
+        g.cxl = mg_ld1(cx, t0 - 1);
+    }
+};
+struct CodeGrp {
+    const uint32_t* pw;
+    int64_t n;
+    const float* dict;
+    const float* tab;    // the dictionary's LDS copy, set by bind()
+    __device__ __forceinline__ void bind() {
+        __shared__ float s_tab[kCodedTableSize];
+        for (int i = threadIdx.x; i < kCodedTableSize; i += blockDim.x) s_tab[i] = dict[i];
+        __syncthreads();
+        tab = s_tab;
+    }
+    __device__ __forceinline__ void load(int64_t t0, int nx, int64_t sp, Grp4& g) const {
+        const MgRsrc w = mg_rsrc(pw, n);
+        const mg_u32x4 o = mg_ldw4(w, t0), zd = mg_ldw4(w, t0 - sp);
+        for (int u = 0; u < 4; ++u) {
+            g.cx[u] = tab[o[u] & 255u];
+            g.cy[u] = tab[(o[u] >> 8) & 255u];
+            g.cz[u] = tab[(o[u] >> 16) & 255u];
+            g.d[u] = tab[o[u] >> 24];
+            g.czd[u] = tab[(zd[u] >> 16) & 255u];
+            g.cyd[u] = tab[(mg_ldw1(w, t0 + u - nx) >> 8) & 255u];
+        }
+        g.cxl = tab[mg_ldw1(w, t0 - 1) & 255u];
+    }
+};
+
+// Values of the vector the operator applies to, around a group: the group,
+// its x-neighbours, the rows above and below, the planes above and below.
+struct Nbr4 {
+    float4 c, zu, zd;
+    float l, r, yu[4], yd[4];
+};
+__device__ __forceinline__ void load_nbr(MgRsrc v, int64_t t0, int nx, int64_t sp, Nbr4& n) {
+    n.c = mg_ld4(v, t0);
+    n.zu = mg_ld4(v, t0 + sp);
+    n.zd = mg_ld4(v, t0 - sp);
+    n.l = mg_ld1(v, t0 - 1);
+    n.r = mg_ld1(v, t0 + 4);
+    for (int u = 0; u < 4; ++u) {
+        n.yu[u] = mg_ld1(v, t0 + u + nx);
+        n.yd[u] = mg_ld1(v, t0 + u - nx);
+    }
+}
+// (A v) for element u of the group, the terms of mg_apply in its order
+__device__ __forceinline__ float apply4(const Grp4& g, const Nbr4& n, int u) {
+    float c = (&n.c.x)[u];
+    float vr = (u == 3) ? n.r : (&n.c.x)[u + 1];
+    float vl = (u == 0) ? n.l : (&n.c.x)[u - 1];
+    float cl = (u == 0) ? g.cxl : g.cx[u - 1];
+    float nb = g.cx[u] * vr;
+    nb += cl * vl;
+    nb += g.cy[u] * n.yu[u];
+    nb += g.cyd[u] * n.yd[u];
+    nb += g.cz[u] * (&n.zu.x)[u];
+    nb += g.czd[u] * (&n.zd.x)[u];
+    return g.d[u] * c - nb;
+}
+
+// MODE 0: out = in + (omega (b - A in)) / d (a sweep); MODE 1: r = b - A x.
+// Grid-stride over groups of four.
+template <int MODE, typename RD>
+__global__ __launch_bounds__(kBS) void k_mg4_sweep(RD op, const float* __restrict__ b, const float* __restrict__ in,
+                                                   float* __restrict__ out, int nx, int64_t sp, int64_t npad,
+                                                   float omega, const SyncState* S) {
+    if (S && stop(S)) return;
+    op.bind();
+    const MgRsrc rin = mg_rsrc(in, npad), rb = mg_rsrc(b, npad), ro = mg_rsrc(out, npad);
+    for (int64_t t0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; t0 < npad;
+         t0 += (int64_t)gridDim.x * blockDim.x * 4) {
+        Grp4 g;
+        op.load(t0, nx, sp, g);
+        Nbr4 n;
+        load_nbr(rin, t0, nx, sp, n);
+        const float4 bv = mg_ld4(rb, t0);
+        float4 o;
+        for (int u = 0; u < 4; ++u) {
+            const float r = (&bv.x)[u] - apply4(g, n, u);
+            g4(o, u) = MODE == 0 ? (&n.c.x)[u] + mg_div(omega * r, g.d[u]) : r;
+        }
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(mg_u32x4, o), ro, (int)mg_off(t0), 0, 0);
+    }
+}
+
+// The last sweep with the block sums of r.z and r.r (block b: positions
+// [b*per, (b+1)*per), per a multiple of 4, groups strided by the block).
+template <typename RD>
+__global__ __launch_bounds__(kBS) void k_mg4_sweep_dot2(RD op, const float* __restrict__ b,
+                                                        const float* __restrict__ in, float* __restrict__ out,
+                                                        int nx, int64_t sp, int64_t npad, float omega, int64_t per,
+                                                        double* __restrict__ partials, const SyncState* S) {
+    if (stop(S)) return;
+    op.bind();
+    const MgRsrc rin = mg_rsrc(in, npad), rb = mg_rsrc(b, npad), ro = mg_rsrc(out, npad);
+    double acc[2] = {0.0, 0.0};
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = min(lo + per, npad);
+    for (int64_t t0 = lo + (int64_t)threadIdx.x * 4; t0 < hi; t0 += kBS * 4) {
+        Grp4 g;
+        op.load(t0, nx, sp, g);
+        Nbr4 n;
+        load_nbr(rin, t0, nx, sp, n);
+        const float4 bv = mg_ld4(rb, t0);
+        float4 o;
+        for (int u = 0; u < 4; ++u) {
+            const float res = (&bv.x)[u] - apply4(g, n, u);
+            const float z = (&n.c.x)[u] + mg_div(omega * res, g.d[u]);
+            g4(o, u) = z;
+            acc[0] += (double)(&bv.x)[u] * (double)z;
+            acc[1] += (double)(&bv.x)[u] * (double)(&bv.x)[u];
+        }
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(mg_u32x4, o), ro, (int)mg_off(t0), 0, 0);
+    }
+    block_sum_store<2>(acc, partials + (size_t)blockIdx.x * kMaxPartials);
+}
+
+// p = z + beta p_old, q = A p and the block sums of p.q (as k_mg_direction_apply).
+template <typename RD>
+__global__ __launch_bounds__(kBS) void k_mg4_direction_apply(RD op, const float* __restrict__ z,
+                                                             const float* __restrict__ pold, float* __restrict__ pnew,
+                                                             float* __restrict__ q, int nx, int64_t sp, int64_t npad,
+                                                             int64_t per, double* __restrict__ partials,
+                                                             const SyncState* S) {
+    if (stop(S)) return;
+    op.bind();
+    const float beta = (float)S->beta;
+    const MgRsrc rz = mg_rsrc(z, npad), rp = mg_rsrc(pold, npad), rpn = mg_rsrc(pnew, npad), rq = mg_rsrc(q, npad);
+    double acc[1] = {0.0};
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = min(lo + per, npad);
+    for (int64_t t0 = lo + (int64_t)threadIdx.x * 4; t0 < hi; t0 += kBS * 4) {
+        Grp4 g;
+        op.load(t0, nx, sp, g);
+        Nbr4 nz, np;
+        load_nbr(rz, t0, nx, sp, nz);
+        load_nbr(rp, t0, nx, sp, np);
+        // the direction at every point the product reads (zero outside the array, as z and p_old are)
+        Nbr4 n;
+        for (int u = 0; u < 4; ++u) {
+            g4(n.c, u) = mg_fma(beta, (&np.c.x)[u], (&nz.c.x)[u]);
+            g4(n.zu, u) = mg_fma(beta, (&np.zu.x)[u], (&nz.zu.x)[u]);
+            g4(n.zd, u) = mg_fma(beta, (&np.zd.x)[u], (&nz.zd.x)[u]);
+            n.yu[u] = mg_fma(beta, np.yu[u], nz.yu[u]);
+            n.yd[u] = mg_fma(beta, np.yd[u], nz.yd[u]);
+        }
+        n.l = mg_fma(beta, np.l, nz.l);
+        n.r = mg_fma(beta, np.r, nz.r);
+        float4 qv;
+        for (int u = 0; u < 4; ++u) {
+            const float qt = apply4(g, n, u);
+            g4(qv, u) = qt;
+            acc[0] += (double)(&n.c.x)[u] * (double)qt;
+        }
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(mg_u32x4, n.c), rpn, (int)mg_off(t0), 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(mg_u32x4, qv), rq, (int)mg_off(t0), 0, 0);
+    }
+    block_sum_store<1>(acc, partials + (size_t)blockIdx.x * kMaxPartials);
+}
+
 // Runs f with the reader of a level's operator: the code words when `cod` is
 // given (FP32 only), else the coefficient arrays.
 template <typename T, typename F>
@@ -602,6 +812,21 @@ void with_reader(const CodeOp* cod, const Op<T>& op, F&& f) {
     }
     f(ArrOp<T>{op});
 }
+// Level 0 in FP32: the four-wide kernels with the code words or the arrays.
+struct Vec4Rd {
+    bool coded;
+    CodeGrp cg;
+    ArrGrp ag;
+};
+template <typename F>
+void with_vec4(const Vec4Rd& v, F&& f) {
+    if (v.coded) f(v.cg);
+    else f(v.ag);
+}
+unsigned vec4_grid(int64_t npad) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((npad / 4 + kBS - 1) / kBS, 2048));
+}
+
 // Blocks of a grid-stride stencil launch: fewer for the coded reader, whose
 // blocks each copy the dictionary into LDS first.
 template <typename RD>
@@ -620,13 +845,36 @@ unsigned reader_grid(unsigned g) {
 // operator through it).
 template <typename T>
 T* vcycle(std::vector<MgLevel<T>>& lv, size_t l, const SyncState* S, hipStream_t st, const DotFuse* fuse = nullptr,
-          T* presmoothed = nullptr, int pre_done = 0, const CodeOp* cod = nullptr) {
+          T* presmoothed = nullptr, int pre_done = 0, const CodeOp* cod = nullptr, const Vec4Rd* v4 = nullptr) {
     MgLevel<T>& m = lv[l];
     const Layout& L = m.L;
     const T om = (T)kMgOmega;
     const unsigned g = mg_grid(L.npad);
     const CodeOp* rd0 = l == 0 ? cod : nullptr;
+    // FP32: level 0 as the caller set it up, the coarser levels with their arrays
+    Vec4Rd vl{};
+    const Vec4Rd* v40 = nullptr;
+    if constexpr (sizeof(T) == 4) {
+        if (l == 0) {
+            v40 = v4;
+        } else if (v4 && L.npad < ((int64_t)1 << 29)) {
+            vl.coded = false;
+            vl.ag = ArrGrp{(const float*)m.op.cx, (const float*)m.op.cy, (const float*)m.op.cz, (const float*)m.op.d,
+                           L.npad};
+            v40 = &vl;
+        }
+    }
     auto jacobi = [&](const T* in, T* out, int from_zero) {
+        if constexpr (sizeof(T) == 4) {
+            if (v40 && !from_zero) {
+                with_vec4(*v40, [&](auto rd) {
+                    hipLaunchKernelGGL((k_mg4_sweep<0, decltype(rd)>), dim3(vec4_grid(L.npad)), dim3(kBS), 0, st, rd,
+                                       (const float*)m.b, (const float*)in, (float*)out, L.nx, L.sp, L.npad,
+                                       (float)om, S);
+                });
+                return;
+            }
+        }
         with_reader<T>(rd0, m.op, [&](auto rd) {
             using RD = decltype(rd);
             hipLaunchKernelGGL((k_mg_jacobi<T, RD>), dim3(reader_grid<RD>(g)), dim3(kBS), 0, st, rd, (const T*)m.b,
@@ -656,21 +904,41 @@ T* vcycle(std::vector<MgLevel<T>>& lv, size_t l, const SyncState* S, hipStream_t
         std::swap(cur, oth);
     }
     T* z = oth;   // the last sweep's output
-    with_reader<T>(rd0, m.op, [&](auto rd) {
-        using RD = decltype(rd);
-        hipLaunchKernelGGL((k_mg_residual<T, RD>), dim3(reader_grid<RD>(g)), dim3(kBS), 0, st, rd, (const T*)m.b,
-                           (const T*)z, m.r, L.nx, L.sp, L.npad, S);
-    });
+    bool done_res = false;
+    if constexpr (sizeof(T) == 4) {
+        if (v40) {
+            with_vec4(*v40, [&](auto rd) {
+                hipLaunchKernelGGL((k_mg4_sweep<1, decltype(rd)>), dim3(vec4_grid(L.npad)), dim3(kBS), 0, st, rd,
+                                   (const float*)m.b, (const float*)z, (float*)m.r, L.nx, L.sp, L.npad, (float)om, S);
+            });
+            done_res = true;
+        }
+    }
+    if (!done_res)
+        with_reader<T>(rd0, m.op, [&](auto rd) {
+            using RD = decltype(rd);
+            hipLaunchKernelGGL((k_mg_residual<T, RD>), dim3(reader_grid<RD>(g)), dim3(kBS), 0, st, rd,
+                               (const T*)m.b, (const T*)z, m.r, L.nx, L.sp, L.npad, S);
+        });
     MgLevel<T>& c = lv[l + 1];
     hipLaunchKernelGGL(k_mg_restrict<T>, plane_grid(c.L.sp, c.L.nz), dim3(kBS), 0, st, (const T*)m.r, L.nx, L.ny,
                        L.nz, L.sp, c.b, c.L.nx, c.L.ny, c.L.nz, c.L.sp, S);
-    T* zc = vcycle(lv, l + 1, S, st);
+    T* zc = vcycle<T>(lv, l + 1, S, st, nullptr, nullptr, 0, nullptr, v4);
     hipLaunchKernelGGL(k_mg_prolong_add<T>, plane_grid((int64_t)(c.L.nx + 1) * (c.L.ny + 1), c.L.nz + 1), dim3(kBS),
                        0, st, (const T*)zc, c.L.nx, c.L.ny, c.L.nz, c.L.sp, z, L.nx, L.ny, L.nz, L.sp, S);
     cur = (z == m.xa) ? m.xb : m.xa;
     oth = z;
     for (int s = 0; s < kMgNu; ++s) {
-        if (fuse && l == 0 && S && s + 1 == kMgNu)
+        bool vec_last = false;
+        if constexpr (sizeof(T) == 4) vec_last = v40 && fuse && l == 0 && S && s + 1 == kMgNu;
+        if (vec_last) {
+            if constexpr (sizeof(T) == 4)
+                with_vec4(*v40, [&](auto rd) {
+                    hipLaunchKernelGGL((k_mg4_sweep_dot2<decltype(rd)>), dim3(fuse->nblk), dim3(kBS), 0, st, rd,
+                                       (const float*)m.b, (const float*)oth, (float*)cur, L.nx, L.sp, L.npad,
+                                       (float)om, fuse->per, fuse->partials, S);
+                });
+        } else if (fuse && l == 0 && S && s + 1 == kMgNu)
             with_reader<T>(rd0, m.op, [&](auto rd) {
                 using RD = decltype(rd);
                 hipLaunchKernelGGL((k_mg_jacobi_dot2<T, RD>), dim3(fuse->nblk), dim3(kBS), 0, st, rd,
@@ -731,6 +999,19 @@ pb_status mg_pcg_impl(const Layout& L0, double h, const double* ex, const double
         }
     }
 
+    // level 0 in FP32 runs the four-wide kernels (the code words or the arrays)
+    Vec4Rd v4_{};
+    const Vec4Rd* v4 = nullptr;
+    if constexpr (sizeof(T) == 4) {
+        if (L0.npad < ((int64_t)1 << 29)) {
+            v4_.coded = cod != nullptr;
+            if (cod) v4_.cg = CodeGrp{lv[0].codes, L0.npad, cod->dict, nullptr};
+            v4_.ag = ArrGrp{(const float*)s.op.cx, (const float*)s.op.cy, (const float*)s.op.cz, (const float*)s.op.d,
+                            L0.npad};
+            v4 = &v4_;
+        }
+    }
+
     const int64_t npad = L0.npad;
     const Ranges R = ranges_for(npad);
     const unsigned g = stream_grid(npad);
@@ -770,22 +1051,34 @@ pb_status mg_pcg_impl(const Layout& L0, double h, const double* ex, const double
             T* pnew = pb_[(it + 1) & 1];
             T* rold = rb[it & 1];
             T* rnew = rb[(it + 1) & 1];
-            with_reader<T>(cod, s.op, [&](auto rd) {
-                using RD = decltype(rd);
-                hipLaunchKernelGGL((k_mg_direction_apply<T, RD>), dim3(R.nblk), dim3(kBS), 0, st, rd, (const T*)z,
-                                   (const T*)pold, pnew, s.q, L0.nx, L0.sp, npad, R.per, partials,
-                                   (const SyncState*)S);
-            });
+            bool vec_dir = false;
+            if constexpr (sizeof(T) == 4) {
+                if (v4) {
+                    with_vec4(*v4, [&](auto rd) {
+                        hipLaunchKernelGGL((k_mg4_direction_apply<decltype(rd)>), dim3(R.nblk), dim3(kBS), 0, st, rd,
+                                           (const float*)z, (const float*)pold, (float*)pnew, (float*)s.q, L0.nx,
+                                           L0.sp, npad, R.per, partials, (const SyncState*)S);
+                    });
+                    vec_dir = true;
+                }
+            }
+            if (!vec_dir)
+                with_reader<T>(cod, s.op, [&](auto rd) {
+                    using RD = decltype(rd);
+                    hipLaunchKernelGGL((k_mg_direction_apply<T, RD>), dim3(R.nblk), dim3(kBS), 0, st, rd,
+                                       (const T*)z, (const T*)pold, pnew, s.q, L0.nx, L0.sp, npad, R.per, partials,
+                                       (const SyncState*)S);
+                });
             hipLaunchKernelGGL(k_scalar_alpha, dim3(1), dim3(kBS), 0, st, S, (const double*)partials, R.nblk);
             lv[0].b = rnew;
             if (lv.size() > 1) {
                 hipLaunchKernelGGL(k_mg_update<T>, dim3(g), dim3(kBS), 0, st, s.x, (const T*)pnew, (const T*)rold,
                                    (const T*)s.q, rnew, s.op.d, lv[0].xa, om, npad, (const SyncState*)S);
-                z = vcycle<T>(lv, 0, S, st, &fuse, lv[0].xa, 1, cod);   // also stores the block sums of r.z and r.r
+                z = vcycle<T>(lv, 0, S, st, &fuse, lv[0].xa, 1, cod, v4);   // also stores the block sums of r.z and r.r
             } else {
                 hipLaunchKernelGGL(k_mg_update<T>, dim3(g), dim3(kBS), 0, st, s.x, (const T*)pnew, (const T*)rold,
                                    (const T*)s.q, rnew, s.op.d, (T*)nullptr, om, npad, (const SyncState*)S);
-                z = vcycle<T>(lv, 0, S, st, nullptr, nullptr, 0, cod);
+                z = vcycle<T>(lv, 0, S, st, nullptr, nullptr, 0, cod, v4);
                 hipLaunchKernelGGL(k_mg_dot2<T>, dim3(R.nblk), dim3(kBS), 0, st, (const T*)rnew, (const T*)z, npad,
                                    R.per, partials, (const SyncState*)S);
             }

@@ -22,12 +22,15 @@ struct Ranges {
 };
 
 // Block ranges of the kernels that also store per-block sums: about 1024
-// positions per block (four per thread), at most 16384 blocks, so that the
-// grid fills the device like a plain one-position-per-thread launch would.
+// positions per block, at most 4096 blocks (the single-workgroup scalar
+// kernels sum every block's partials; at 16384 blocks that alone took about
+// 15 us per reduction). The block length is a multiple of 4 (the four-wide
+// kernels' groups).
 Ranges ranges_for(int64_t npad) {
     Ranges r;
-    r.nblk = (int)std::min<int64_t>(16384, std::max<int64_t>(1, (npad + 1023) / 1024));
-    r.per = (npad + r.nblk - 1) / r.nblk;
+    const int64_t nb = std::min<int64_t>(4096, std::max<int64_t>(1, (npad + 1023) / 1024));
+    r.per = ((npad + nb - 1) / nb + 3) / 4 * 4;
+    r.nblk = (int)((npad + r.per - 1) / r.per);
     return r;
 }
 

@@ -37,6 +37,77 @@ namespace {
 constexpr double kInnerTol = 1e-4;
 constexpr int kMaxOuter = 20;
 
+// A request's tiling: the batch kernel's, with the z-chunk cut (down to
+// kServeMinZ planes) until the request has kServeTiles tiles, so that a
+// small or mid-size grid spreads over enough workgroups to iterate quickly
+// when the server is lightly loaded. It depends on the request's grid only
+// (and the device's batch z-chunk), so a request's arithmetic is the same
+// whatever else is in flight.
+constexpr int kServeTiles = 128;
+constexpr int kServeMinZ = 8;
+
+Tiling serve_tiling(const Layout& L) {
+    Tiling t = batch_tiling<float>(L);
+    if (t.ntiles <= 0 || t.ntiles >= kServeTiles || t.zchunk <= kServeMinZ) return t;
+    const int nzc = (kServeTiles + t.nseg - 1) / t.nseg;
+    const int z = std::max(kServeMinZ, (L.nz + nzc - 1) / nzc);
+    return z < t.zchunk ? batch_tiling<float>(L, z) : t;
+}
+
+// Per-iteration cost of one running request, in node updates of its busiest
+// workgroup: the tiles that workgroup owns (tiles are whole, so the count is
+// a ceiling) each take zchunk + 2 plane steps of one segment, plus the
+// request's grid barrier and reductions, about 5.5 us, which the fused pass
+// at 257^3 spends on about 3,500 node updates per workgroup (1.6 ns each).
+constexpr double kBarrierNodes = 3500.0;
+// A request advances by at most this many times the caller's chunk per launch.
+constexpr int kMaxChunkScale = 16;
+
+double iter_cost(const Tiling& t, int g) {
+    const int per = (t.ntiles + g - 1) / g;
+    return (double)per * (double)t.seglen * (double)(t.zchunk + 2) + kBarrierNodes;
+}
+
+// Workgroups and iteration counts of one launch over the running requests.
+// Workgroups go, one useful step at a time, to the request whose iterations
+// are the slowest (a step is the fewest extra workgroups that take one tile
+// off its busiest workgroup), so the launch's slowest iteration is as short
+// as the co-resident capacity allows. Every request then runs as many
+// iterations as fit into the slowest request's `chunk` iterations (at least
+// `chunk`, at most kMaxChunkScale times it): cheap requests (small grids, or
+// the ones that got all the workgroups they can use) do not idle while the
+// slow ones finish, and finish in fewer launches. Neither the workgroup
+// count nor the iteration count of a launch changes a request's arithmetic.
+void share_launch(const std::vector<Tiling>& Ts, int cap, int chunk, std::vector<int>& first,
+                  std::vector<int>& chunks) {
+    const int n = (int)Ts.size();
+    std::vector<int> g(n, 1);
+    std::vector<char> stuck(n, 0);
+    int used = n;
+    for (;;) {
+        int best = -1;
+        for (int i = 0; i < n; ++i)
+            if (!stuck[i] && g[i] < Ts[i].ntiles && (best < 0 || iter_cost(Ts[i], g[i]) > iter_cost(Ts[best], g[best])))
+                best = i;
+        if (best < 0) break;
+        const int nt = Ts[best].ntiles, per = (nt + g[best] - 1) / g[best];
+        const int want = (nt + per - 2) / (per - 1);   // fewest workgroups with per - 1 tiles each
+        if (used + (want - g[best]) > cap) {
+            stuck[best] = 1;
+            continue;
+        }
+        used += want - g[best];
+        g[best] = want;
+    }
+    double cmax = 0.0;
+    for (int i = 0; i < n; ++i) cmax = std::max(cmax, iter_cost(Ts[i], g[i]));
+    for (int i = 0; i < n; ++i) {
+        first[i + 1] = first[i] + g[i];
+        const double scale = std::min<double>(kMaxChunkScale, cmax / iter_cost(Ts[i], g[i]));
+        chunks[i] = std::max(chunk, (int)std::min<double>(2e9, std::floor(chunk * scale)));
+    }
+}
+
 struct SlotRec {   // per-slot results written by kernels and read by the host
     int flags;
     int fit;       // 1: the FP32 operator fits the coded-coefficient dictionary
@@ -229,7 +300,7 @@ extern "C" size_t pb_server_request_bytes(const pb_problem* req) {
     if (!req || req->nx < 1 || req->ny < 1 || req->nz < 1) return 0;
     Slot s;
     s.L = make_layout(req->nx, req->ny, req->nz);
-    s.t = batch_tiling<float>(s.L);
+    s.t = serve_tiling(s.L);
     if (s.t.ntiles <= 0) return 0;
     return carve_slot(nullptr, s);
 }
@@ -276,7 +347,7 @@ extern "C" pb_status pb_server_submit(pb_server* S, const pb_problem* req, int32
     s->req = *req;
     s->precision = precision;
     s->L = make_layout(req->nx, req->ny, req->nz);
-    s->t = batch_tiling<float>(s->L);
+    s->t = serve_tiling(s->L);
     PB_ARG(s->t.ntiles > 0, "pb_server_submit: grid too wide for the batch kernel (nx <= 512)");
     s->bytes = carve_slot(nullptr, *s);
     PB_ARG(s->bytes <= S->arena_bytes - S->reserved, "pb_server_submit: request larger than the whole arena");
@@ -294,7 +365,7 @@ extern "C" size_t pb_server_request_bytes_atoms(const pb_grid* grid, int64_t nat
     s.from_atoms = true;
     s.natoms = natoms;
     s.L = make_layout(grid->nx, grid->ny, grid->nz);
-    s.t = batch_tiling<float>(s.L);
+    s.t = serve_tiling(s.L);
     if (s.t.ntiles <= 0) return 0;
     return carve_slot(nullptr, s);
 }
@@ -337,7 +408,7 @@ extern "C" pb_status pb_server_submit_atoms(pb_server* S, const pb_grid* grid, i
     s->req.x = x;
     s->precision = precision;
     s->L = make_layout(grid->nx, grid->ny, grid->nz);
-    s->t = batch_tiling<float>(s->L);
+    s->t = serve_tiling(s->L);
     PB_ARG(s->t.ntiles > 0, "pb_server_submit_atoms: grid too wide for the batch kernel (nx <= 512)");
     s->bytes = carve_slot(nullptr, *s);
     PB_ARG(s->bytes <= S->arena_bytes - S->reserved, "pb_server_submit_atoms: request larger than the whole arena");
@@ -482,35 +553,14 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
             set_error("pb_server_step: %zu active solves exceed %d co-resident workgroups", run.size(), cap);
             return PB_ERR_ARG;
         }
-        std::vector<int> first(run.size() + 1, 0);
-        {
-            // workgroups in proportion to work, at least one each (same rule
-            // as the batch). Giving the requests with the least remaining work
-            // the spare workgroups first was measured on the config-4 trace:
-            // light-load latency fell but saturated throughput halved (small
-            // requests with many workgroups are barrier-bound, large ones
-            // with one workgroup need many launches).
-            std::vector<double> w(run.size());
-            std::vector<int> g(run.size(), 1);
-            for (size_t i = 0; i < run.size(); ++i)
-                w[i] = (double)Ls[i].n * std::max(Ls[i].nx, std::max(Ls[i].ny, Ls[i].nz));
-            int used = (int)run.size();
-            while (used < cap) {
-                int best = -1;
-                for (size_t i = 0; i < run.size(); ++i)
-                    if (g[i] < Ts[i].ntiles && (best < 0 || w[i] / g[i] > w[best] / g[best])) best = (int)i;
-                if (best < 0) break;
-                ++g[best];
-                ++used;
-            }
-            for (size_t i = 0; i < run.size(); ++i) first[i + 1] = first[i] + g[i];
-        }
+        std::vector<int> first(run.size() + 1, 0), chunks(run.size(), chunk);
+        share_launch(Ts, cap, chunk, first, chunks);
         const size_t kb = batch_kargs_bytes<float>();
         for (size_t i = 0; i < run.size(); ++i) {
             Slot& s = *run[i];
             const double tol = s.precision == PB_F32 ? s.req.tol : kInnerTol;
             batch_fill_kargs<float>(S->host_table.data() + kb * i, s.L, s.s, s.S, s.partials, s.t, tol, s.maxiter,
-                                    s.resume ? 1 : 0, chunk, coded ? (const float*)s.s.q2 : nullptr,
+                                    s.resume ? 1 : 0, chunks[i], coded ? (const float*)s.s.q2 : nullptr,
                                     coded ? dictionary_table(s.s.q) : nullptr);
         }
         PB_HIP(hipMemcpyAsync(S->table, S->host_table.data(), kb * run.size(), hipMemcpyHostToDevice, st));

@@ -470,26 +470,57 @@ def bench_serving(pbgpu, torch, synth, dev, nreq=2200, warm=200, rate=200.0, chu
                 "device_s": round(stats["device_seconds"], 3),
                 "energies_returned": sum(1 for i in range(nr) if done_at[i][2] is not None)}
 
-    full = run(nreq, rate, 4999)
-    light_rate = round(0.7 * full["solves_per_s"], 1)
-    light = run(max(400, nreq // 4), light_rate, 5999)
-    # the same requests one at a time: setup + fused solve + energy
-    lat_seq = []
-    for i in range(seq_sample):
+    def one(i):   # one request alone: setup + fused solve + energy
         p = reqs[i]
         xyz, rad, q = dev_atoms[i]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
         sysm = pbgpu.setup(p.grid, xyz, rad, q, p.eps_in, p.eps_out, p.kappa_d2, device=dev)
         x, _ = pbgpu.solve(sysm, tol=p.tol, precision=p.precision, out=out_for(p))
         pbgpu.energy(p.grid, xyz, q, x)
         torch.cuda.synchronize()
+
+    def run_fifo(nr, rate_, seed):
+        """The same arrival trace served one request at a time in arrival order."""
+        arrivals = synth.config4_arrivals(nr, rate=rate_, seed=seed)
+        done = np.zeros(nr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(nr):
+            wait = arrivals[i] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            one(i)
+            done[i] = time.perf_counter() - t0
+        w0 = warm if nr > warm else 0
+        lat = done[w0:] - arrivals[w0:nr]
+        thr = len(lat) / max(done[w0:].max() - min(arrivals[w0], done[w0:].min()), 1e-9)
+        return {"requests": nr, "offered_per_s": rate_, "solves_per_s": round(float(thr), 2),
+                "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2)}
+
+    full = run(nreq, rate, 4999)
+    # the same requests one at a time, back to back: the service time alone
+    lat_seq = []
+    for i in range(seq_sample):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        one(i)
         lat_seq.append(time.perf_counter() - t0)
     lat_seq = np.array(lat_seq)
+    seq_rate = float(len(lat_seq) / lat_seq.sum())
+    # latency under load, the server against a sequential FIFO server on the
+    # same arrival traces: at 0.7x the server's saturated rate (beyond what
+    # the sequential server can sustain) and at half the sequential rate
+    light_rate = round(0.7 * full["solves_per_s"], 1)
+    nl = max(400, nreq // 4)
+    light = run(nl, light_rate, 5999)
+    light["sequential_fifo"] = run_fifo(nl, light_rate, 5999)
+    half_rate = round(0.5 * seq_rate, 1)
+    half = run(nl, half_rate, 6999)
+    half["sequential_fifo"] = run_fifo(nl, half_rate, 6999)
     del dev_atoms, outs
     torch.cuda.empty_cache()
-    return {"trace": full, "at_0.7x_capacity": light,
-            "plain_fused_sequential": {"solves_per_s": round(float(len(lat_seq) / lat_seq.sum()), 2),
+    return {"trace": full, "at_0.7x_capacity": light, "at_0.5x_sequential_rate": half,
+            "plain_fused_sequential": {"solves_per_s": round(seq_rate, 2),
                                        "p50_ms": round(1e3 * float(np.percentile(lat_seq, 50)), 2),
                                        "p99_ms": round(1e3 * float(np.percentile(lat_seq, 99)), 2),
                                        "sample": len(lat_seq)},

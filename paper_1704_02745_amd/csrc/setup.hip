@@ -462,41 +462,58 @@ constexpr int kDhBlock = 256;
 // 1/sqrt(r2) for r2 > 0: the hardware estimate and two Newton steps,
 // y <- y (1 + (1 - r2 y^2)/2), each roughly doubling the correct bits.
 __device__ __forceinline__ double rsqrt_nr(double r2) {
+    // the hardware estimate, then two Newton steps y += y (1/2 - (r2/2) y^2)
+    const double h = 0.5 * r2;
     double y = __builtin_amdgcn_rsq(r2);
-    y = fma(0.5 * y, fma(-(r2 * y), y, 1.0), y);
-    y = fma(0.5 * y, fma(-(r2 * y), y, 1.0), y);
+    y = fma(y, fma(-(h * y), y, 0.5), y);
+    y = fma(y, fma(-(h * y), y, 0.5), y);
     return y;
 }
 
+// 2^(j/64), j = 0..63, each the double nearest to the exact value.
+constexpr int kExpTab = 64;
+__constant__ double kExp2Frac[kExpTab] = {
+    0x1.0000000000000p+0, 0x1.02c9a3e778061p+0, 0x1.059b0d3158574p+0, 0x1.0874518759bc8p+0,
+    0x1.0b5586cf9890fp+0, 0x1.0e3ec32d3d1a2p+0, 0x1.11301d0125b51p+0, 0x1.1429aaea92de0p+0,
+    0x1.172b83c7d517bp+0, 0x1.1a35beb6fcb75p+0, 0x1.1d4873168b9aap+0, 0x1.2063b88628cd6p+0,
+    0x1.2387a6e756238p+0, 0x1.26b4565e27cddp+0, 0x1.29e9df51fdee1p+0, 0x1.2d285a6e4030bp+0,
+    0x1.306fe0a31b715p+0, 0x1.33c08b26416ffp+0, 0x1.371a7373aa9cbp+0, 0x1.3a7db34e59ff7p+0,
+    0x1.3dea64c123422p+0, 0x1.4160a21f72e2ap+0, 0x1.44e086061892dp+0, 0x1.486a2b5c13cd0p+0,
+    0x1.4bfdad5362a27p+0, 0x1.4f9b2769d2ca7p+0, 0x1.5342b569d4f82p+0, 0x1.56f4736b527dap+0,
+    0x1.5ab07dd485429p+0, 0x1.5e76f15ad2148p+0, 0x1.6247eb03a5585p+0, 0x1.6623882552225p+0,
+    0x1.6a09e667f3bcdp+0, 0x1.6dfb23c651a2fp+0, 0x1.71f75e8ec5f74p+0, 0x1.75feb564267c9p+0,
+    0x1.7a11473eb0187p+0, 0x1.7e2f336cf4e62p+0, 0x1.82589994cce13p+0, 0x1.868d99b4492edp+0,
+    0x1.8ace5422aa0dbp+0, 0x1.8f1ae99157736p+0, 0x1.93737b0cdc5e5p+0, 0x1.97d829fde4e50p+0,
+    0x1.9c49182a3f090p+0, 0x1.a0c667b5de565p+0, 0x1.a5503b23e255dp+0, 0x1.a9e6b5579fdbfp+0,
+    0x1.ae89f995ad3adp+0, 0x1.b33a2b84f15fbp+0, 0x1.b7f76f2fb5e47p+0, 0x1.bcc1e904bc1d2p+0,
+    0x1.c199bdd85529cp+0, 0x1.c67f12e57d14bp+0, 0x1.cb720dcef9069p+0, 0x1.d072d4a07897cp+0,
+    0x1.d5818dcfba487p+0, 0x1.da9e603db3285p+0, 0x1.dfc97337b9b5fp+0, 0x1.e502ee78b3ff6p+0,
+    0x1.ea4afa2a490dap+0, 0x1.efa1bee615a27p+0, 0x1.f50765b6e4540p+0, 0x1.fa7c1819e90d8p+0,
+};
+
 // e^x for x <= 0 (the screening factor e^(-kappa d)), without the range
-// checks of a general exponential. Cody and Waite's argument reduction,
-// x = n ln2 + r with |r| <= ln2/2, takes ln 2 in two parts: a head with 32
-// significant bits, so that n * head is exact for any n this range gives,
-// and the rounded remainder. e^r is the Taylor series to degree 13, whose
-// truncation is below 5e-18 relative on that interval, evaluated by Horner's
-// rule; ldexp applies 2^n and rounds results below the normal range as they
-// underflow.
-__device__ __forceinline__ double exp_nonpos(double x) {
-    constexpr double kInvLn2 = 1.4426950408889634;
-    constexpr double kLn2Head = 0x1.62e42fee00000p-1;
-    constexpr double kLn2Tail = 0x1.a39ef35793c76p-33;
-    const double fn = rint(x * kInvLn2);
-    const double r = fma(-fn, kLn2Tail, fma(-fn, kLn2Head, x));
-    double p = 1.0 / 6227020800.0;           // 1/13!
-    p = fma(p, r, 1.0 / 479001600.0);        // 1/12!
-    p = fma(p, r, 1.0 / 39916800.0);         // 1/11!
-    p = fma(p, r, 1.0 / 3628800.0);          // 1/10!
-    p = fma(p, r, 1.0 / 362880.0);           // 1/9!
-    p = fma(p, r, 1.0 / 40320.0);            // 1/8!
-    p = fma(p, r, 1.0 / 5040.0);             // 1/7!
-    p = fma(p, r, 1.0 / 720.0);              // 1/6!
-    p = fma(p, r, 1.0 / 120.0);              // 1/5!
-    p = fma(p, r, 1.0 / 24.0);               // 1/4!
-    p = fma(p, r, 1.0 / 6.0);                // 1/3!
-    p = fma(p, r, 0.5);                      // 1/2!
-    p = fma(p, r, 1.0);
-    p = fma(p, r, 1.0);
-    return ldexp(p, (int)fn);
+// checks of a general exponential, with `tab` the table above (an LDS copy
+// on the device). Tang's table-driven reduction: x = (64 n + j) ln2/64 + r,
+// |r| <= ln2/128, so e^x = 2^n 2^(j/64) e^r. ln2/64 is taken in two parts, a
+// head with 32 significant bits (n * head is exact for any n this range
+// gives) and the rounded remainder. e^r - 1 is the Taylor series to degree
+// 5, whose truncation is below 4e-17 relative on that interval; the result
+// is 2^(j/64) + 2^(j/64) (e^r - 1) in one rounding, and ldexp applies 2^n
+// (rounding results below the normal range as they underflow).
+__device__ __forceinline__ double exp_nonpos(double x, const double* tab) {
+    constexpr double k64InvLn2 = 92.332482616893658;
+    constexpr double kHead = 0x1.62e42fee00000p-7;
+    constexpr double kTail = 0x1.a39ef35793c76p-39;
+    const double fk = rint(x * k64InvLn2);
+    const int k = (int)fk;
+    const double r = fma(-fk, kTail, fma(-fk, kHead, x));
+    const double r2 = r * r;
+    double p = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    const double em1 = fma(p, r2, r);
+    const double t = tab[k & (kExpTab - 1)];
+    return ldexp(fma(t, em1, t), k >> 6);
 }
 
 // Screened Coulomb sum of every atom at each ghost-face point, atoms in
@@ -507,6 +524,8 @@ __global__ __launch_bounds__(kDhBlock) void k_dh_faces(
         int nx, int ny, int nz, double h, double ox, double oy, double oz,
         double kd, double eout, double* __restrict__ ghost, int64_t nghost) {
     __shared__ double4 sa[kDhBlock];
+    __shared__ double s_tab[kExpTab];
+    if (threadIdx.x < kExpTab) s_tab[threadIdx.x] = kExp2Frac[threadIdx.x];
     const int64_t t = (int64_t)blockIdx.x * kDhBlock + threadIdx.x;
     double px = 0, py = 0, pz = 0;
     if (t < nghost) ghost_point(t, nx, ny, nz, h, ox, oy, oz, px, py, pz);
@@ -532,7 +551,7 @@ __global__ __launch_bounds__(kDhBlock) void k_dh_faces(
                 const double dx = px - c.x, dy = py - c.y, dz = pz - c.z;
                 const double r2 = dx * dx + dy * dy + dz * dz;
                 const double y = rsqrt_nr(r2);
-                s = fma(c.w * exp_nonpos(-kd * (r2 * y)), y, s);
+                s = fma(c.w * exp_nonpos(-kd * (r2 * y), s_tab), y, s);
             }
         }
     }

@@ -1,11 +1,13 @@
 """The boundary sum's exponential, built for the host from its device text.
 
 k_dh_faces takes the screening factor e^(-kappa d) from exp_nonpos (setup.hip):
-Cody-Waite reduction with a two-part ln 2 and the degree-13 Taylor series.
-Its text is extracted from setup.hip, compiled with g++ and compared with the
-C library's exp on x in [-745, 0]: within 2 units in the last place where the
-result is normal, within 2 subnormal steps below that, exactly 1 at 0 and
-monotone.
+Tang's table-driven reduction by ln2/64 (a 64-entry table of 2^(j/64), ln2/64
+in two parts) and the degree-5 Taylor series of e^r - 1. Its text and the
+table are extracted from setup.hip, compiled with g++ and compared with the C
+library's exp on x in [-745, 0], and densely on [-40, 0] (the screening
+factors of the benchmark workloads): within 2 units in the last place where
+the result is normal, within 2 subnormal steps below that, exactly 1 at 0 and
+monotone (also across the table's seams).
 """
 import re
 import shutil
@@ -22,16 +24,19 @@ DRIVER = r"""
 #include <cmath>
 #include <cstdio>
 #define __device__
+#define __constant__
 #define __forceinline__ inline
 using std::fma; using std::rint; using std::ldexp;
 #include "exp.inc"
 int main() {
-    const int n = 2000001;
+    const int n = 2000001, nd = 4000001;
     double worst_ulp = 0.0, worst_sub = 0.0, prev = 0.0;
     int nonmono = 0;
-    for (int i = 0; i < n; ++i) {
-        const double x = -745.0 + 745.0 * i / (n - 1);   // increasing x: results must not decrease
-        const double got = exp_nonpos(x), want = std::exp(x);
+    for (int i = 0; i < n + nd; ++i) {
+        // increasing x over [-745, 0], then again over [-40, 0]
+        const double x = i < n ? -745.0 + 745.0 * i / (n - 1) : -40.0 + 40.0 * (i - n) / (nd - 1);
+        const double got = exp_nonpos(x, kExp2Frac), want = std::exp(x);
+        if (i == n) prev = 0.0;
         if (i > 0 && got < prev) ++nonmono;
         prev = got;
         if (want >= DBL_MIN) {
@@ -41,14 +46,14 @@ int main() {
             worst_sub = std::fmax(worst_sub, std::fabs(got - want) / std::numeric_limits<double>::denorm_min());
         }
     }
-    std::printf("%.3f %.3f %d %.17g\n", worst_ulp, worst_sub, nonmono, exp_nonpos(0.0));
+    std::printf("%.3f %.3f %d %.17g\n", worst_ulp, worst_sub, nonmono, exp_nonpos(0.0, kExp2Frac));
     return 0;
 }
 """
 
 
 def _extract(src, name):
-    m = re.search(r"__device__ __forceinline__ double " + name + r"\(double x\) \{", src)
+    m = re.search(r"__device__ __forceinline__ double " + name + r"\(double x, const double\* tab\) \{", src)
     assert m, name
     depth, i = 0, m.end() - 1
     while True:
@@ -64,7 +69,10 @@ def _extract(src, name):
 def test_exp_nonpos_against_c_library(tmp_path):
     if shutil.which("g++") is None:
         pytest.skip("g++ not available")
-    text = _extract(SETUP.read_text(), "exp_nonpos")
+    src = SETUP.read_text()
+    tab = re.search(r"constexpr int kExpTab = 64;\n__constant__ double kExp2Frac\[kExpTab\] = \{[^}]*\};", src)
+    assert tab, "table"
+    text = tab.group(0) + "\n" + _extract(src, "exp_nonpos")
     (tmp_path / "exp.inc").write_text(text + "\n")
     (tmp_path / "drv.cpp").write_text(DRIVER.replace("#include <cstdio>", "#include <cstdio>\n#include <limits>"))
     exe = tmp_path / "drv"

@@ -241,21 +241,25 @@ __device__ __forceinline__ T mg_x1(const Op<T>& op, const T* __restrict__ b, int
 }
 
 template <typename T>
+__device__ __forceinline__ T mg_jacobi2z_at(const Op<T>& op, const T* __restrict__ b, int64_t t, int nx, int64_t sp,
+                                            int64_t npad, T omega) {
+    T nb = op.cx[t] * (t + 1 < npad ? mg_x1(op, b, t + 1, omega) : T(0));
+    nb += (t >= 1 ? op.cx[t - 1] * mg_x1(op, b, t - 1, omega) : T(0));
+    nb += op.cy[t] * (t + nx < npad ? mg_x1(op, b, t + nx, omega) : T(0));
+    nb += (t >= nx ? op.cy[t - nx] * mg_x1(op, b, t - nx, omega) : T(0));
+    nb += op.cz[t] * (t + sp < npad ? mg_x1(op, b, t + sp, omega) : T(0));
+    nb += (t >= sp ? op.cz[t - sp] * mg_x1(op, b, t - sp, omega) : T(0));
+    const T x1 = mg_x1(op, b, t, omega);
+    const T r = b[t] - (op.d[t] * x1 - nb);
+    return x1 + mg_div(omega * r, op.d[t]);
+}
+template <typename T>
 __global__ void k_mg_jacobi2z(Op<T> op, const T* __restrict__ b, T* __restrict__ out, int nx, int64_t sp,
                               int64_t npad, T omega, const SyncState* S) {
     if (S && stop(S)) return;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npad;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        T nb = op.cx[t] * (t + 1 < npad ? mg_x1(op, b, t + 1, omega) : T(0));
-        nb += (t >= 1 ? op.cx[t - 1] * mg_x1(op, b, t - 1, omega) : T(0));
-        nb += op.cy[t] * (t + nx < npad ? mg_x1(op, b, t + nx, omega) : T(0));
-        nb += (t >= nx ? op.cy[t - nx] * mg_x1(op, b, t - nx, omega) : T(0));
-        nb += op.cz[t] * (t + sp < npad ? mg_x1(op, b, t + sp, omega) : T(0));
-        nb += (t >= sp ? op.cz[t - sp] * mg_x1(op, b, t - sp, omega) : T(0));
-        const T x1 = mg_x1(op, b, t, omega);
-        const T r = b[t] - (op.d[t] * x1 - nb);
-        out[t] = x1 + mg_div(omega * r, op.d[t]);
-    }
+         t += (int64_t)gridDim.x * blockDim.x)
+        out[t] = mg_jacobi2z_at(op, b, t, nx, sp, npad, omega);
 }
 
 // The finest level's last post-smoothing sweep fused with the outer
@@ -305,6 +309,26 @@ __global__ void k_mg_apply(Op<T> op, const T* __restrict__ v, T* __restrict__ q,
 // Grid: blockIdx.y is the coarse plane K; the x-dimension strides over the
 // coarse plane's positions (pad slots get zero).
 template <typename T>
+__device__ __forceinline__ T mg_restrict_at(const T* __restrict__ r, int nx, int ny, int nz, int64_t sp, int I, int J,
+                                            int K) {
+    T acc = T(0);
+    for (int c = -1; c <= 1; ++c) {
+        const int k = 2 * K + 1 + c;
+        if (k < 0 || k >= nz) continue;
+        for (int b = -1; b <= 1; ++b) {
+            const int j = 2 * J + 1 + b;
+            if (j < 0 || j >= ny) continue;
+            const T* row = r + (int64_t)k * sp + (int64_t)j * nx;
+            for (int a = -1; a <= 1; ++a) {
+                const int i = 2 * I + 1 + a;
+                if (i < 0 || i >= nx) continue;
+                acc += (T)(w3(a) * w3(b) * w3(c)) * row[i];
+            }
+        }
+    }
+    return acc;
+}
+template <typename T>
 __global__ void k_mg_restrict(const T* __restrict__ r, int nx, int ny, int nz, int64_t sp, T* __restrict__ bc,
                               int ncx, int ncy, int ncz, int64_t spc, const SyncState* S) {
     if (S && stop(S)) return;
@@ -317,22 +341,7 @@ __global__ void k_mg_restrict(const T* __restrict__ r, int nx, int ny, int nz, i
             continue;
         }
         const int J = pp / ncx, I = pp - J * ncx;
-        T acc = T(0);
-        for (int c = -1; c <= 1; ++c) {
-            const int k = 2 * K + 1 + c;
-            if (k < 0 || k >= nz) continue;
-            for (int b = -1; b <= 1; ++b) {
-                const int j = 2 * J + 1 + b;
-                if (j < 0 || j >= ny) continue;
-                const T* row = r + (int64_t)k * sp + (int64_t)j * nx;
-                for (int a = -1; a <= 1; ++a) {
-                    const int i = 2 * I + 1 + a;
-                    if (i < 0 || i >= nx) continue;
-                    acc += (T)(w3(a) * w3(b) * w3(c)) * row[i];
-                }
-            }
-        }
-        bc[t] = acc;
+        bc[t] = mg_restrict_at(r, nx, ny, nz, sp, I, J, K);
     }
 }
 
@@ -344,6 +353,57 @@ __global__ void k_mg_restrict(const T* __restrict__ r, int nx, int ny, int nz, i
 // once. Each fine node sums its terms in z, y, x order, zero weights skipped.
 // Grid: blockIdx.y is K+1; the x-dimension strides over (I, J).
 template <typename T>
+__device__ __forceinline__ void mg_prolong_cell(const T* __restrict__ xc, int ncx, int ncy, int ncz, int64_t spc,
+                                                T* __restrict__ x, int nx, int ny, int nz, int64_t sp, int I, int J,
+                                                int K) {
+    T v[2][2][2];   // coarse (K+kk, J+jj, I+ii), zero outside the coarse grid
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+            for (int ii = 0; ii < 2; ++ii) {
+                const int ck = K + kk, cj = J + jj, ci = I + ii;
+                const bool in = ck >= 0 && ck < ncz && cj >= 0 && cj < ncy && ci >= 0 && ci < ncx;
+                v[kk][jj][ii] = in ? xc[(int64_t)ck * spc + (int64_t)cj * ncx + ci] : T(0);
+            }
+    // per axis, fine node 2C+1+e (e = 0 odd, 1 even): its terms (coarse
+    // offset, weight) in order; n = number of terms
+#pragma unroll
+    for (int ez = 0; ez < 2; ++ez) {
+        const int k = 2 * K + 1 + ez;
+        if (k < 0 || k >= nz) continue;
+#pragma unroll
+        for (int ey = 0; ey < 2; ++ey) {
+            const int j = 2 * J + 1 + ey;
+            if (j < 0 || j >= ny) continue;
+#pragma unroll
+            for (int ex = 0; ex < 2; ++ex) {
+                const int i = 2 * I + 1 + ex;
+                if (i < 0 || i >= nx) continue;
+                T add = T(0);
+                for (int tz = 0; tz <= ez; ++tz) {
+                    const int ck = K + tz;
+                    if (ck < 0 || ck >= ncz) continue;
+                    const T wz = ez ? T(0.5) : T(1);
+                    for (int ty = 0; ty <= ey; ++ty) {
+                        const int cj = J + ty;
+                        if (cj < 0 || cj >= ncy) continue;
+                        const T wy = ey ? T(0.5) : T(1);
+                        for (int tx = 0; tx <= ex; ++tx) {
+                            const int ci = I + tx;
+                            if (ci < 0 || ci >= ncx) continue;
+                            const T wx = ex ? T(0.5) : T(1);
+                            add += wx * wy * wz * v[tz][ty][tx];
+                        }
+                    }
+                }
+                x[(int64_t)k * sp + (int64_t)j * nx + i] += add;
+            }
+        }
+    }
+}
+template <typename T>
 __global__ void k_mg_prolong_add(const T* __restrict__ xc, int ncx, int ncy, int ncz, int64_t spc,
                                  T* __restrict__ x, int nx, int ny, int nz, int64_t sp, const SyncState* S) {
     if (S && stop(S)) return;
@@ -351,52 +411,7 @@ __global__ void k_mg_prolong_add(const T* __restrict__ xc, int ncx, int ncy, int
     const int cw = ncx + 1, cells = cw * (ncy + 1);
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += gridDim.x * blockDim.x) {
         const int J = c / cw - 1, I = c - (J + 1) * cw - 1;
-        T v[2][2][2];   // coarse (K+kk, J+jj, I+ii), zero outside the coarse grid
-#pragma unroll
-        for (int kk = 0; kk < 2; ++kk)
-#pragma unroll
-            for (int jj = 0; jj < 2; ++jj)
-#pragma unroll
-                for (int ii = 0; ii < 2; ++ii) {
-                    const int ck = K + kk, cj = J + jj, ci = I + ii;
-                    const bool in = ck >= 0 && ck < ncz && cj >= 0 && cj < ncy && ci >= 0 && ci < ncx;
-                    v[kk][jj][ii] = in ? xc[(int64_t)ck * spc + (int64_t)cj * ncx + ci] : T(0);
-                }
-        // per axis, fine node 2C+1+e (e = 0 odd, 1 even): its terms (coarse
-        // offset, weight) in order; n = number of terms
-#pragma unroll
-        for (int ez = 0; ez < 2; ++ez) {
-            const int k = 2 * K + 1 + ez;
-            if (k < 0 || k >= nz) continue;
-#pragma unroll
-            for (int ey = 0; ey < 2; ++ey) {
-                const int j = 2 * J + 1 + ey;
-                if (j < 0 || j >= ny) continue;
-#pragma unroll
-                for (int ex = 0; ex < 2; ++ex) {
-                    const int i = 2 * I + 1 + ex;
-                    if (i < 0 || i >= nx) continue;
-                    T add = T(0);
-                    for (int tz = 0; tz <= ez; ++tz) {
-                        const int ck = K + tz;
-                        if (ck < 0 || ck >= ncz) continue;
-                        const T wz = ez ? T(0.5) : T(1);
-                        for (int ty = 0; ty <= ey; ++ty) {
-                            const int cj = J + ty;
-                            if (cj < 0 || cj >= ncy) continue;
-                            const T wy = ey ? T(0.5) : T(1);
-                            for (int tx = 0; tx <= ex; ++tx) {
-                                const int ci = I + tx;
-                                if (ci < 0 || ci >= ncx) continue;
-                                const T wx = ex ? T(0.5) : T(1);
-                                add += wx * wy * wz * v[tz][ty][tx];
-                            }
-                        }
-                    }
-                    x[(int64_t)k * sp + (int64_t)j * nx + i] += add;
-                }
-            }
-        }
+        mg_prolong_cell(xc, ncx, ncy, ncz, spc, x, nx, ny, nz, sp, I, J, K);
     }
 }
 
@@ -474,6 +489,137 @@ __global__ __launch_bounds__(1024) void k_mg_coarse(Op<T> op, const T* __restric
             }
         }
         __syncthreads();
+    }
+}
+
+// The coarse end of the V-cycle in one workgroup: from level lv[0] (its
+// right-hand side already restricted from the finer level) down to the
+// coarsest level lv[n-1] and back up, each step with the per-node arithmetic
+// of the level kernels (so the same results bit for bit), the steps separated
+// by workgroup barriers instead of kernel launches. The coarsest level's
+// sweeps run on LDS copies of its operator, right-hand side and iterates when
+// `lds` is set (the launch then brings 7 npad values of dynamic LDS); its
+// result is written to the buffer k_mg_coarse would leave it in. The result
+// of the whole tail is lv[0].xa (the post-smoothing sweeps alternate
+// xb <- xa, xa <- xb).
+constexpr int kMgTailLevels = 4;
+constexpr int64_t kMgTailNodes = 8192;   // levels with at most this many padded positions join the tail
+template <typename T>
+struct TailLevel {
+    Op<T> op;
+    T *b, *xa, *xb, *r;
+    int nx, ny, nz;
+    int64_t sp, npad;
+};
+template <typename T>
+struct TailArgs {
+    TailLevel<T> lv[kMgTailLevels];
+    int n;
+    int lds;
+};
+static_assert(kMgNu == 2, "the tail's buffer rotation assumes two sweeps before and after");
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_mg_tail(TailArgs<T> A, T omega, const SyncState* S) {
+    if (S && stop(S)) return;
+    extern __shared__ __align__(16) unsigned char tail_lds[];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    // down: two sweeps from zero, the residual, the restriction
+    for (int l = 0; l + 1 < A.n; ++l) {
+        const TailLevel<T>& m = A.lv[l];
+        for (int64_t t = tid; t < m.npad; t += nt) m.xa[t] = mg_jacobi2z_at(m.op, (const T*)m.b, t, m.nx, m.sp, m.npad, omega);
+        __syncthreads();
+        for (int64_t t = tid; t < m.npad; t += nt)
+            m.r[t] = m.b[t] - mg_apply(m.op, (const T*)m.xa, t, m.nx, m.sp, m.npad);
+        __syncthreads();
+        const TailLevel<T>& c = A.lv[l + 1];
+        const int pc = c.nx * c.ny;
+        for (int64_t q = tid; q < (int64_t)c.nz * c.sp; q += nt) {
+            const int K = (int)(q / c.sp), pp = (int)(q - (int64_t)K * c.sp);
+            if (pp >= pc) {
+                c.b[q] = T(0);
+                continue;
+            }
+            const int J = pp / c.nx, I = pp - J * c.nx;
+            c.b[q] = mg_restrict_at((const T*)m.r, m.nx, m.ny, m.nz, m.sp, I, J, K);
+        }
+        __syncthreads();
+    }
+    // the coarsest level: the sweeps of k_mg_coarse
+    {
+        const TailLevel<T>& m = A.lv[A.n - 1];
+        const int64_t n = m.npad;
+        T* out_last = ((kMgCoarseSweeps - 1) & 1) ? m.xb : m.xa;
+        if (A.lds) {
+            T* cx = reinterpret_cast<T*>(tail_lds);
+            T* cy = cx + n;
+            T* cz = cy + n;
+            T* d = cz + n;
+            T* b = d + n;
+            T* u0 = b + n;
+            T* u1 = u0 + n;
+            for (int64_t t = tid; t < n; t += nt) {
+                cx[t] = m.op.cx[t];
+                cy[t] = m.op.cy[t];
+                cz[t] = m.op.cz[t];
+                d[t] = m.op.d[t];
+                b[t] = m.b[t];
+            }
+            __syncthreads();
+            const Op<T> lop{cx, cy, cz, d};
+            for (int it = 0; it < kMgCoarseSweeps; ++it) {
+                const T* in = (it & 1) ? u0 : u1;
+                T* out = (it & 1) ? u1 : u0;
+                for (int64_t t = tid; t < n; t += nt) {
+                    if (it == 0) {
+                        out[t] = mg_div(omega * b[t], d[t]);
+                    } else {
+                        const T r = b[t] - mg_apply(lop, in, t, m.nx, m.sp, n);
+                        out[t] = in[t] + mg_div(omega * r, d[t]);
+                    }
+                }
+                __syncthreads();
+            }
+            const T* res = ((kMgCoarseSweeps - 1) & 1) ? u1 : u0;
+            for (int64_t t = tid; t < n; t += nt) out_last[t] = res[t];
+        } else {
+            for (int it = 0; it < kMgCoarseSweeps; ++it) {
+                const T* in = (it & 1) ? m.xa : m.xb;
+                T* out = (it & 1) ? m.xb : m.xa;
+                for (int64_t t = tid; t < n; t += nt) {
+                    if (it == 0) {
+                        out[t] = mg_div(omega * m.b[t], m.op.d[t]);
+                    } else {
+                        const T r = m.b[t] - mg_apply(m.op, in, t, m.nx, m.sp, n);
+                        out[t] = in[t] + mg_div(omega * r, m.op.d[t]);
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+    }
+    // up: prolongation-add into the level's smoothed iterate (xa), two sweeps
+    for (int l = A.n - 2; l >= 0; --l) {
+        const TailLevel<T>& m = A.lv[l];
+        const TailLevel<T>& c = A.lv[l + 1];
+        const T* zc = (l + 2 == A.n) ? (((kMgCoarseSweeps - 1) & 1) ? c.xb : c.xa) : c.xa;
+        const int cw = c.nx + 1, cells = cw * (c.ny + 1);
+        for (int64_t q = tid; q < (int64_t)cells * (c.nz + 1); q += nt) {
+            const int K = (int)(q / cells) - 1, cc = (int)(q % cells);
+            const int J = cc / cw - 1, I = cc - (J + 1) * cw - 1;
+            mg_prolong_cell(zc, c.nx, c.ny, c.nz, c.sp, m.xa, m.nx, m.ny, m.nz, m.sp, I, J, K);
+        }
+        __syncthreads();
+        for (int s = 0; s < kMgNu; ++s) {
+            const T* in = (s & 1) ? m.xb : m.xa;
+            T* out = (s & 1) ? m.xa : m.xb;
+            for (int64_t t = tid; t < m.npad; t += nt) {
+                const T r = m.b[t] - mg_apply(m.op, in, t, m.nx, m.sp, m.npad);
+                out[t] = in[t] + mg_div(omega * r, m.op.d[t]);
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -843,6 +989,34 @@ unsigned reader_grid(unsigned g) {
 // level l into that buffer (one of the level's two iterate buffers). `cod`:
 // level 0's coded reader (the sweeps and the residual of level 0 read the
 // operator through it).
+// The first level of the single-workgroup tail: the coarsest level, and the
+// finer levels above it while they have at most kMgTailNodes padded
+// positions (at most kMgTailLevels levels in all, level 0 never).
+template <typename T>
+size_t mg_tail_start(const std::vector<MgLevel<T>>& lv) {
+    size_t i = lv.size() - 1;
+    while (i > 1 && lv.size() - (i - 1) <= (size_t)kMgTailLevels && lv[i - 1].L.npad <= kMgTailNodes) --i;
+    return i;
+}
+constexpr size_t kMgTailLds = 60 * 1024;   // dynamic LDS for the coarsest level's copies
+
+// The V-cycle from level ts (ts >= 1) down, in one launch; returns the
+// buffer holding level ts's result.
+template <typename T>
+T* launch_tail(std::vector<MgLevel<T>>& lv, size_t ts, const SyncState* S, hipStream_t st) {
+    TailArgs<T> A{};
+    A.n = (int)(lv.size() - ts);
+    for (int i = 0; i < A.n; ++i) {
+        MgLevel<T>& m = lv[ts + i];
+        A.lv[i] = TailLevel<T>{m.op, m.b, m.xa, m.xb, m.r, m.L.nx, m.L.ny, m.L.nz, m.L.sp, m.L.npad};
+    }
+    const size_t lds = 7 * sizeof(T) * (size_t)lv.back().L.npad;
+    A.lds = lds <= kMgTailLds ? 1 : 0;
+    hipLaunchKernelGGL(k_mg_tail<T>, dim3(1), dim3(1024), A.lds ? lds : 0, st, A, (T)kMgOmega, S);
+    if (A.n == 1) return ((kMgCoarseSweeps - 1) & 1) ? lv.back().xb : lv.back().xa;
+    return lv[ts].xa;
+}
+
 template <typename T>
 T* vcycle(std::vector<MgLevel<T>>& lv, size_t l, const SyncState* S, hipStream_t st, const DotFuse* fuse = nullptr,
           T* presmoothed = nullptr, int pre_done = 0, const CodeOp* cod = nullptr, const Vec4Rd* v4 = nullptr) {
@@ -923,7 +1097,8 @@ T* vcycle(std::vector<MgLevel<T>>& lv, size_t l, const SyncState* S, hipStream_t
     MgLevel<T>& c = lv[l + 1];
     hipLaunchKernelGGL(k_mg_restrict<T>, plane_grid(c.L.sp, c.L.nz), dim3(kBS), 0, st, (const T*)m.r, L.nx, L.ny,
                        L.nz, L.sp, c.b, c.L.nx, c.L.ny, c.L.nz, c.L.sp, S);
-    T* zc = vcycle<T>(lv, l + 1, S, st, nullptr, nullptr, 0, nullptr, v4);
+    T* zc = (l + 1 == mg_tail_start(lv)) ? launch_tail<T>(lv, l + 1, S, st)
+                                          : vcycle<T>(lv, l + 1, S, st, nullptr, nullptr, 0, nullptr, v4);
     hipLaunchKernelGGL(k_mg_prolong_add<T>, plane_grid((int64_t)(c.L.nx + 1) * (c.L.ny + 1), c.L.nz + 1), dim3(kBS),
                        0, st, (const T*)zc, c.L.nx, c.L.ny, c.L.nz, c.L.sp, z, L.nx, L.ny, L.nz, L.sp, S);
     cur = (z == m.xa) ? m.xb : m.xa;

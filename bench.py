@@ -233,6 +233,39 @@ def bench_c1(pbgpu, torch, synth, dev, reps=3):
     return out
 
 
+def bench_small(pbgpu, torch, synth, dev, reps=5):
+    """Small grids (the served requests' range), FP32 to 1e-6: the fused
+    kernel (one grid barrier and one reduction of all its sums per iteration,
+    one launch per solve) against the DIA form (the listing's two reductions
+    per iteration in separate kernels, host-driven): wall time per solve and
+    per iteration."""
+    out = {}
+    for n, natoms in ((33, 40), (49, 120), (65, 300), (97, 900)):
+        p = synth.small_problem(n, n, n, natoms, seed=900 + n, precision="f32", tol=1e-6)
+        g = p.grid
+        sm = pbgpu.setup(g, p.mol.xyz, p.mol.radius, p.mol.charge, p.eps_in, p.eps_out, p.kappa_d2, device=dev)
+        row = {}
+        for op in ("stencil", "dia"):
+            pbgpu.solve(sm, tol=1e-6, precision="f32", op=op)
+            best = None
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info = pbgpu.solve(sm, tol=1e-6, precision="f32", op=op)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                if best is None or dt < best[0]:
+                    best = (dt, info)
+            dt, info = best
+            row[op] = {"iters": info["iters"], "solve_ms": round(1e3 * dt, 3),
+                       "us_per_iter_wall": round(1e6 * dt / max(info["iters"], 1), 2)}
+        row["speedup_fused_vs_dia"] = round(row["dia"]["solve_ms"] / row["stencil"]["solve_ms"], 2)
+        out[f"{n}^3"] = row
+        del sm
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_slab(pbgpu, torch, synth, dev, iters=200):
     """One GPU's share of an 8-way z-slab split of the 257^3 solve: the fused
     kernel alone on 257 x 257 x 33 nodes (the halo exchange and the all-reduce
@@ -529,7 +562,7 @@ def bench_serving(pbgpu, torch, synth, dev, nreq=2200, warm=200, rate=200.0, chu
 
 
 # Forms reported beside the main line (also runnable alone with --forms-only).
-FORMS = {"c1": bench_c1, "mg": bench_mg, "f1_solvation": bench_solvation, "f2_periodic": bench_periodic,
+FORMS = {"c1": bench_c1, "small": bench_small, "mg": bench_mg, "f1_solvation": bench_solvation, "f2_periodic": bench_periodic,
          "slab": bench_slab, "batched": bench_batched, "served": bench_serving}
 
 
@@ -677,6 +710,9 @@ def main():
         print("bench: config 1 (129^3 stencil vs DIA)", file=sys.stderr, flush=True)
         forms["c1_129_stencil_vs_dia"] = bench_c1(pbgpu, torch, synth, dev)
         print(f"bench: {forms['c1_129_stencil_vs_dia']}", file=sys.stderr, flush=True)
+        print("bench: small grids, fused single-reduction vs DIA", file=sys.stderr, flush=True)
+        forms["small_grids_fused_vs_dia"] = bench_small(pbgpu, torch, synth, dev)
+        print(f"bench: {forms['small_grids_fused_vs_dia']}", file=sys.stderr, flush=True)
         print("bench: multigrid-preconditioned CG (config 2)", file=sys.stderr, flush=True)
         forms["c2_multigrid_vs_jacobi"] = bench_mg(pbgpu, torch, synth, dev)
         print(f"bench: {forms['c2_multigrid_vs_jacobi']}", file=sys.stderr, flush=True)

@@ -472,155 +472,56 @@ __global__ void k_mg_update(T* __restrict__ x, const T* __restrict__ p, const T*
 
 // The coarsest level: `sweeps` damped-Jacobi sweeps from zero by one
 // workgroup (the level is small); buf[(sweeps-1) & 1] holds the result.
+// With `lds` set the sweeps run on LDS copies of the operator, right-hand
+// side and iterates (the launch brings 7 npad values of dynamic LDS), with
+// the same arithmetic, and the result is copied out at the end.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_mg_coarse(Op<T> op, const T* __restrict__ b, T* __restrict__ buf0,
-                                                    T* __restrict__ buf1, int nx, int64_t sp, int64_t npad, T omega,
-                                                    int sweeps, const SyncState* S) {
-    if (S && stop(S)) return;
+__device__ __forceinline__ void mg_coarse_sweeps(const Op<T>& o, const T* __restrict__ b, T* __restrict__ u0,
+                                                 T* __restrict__ u1, int nx, int64_t sp, int64_t npad, T omega,
+                                                 int sweeps) {
     for (int it = 0; it < sweeps; ++it) {
-        const T* in = (it & 1) ? buf0 : buf1;
-        T* out = (it & 1) ? buf1 : buf0;
+        const T* in = (it & 1) ? u0 : u1;
+        T* out = (it & 1) ? u1 : u0;
         for (int64_t t = threadIdx.x; t < npad; t += blockDim.x) {
             if (it == 0) {
-                out[t] = mg_div(omega * b[t], op.d[t]);
+                out[t] = mg_div(omega * b[t], o.d[t]);
             } else {
-                const T r = b[t] - mg_apply(op, in, t, nx, sp, npad);
-                out[t] = in[t] + mg_div(omega * r, op.d[t]);
+                const T r = b[t] - mg_apply(o, in, t, nx, sp, npad);
+                out[t] = in[t] + mg_div(omega * r, o.d[t]);
             }
         }
         __syncthreads();
     }
 }
-
-// The coarse end of the V-cycle in one workgroup: from level lv[0] (its
-// right-hand side already restricted from the finer level) down to the
-// coarsest level lv[n-1] and back up, each step with the per-node arithmetic
-// of the level kernels (so the same results bit for bit), the steps separated
-// by workgroup barriers instead of kernel launches. The coarsest level's
-// sweeps run on LDS copies of its operator, right-hand side and iterates when
-// `lds` is set (the launch then brings 7 npad values of dynamic LDS); its
-// result is written to the buffer k_mg_coarse would leave it in. The result
-// of the whole tail is lv[0].xa (the post-smoothing sweeps alternate
-// xb <- xa, xa <- xb).
-constexpr int kMgTailLevels = 4;
-constexpr int64_t kMgTailNodes = 8192;   // levels with at most this many padded positions join the tail
 template <typename T>
-struct TailLevel {
-    Op<T> op;
-    T *b, *xa, *xb, *r;
-    int nx, ny, nz;
-    int64_t sp, npad;
-};
-template <typename T>
-struct TailArgs {
-    TailLevel<T> lv[kMgTailLevels];
-    int n;
-    int lds;
-};
-static_assert(kMgNu == 2, "the tail's buffer rotation assumes two sweeps before and after");
-
-template <typename T>
-__global__ __launch_bounds__(1024) void k_mg_tail(TailArgs<T> A, T omega, const SyncState* S) {
+__global__ __launch_bounds__(1024) void k_mg_coarse(Op<T> op, const T* __restrict__ b, T* __restrict__ buf0,
+                                                    T* __restrict__ buf1, int nx, int64_t sp, int64_t npad, T omega,
+                                                    int sweeps, int lds, const SyncState* S) {
     if (S && stop(S)) return;
-    extern __shared__ __align__(16) unsigned char tail_lds[];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    // down: two sweeps from zero, the residual, the restriction
-    for (int l = 0; l + 1 < A.n; ++l) {
-        const TailLevel<T>& m = A.lv[l];
-        for (int64_t t = tid; t < m.npad; t += nt) m.xa[t] = mg_jacobi2z_at(m.op, (const T*)m.b, t, m.nx, m.sp, m.npad, omega);
-        __syncthreads();
-        for (int64_t t = tid; t < m.npad; t += nt)
-            m.r[t] = m.b[t] - mg_apply(m.op, (const T*)m.xa, t, m.nx, m.sp, m.npad);
-        __syncthreads();
-        const TailLevel<T>& c = A.lv[l + 1];
-        const int pc = c.nx * c.ny;
-        for (int64_t q = tid; q < (int64_t)c.nz * c.sp; q += nt) {
-            const int K = (int)(q / c.sp), pp = (int)(q - (int64_t)K * c.sp);
-            if (pp >= pc) {
-                c.b[q] = T(0);
-                continue;
-            }
-            const int J = pp / c.nx, I = pp - J * c.nx;
-            c.b[q] = mg_restrict_at((const T*)m.r, m.nx, m.ny, m.nz, m.sp, I, J, K);
-        }
-        __syncthreads();
+    if (!lds) {
+        mg_coarse_sweeps(op, b, buf0, buf1, nx, sp, npad, omega, sweeps);
+        return;
     }
-    // the coarsest level: the sweeps of k_mg_coarse
-    {
-        const TailLevel<T>& m = A.lv[A.n - 1];
-        const int64_t n = m.npad;
-        T* out_last = ((kMgCoarseSweeps - 1) & 1) ? m.xb : m.xa;
-        if (A.lds) {
-            T* cx = reinterpret_cast<T*>(tail_lds);
-            T* cy = cx + n;
-            T* cz = cy + n;
-            T* d = cz + n;
-            T* b = d + n;
-            T* u0 = b + n;
-            T* u1 = u0 + n;
-            for (int64_t t = tid; t < n; t += nt) {
-                cx[t] = m.op.cx[t];
-                cy[t] = m.op.cy[t];
-                cz[t] = m.op.cz[t];
-                d[t] = m.op.d[t];
-                b[t] = m.b[t];
-            }
-            __syncthreads();
-            const Op<T> lop{cx, cy, cz, d};
-            for (int it = 0; it < kMgCoarseSweeps; ++it) {
-                const T* in = (it & 1) ? u0 : u1;
-                T* out = (it & 1) ? u1 : u0;
-                for (int64_t t = tid; t < n; t += nt) {
-                    if (it == 0) {
-                        out[t] = mg_div(omega * b[t], d[t]);
-                    } else {
-                        const T r = b[t] - mg_apply(lop, in, t, m.nx, m.sp, n);
-                        out[t] = in[t] + mg_div(omega * r, d[t]);
-                    }
-                }
-                __syncthreads();
-            }
-            const T* res = ((kMgCoarseSweeps - 1) & 1) ? u1 : u0;
-            for (int64_t t = tid; t < n; t += nt) out_last[t] = res[t];
-        } else {
-            for (int it = 0; it < kMgCoarseSweeps; ++it) {
-                const T* in = (it & 1) ? m.xa : m.xb;
-                T* out = (it & 1) ? m.xb : m.xa;
-                for (int64_t t = tid; t < n; t += nt) {
-                    if (it == 0) {
-                        out[t] = mg_div(omega * m.b[t], m.op.d[t]);
-                    } else {
-                        const T r = m.b[t] - mg_apply(m.op, in, t, m.nx, m.sp, n);
-                        out[t] = in[t] + mg_div(omega * r, m.op.d[t]);
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        __syncthreads();
+    extern __shared__ __align__(16) unsigned char coarse_lds[];
+    T* cx = reinterpret_cast<T*>(coarse_lds);
+    T* cy = cx + npad;
+    T* cz = cy + npad;
+    T* d = cz + npad;
+    T* bl = d + npad;
+    T* u0 = bl + npad;
+    T* u1 = u0 + npad;
+    for (int64_t t = threadIdx.x; t < npad; t += blockDim.x) {
+        cx[t] = op.cx[t];
+        cy[t] = op.cy[t];
+        cz[t] = op.cz[t];
+        d[t] = op.d[t];
+        bl[t] = b[t];
     }
-    // up: prolongation-add into the level's smoothed iterate (xa), two sweeps
-    for (int l = A.n - 2; l >= 0; --l) {
-        const TailLevel<T>& m = A.lv[l];
-        const TailLevel<T>& c = A.lv[l + 1];
-        const T* zc = (l + 2 == A.n) ? (((kMgCoarseSweeps - 1) & 1) ? c.xb : c.xa) : c.xa;
-        const int cw = c.nx + 1, cells = cw * (c.ny + 1);
-        for (int64_t q = tid; q < (int64_t)cells * (c.nz + 1); q += nt) {
-            const int K = (int)(q / cells) - 1, cc = (int)(q % cells);
-            const int J = cc / cw - 1, I = cc - (J + 1) * cw - 1;
-            mg_prolong_cell(zc, c.nx, c.ny, c.nz, c.sp, m.xa, m.nx, m.ny, m.nz, m.sp, I, J, K);
-        }
-        __syncthreads();
-        for (int s = 0; s < kMgNu; ++s) {
-            const T* in = (s & 1) ? m.xb : m.xa;
-            T* out = (s & 1) ? m.xa : m.xb;
-            for (int64_t t = tid; t < m.npad; t += nt) {
-                const T r = m.b[t] - mg_apply(m.op, in, t, m.nx, m.sp, m.npad);
-                out[t] = in[t] + mg_div(omega * r, m.op.d[t]);
-            }
-            __syncthreads();
-        }
-    }
+    __syncthreads();
+    mg_coarse_sweeps(Op<T>{cx, cy, cz, d}, (const T*)bl, u0, u1, nx, sp, npad, omega, sweeps);
+    const T* res = ((sweeps - 1) & 1) ? u1 : u0;
+    T* dst = ((sweeps - 1) & 1) ? buf1 : buf0;
+    for (int64_t t = threadIdx.x; t < npad; t += blockDim.x) dst[t] = res[t];
 }
 
 // Outer-iteration pieces: p = z with the sums r.z, r.r, b.b; and r.z, r.r.
@@ -989,33 +890,7 @@ unsigned reader_grid(unsigned g) {
 // level l into that buffer (one of the level's two iterate buffers). `cod`:
 // level 0's coded reader (the sweeps and the residual of level 0 read the
 // operator through it).
-// The first level of the single-workgroup tail: the coarsest level, and the
-// finer levels above it while they have at most kMgTailNodes padded
-// positions (at most kMgTailLevels levels in all, level 0 never).
-template <typename T>
-size_t mg_tail_start(const std::vector<MgLevel<T>>& lv) {
-    size_t i = lv.size() - 1;
-    while (i > 1 && lv.size() - (i - 1) <= (size_t)kMgTailLevels && lv[i - 1].L.npad <= kMgTailNodes) --i;
-    return i;
-}
-constexpr size_t kMgTailLds = 60 * 1024;   // dynamic LDS for the coarsest level's copies
-
-// The V-cycle from level ts (ts >= 1) down, in one launch; returns the
-// buffer holding level ts's result.
-template <typename T>
-T* launch_tail(std::vector<MgLevel<T>>& lv, size_t ts, const SyncState* S, hipStream_t st) {
-    TailArgs<T> A{};
-    A.n = (int)(lv.size() - ts);
-    for (int i = 0; i < A.n; ++i) {
-        MgLevel<T>& m = lv[ts + i];
-        A.lv[i] = TailLevel<T>{m.op, m.b, m.xa, m.xb, m.r, m.L.nx, m.L.ny, m.L.nz, m.L.sp, m.L.npad};
-    }
-    const size_t lds = 7 * sizeof(T) * (size_t)lv.back().L.npad;
-    A.lds = lds <= kMgTailLds ? 1 : 0;
-    hipLaunchKernelGGL(k_mg_tail<T>, dim3(1), dim3(1024), A.lds ? lds : 0, st, A, (T)kMgOmega, S);
-    if (A.n == 1) return ((kMgCoarseSweeps - 1) & 1) ? lv.back().xb : lv.back().xa;
-    return lv[ts].xa;
-}
+constexpr size_t kMgCoarseLds = 60 * 1024;   // dynamic LDS for the coarsest level's copies
 
 template <typename T>
 T* vcycle(std::vector<MgLevel<T>>& lv, size_t l, const SyncState* S, hipStream_t st, const DotFuse* fuse = nullptr,
@@ -1056,8 +931,10 @@ T* vcycle(std::vector<MgLevel<T>>& lv, size_t l, const SyncState* S, hipStream_t
         });
     };
     if (l + 1 == lv.size()) {
-        hipLaunchKernelGGL(k_mg_coarse<T>, dim3(1), dim3(1024), 0, st, m.op, (const T*)m.b, m.xa, m.xb, L.nx, L.sp,
-                           L.npad, om, kMgCoarseSweeps, S);
+        const size_t lds = 7 * sizeof(T) * (size_t)L.npad;
+        const int use_lds = lds <= kMgCoarseLds ? 1 : 0;
+        hipLaunchKernelGGL(k_mg_coarse<T>, dim3(1), dim3(1024), use_lds ? lds : 0, st, m.op, (const T*)m.b, m.xa,
+                           m.xb, L.nx, L.sp, L.npad, om, kMgCoarseSweeps, use_lds, S);
         return ((kMgCoarseSweeps - 1) & 1) ? m.xb : m.xa;
     }
     T* cur = m.xa;
@@ -1097,8 +974,7 @@ T* vcycle(std::vector<MgLevel<T>>& lv, size_t l, const SyncState* S, hipStream_t
     MgLevel<T>& c = lv[l + 1];
     hipLaunchKernelGGL(k_mg_restrict<T>, plane_grid(c.L.sp, c.L.nz), dim3(kBS), 0, st, (const T*)m.r, L.nx, L.ny,
                        L.nz, L.sp, c.b, c.L.nx, c.L.ny, c.L.nz, c.L.sp, S);
-    T* zc = (l + 1 == mg_tail_start(lv)) ? launch_tail<T>(lv, l + 1, S, st)
-                                          : vcycle<T>(lv, l + 1, S, st, nullptr, nullptr, 0, nullptr, v4);
+    T* zc = vcycle<T>(lv, l + 1, S, st, nullptr, nullptr, 0, nullptr, v4);
     hipLaunchKernelGGL(k_mg_prolong_add<T>, plane_grid((int64_t)(c.L.nx + 1) * (c.L.ny + 1), c.L.nz + 1), dim3(kBS),
                        0, st, (const T*)zc, c.L.nx, c.L.ny, c.L.nz, c.L.sp, z, L.nx, L.ny, L.nz, L.sp, S);
     cur = (z == m.xa) ? m.xb : m.xa;

@@ -393,6 +393,37 @@ __global__ void k_bitonic_step(uint64_t* __restrict__ a, int64_t n, int64_t j, i
     }
 }
 
+// The steps of the same network whose pairs lie within one aligned chunk of
+// kSortChunk keys (j < kSortChunk), in LDS: block b sorts chunk b through
+// stages k_first..k_last (powers of two), starting stage k_first at j_first.
+// The keys are distinct, so any correct sort leaves the same order.
+constexpr int kSortChunk = 2048;
+__global__ __launch_bounds__(1024) void k_bitonic_local(uint64_t* __restrict__ a, int64_t n, int64_t k_first,
+                                                        int64_t k_last, int64_t j_first) {
+    __shared__ uint64_t s[kSortChunk];
+    const int chunk = (int)min<int64_t>(n, kSortChunk);
+    const int64_t base = (int64_t)blockIdx.x * chunk;
+    for (int e = threadIdx.x; e < chunk; e += blockDim.x) s[e] = a[base + e];
+    __syncthreads();
+    for (int64_t k = k_first; k <= k_last; k <<= 1) {
+        for (int64_t j = (k == k_first) ? j_first : (k >> 1); j > 0; j >>= 1) {
+            for (int e = threadIdx.x; e < chunk; e += blockDim.x) {
+                const int le = e ^ (int)j;
+                if (le > e) {
+                    const uint64_t x = s[e], y = s[le];
+                    const bool up = ((base + e) & k) == 0;
+                    if ((x > y) == up) {
+                        s[e] = y;
+                        s[le] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = threadIdx.x; e < chunk; e += blockDim.x) a[base + e] = s[e];
+}
+
 // Charge spreading, step 2: the first key of each node's run sums the run in
 // key order (increasing atom index), starting from zero, and stores q_node.
 __global__ void k_spread_sum(const uint64_t* __restrict__ keys, int64_t npairs,
@@ -660,6 +691,22 @@ inline unsigned blocks_for(int64_t n, int bs, int64_t cap = 65536) {
     return (unsigned)b;
 }
 
+// Ascending sort of n keys (n a power of two >= 2): the stages up to the
+// chunk size in one LDS launch; each later stage k takes its steps with
+// j >= kSortChunk one launch each, then the rest in one LDS launch.
+pb_status bitonic_sort(uint64_t* keys, int64_t n, hipStream_t st) {
+    const int64_t chunk = std::min<int64_t>(n, kSortChunk);
+    const unsigned nb = (unsigned)(n / chunk);
+    hipLaunchKernelGGL(k_bitonic_local, dim3(nb), dim3(1024), 0, st, keys, n, (int64_t)2, chunk, (int64_t)1);
+    for (int64_t k = 2 * chunk; k <= n; k <<= 1) {
+        for (int64_t j = k >> 1; j >= chunk; j >>= 1)
+            hipLaunchKernelGGL(k_bitonic_step, dim3(blocks_for(n, 256, 1 << 30)), dim3(256), 0, st, keys, n, j, k);
+        hipLaunchKernelGGL(k_bitonic_local, dim3(nb), dim3(1024), 0, st, keys, n, k, k, chunk >> 1);
+    }
+    PB_HIP(hipGetLastError());
+    return PB_OK;
+}
+
 
 }  // namespace
 
@@ -786,10 +833,8 @@ pb_status setup_enqueue(const pb_grid* g, int64_t natoms, const double* xyz, con
         hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(P, 256)), dim3(256), 0, st, w.keys, P, ~0ull);
         hipLaunchKernelGGL(k_spread_keys, dim3(blocks_for(np, 256, 1 << 30)), dim3(256), 0, st, xyz,
                            natoms, nx, ny, nz, h, ox, oy, oz, per, w.keys, w.flags);
-        for (int64_t k = 2; k <= P; k <<= 1)
-            for (int64_t j = k >> 1; j > 0; j >>= 1)
-                hipLaunchKernelGGL(k_bitonic_step, dim3(blocks_for(P, 256, 1 << 30)), dim3(256), 0, st,
-                                   w.keys, P, j, k);
+        const pb_status es = bitonic_sort(w.keys, P, st);
+        if (es != PB_OK) return es;
         hipLaunchKernelGGL(k_spread_sum, dim3(blocks_for(np, 256, 1 << 30)), dim3(256), 0, st, w.keys,
                            np, xyz, charge, nx, ny, nz, h, ox, oy, oz, per, q);
     }

@@ -498,6 +498,13 @@ pb_status pb_server_submit_atoms(pb_server* server, const pb_grid* grid, int64_t
 size_t pb_server_request_bytes_atoms(const pb_grid* grid, int64_t natoms);
 /*
  * One admission + chunk + retirement round on `stream` (synchronises it).
+ * Admissions (the setup of molecule requests, preparation) run on a stream
+ * of the server's own, ordered after the work enqueued on `stream` before
+ * the call and overlapping the running chunk; a request admitted by a step
+ * joins the next step's launch, or this one's when no other request is
+ * running. The chunk runs as a plain (not cooperative) persistent launch
+ * sized to co-residency, so it must not share the device with kernels that
+ * never finish.
  * Up to max_done finished requests are reported in done_ids/done_infos
  * (pb_info.seconds = submit-to-completion time); *n_done receives the count.
  * Finished requests beyond max_done are reported by later steps.

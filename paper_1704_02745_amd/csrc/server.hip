@@ -137,6 +137,7 @@ struct Slot {
     int maxiter = 0;
     bool resume = false;             // inner solve already initialised
     bool solving = false;            // inner solve in progress
+    bool ready = false;              // admission's read-back processed: the slot may join a launch
     int outer = 0, iters = 0;
     double rr_prev = -1.0;
     int status = PB_OK;
@@ -225,6 +226,8 @@ struct Server {
     int64_t coded_launches = 0;
     double device_seconds = 0.0;
     hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev_in = nullptr;      // the caller's stream at the start of a step
+    hipStream_t adm = nullptr;       // admissions (setup, preparation), overlapping the running launch
     std::vector<char> host_table;
     std::vector<int> host_first;
     std::vector<StateDigest> host_digests;
@@ -332,6 +335,8 @@ extern "C" pb_status pb_server_create(void* arena, size_t arena_bytes, int32_t m
     S->host_first.resize(max_slots + 1);
     PB_HIP(hipEventCreate(&S->ev[0]));
     PB_HIP(hipEventCreate(&S->ev[1]));
+    PB_HIP(hipEventCreateWithFlags(&S->ev_in, hipEventDisableTiming));
+    PB_HIP(hipStreamCreateWithFlags(&S->adm, hipStreamNonBlocking));
     *out = S.release();
     return PB_OK;
 }
@@ -441,7 +446,16 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
     pb_status e;
 
     // ---- admission (arrival order; stops at the first request that does not fit)
+    // Admissions run on the server's own stream (after everything the caller
+    // enqueued before this step), overlapping this step's launch; a request
+    // admitted here joins the launch of the next step, or of this one when
+    // no other request is running.
     std::vector<Slot*> admitted;
+    hipStream_t ad = S->adm;
+    if (!S->pending.empty()) {
+        PB_HIP(hipEventRecord(S->ev_in, st));
+        PB_HIP(hipStreamWaitEvent(ad, S->ev_in, 0));
+    }
     while (!S->pending.empty() && (int)S->active.size() < S->max_slots) {
         Slot& s = *S->pending.front();
         size_t off = 0;
@@ -451,45 +465,49 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
         s.rec_idx = S->free_recs.back();
         S->free_recs.pop_back();
         s.rec = S->recs + s.rec_idx;
-        e = launch_fill<int>((int*)s.rec, (int64_t)(sizeof(SlotRec) / sizeof(int)), 0, st);
+        e = launch_fill<int>((int*)s.rec, (int64_t)(sizeof(SlotRec) / sizeof(int)), 0, ad);
         if (e != PB_OK) return e;
         if (s.from_atoms) {
             e = setup_enqueue(&s.grid, s.natoms, s.xyz, s.radius, s.charge, s.eps_in, s.eps_out, s.kappa_d2, false,
                               (double*)s.req.eps_x, (double*)s.req.eps_y, (double*)s.req.eps_z,
-                              (double*)s.req.kappa2, (double*)s.req.rhs, nullptr, nullptr, s.sw, st);
+                              (double*)s.req.kappa2, (double*)s.req.rhs, nullptr, nullptr, s.sw, ad);
             if (e != PB_OK) return e;
-            PB_HIP(hipMemcpyAsync(&s.rec->setup_flags, s.sw.flags, sizeof(int), hipMemcpyDeviceToDevice, st));
+            PB_HIP(hipMemcpyAsync(&s.rec->setup_flags, s.sw.flags, sizeof(int), hipMemcpyDeviceToDevice, ad));
         }
         e = launch_prepare64(s.req.eps_x, s.req.eps_y, s.req.eps_z, s.req.kappa2, s.req.rhs, s.req.x,
-                             s.req.warm_start ? 1 : 0, 0, s.L, s.req.h, s.op64, s.b64, s.x64, &s.rec->flags, st);
+                             s.req.warm_start ? 1 : 0, 0, s.L, s.req.h, s.op64, s.b64, s.x64, &s.rec->flags, ad);
         if (e != PB_OK) return e;
         if (s.precision == PB_F32) {
-            e = launch_round32(s.op64, s.b64, s.x64, s.L.npad, s.s.op, (float*)s.s.b, s.s.x, st);
+            e = launch_round32(s.op64, s.b64, s.x64, s.L.npad, s.s.op, (float*)s.s.b, s.s.x, ad);
             if (e != PB_OK) return e;
-            e = launch_fill<int>((int*)s.S, (int64_t)(sizeof(SyncState) / sizeof(int)), 0, st);
+            e = launch_fill<int>((int*)s.S, (int64_t)(sizeof(SyncState) / sizeof(int)), 0, ad);
             if (e != PB_OK) return e;
             s.s.warm = s.req.warm_start ? 1 : 0;
             s.resume = false;
             s.solving = true;
         } else {
-            e = launch_round32(s.op64, s.b64, s.x64, s.L.npad, s.s.op, nullptr, nullptr, st);
+            e = launch_round32(s.op64, s.b64, s.x64, s.L.npad, s.s.op, nullptr, nullptr, ad);
             if (e != PB_OK) return e;
             s.s.warm = 0;
-            e = enqueue_outer_residual(s, st);
+            e = enqueue_outer_residual(s, ad);
             if (e != PB_OK) return e;
         }
         // coded coefficients: the dictionary now, the code words once the fit flag is read back
         if (coded_coefficients() && coded_layout_ok(s.L)) {
-            e = enqueue_dictionary(s.s.op, s.L.npad, (void*)s.s.q, &s.rec->fit, st);
+            e = enqueue_dictionary(s.s.op, s.L.npad, (void*)s.s.q, &s.rec->fit, ad);
             if (e != PB_OK) return e;
         }
         admitted.push_back(&s);
         S->active.push_back(std::move(S->pending.front()));
         S->pending.pop_front();
     }
-    if (!admitted.empty()) {
-        if ((e = S->read_recs(st)) != PB_OK) return e;
-        PB_HIP(hipStreamSynchronize(st));
+    // the admissions' read-back: setup and coefficient flags, the fit flag,
+    // the first FP64 residual of refinement requests; their follow-up work
+    // goes to the caller's stream
+    auto process_admitted = [&]() -> pb_status {
+        PB_HIP(hipStreamSynchronize(ad));
+        if ((e = S->read_recs(ad)) != PB_OK) return e;
+        PB_HIP(hipStreamSynchronize(ad));
         for (Slot* sp : admitted) {
             Slot& s = *sp;
             const SlotRec r = S->host_recs[s.rec_idx];
@@ -525,12 +543,19 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
                 if (e != PB_OK) return e;
             }
         }
-    }
+        for (Slot* sp : admitted) sp->ready = true;
+        admitted.clear();
+        return PB_OK;
+    };
+    bool running = false;
+    for (auto& up : S->active)
+        if (up->solving && up->ready) running = true;
+    if (!admitted.empty() && !running && (e = process_admitted()) != PB_OK) return e;
 
     // ---- one persistent launch over every slot with an inner solve in progress
     std::vector<Slot*> run;
     for (auto& up : S->active)
-        if (up->solving) run.push_back(up.get());
+        if (up->solving && up->ready) run.push_back(up.get());
     if (!run.empty()) {
         std::vector<Layout> Ls;
         std::vector<Tiling> Ts;
@@ -568,7 +593,10 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
         e = batch_reset_arrivals<float>(S->table, (int)run.size(), st);
         if (e != PB_OK) return e;
         PB_HIP(hipEventRecord(S->ev[0], st));
-        e = batch_launch<float>(S->table, S->first, (int)run.size(), first.back(), lds, st, true, coded);
+        // a plain launch sized to co-residency (a cooperative launch would
+        // keep the admissions from running beside it): workgroups still
+        // waiting for a slot get one as the admissions' kernels finish
+        e = batch_launch<float>(S->table, S->first, (int)run.size(), first.back(), lds, st, false, coded);
         if (e != PB_OK) return e;
         PB_HIP(hipEventRecord(S->ev[1], st));
         // every running request's scalars in one read-back
@@ -576,6 +604,8 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
         if (e != PB_OK) return e;
         PB_HIP(hipMemcpyAsync(S->host_digests.data(), S->digests, sizeof(StateDigest) * run.size(),
                               hipMemcpyDeviceToHost, st));
+        // this step's admissions, while the launch runs
+        if (!admitted.empty() && (e = process_admitted()) != PB_OK) return e;
         PB_HIP(hipStreamSynchronize(st));
         float ms = 0;
         PB_HIP(hipEventElapsedTime(&ms, S->ev[0], S->ev[1]));
@@ -642,6 +672,8 @@ extern "C" pb_status pb_server_step(pb_server* S, int32_t chunk, void* stream, i
         }
     }
 
+    if (!admitted.empty() && (e = process_admitted()) != PB_OK) return e;
+
     // ---- retire finished slots (their potential was handed back on the
     // stream); molecule requests first get their energy from that potential
     bool energies = false;
@@ -700,7 +732,10 @@ extern "C" pb_status pb_server_stats(const pb_server* S, pb_server_stats_t* out)
 
 extern "C" void pb_server_destroy(pb_server* S) {
     if (!S) return;
+    if (S->adm) (void)hipStreamSynchronize(S->adm);
     if (S->ev[0]) (void)hipEventDestroy(S->ev[0]);
     if (S->ev[1]) (void)hipEventDestroy(S->ev[1]);
+    if (S->ev_in) (void)hipEventDestroy(S->ev_in);
+    if (S->adm) (void)hipStreamDestroy(S->adm);
     delete S;
 }

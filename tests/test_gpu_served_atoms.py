@@ -101,3 +101,45 @@ def test_served_molecule_outside_box_fails_alone(pb):
     for i in range(3):
         assert out[i][2]["status"] == pb.PB_OK
         assert torch.equal(out[i][0], good[i][0])
+
+
+def test_served_molecules_admitted_while_others_run(pb):
+    """Molecules submitted while earlier requests are mid-solve: their setup
+    runs on the server's admission stream beside the running launch, and they
+    join the following launches. Every result is bitwise the one it gets
+    alone."""
+    reqs = _requests()
+    alone = {i: _serve(pb, reqs, [i])[i] for i in range(len(reqs))}
+    arena = sum(pb.Server.request_bytes_atoms(p.grid, p.mol.natoms) for p in reqs) + (64 << 20)
+    srv = pb.Server(arena, max_slots=32, device=DEV)
+    ids, out = {}, {}
+
+    def submit(i):
+        p = reqs[i]
+        rid = srv.submit_atoms(p.grid, p.mol.xyz, p.mol.radius, p.mol.charge, p.eps_in, p.eps_out, p.kappa_d2,
+                               tol=p.tol, precision=p.precision)
+        ids[rid] = i
+
+    def step():
+        for rid, info in srv.step(chunk=8):
+            out[ids[rid]] = (srv.outputs[rid].clone(), srv.energies.get(rid), info)
+
+    submit(1)
+    submit(3)
+    step()
+    step()
+    assert srv.stats()["active"] == 2          # both still running
+    for i in (0, 2, 4):
+        submit(i)
+        step()
+    for _ in range(100000):
+        if len(out) == len(reqs):
+            break
+        step()
+    srv.close()
+    for i in range(len(reqs)):
+        x, e, info = out[i]
+        print(f"molecule {i}: iters {info['iters']} status {info['status']}", flush=True)
+        assert info["status"] == pb.PB_OK
+        assert torch.equal(x, alone[i][0]), i
+        assert e == alone[i][1] and info["iters"] == alone[i][2]["iters"], i

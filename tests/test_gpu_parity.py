@@ -6,7 +6,8 @@ Bars (stated here, derived in the design notes):
   * right-hand side: max-norm relative difference <= 1e-12 (the boundary sum
     over atoms runs in a different order);
   * FP64 solves: true relative residual < 1e-6 at tol 1e-6 and the potential
-    within 1e-8 (relative to max|phi|) of the oracle's own iterate;
+    within 1e-8 (relative to max|phi|) of the oracle's own iterate, and within
+    1e-12 of the oracle's iterate after the same number of iterations;
   * FP32 solves: true relative residual <= 1e-5 and max|phi - phi*| /
     max|phi*| <= 1e-5 against the oracle solved to 1e-12;
   * refinement: true relative residual below the requested 1e-10 and
@@ -138,6 +139,12 @@ def test_fp64_solve_config0(pb, c0, op):
     assert np.abs(xg - o.x).max() <= 1e-8 * scale
     exact = pcg.jpcg(ref, 1e-12).x
     assert np.abs(xg - exact).max() <= 1e-5 * scale
+    # the oracle's iterate after the same number of iterations: equal up to the
+    # order of the sums (FP64 rounding, ~1e-16 relative per operation)
+    same = pcg.jpcg(ref, 1e-300, maxiter=info["iters"]).x
+    d = np.abs(xg - same).max() / scale
+    print(f"c0 f64 {op}: against the oracle's iterate {info['iters']}: {d:.3e}", flush=True)
+    assert d <= 1e-12
 
 
 @pytest.fixture(scope="module")

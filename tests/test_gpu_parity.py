@@ -415,6 +415,24 @@ def test_solvation_molecule_with_salt(pb, c0):
     assert np.abs(r["phi_ref"].cpu().numpy() - sol.phi_ref).max() <= 1e-8 * np.abs(sol.phi_ref).max()
 
 
+@pytest.mark.parametrize("prec,tol,bar", [("f64", 1e-10, 1e-7), ("f32_refine64", 1e-10, 1e-7)])
+def test_solvation_molecule_multigrid(pb, c0, prec, tol, bar):
+    """The same dG with both solves preconditioned by the multigrid V-cycle:
+    within the bar of the oracle's two Jacobi-PCG solves, with far fewer
+    iterations for the uniform reference."""
+    prob = c0[0]
+    g = prob.grid
+    sol = solvation.solvation_energy(g.nx, g.ny, g.nz, g.h, g.origin, prob.mol.xyz, prob.mol.radius,
+                                     prob.mol.charge, prob.eps_in, prob.eps_out, prob.kappa_d2, tol=1e-10)
+    r = pb.solvation_energy(g, prob.mol.xyz, prob.mol.radius, prob.mol.charge, prob.eps_in, prob.eps_out,
+                            prob.kappa_d2, tol=tol, precision=prec, op="mg")
+    print(f"c0 dG mg {prec}: gpu {r['dG']:.9f} oracle {sol.dG:.9f} iters {r['info_solv']['iters']}/"
+          f"{r['info_ref']['iters']} (oracle JPCG {sol.iters_solv}/{sol.iters_ref})", flush=True)
+    assert r["status"] == pb.PB_OK
+    assert abs(r["dG"] - sol.dG) <= bar * abs(sol.dG)
+    assert r["info_ref"]["iters"] * 5 < sol.iters_ref
+
+
 # ------------------------------------------------------------------ batched form
 
 BATCH_SHAPES = [(37, 29, 23, 20), (45, 45, 45, 60), (21, 30, 17, 8), (64, 9, 33, 12), (33, 33, 65, 40)]

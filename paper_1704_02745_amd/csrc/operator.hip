@@ -240,6 +240,69 @@ __global__ void k_f32_to_f64(const float* __restrict__ a, double* __restrict__ b
         b[t] = (double)a[t];
 }
 
+// The free-space k_residual64 with two consecutive positions per thread
+// (16-byte loads of the node's own values and of the planes above and below;
+// per_block even, so every pair is aligned): each r is formed with the same
+// operations in the same order, so r64 and r32 are bit for bit those of
+// k_residual64; the partial sums add the pair's two terms in turn.
+__device__ __forceinline__ double2 ld2(const double* p) { return *reinterpret_cast<const double2*>(p); }
+template <int BS>
+__global__ __launch_bounds__(BS) void k_residual64_pairs(
+        const double* __restrict__ cx, const double* __restrict__ cy, const double* __restrict__ cz,
+        const double* __restrict__ d, const double* __restrict__ b, const double* __restrict__ x, int nx,
+        int64_t sp, int64_t npad, int64_t per_block, double* __restrict__ r64, float* __restrict__ r32,
+        double* __restrict__ partials) {
+    const int64_t lo = (int64_t)blockIdx.x * per_block;
+    const int64_t hi = min(lo + per_block, npad);
+    double rr = 0.0, bb = 0.0;
+    for (int64_t t = lo + 2 * (int64_t)threadIdx.x; t < hi; t += 2 * BS) {
+        const double2 cxv = ld2(cx + t), cyv = ld2(cy + t), czv = ld2(cz + t), dv = ld2(d + t), bv2 = ld2(b + t),
+                      xv = ld2(x + t);
+        const double2 xzu = t + sp < npad ? ld2(x + t + sp) : make_double2(0.0, 0.0);
+        const double2 xzd = t >= sp ? ld2(x + t - sp) : make_double2(0.0, 0.0);
+        const double2 czd = t >= sp ? ld2(cz + t - sp) : make_double2(0.0, 0.0);
+        const double xl = t >= 1 ? x[t - 1] : 0.0, cxl = t >= 1 ? cx[t - 1] : 0.0;
+        const double xr = t + 2 < npad ? x[t + 2] : 0.0;
+        double r2[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int64_t q = t + u;
+            const double cxq = u ? cxv.y : cxv.x, cyq = u ? cyv.y : cyv.x, czq = u ? czv.y : czv.x;
+            const double xq = u ? xv.y : xv.x;
+            const double xnext = u ? xr : xv.y;                 // x[q + 1]
+            const double xprev = u ? xv.x : xl, cprev = u ? cxv.x : cxl;   // x[q - 1], cx[q - 1]
+            double nb = cxq * (q + 1 < npad ? xnext : 0.0);
+            nb += (q >= 1 ? cprev * xprev : 0.0);
+            nb += cyq * (q + nx < npad ? x[q + nx] : 0.0);
+            nb += (q >= nx ? cy[q - nx] * x[q - nx] : 0.0);
+            nb += czq * (q + sp < npad ? (u ? xzu.y : xzu.x) : 0.0);
+            nb += (q >= sp ? (u ? czd.y : czd.x) * (u ? xzd.y : xzd.x) : 0.0);
+            const double bq = u ? bv2.y : bv2.x;
+            const double rv = bq - ((u ? dv.y : dv.x) * xq - nb);
+            r2[u] = rv;
+            rr += rv * rv;
+            bb += bq * bq;
+        }
+        if (r64) *reinterpret_cast<double2*>(r64 + t) = make_double2(r2[0], r2[1]);
+        if (r32) *reinterpret_cast<float2*>(r32 + t) = make_float2((float)r2[0], (float)r2[1]);
+    }
+    __shared__ double s[2][BS];
+    s[0][threadIdx.x] = rr;
+    s[1][threadIdx.x] = bb;
+    __syncthreads();
+    for (int w = BS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s[0][threadIdx.x] += s[0][threadIdx.x + w];
+            s[1][threadIdx.x] += s[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = s[0][0];
+        partials[2 * blockIdx.x + 1] = s[1][0];
+    }
+}
+
 // ---------------------------------------------------------------- host wrappers
 
 static unsigned grid_for(int64_t n, int bs = 256, int64_t cap = 8192) {
@@ -272,14 +335,17 @@ int residual_blocks(const Layout& L) {
 
 pb_status launch_residual64(Op<double> op, const double* b, const double* x, const Layout& L, int periodic,
                             double* r64, float* r32, double* partials, double* out2, hipStream_t st) {
-    const int nblk = residual_blocks(L);
-    const int64_t per = (L.npad + nblk - 1) / nblk;
-    if (periodic)
+    int nblk = residual_blocks(L);
+    int64_t per = (L.npad + nblk - 1) / nblk;
+    if (periodic) {
         hipLaunchKernelGGL((k_residual64<256, true>), dim3(nblk), dim3(256), 0, st, op.cx, op.cy, op.cz, op.d, b,
                            x, L.nx, L.ny, L.nz, L.sp, L.npad, per, r64, r32, partials);
-    else
-        hipLaunchKernelGGL((k_residual64<256, false>), dim3(nblk), dim3(256), 0, st, op.cx, op.cy, op.cz, op.d,
-                           b, x, L.nx, L.ny, L.nz, L.sp, L.npad, per, r64, r32, partials);
+    } else {
+        per = (per + 1) & ~(int64_t)1;   // pairs: even ranges (npad is a multiple of 64)
+        nblk = (int)((L.npad + per - 1) / per);
+        hipLaunchKernelGGL(k_residual64_pairs<256>, dim3(nblk), dim3(256), 0, st, op.cx, op.cy, op.cz, op.d, b, x,
+                           L.nx, L.sp, L.npad, per, r64, r32, partials);
+    }
     hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(256), 0, st, partials, nblk, out2);
     PB_HIP(hipGetLastError());
     return PB_OK;

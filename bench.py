@@ -605,9 +605,8 @@ def main():
                          "(profiling): " + ", ".join(sorted(FORMS)))
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "independent solves shard across GPUs without communication, see the design notes.",
-              file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {args.gpus}); independent "
+              "solves would shard across GPUs without communication, one process per GPU.", file=sys.stderr)
         sys.exit(2)
 
     import torch
